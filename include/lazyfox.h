@@ -1,0 +1,182 @@
+/*
+ * lazyfox.h -- C ABI of the MI355X (gfx950) LazyFox hot-path library.
+ *
+ * The library runs the data-parallel hot path of LazyFox (Garrels et al., arXiv 2210.03211)
+ * on one GPU: graph preprocessing, per-node triangles / clustering coefficients / node
+ * order, the greedy initial clustering, and LazyFox iterations (queue-batched evaluation of
+ * the WCC-hat change of every join and leave action, argmax decision, bulk apply, stopping
+ * rule and removal of degenerate communities).
+ *
+ * Conventions for every function below:
+ *  - return value: LF_OK (0) or a negative LF_E* status; the text of the last error is
+ *    available from lf_last_error(h);
+ *  - "host" pointers are ordinary CPU memory owned by the caller; "device" pointers are
+ *    HIP device memory on the handle's device, also owned by the caller;
+ *  - inputs are copied: the caller may free or reuse them after the call returns;
+ *  - every call is synchronous with respect to the host and stream-ordered on the handle's
+ *    HIP stream; a handle must be used by one host thread at a time, separate handles are
+ *    independent;
+ *  - node ids are dense 0..n-1 after lf_load_graph; community ids are the creation index of
+ *    the initial clustering (0..K-1) and are never renumbered.
+ */
+#ifndef LAZYFOX_H
+#define LAZYFOX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LF_OK 0
+#define LF_EINVAL (-1)      /* bad argument: q < 1, theta NaN or < 0, id out of range, ... */
+#define LF_ESTATE (-2)      /* call out of order (e.g. run before init) */
+#define LF_ENOMEM (-3)      /* device or host allocation failed */
+#define LF_EDEVICE (-4)     /* HIP runtime error (text in lf_last_error) */
+#define LF_ERANGE (-5)      /* caller buffer too small */
+#define LF_EOVERFLOW (-6)   /* size beyond the supported integer ranges */
+#define LF_EINTERNAL (-8)   /* an internal consistency check failed */
+
+/* lf_load_graph flags */
+#define LF_RELABEL 1u       /* compact the ids that occur to 0..n-1, order-preserving */
+#define LF_DEVICE_PTR 2u    /* src/dst are device pointers (else host pointers) */
+
+typedef struct lf_handle lf_handle;
+
+/* Result of lf_run_iterations.  The four array pointers are caller-owned host buffers
+   (any may be NULL): wtilde_hist has max_iters + 1 entries (entry 0 = before iteration 1),
+   the others max_iters entries. */
+typedef struct {
+    int32_t iterations;     /* iterations run in this call */
+    int32_t converged;      /* stopping rule met (or nothing to optimise) */
+    int32_t hit_max;        /* stopped because max_iters was reached */
+    int32_t pad;
+    double wcc_hat;         /* WCC-hat(P) of the final partition (0 if cc == 0) */
+    double wtilde;          /* cc * WCC-hat(P): the cc-free partition score */
+    double *wtilde_hist;
+    int64_t *joins;         /* join actions applied per iteration */
+    int64_t *leaves;        /* leave actions applied per iteration */
+    int64_t *communities;   /* communities with >= 2 members after each iteration */
+} lf_run_info;
+
+/* Per-kernel-class timing, collected with HIP events on the handle's stream when
+   profiling is enabled (lf_set_profiling). */
+#define LF_K_BUILD 0        /* graph build (sorts, CSR) */
+#define LF_K_TRIANGLES 1    /* triangle counting (all launches) */
+#define LF_K_ORDER 2        /* CC, cc reduction, node order */
+#define LF_K_INITCLUST 3    /* initial clustering and state set-up */
+#define LF_K_EVAL 4         /* join/leave evaluation (wave path) */
+#define LF_K_EVAL_HUB 5     /* join/leave evaluation (workgroup path) */
+#define LF_K_APPLY 6        /* bulk apply: membership edits, in-counts, community re-sums */
+#define LF_K_ITEREND 7      /* iteration end: degenerate removal, compaction, score */
+#define LF_K_COUNT 8
+typedef struct {
+    int64_t launches[LF_K_COUNT];
+    double ms[LF_K_COUNT];
+    int64_t chunks;          /* chunks processed */
+    int64_t node_evals;      /* queued-node evaluations */
+    int64_t visits;          /* neighbour-membership visits in the evaluation kernels */
+    int64_t candidates;      /* candidate communities evaluated */
+} lf_profile;
+
+/* Create a handle on HIP device `device`.  `hip_stream` is a hipStream_t (for example
+   torch.cuda.current_stream().cuda_stream) or NULL for a library-owned stream.
+   flags: reserved, pass 0. */
+int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags);
+
+/* Free every device and host resource of the handle.  NULL is accepted. */
+int lf_destroy(lf_handle *h);
+
+/* Text of the last error on this handle (static storage owned by the handle). */
+const char *lf_last_error(lf_handle *h);
+
+/*
+ * Input and preprocessing (Methods, "Input Data" and "Preprocessing": multi-edge removal,
+ * dense node labels).  src[e], dst[e] (int64, n_pairs entries, host or device memory per
+ * LF_DEVICE_PTR) are undirected edges; duplicates and both directions are allowed and
+ * merged, self-loops are dropped.  Without LF_RELABEL ids must lie in [0, n) (isolated
+ * nodes are allowed); with LF_RELABEL the argument n is ignored and the ids that occur in
+ * a non-self-loop pair are compacted to 0..n-1 in increasing order.
+ * Builds a symmetric CSR with every row sorted ascending.  Resets any previous state.
+ * Errors: LF_EINVAL (negative sizes, id out of range), LF_EOVERFLOW (n >= 2^31 or
+ * 2|E| >= 2^31), LF_ENOMEM, LF_EDEVICE.
+ */
+int lf_load_graph(lf_handle *h, int64_t n, int64_t n_pairs, const int64_t *src,
+                  const int64_t *dst, uint32_t flags);
+
+/*
+ * Node statistics and initial clustering (Methods, "Node Order", "Initial Clustering";
+ * global cc from the WCC-hat subsection): triangles k_i, local CC(i) = k_i / (d_i(d_i-1)/2)
+ * (0 if d_i <= 1), node order by CC descending, then degree descending, then id
+ * ascending; cc = mean of all local CCs; greedy clustering in node order (a node without a
+ * community opens one and its unassigned neighbours join it); per-community size, internal
+ * edges and WCC-hat.  Calling it again restarts from the initial clustering.
+ * Errors: LF_ESTATE (no graph), LF_ENOMEM, LF_EDEVICE.
+ */
+int lf_init_communities(lf_handle *h);
+
+/*
+ * LazyFox iterations (Methods, "Node Changes", Algorithm 2, "Stopping Criteria",
+ * "Post-processing").  Each iteration walks the node order in consecutive queues of
+ * `queue_size` nodes (the last one partial); every node of a queue gets its best join
+ * (largest strictly positive WCC-hat gain over communities of its neighbours it is not
+ * in) and best leave (same over its own communities), ties to the lowest community id,
+ * all evaluated on the state at the start of the queue; then all of them are applied.
+ * After each iteration communities with fewer than two members are removed; the run stops
+ * when the relative WCC-hat improvement over the previous iteration is below `threshold`
+ * (iteration 1 compares with the initial clustering), or after `max_iters` iterations.
+ * A later call continues from the current partition.  `out` may be NULL.
+ * Errors: LF_EINVAL (queue_size < 1, threshold NaN or < 0, max_iters < 0), LF_ESTATE.
+ */
+int lf_run_iterations(lf_handle *h, int32_t queue_size, double threshold, int32_t max_iters,
+                      lf_run_info *out);
+
+/*
+ * Memberships of every node (host buffers).  offsets: n + 1 entries; comm_ids: capacity
+ * entries; per node the community ids ascending.  With offsets == NULL or comm_ids == NULL
+ * only *total is written (two-call pattern).  LF_ERANGE if capacity < *total.
+ */
+int lf_get_memberships(lf_handle *h, int64_t *offsets, int32_t *comm_ids, int64_t capacity,
+                       int64_t *total);
+
+/* Graph sizes: nodes, undirected edges, communities created by the initial clustering
+   (-1 before lf_init_communities).  Any pointer may be NULL. */
+int lf_get_graph_info(lf_handle *h, int64_t *n, int64_t *nedges, int64_t *ncommunities);
+
+/* The CSR built by lf_load_graph (host buffers: rowptr n + 1, col 2|E|) and, with
+   LF_RELABEL, the input id of every dense node (orig_ids n entries; may be NULL). */
+int lf_get_csr(lf_handle *h, int64_t *rowptr, int32_t *col, int64_t *orig_ids);
+
+/* Node statistics (host buffers of n entries; any may be NULL): triangles k_i, local
+   clustering coefficient, node order (order[r] = node processed r-th). */
+int lf_get_node_stats(lf_handle *h, int64_t *tri, double *cc_local, int32_t *order);
+
+/* Scores (any pointer may be NULL): WCC-hat(P), global cc, number of triangles T,
+   cc-free score cc * WCC-hat(P). */
+int lf_get_scores(lf_handle *h, double *wcc_hat, double *cc, int64_t *triangles,
+                  double *wtilde);
+
+/* Per community id (host buffers of ncommunities entries; any may be NULL): member count,
+   internal edges, cc-free score p_C * sum_x g (WCC-hat(C) * cc). */
+int lf_get_communities(lf_handle *h, int32_t *size, int64_t *internal_edges, double *score);
+
+/* in[j] = |N(x) ∩ C| for the j-th membership in the lf_get_memberships listing. */
+int lf_get_in_counts(lf_handle *h, int32_t *in, int64_t capacity);
+
+/* Kernel timing collection (HIP events around each launch) on/off, read, reset. */
+int lf_set_profiling(lf_handle *h, int enable);
+int lf_get_profile(lf_handle *h, lf_profile *out);
+int lf_reset_profile(lf_handle *h);
+
+/*
+ * Diagnostic: the exact sum of n doubles (device pointer), rounded once to nearest-even,
+ * computed by the library's device accumulator (the one behind every score sum).
+ * Values must be finite with magnitude in [2^-113, 2^30] or zero; LF_EOVERFLOW otherwise.
+ */
+int lf_debug_exact_sum(lf_handle *h, const double *values_dev, int64_t n, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

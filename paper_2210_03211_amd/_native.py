@@ -1,0 +1,287 @@
+"""ctypes binding of liblazyfox.so: one Python method per C entry point, same names."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblazyfox.so")
+
+LF_OK, LF_EINVAL, LF_ESTATE, LF_ENOMEM, LF_EDEVICE, LF_ERANGE, LF_EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
+LF_EINTERNAL = -8
+LF_RELABEL = 1
+LF_DEVICE_PTR = 2
+KERNEL_CLASSES = ["build", "triangles", "order", "init_clustering", "eval", "eval_hub", "apply",
+                  "iteration_end"]
+
+
+class LazyFoxError(RuntimeError):
+    def __init__(self, code, what, text):
+        super().__init__("%s failed (status %d): %s" % (what, code, text))
+        self.code = code
+
+
+class RunInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("hit_max", C.c_int32),
+                ("pad", C.c_int32), ("wcc_hat", C.c_double), ("wtilde", C.c_double),
+                ("wtilde_hist", C.POINTER(C.c_double)), ("joins", C.POINTER(C.c_int64)),
+                ("leaves", C.POINTER(C.c_int64)), ("communities", C.POINTER(C.c_int64))]
+
+
+class Profile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8), ("chunks", C.c_int64),
+                ("node_evals", C.c_int64), ("visits", C.c_int64), ("candidates", C.c_int64)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load liblazyfox.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("liblazyfox.so is not built (run `python -m paper_2210_03211_amd.build` "
+                          "or __graft_entry__.build()); the HIP library is required")
+    L = C.CDLL(_LIB_PATH)
+    vp, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
+    sig = {
+        "lf_create": [C.POINTER(vp), C.c_int, vp, u32],
+        "lf_destroy": [vp],
+        "lf_load_graph": [vp, i64, i64, vp, vp, u32],
+        "lf_init_communities": [vp],
+        "lf_run_iterations": [vp, i32, dbl, i32, C.POINTER(RunInfo)],
+        "lf_get_memberships": [vp, vp, vp, i64, C.POINTER(i64)],
+        "lf_get_graph_info": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
+        "lf_get_csr": [vp, vp, vp, vp],
+        "lf_get_node_stats": [vp, vp, vp, vp],
+        "lf_get_scores": [vp, vp, vp, vp, vp],
+        "lf_get_communities": [vp, vp, vp, vp],
+        "lf_get_in_counts": [vp, vp, i64],
+        "lf_set_profiling": [vp, C.c_int],
+        "lf_get_profile": [vp, C.POINTER(Profile)],
+        "lf_reset_profile": [vp],
+        "lf_debug_exact_sum": [vp, vp, i64, C.POINTER(dbl)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.lf_last_error.argtypes = [vp]
+    L.lf_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    """(address, is_device) of a numpy array or a torch tensor."""
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data, False
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr(), bool(a.is_cuda)
+    raise TypeError("expected a numpy array or a torch tensor")
+
+
+def _current_stream(device):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    except ImportError:
+        pass
+    return None
+
+
+class Handle:
+    """One graph's device-resident LazyFox state (``lf_handle``)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.L = load_library()
+        self.h = C.c_void_p()
+        if stream is None:
+            stream = _current_stream(device)
+        elif hasattr(stream, "cuda_stream"):
+            stream = C.c_void_p(stream.cuda_stream)
+        rc = self.L.lf_create(C.byref(self.h), int(device), stream, 0)
+        if rc != 0:
+            raise LazyFoxError(rc, "lf_create", "device %d unavailable" % device)
+        self.device = device
+
+    # -- lifetime ------------------------------------------------------------------
+    def lf_destroy(self):
+        if self.h:
+            self.L.lf_destroy(self.h)
+            self.h = C.c_void_p()
+
+    close = lf_destroy
+
+    def __del__(self):
+        try:
+            self.lf_destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.lf_destroy()
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise LazyFoxError(rc, what, self.L.lf_last_error(self.h).decode(errors="replace"))
+
+    # -- C entry points ------------------------------------------------------------
+    def lf_load_graph(self, n, src, dst, relabel=False):
+        ps, ds = _ptr(src)
+        pd, dd = _ptr(dst)
+        if ds != dd:
+            raise ValueError("src and dst must both be host or both be device arrays")
+        for a in (src, dst):
+            if str(getattr(a, "dtype", "")) not in ("int64", "torch.int64"):
+                raise TypeError("edge arrays must be int64")
+        npairs = int(src.shape[0])
+        if int(dst.shape[0]) != npairs:
+            raise ValueError("src and dst differ in length")
+        flags = (LF_RELABEL if relabel else 0) | (LF_DEVICE_PTR if ds else 0)
+        self._check(self.L.lf_load_graph(self.h, int(n), npairs, C.c_void_p(ps), C.c_void_p(pd), flags),
+                    "lf_load_graph")
+        return self
+
+    load_graph = lf_load_graph
+
+    def lf_init_communities(self):
+        self._check(self.L.lf_init_communities(self.h), "lf_init_communities")
+        return self
+
+    init_communities = lf_init_communities
+
+    def lf_run_iterations(self, queue_size, threshold=0.01, max_iters=50):
+        hist = np.zeros(max_iters + 1, np.float64)
+        joins = np.zeros(max(1, max_iters), np.int64)
+        leaves = np.zeros(max(1, max_iters), np.int64)
+        comms = np.zeros(max(1, max_iters), np.int64)
+        info = RunInfo()
+        info.wtilde_hist = hist.ctypes.data_as(C.POINTER(C.c_double))
+        info.joins = joins.ctypes.data_as(C.POINTER(C.c_int64))
+        info.leaves = leaves.ctypes.data_as(C.POINTER(C.c_int64))
+        info.communities = comms.ctypes.data_as(C.POINTER(C.c_int64))
+        self._check(self.L.lf_run_iterations(self.h, int(queue_size), float(threshold), int(max_iters),
+                                             C.byref(info)), "lf_run_iterations")
+        it = info.iterations
+        return dict(iterations=it, converged=bool(info.converged), hit_max=bool(info.hit_max),
+                    wcc_hat=info.wcc_hat, wtilde=info.wtilde, wtilde_hist=hist[: it + 1].copy(),
+                    joins=joins[:it].copy(), leaves=leaves[:it].copy(), communities=comms[:it].copy())
+
+    run_iterations = lf_run_iterations
+
+    def lf_get_graph_info(self):
+        n, ne, k = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self.L.lf_get_graph_info(self.h, C.byref(n), C.byref(ne), C.byref(k)), "lf_get_graph_info")
+        return n.value, ne.value, k.value
+
+    @property
+    def n(self):
+        return self.lf_get_graph_info()[0]
+
+    @property
+    def nedges(self):
+        return self.lf_get_graph_info()[1]
+
+    def lf_get_memberships(self):
+        tot = C.c_int64()
+        self._check(self.L.lf_get_memberships(self.h, None, None, 0, C.byref(tot)), "lf_get_memberships")
+        n = self.n
+        off = np.zeros(n + 1, np.int64)
+        ids = np.zeros(max(1, tot.value), np.int32)
+        self._check(self.L.lf_get_memberships(self.h, C.c_void_p(off.ctypes.data), C.c_void_p(ids.ctypes.data),
+                                              ids.size, C.byref(tot)), "lf_get_memberships")
+        return off, ids[: tot.value]
+
+    get_memberships = lf_get_memberships
+    memberships = lf_get_memberships
+
+    def lf_get_in_counts(self):
+        off, ids = self.lf_get_memberships()
+        inc = np.zeros(max(1, ids.size), np.int32)
+        self._check(self.L.lf_get_in_counts(self.h, C.c_void_p(inc.ctypes.data), inc.size), "lf_get_in_counts")
+        return inc[: ids.size]
+
+    in_counts = lf_get_in_counts
+
+    def lf_get_csr(self):
+        n, ne, _ = self.lf_get_graph_info()
+        rp = np.zeros(n + 1, np.int64)
+        col = np.zeros(max(1, 2 * ne), np.int32)
+        ids = np.zeros(max(1, n), np.int64)
+        self._check(self.L.lf_get_csr(self.h, C.c_void_p(rp.ctypes.data), C.c_void_p(col.ctypes.data),
+                                      C.c_void_p(ids.ctypes.data)), "lf_get_csr")
+        return rp, col[: 2 * ne], ids[:n]
+
+    def csr(self):
+        rp, col, _ = self.lf_get_csr()
+        return rp, col
+
+    def orig_ids(self):
+        return self.lf_get_csr()[2]
+
+    def lf_get_node_stats(self):
+        n = self.n
+        tri = np.zeros(max(1, n), np.int64)
+        ccl = np.zeros(max(1, n), np.float64)
+        order = np.zeros(max(1, n), np.int32)
+        self._check(self.L.lf_get_node_stats(self.h, C.c_void_p(tri.ctypes.data), C.c_void_p(ccl.ctypes.data),
+                                             C.c_void_p(order.ctypes.data)), "lf_get_node_stats")
+        return tri[:n], ccl[:n], order[:n]
+
+    node_stats = lf_get_node_stats
+
+    def lf_get_scores(self):
+        w, cc, wt = C.c_double(), C.c_double(), C.c_double()
+        T = C.c_int64()
+        self._check(self.L.lf_get_scores(self.h, C.byref(w), C.byref(cc), C.byref(T), C.byref(wt)),
+                    "lf_get_scores")
+        return dict(wcc_hat=w.value, cc=cc.value, triangles=T.value, wtilde=wt.value)
+
+    scores = lf_get_scores
+
+    def lf_get_communities(self):
+        K = self.lf_get_graph_info()[2]
+        s = np.zeros(max(1, K), np.int32)
+        m = np.zeros(max(1, K), np.int64)
+        W = np.zeros(max(1, K), np.float64)
+        self._check(self.L.lf_get_communities(self.h, C.c_void_p(s.ctypes.data), C.c_void_p(m.ctypes.data),
+                                              C.c_void_p(W.ctypes.data)), "lf_get_communities")
+        return s[:K], m[:K], W[:K]
+
+    communities = lf_get_communities
+
+    def lf_set_profiling(self, enable=True):
+        self._check(self.L.lf_set_profiling(self.h, int(bool(enable))), "lf_set_profiling")
+
+    def lf_reset_profile(self):
+        self._check(self.L.lf_reset_profile(self.h), "lf_reset_profile")
+
+    def lf_get_profile(self):
+        p = Profile()
+        self._check(self.L.lf_get_profile(self.h, C.byref(p)), "lf_get_profile")
+        return dict(launches={k: int(p.launches[i]) for i, k in enumerate(KERNEL_CLASSES)},
+                    ms={k: float(p.ms[i]) for i, k in enumerate(KERNEL_CLASSES)},
+                    chunks=int(p.chunks), node_evals=int(p.node_evals), visits=int(p.visits),
+                    candidates=int(p.candidates))
+
+    def lf_debug_exact_sum(self, values_dev):
+        p, is_dev = _ptr(values_dev)
+        if not is_dev:
+            raise ValueError("lf_debug_exact_sum takes a device array")
+        out = C.c_double()
+        self._check(self.L.lf_debug_exact_sum(self.h, C.c_void_p(p), int(values_dev.numel()), C.byref(out)),
+                    "lf_debug_exact_sum")
+        return out.value

@@ -1,0 +1,254 @@
+// api.hip -- the C ABI declared in include/lazyfox.h.
+#include <math.h>
+#include <stdlib.h>
+
+#include "lf_internal.h"
+
+extern "C" {
+
+int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
+{
+    (void)flags;
+    if (!out) return LF_EINVAL;
+    *out = nullptr;
+    lf_handle *h = (lf_handle *)calloc(1, sizeof(lf_handle));
+    if (!h) return LF_ENOMEM;
+    h->allocs = new std::vector<void *>();
+    h->device = device;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        delete h->allocs;
+        free(h);
+        return LF_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        delete h->allocs;
+        free(h);
+        return LF_EDEVICE;
+    }
+    if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+        h->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete h->allocs;
+            free(h);
+            return LF_EDEVICE;
+        }
+        h->own_stream = true;
+    }
+    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+        if (h->own_stream) (void)hipStreamDestroy(h->stream);
+        delete h->allocs;
+        free(h);
+        return LF_EDEVICE;
+    }
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    h->eval_wave_cap = 128;
+    h->hub_lds_entries = 2048;
+    h->hub_blocks = 2 * cus;
+    h->refresh_blocks = 2 * cus;
+    h->K = -1;
+    *out = h;
+    return LF_OK;
+}
+
+int lf_destroy(lf_handle *h)
+{
+    if (!h) return LF_OK;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    for (void *p : *h->allocs) (void)hipFree(p);
+    delete h->allocs;
+    (void)hipEventDestroy(h->ev0);
+    (void)hipEventDestroy(h->ev1);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    free(h);
+    return LF_OK;
+}
+
+const char *lf_last_error(lf_handle *h) { return h ? h->err : "null handle"; }
+
+static void reset_graph(lf_handle *h)
+{
+    lf_free_partition(h);
+    void **ptrs[] = {(void **)&h->rowptr, (void **)&h->col, (void **)&h->deg, (void **)&h->orig_id,
+                     (void **)&h->tri, (void **)&h->ccl, (void **)&h->order, (void **)&h->rank};
+    for (void **p : ptrs) {
+        lf_dev_free(h, *p);
+        *p = nullptr;
+    }
+    h->n = h->ne = 0;
+    h->K = -1;
+    h->state = 0;
+    h->cc = 0.0;
+    h->T = 0;
+    h->Wt = 0.0;
+}
+
+int lf_load_graph(lf_handle *h, int64_t n, int64_t n_pairs, const int64_t *src, const int64_t *dst,
+                  uint32_t flags)
+{
+    if (!h) return LF_EINVAL;
+    LF_HIP(h, hipSetDevice(h->device));
+    if (n_pairs < 0 || (!(flags & LF_RELABEL) && n < 0))
+        return lf_set_error(h, LF_EINVAL, "negative size");
+    if (n_pairs > 0 && (!src || !dst)) return lf_set_error(h, LF_EINVAL, "null edge arrays");
+    if (n_pairs >= (1ll << 31) - 1) return lf_set_error(h, LF_EOVERFLOW, "n_pairs >= 2^31 - 1");
+    if (!(flags & LF_RELABEL) && n >= (1ll << 31) - 1)
+        return lf_set_error(h, LF_EOVERFLOW, "n >= 2^31 - 1");
+    reset_graph(h);
+    LF_HIP(h, hipStreamSynchronize(h->stream));
+    LF_TRY(lf_prof_begin(h));
+    int rc = lf_build_graph(h, n, n_pairs, (const long long *)src, (const long long *)dst, flags);
+    if (rc != LF_OK) {
+        char keep[512];
+        memcpy(keep, h->err, sizeof keep);
+        reset_graph(h);
+        memcpy(h->err, keep, sizeof keep);
+        return rc;
+    }
+    LF_TRY(lf_prof_end(h, LF_K_BUILD, 8));
+    h->state = 1;
+    return LF_OK;
+}
+
+int lf_init_communities(lf_handle *h)
+{
+    if (!h) return LF_EINVAL;
+    if (h->state < 1) return lf_set_error(h, LF_ESTATE, "lf_load_graph has not been called");
+    LF_HIP(h, hipSetDevice(h->device));
+    if (h->state == 1 || !h->order) {
+        void **ptrs[] = {(void **)&h->tri, (void **)&h->ccl, (void **)&h->order, (void **)&h->rank};
+        for (void **p : ptrs) {
+            lf_dev_free(h, *p);
+            *p = nullptr;
+        }
+        LF_TRY(lf_node_stats(h));
+    }
+    h->state = 1;
+    LF_TRY(lf_initial_clustering(h));
+    h->state = 2;
+    return LF_OK;
+}
+
+int lf_run_iterations(lf_handle *h, int32_t queue_size, double threshold, int32_t max_iters, lf_run_info *out)
+{
+    if (!h) return LF_EINVAL;
+    if (queue_size < 1 || isnan(threshold) || threshold < 0.0 || max_iters < 0)
+        return lf_set_error(h, LF_EINVAL, "bad argument (queue_size %d, threshold %g, max_iters %d)", queue_size,
+                            threshold, max_iters);
+    if (h->state < 2) return lf_set_error(h, LF_ESTATE, "lf_init_communities has not been called");
+    LF_HIP(h, hipSetDevice(h->device));
+    return lf_iterate(h, queue_size, threshold, max_iters, out);
+}
+
+int lf_get_memberships(lf_handle *h, int64_t *offsets, int32_t *comm_ids, int64_t capacity, int64_t *total)
+{
+    if (!h || !total) return LF_EINVAL;
+    if (h->state < 2) return lf_set_error(h, LF_ESTATE, "no communities yet");
+    LF_HIP(h, hipSetDevice(h->device));
+    long long tot = 0;
+    int rc = lf_fetch_memberships(h, (long long *)offsets, comm_ids, capacity, &tot,
+                                  nullptr);
+    *total = tot;
+    return rc;
+}
+
+int lf_get_in_counts(lf_handle *h, int32_t *in, int64_t capacity)
+{
+    if (!h || !in) return LF_EINVAL;
+    if (h->state < 2) return lf_set_error(h, LF_ESTATE, "no communities yet");
+    LF_HIP(h, hipSetDevice(h->device));
+    std::vector<long long> off((size_t)h->n + 1);
+    long long tot = 0;
+    return lf_fetch_memberships(h, off.data(), nullptr, capacity, &tot, in);
+}
+
+int lf_get_graph_info(lf_handle *h, int64_t *n, int64_t *nedges, int64_t *ncommunities)
+{
+    if (!h) return LF_EINVAL;
+    if (n) *n = h->n;
+    if (nedges) *nedges = h->ne;
+    if (ncommunities) *ncommunities = h->state >= 2 ? h->K : -1;
+    return LF_OK;
+}
+
+int lf_get_csr(lf_handle *h, int64_t *rowptr, int32_t *col, int64_t *orig_ids)
+{
+    if (!h) return LF_EINVAL;
+    if (h->state < 1) return lf_set_error(h, LF_ESTATE, "no graph loaded");
+    LF_HIP(h, hipSetDevice(h->device));
+    if (rowptr) LF_HIP(h, hipMemcpy(rowptr, h->rowptr, sizeof(long long) * (h->n + 1), hipMemcpyDeviceToHost));
+    if (col && h->ne > 0) LF_HIP(h, hipMemcpy(col, h->col, sizeof(int) * 2 * h->ne, hipMemcpyDeviceToHost));
+    if (orig_ids && h->n > 0) LF_HIP(h, hipMemcpy(orig_ids, h->orig_id, sizeof(long long) * h->n, hipMemcpyDeviceToHost));
+    return LF_OK;
+}
+
+int lf_get_node_stats(lf_handle *h, int64_t *tri, double *cc_local, int32_t *order)
+{
+    if (!h) return LF_EINVAL;
+    if (h->state < 2) return lf_set_error(h, LF_ESTATE, "lf_init_communities has not been called");
+    LF_HIP(h, hipSetDevice(h->device));
+    size_t n = (size_t)h->n;
+    if (n == 0) return LF_OK;
+    if (tri) LF_HIP(h, hipMemcpy(tri, h->tri, sizeof(long long) * n, hipMemcpyDeviceToHost));
+    if (cc_local) LF_HIP(h, hipMemcpy(cc_local, h->ccl, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (order) LF_HIP(h, hipMemcpy(order, h->order, sizeof(int) * n, hipMemcpyDeviceToHost));
+    return LF_OK;
+}
+
+int lf_get_scores(lf_handle *h, double *wcc_hat, double *cc, int64_t *triangles, double *wtilde)
+{
+    if (!h) return LF_EINVAL;
+    if (h->state < 2) return lf_set_error(h, LF_ESTATE, "lf_init_communities has not been called");
+    if (cc) *cc = h->cc;
+    if (triangles) *triangles = h->T;
+    if (wtilde) *wtilde = h->Wt;
+    if (wcc_hat) *wcc_hat = h->cc > 0.0 ? h->Wt / h->cc : 0.0;
+    return LF_OK;
+}
+
+int lf_get_communities(lf_handle *h, int32_t *size, int64_t *internal_edges, double *score)
+{
+    if (!h) return LF_EINVAL;
+    if (h->state < 2) return lf_set_error(h, LF_ESTATE, "lf_init_communities has not been called");
+    LF_HIP(h, hipSetDevice(h->device));
+    size_t K = (size_t)h->K;
+    if (K == 0) return LF_OK;
+    if (size) LF_HIP(h, hipMemcpy(size, h->cs, sizeof(int) * K, hipMemcpyDeviceToHost));
+    if (internal_edges) LF_HIP(h, hipMemcpy(internal_edges, h->cm, sizeof(long long) * K, hipMemcpyDeviceToHost));
+    if (score) LF_HIP(h, hipMemcpy(score, h->cW, sizeof(double) * K, hipMemcpyDeviceToHost));
+    return LF_OK;
+}
+
+int lf_set_profiling(lf_handle *h, int enable)
+{
+    if (!h) return LF_EINVAL;
+    h->profiling = enable ? 1 : 0;
+    return LF_OK;
+}
+
+int lf_get_profile(lf_handle *h, lf_profile *out)
+{
+    if (!h || !out) return LF_EINVAL;
+    *out = h->prof;
+    return LF_OK;
+}
+
+int lf_reset_profile(lf_handle *h)
+{
+    if (!h) return LF_EINVAL;
+    memset(&h->prof, 0, sizeof h->prof);
+    return LF_OK;
+}
+
+int lf_debug_exact_sum(lf_handle *h, const double *values_dev, int64_t n, double *out)
+{
+    if (!h || !out || n < 0 || (n > 0 && !values_dev)) return LF_EINVAL;
+    LF_HIP(h, hipSetDevice(h->device));
+    return lf_exact_sum_dev(h, values_dev, n, out);
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// prims.hip -- library primitives: device radix sorts and prefix sums (hipCUB), plus
+// the handle's allocation registry and error/profiling helpers.
+#include <stdarg.h>
+
+#include <hipcub/hipcub.hpp>
+
+#include "lf_internal.h"
+
+int lf_set_error(lf_handle *h, int code, const char *fmt, ...)
+{
+    if (h) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(h->err, sizeof h->err, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+int lf_dev_alloc(lf_handle *h, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return lf_set_error(h, LF_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    h->allocs->push_back(*p);
+    return LF_OK;
+}
+
+void lf_dev_free(lf_handle *h, void *p)
+{
+    if (!p) return;
+    for (size_t k = 0; k < h->allocs->size(); k++)
+        if ((*h->allocs)[k] == p) {
+            (*h->allocs)[k] = h->allocs->back();
+            h->allocs->pop_back();
+            break;
+        }
+    (void)hipFree(p);
+}
+
+int lf_ensure_tmp(lf_handle *h, size_t bytes)
+{
+    if (bytes <= h->tmp_bytes) return LF_OK;
+    if (h->tmp) {
+        LF_HIP(h, hipStreamSynchronize(h->stream));
+        lf_dev_free(h, h->tmp);
+        h->tmp = nullptr;
+    }
+    size_t want = bytes + bytes / 4 + 4096;
+    LF_TRY(lf_dev_alloc(h, &h->tmp, want));
+    h->tmp_bytes = want;
+    return LF_OK;
+}
+
+int lf_prof_begin(lf_handle *h)
+{
+    if (!h->profiling) return LF_OK;
+    LF_HIP(h, hipEventRecord(h->ev0, h->stream));
+    return LF_OK;
+}
+
+int lf_prof_end(lf_handle *h, int kind, int launches)
+{
+    if (!h->profiling) return LF_OK;
+    LF_HIP(h, hipEventRecord(h->ev1, h->stream));
+    LF_HIP(h, hipEventSynchronize(h->ev1));
+    float ms = 0.f;
+    LF_HIP(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->prof.ms[kind] += ms;
+    h->prof.launches[kind] += launches;
+    return LF_OK;
+}
+
+int lf_sort_u64(lf_handle *h, unsigned long long *keys, unsigned long long *keys_alt, long long n,
+                int end_bit, unsigned long long **result)
+{
+    *result = keys;
+    if (n <= 1) return LF_OK;
+    hipcub::DoubleBuffer<unsigned long long> db(keys, keys_alt);
+    size_t bytes = 0;
+    LF_HIP(h, hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, db, (int)n, 0, end_bit, h->stream));
+    LF_TRY(lf_ensure_tmp(h, bytes));
+    bytes = h->tmp_bytes;
+    LF_HIP(h, hipcub::DeviceRadixSort::SortKeys(h->tmp, bytes, db, (int)n, 0, end_bit, h->stream));
+    *result = db.Current();
+    return LF_OK;
+}
+
+int lf_sort_pairs_u64_i32(lf_handle *h, unsigned long long *keys, unsigned long long *keys_alt,
+                          int *vals, int *vals_alt, long long n, int end_bit,
+                          unsigned long long **rkeys, int **rvals)
+{
+    *rkeys = keys;
+    *rvals = vals;
+    if (n <= 1) return LF_OK;
+    hipcub::DoubleBuffer<unsigned long long> dk(keys, keys_alt);
+    hipcub::DoubleBuffer<int> dv(vals, vals_alt);
+    size_t bytes = 0;
+    LF_HIP(h, hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, dk, dv, (int)n, 0, end_bit, h->stream));
+    LF_TRY(lf_ensure_tmp(h, bytes));
+    bytes = h->tmp_bytes;
+    LF_HIP(h, hipcub::DeviceRadixSort::SortPairs(h->tmp, bytes, dk, dv, (int)n, 0, end_bit, h->stream));
+    *rkeys = dk.Current();
+    *rvals = dv.Current();
+    return LF_OK;
+}
+
+int lf_sort_pairs_u32_i32(lf_handle *h, unsigned *keys, unsigned *keys_alt, int *vals,
+                          int *vals_alt, long long n, unsigned **rkeys, int **rvals)
+{
+    *rkeys = keys;
+    *rvals = vals;
+    if (n <= 1) return LF_OK;
+    hipcub::DoubleBuffer<unsigned> dk(keys, keys_alt);
+    hipcub::DoubleBuffer<int> dv(vals, vals_alt);
+    size_t bytes = 0;
+    LF_HIP(h, hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, dk, dv, (int)n, 0, 32, h->stream));
+    LF_TRY(lf_ensure_tmp(h, bytes));
+    bytes = h->tmp_bytes;
+    LF_HIP(h, hipcub::DeviceRadixSort::SortPairs(h->tmp, bytes, dk, dv, (int)n, 0, 32, h->stream));
+    *rkeys = dk.Current();
+    *rvals = dv.Current();
+    return LF_OK;
+}
+
+int lf_exclusive_scan_i64(lf_handle *h, const long long *in, long long *out, long long n)
+{
+    if (n <= 0) return LF_OK;
+    size_t bytes = 0;
+    LF_HIP(h, hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, h->stream));
+    LF_TRY(lf_ensure_tmp(h, bytes));
+    bytes = h->tmp_bytes;
+    LF_HIP(h, hipcub::DeviceScan::ExclusiveSum(h->tmp, bytes, in, out, (int)n, h->stream));
+    return LF_OK;
+}
+
+struct I32ToI64 {
+    __host__ __device__ long long operator()(const int &v) const { return (long long)v; }
+};
+
+int lf_exclusive_scan_i32_to_i64(lf_handle *h, const int *in, long long *out, long long n)
+{
+    if (n <= 0) return LF_OK;
+    hipcub::TransformInputIterator<long long, I32ToI64, const int *> it(in, I32ToI64());
+    size_t bytes = 0;
+    LF_HIP(h, hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, it, out, (int)n, h->stream));
+    LF_TRY(lf_ensure_tmp(h, bytes));
+    bytes = h->tmp_bytes;
+    LF_HIP(h, hipcub::DeviceScan::ExclusiveSum(h->tmp, bytes, it, out, (int)n, h->stream));
+    return LF_OK;
+}

@@ -1,0 +1,296 @@
+"""GPU hot path vs the CPU oracle, element by element, through the C ABI (needs a GPU).
+
+Bar: bit-exact for every integer and index result (CSR, triangles, order, memberships,
+in-counts, sizes, internal edges, iteration counts) and -- because every decision sum is
+exact on both sides and rounded once -- bit-exact for the FP64 scores too (clustering
+coefficients, cc, community scores, the WCC-hat history), which is stricter than the
+1e-12 relative tolerance the method's contract allows.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as G
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lf():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2210_03211_amd as lfmod
+    lfmod.load_library()
+    return lfmod
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def cliques(sizes):
+    src, dst, off = [], [], 0
+    for s in sizes:
+        iu, ju = np.triu_indices(s, 1)
+        src.append(iu + off)
+        dst.append(ju + off)
+        off += s
+    return G.Graph(off, np.concatenate(src).astype(np.int64), np.concatenate(dst).astype(np.int64))
+
+
+def path(n):
+    return G.Graph(n, np.arange(n - 1, dtype=np.int64), np.arange(1, n, dtype=np.int64))
+
+
+def gpu_graph(lf, g, relabel=False, device_ptr=True):
+    import torch
+    h = lf.Handle(0)
+    if device_ptr:
+        h.load_graph(g.n, torch.from_numpy(g.src).cuda(), torch.from_numpy(g.dst).cuda(), relabel=relabel)
+    else:
+        h.load_graph(g.n, g.src, g.dst, relabel=relabel)
+    return h
+
+
+def oracle_graph(orc, g, relabel=False):
+    return orc.Oracle().load_graph(g.n, g.src, g.dst, relabel=relabel)
+
+
+SMALL = {
+    "sbm2000": lambda: G.named_config("tiny_sbm"),
+    "copurchase_1pct": lambda: G.named_config("copurchase", scale=0.01),
+    "gnp60": lambda: G.random_gnp(60, 0.2, 11),
+    "cliques": lambda: cliques([3, 7, 4, 12]),
+    "path": lambda: path(9),
+    "social_0.2pct": lambda: G.named_config("social", scale=0.002),
+}
+
+
+# ------------------------------------------------------------------ accumulator
+def test_device_exact_sum(lf):
+    import torch
+    rng = np.random.default_rng(3)
+    h = lf.Handle(0)
+    for trial in range(40):
+        n = int(rng.integers(1, 200000))
+        if trial % 3 == 0:
+            v = rng.random(n)
+        elif trial % 3 == 1:
+            v = 2.0 ** rng.uniform(-60, 20, n) * np.where(rng.random(n) < 0.5, -1, 1)
+        else:
+            x = rng.random(n // 2 + 1) * 1e6
+            v = np.concatenate([x, -x, [2.0 ** -100 * 3]])
+        say("exact_sum", trial, n)
+        got = h.lf_debug_exact_sum(torch.from_numpy(v).cuda())
+        assert got == math.fsum(v.tolist())
+    with pytest.raises(lf.LazyFoxError):
+        h.lf_debug_exact_sum(torch.tensor([2.0 ** 40], dtype=torch.float64).cuda())
+
+
+# ------------------------------------------------------------------ preprocessing
+@pytest.mark.parametrize("name", list(SMALL))
+def test_csr_parity(lf, orc, name):
+    say("csr", name)
+    g = SMALL[name]()
+    h = gpu_graph(lf, g)
+    o = oracle_graph(orc, g)
+    rp, col = h.csr()
+    orp, ocol = o.csr()
+    assert h.n == o.n and h.nedges == o.nedges
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+
+
+def test_relabel_and_host_pointers(lf, orc):
+    say("relabel")
+    g = G.named_config("copurchase", scale=0.005)
+    ids = np.unique(np.concatenate([g.src, g.dst]))
+    remap = np.full(g.n, -1, np.int64)
+    remap[ids] = ids * 13 + 5_000_000_000      # sparse ids beyond 2^32
+    src = np.concatenate([remap[g.src], [7, 7]])   # plus a self-loop-only id (dropped)
+    dst = np.concatenate([remap[g.dst], [7, 7]])
+    g2 = G.Graph(0, src, dst)
+    for dev in (True, False):
+        h = gpu_graph(lf, g2, relabel=True, device_ptr=dev)
+        o = oracle_graph(orc, g2, relabel=True)
+        assert h.n == o.n == ids.size
+        rp, col = h.csr()
+        orp, ocol = o.csr()
+        assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+        assert np.array_equal(h.orig_ids(), o.orig_ids())
+
+
+def test_load_graph_errors(lf):
+    say("load errors")
+    h = lf.Handle(0)
+    with pytest.raises(lf.LazyFoxError) as e:
+        h.load_graph(3, np.array([0, 1], np.int64), np.array([1, 3], np.int64))
+    assert e.value.code == lf.LF_EINVAL
+    with pytest.raises(lf.LazyFoxError) as e:
+        h.init_communities()
+    assert e.value.code == lf.LF_ESTATE
+    with pytest.raises(lf.LazyFoxError) as e:
+        h.run_iterations(4)
+    assert e.value.code == lf.LF_ESTATE
+
+
+# ------------------------------------------------------------------ node statistics
+@pytest.mark.parametrize("name", list(SMALL))
+def test_node_stats_parity(lf, orc, name):
+    say("node_stats", name)
+    g = SMALL[name]()
+    h = gpu_graph(lf, g).init_communities()
+    o = oracle_graph(orc, g).init_communities()
+    tri, ccl, order = h.node_stats()
+    otri, occl, oorder = o.node_stats()
+    assert np.array_equal(tri, otri)
+    assert np.array_equal(ccl.view(np.int64), occl.view(np.int64))
+    assert np.array_equal(order, oorder)
+    s, os_ = h.scores(), o.scores()
+    assert s["triangles"] == os_["triangles"] and s["cc"] == os_["cc"]
+    assert 3 * s["triangles"] == tri.sum()
+
+
+def test_initial_state_parity(lf, orc):
+    for name in SMALL:
+        say("init_state", name)
+        g = SMALL[name]()
+        h = gpu_graph(lf, g).init_communities()
+        o = oracle_graph(orc, g).init_communities()
+        off, ids = h.memberships()
+        ooff, oids = o.memberships()
+        assert np.array_equal(off, ooff) and np.array_equal(ids, oids)
+        assert np.array_equal(h.in_counts(), o.in_counts())
+        for a, b in zip(h.communities(), o.communities()):
+            assert np.array_equal(np.asarray(a).view(np.int64) if a.dtype == np.float64 else a,
+                                  np.asarray(b).view(np.int64) if b.dtype == np.float64 else b)
+        assert h.scores()["wtilde"] == o.scores()["wtilde"]
+
+
+# ------------------------------------------------------------------ full runs
+def compare_runs(lf, orc, g, q, theta=0.01, max_iters=50):
+    h = gpu_graph(lf, g).init_communities()
+    info = h.run_iterations(q, theta, max_iters)
+    o = oracle_graph(orc, g).init_communities()
+    oinfo = o.run_iterations(q, theta, max_iters, mode=orc.MODE_FAST)
+    assert info["iterations"] == oinfo["iterations"]
+    assert np.array_equal(info["wtilde_hist"].view(np.int64), oinfo["wtilde_hist"].view(np.int64))
+    assert np.array_equal(info["joins"], oinfo["joins"]) and np.array_equal(info["leaves"], oinfo["leaves"])
+    assert np.array_equal(info["communities"], oinfo["communities"])
+    off, ids = h.memberships()
+    ooff, oids = o.memberships()
+    assert np.array_equal(off, ooff) and np.array_equal(ids, oids)
+    assert np.array_equal(h.in_counts(), o.in_counts())
+    s, m, W = h.communities()
+    os_, om, oW = o.communities()
+    assert np.array_equal(s, os_) and np.array_equal(m, om) and np.array_equal(W.view(np.int64), oW.view(np.int64))
+    assert info["wcc_hat"] == oinfo["wcc_hat"]
+    return info
+
+
+@pytest.mark.parametrize("q", [1, 2, 7, 64, 100000])
+def test_run_parity_random_graphs(lf, orc, q):
+    for seed in range(6):
+        say("run gnp", seed, "q", q)
+        compare_runs(lf, orc, G.random_gnp(80, 0.12, 500 + seed), q)
+
+
+@pytest.mark.parametrize("name,q", [("sbm2000", 64), ("sbm2000", 1), ("sbm2000", 2000),
+                                    ("copurchase_1pct", 32), ("social_0.2pct", 256),
+                                    ("cliques", 3), ("path", 2)])
+def test_run_parity_named(lf, orc, name, q):
+    say("run", name, "q", q)
+    compare_runs(lf, orc, SMALL[name](), q)
+
+
+def test_run_parity_copurchase_full(lf, orc):
+    """The co-purchase-shaped graph at its full size (335,000 nodes), queue 256."""
+    say("run copurchase full q=256")
+    info = compare_runs(lf, orc, G.named_config("copurchase"), 256)
+    assert info["iterations"] >= 2
+
+
+def test_hub_path_parity(lf, orc):
+    """Nodes of high degree go through the workgroup evaluation path; a star-of-cliques
+    graph forces candidate tables far beyond one wave's."""
+    say("hub path")
+    rng = np.random.default_rng(9)
+    src, dst = [], []
+    hub = 0
+    off = 1
+    for c in range(300):
+        s = int(rng.integers(3, 9))
+        iu, ju = np.triu_indices(s, 1)
+        src.append(iu + off)
+        dst.append(ju + off)
+        members = np.arange(off, off + s)
+        src.append(np.full(s, hub))
+        dst.append(members)
+        off += s
+    g = G.Graph(off, np.concatenate(src).astype(np.int64), np.concatenate(dst).astype(np.int64))
+    for q in (1, 16, 4096):
+        compare_runs(lf, orc, g, q)
+
+
+def test_closed_forms_on_gpu(lf):
+    say("closed forms")
+    g = cliques([5])
+    h = gpu_graph(lf, g).init_communities()
+    assert h.scores()["wcc_hat"] == 5.0
+    info = h.run_iterations(2, 0.01, 10)
+    assert info["iterations"] == 1 and info["joins"].tolist() == [0] and info["leaves"].tolist() == [0]
+    h = gpu_graph(lf, path(12)).init_communities()
+    assert h.scores()["cc"] == 0.0
+    assert h.run_iterations(4)["iterations"] == 0
+    h = gpu_graph(lf, G.Graph(6, np.zeros(0, np.int64), np.zeros(0, np.int64))).init_communities()
+    assert h.n == 6 and h.nedges == 0 and h.run_iterations(4)["iterations"] == 0
+    off, ids = h.memberships()
+    assert ids.tolist() == [0, 1, 2, 3, 4, 5]
+
+
+def test_run_argument_errors(lf):
+    say("run errors")
+    h = gpu_graph(lf, cliques([4, 4])).init_communities()
+    for q, th in ((0, 0.01), (4, float("nan")), (4, -0.5)):
+        with pytest.raises(lf.LazyFoxError) as e:
+            h.run_iterations(q, th)
+        assert e.value.code == lf.LF_EINVAL
+
+
+def test_determinism_and_resume(lf, orc):
+    """Two runs are bitwise equal; iterations split over several calls equal one call."""
+    say("determinism")
+    g = G.named_config("copurchase", scale=0.02)
+    a = gpu_graph(lf, g).init_communities()
+    ia = a.run_iterations(128, 0.0, 4)
+    b = gpu_graph(lf, g).init_communities()
+    for _ in range(4):
+        b.run_iterations(128, 0.0, 1)
+    o = oracle_graph(orc, g).init_communities()
+    oi = o.run_iterations(128, 0.0, 4)
+    for h in (a, b):
+        off, ids = h.memberships()
+        ooff, oids = o.memberships()
+        assert np.array_equal(off, ooff) and np.array_equal(ids, oids)
+    assert ia["iterations"] == oi["iterations"] == 4
+
+
+def test_reinit_restarts(lf):
+    say("reinit")
+    g = G.named_config("tiny_sbm")
+    h = gpu_graph(lf, g).init_communities()
+    off0, ids0 = h.memberships()
+    h.run_iterations(64, 0.01, 3)
+    h.init_communities()
+    off1, ids1 = h.memberships()
+    assert np.array_equal(off0, off1) and np.array_equal(ids0, ids1)
