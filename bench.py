@@ -1,0 +1,199 @@
+"""Benchmark of the LazyFox hot path on one MI355X.
+
+One step = the whole hot path on one synthetic graph whose edge list is already resident
+in HBM: graph build (dedup, CSR), triangles / local CC / node order, greedy initial
+clustering, LazyFox iterations until the stopping rule (threshold 0.01), memberships
+copied back.  Metric: node evaluations per second over the whole step (n x iterations /
+step time); the end-to-end seconds are ms_per_step.
+
+Prints one JSON line with, besides the contract fields, the roofline of the dominant
+kernel (algorithmic bytes per launch / average launch duration measured with HIP events
+on the library's stream inside the timed region) and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+WORKLOADS = {
+    # name: (graphgen config, default queue size, description)
+    "social": ("social", 4096, "social-shaped planted-overlap power-law graph, 4,000,000 nodes, "
+                               "~35M edges (exp 2.3, max degree 15,000, 1-4 memberships, mixing 0.4)"),
+    "copurchase": ("copurchase", 256, "co-purchase-shaped graph, 335,000 nodes, ~926k edges"),
+    "tiny_sbm": ("tiny_sbm", 64, "2,000-node overlapping SBM"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="social", choices=sorted(WORKLOADS))
+    ap.add_argument("--queue", type=int, default=0, help="queue size (default per workload)")
+    ap.add_argument("--threshold", type=float, default=0.01)
+    ap.add_argument("--max-iters", type=int, default=50)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-scale", type=float, default=0.05)
+    ap.add_argument("--sweep", default="", help="comma-separated queue sizes: extra untimed-line runs")
+    return ap.parse_args()
+
+
+def eval_bytes(prof, nedges_directed_per_iter, iterations):
+    """Algorithmic bytes of the evaluation kernels (both paths), per the layout:
+    per queued node 60 B (order 4, node header 16, row offsets 16, decision 24);
+    per neighbour 20 B (column index 4, node header 16); per neighbour membership
+    12 B (slot 8, community size 4); per candidate 44 B (size 4, internal edges 8,
+    score 8, exact sum 24)."""
+    return (60.0 * prof["node_evals"] + 20.0 * nedges_directed_per_iter * iterations
+            + 12.0 * prof["visits"] + 44.0 * prof["candidates"])
+
+
+def cpu_baseline(args, wl):
+    import oracle
+    import graphgen
+    nthreads = min(16, os.cpu_count() or 1)
+    g = graphgen.named_config(wl[0], seed=args.seed, scale=args.cpu_sample_scale)
+    q = args.queue or wl[1]
+    q = max(1, int(q * args.cpu_sample_scale)) if args.cpu_sample_scale < 1 else q
+    t0 = time.perf_counter()
+    o = oracle.Oracle().load_graph(g.n, g.src, g.dst).init_communities(nthreads)
+    info = o.run_iterations(q, args.threshold, args.max_iters, mode=oracle.MODE_FAST, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    evals = o.n * info["iterations"]
+    return {"value": evals / dt, "unit": "node-evals/s", "cores": nthreads, "kind": "oracle",
+            "sample": "same generator at %.0f%% scale (%d nodes, %d edges), queue %d, whole path "
+                      "(build, triangles, order, init, %d iterations) in %.1f s"
+                      % (100 * args.cpu_sample_scale, o.n, o.nedges, q, info["iterations"], dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2210_03211_amd as lf
+
+    wl = WORKLOADS[args.workload]
+    q = args.queue or wl[1]
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    g = graphgen.named_config(wl[0], seed=args.seed, scale=args.scale)
+    gen_s = time.perf_counter() - t0
+    print("[bench] generated %s: n=%d pairs=%d in %.1fs" % (args.workload, g.n, g.npairs, gen_s),
+          file=sys.stderr, flush=True)
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    h = lf.Handle(0)
+
+    def step(profile_mask=0):
+        h.lf_set_profiling(profile_mask)
+        h.load_graph(g.n, src, dst)
+        h.init_communities()
+        info = h.run_iterations(q, args.threshold, args.max_iters)
+        off, ids = h.get_memberships()
+        return info, off, ids
+
+    for w in range(args.warmup):
+        info, off, ids = step()
+        print("[bench] warmup %d: %d iterations" % (w, info["iterations"]), file=sys.stderr, flush=True)
+    # untimed profiled pass: which kernel class dominates
+    h.lf_reset_profile()
+    step(0x1FF)
+    cls_prof = h.lf_get_profile()
+    dom = max(("eval", "eval_hub", "apply", "triangles"), key=lambda k: cls_prof["ms"][k])
+    dom_bit = 1 << lf.KERNEL_CLASSES.index(dom)
+    print("[bench] per-class ms (profiled pass): %s" % json.dumps(cls_prof["ms"]), file=sys.stderr, flush=True)
+
+    h.lf_reset_profile()
+    hashes = set()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for k in range(args.steps):
+        info, off, ids = step(dom_bit)
+        iters.append(info["iterations"])
+        hashes.add(hashlib.sha256(off.tobytes() + ids.tobytes()).hexdigest())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = h.lf_get_profile()
+    if len(hashes) != 1:
+        print("[bench] ERROR: runs differ", file=sys.stderr)
+        sys.exit(1)
+    n, ne, K = h.lf_get_graph_info()
+    ms_per_step = 1000.0 * dt / args.steps
+    evals_per_step = n * iters[0]
+    value = evals_per_step / (ms_per_step / 1000.0)
+
+    # roofline of the dominant kernel class over the timed region
+    launches = prof["launches"][dom]
+    kms = prof["ms"][dom]
+    if dom in ("eval", "eval_hub"):
+        # bytes of both evaluation paths, attributed by launch to the dominant one
+        # work counters come from the profiled pass (same deterministic run), per step
+        per_step = dict(node_evals=cls_prof["node_evals"], visits=cls_prof["visits"],
+                        candidates=cls_prof["candidates"])
+        total_b = eval_bytes(per_step, 2 * ne, iters[0])
+        per_launch = total_b / max(1, cls_prof["chunks"])
+        avg_ms = kms / max(1, launches)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    else:
+        per_launch = None
+        avg_ms = kms / max(1, launches)
+        achieved = None
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+            "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches": launches}
+    out = {
+        "metric": "dWCC-hat node-evals/s (whole hot path, end-to-end)",
+        "value": value, "unit": "node-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl[2], "name": args.workload, "nodes": n, "edges": ne, "queue": q,
+                   "threshold": args.threshold, "iterations": iters[0], "seed": args.seed,
+                   "communities_created": K, "memberships_sha256": next(iter(hashes))[:16]},
+        "end_to_end_s": ms_per_step / 1000.0,
+        "kernel_node_evals_per_s": cls_prof["node_evals"] / max(1e-9, (cls_prof["ms"]["eval"] + cls_prof["ms"]["eval_hub"]) * 1e-3),
+        "work_per_step": {"node_evals": cls_prof["node_evals"], "visits": cls_prof["visits"],
+                          "candidates": cls_prof["candidates"], "chunks": cls_prof["chunks"]},
+        "class_ms_profiled_pass": cls_prof["ms"],
+        "roofline": roof,
+    }
+    if args.sweep:
+        sweep = {}
+        for qq in [int(x) for x in args.sweep.split(",") if x]:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            h.lf_set_profiling(0)
+            h.load_graph(g.n, src, dst)
+            h.init_communities()
+            si = h.run_iterations(qq, args.threshold, args.max_iters)
+            h.get_memberships()
+            torch.cuda.synchronize()
+            s = time.perf_counter() - t1
+            sweep[str(qq)] = {"end_to_end_s": s, "iterations": si["iterations"],
+                              "node_evals_per_s": n * si["iterations"] / s, "wcc_hat": si["wcc_hat"]}
+            print("[bench] sweep q=%d: %.3fs %d iterations" % (qq, s, si["iterations"]), file=sys.stderr, flush=True)
+        out["queue_sweep"] = sweep
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args, wl)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

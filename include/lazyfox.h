@@ -71,6 +71,8 @@ typedef struct {
 #define LF_K_APPLY 6        /* bulk apply: membership edits, in-counts, community re-sums */
 #define LF_K_ITEREND 7      /* iteration end: degenerate removal, compaction, score */
 #define LF_K_COUNT 8
+#define LF_PROF_COUNTERS_BIT 8  /* profiling mask bit: also count visits and candidates
+                                   (adds a few global atomics to the evaluation kernels) */
 typedef struct {
     int64_t launches[LF_K_COUNT];
     double ms[LF_K_COUNT];
@@ -164,10 +166,25 @@ int lf_get_communities(lf_handle *h, int32_t *size, int64_t *internal_edges, dou
 /* in[j] = |N(x) ∩ C| for the j-th membership in the lf_get_memberships listing. */
 int lf_get_in_counts(lf_handle *h, int32_t *in, int64_t capacity);
 
-/* Kernel timing collection (HIP events around each launch) on/off, read, reset. */
-int lf_set_profiling(lf_handle *h, int enable);
+/* Kernel timing: `mask` selects the kernel classes to time (bit 1 << LF_K_*; 0 = off).
+   HIP events are recorded around each timed launch on the handle's stream and resolved at
+   the end of the API call, so timing does not stall the host.  chunks and node_evals are
+   always counted; visits and candidates only with bit 1 << LF_PROF_COUNTERS_BIT. */
+int lf_set_profiling(lf_handle *h, int mask);
 int lf_get_profile(lf_handle *h, lf_profile *out);
 int lf_reset_profile(lf_handle *h);
+
+/* Tuning options (lf_set_option / lf_get_option).  Results never depend on them. */
+#define LF_OPT_TRI_LDS_CAP 1       /* max out-list length staged in LDS by the workgroup
+                                      triangle kernel (0 = as much as LDS holds); longer
+                                      out-lists use global scratch */
+#define LF_OPT_HUB_BLOCKS 3        /* workgroups of the table-path evaluation kernels */
+#define LF_OPT_REFRESH_BLOCKS 4    /* workgroups of the in-count and re-sum kernels */
+#define LF_OPT_WAVE_TABLE 5        /* candidate-table entries per wave in the wave path
+                                      (power of two, 16 .. 128); nodes needing more go to
+                                      the table path */
+int lf_set_option(lf_handle *h, int option, int64_t value);
+int lf_get_option(lf_handle *h, int option, int64_t *value);
 
 /*
  * Diagnostic: the exact sum of n doubles (device pointer), rounded once to nearest-even,

@@ -13,6 +13,7 @@ LF_OK, LF_EINVAL, LF_ESTATE, LF_ENOMEM, LF_EDEVICE, LF_ERANGE, LF_EOVERFLOW = 0,
 LF_EINTERNAL = -8
 LF_RELABEL = 1
 LF_DEVICE_PTR = 2
+OPTIONS = {"tri_lds_cap": 1, "hub_blocks": 3, "refresh_blocks": 4, "wave_table": 5}
 KERNEL_CLASSES = ["build", "triangles", "order", "init_clustering", "eval", "eval_hub", "apply",
                   "iteration_end"]
 
@@ -69,6 +70,8 @@ def load_library():
         "lf_get_profile": [vp, C.POINTER(Profile)],
         "lf_reset_profile": [vp],
         "lf_debug_exact_sum": [vp, vp, i64, C.POINTER(dbl)],
+        "lf_set_option": [vp, C.c_int, i64],
+        "lf_get_option": [vp, C.c_int, C.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -263,8 +266,11 @@ class Handle:
 
     communities = lf_get_communities
 
-    def lf_set_profiling(self, enable=True):
-        self._check(self.L.lf_set_profiling(self.h, int(bool(enable))), "lf_set_profiling")
+    def lf_set_profiling(self, mask=0xFF):
+        """mask: kernel classes to time (bit i = KERNEL_CLASSES[i]); True = all, 0 = off."""
+        if mask is True:
+            mask = 0xFF
+        self._check(self.L.lf_set_profiling(self.h, int(mask)), "lf_set_profiling")
 
     def lf_reset_profile(self):
         self._check(self.L.lf_reset_profile(self.h), "lf_reset_profile")
@@ -276,6 +282,15 @@ class Handle:
                     ms={k: float(p.ms[i]) for i, k in enumerate(KERNEL_CLASSES)},
                     chunks=int(p.chunks), node_evals=int(p.node_evals), visits=int(p.visits),
                     candidates=int(p.candidates))
+
+    def lf_set_option(self, name, value):
+        self._check(self.L.lf_set_option(self.h, OPTIONS[name], int(value)), "lf_set_option")
+        return self
+
+    def lf_get_option(self, name):
+        v = C.c_int64()
+        self._check(self.L.lf_get_option(self.h, OPTIONS[name], C.byref(v)), "lf_get_option")
+        return v.value
 
     def lf_debug_exact_sum(self, values_dev):
         p, is_dev = _ptr(values_dev)

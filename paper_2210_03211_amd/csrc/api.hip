@@ -14,6 +14,9 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     lf_handle *h = (lf_handle *)calloc(1, sizeof(lf_handle));
     if (!h) return LF_ENOMEM;
     h->allocs = new std::vector<void *>();
+    h->evpool = new std::vector<hipEvent_t>();
+    h->evkind = new std::vector<int>();
+    h->evlaunch = new std::vector<int>();
     h->device = device;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -46,7 +49,6 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     h->eval_wave_cap = 128;
-    h->hub_lds_entries = 2048;
     h->hub_blocks = 2 * cus;
     h->refresh_blocks = 2 * cus;
     h->K = -1;
@@ -61,6 +63,10 @@ int lf_destroy(lf_handle *h)
     (void)hipStreamSynchronize(h->stream);
     for (void *p : *h->allocs) (void)hipFree(p);
     delete h->allocs;
+    for (hipEvent_t e : *h->evpool) (void)hipEventDestroy(e);
+    delete h->evpool;
+    delete h->evkind;
+    delete h->evlaunch;
     (void)hipEventDestroy(h->ev0);
     (void)hipEventDestroy(h->ev1);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
@@ -100,7 +106,7 @@ int lf_load_graph(lf_handle *h, int64_t n, int64_t n_pairs, const int64_t *src, 
         return lf_set_error(h, LF_EOVERFLOW, "n >= 2^31 - 1");
     reset_graph(h);
     LF_HIP(h, hipStreamSynchronize(h->stream));
-    LF_TRY(lf_prof_begin(h));
+    LF_TRY(lf_prof_begin(h, LF_K_BUILD));
     int rc = lf_build_graph(h, n, n_pairs, (const long long *)src, (const long long *)dst, flags);
     if (rc != LF_OK) {
         char keep[512];
@@ -110,6 +116,7 @@ int lf_load_graph(lf_handle *h, int64_t n, int64_t n_pairs, const int64_t *src, 
         return rc;
     }
     LF_TRY(lf_prof_end(h, LF_K_BUILD, 8));
+    LF_TRY(lf_prof_flush(h));
     h->state = 1;
     return LF_OK;
 }
@@ -217,16 +224,20 @@ int lf_get_communities(lf_handle *h, int32_t *size, int64_t *internal_edges, dou
     LF_HIP(h, hipSetDevice(h->device));
     size_t K = (size_t)h->K;
     if (K == 0) return LF_OK;
-    if (size) LF_HIP(h, hipMemcpy(size, h->cs, sizeof(int) * K, hipMemcpyDeviceToHost));
-    if (internal_edges) LF_HIP(h, hipMemcpy(internal_edges, h->cm, sizeof(long long) * K, hipMemcpyDeviceToHost));
-    if (score) LF_HIP(h, hipMemcpy(score, h->cW, sizeof(double) * K, hipMemcpyDeviceToHost));
+    std::vector<CommRec> rec(K);
+    LF_HIP(h, hipMemcpy(rec.data(), h->cr, sizeof(CommRec) * K, hipMemcpyDeviceToHost));
+    for (size_t c = 0; c < K; c++) {
+        if (size) size[c] = rec[c].s;
+        if (internal_edges) internal_edges[c] = rec[c].m;
+        if (score) score[c] = rec[c].W;
+    }
     return LF_OK;
 }
 
-int lf_set_profiling(lf_handle *h, int enable)
+int lf_set_profiling(lf_handle *h, int mask)
 {
     if (!h) return LF_EINVAL;
-    h->profiling = enable ? 1 : 0;
+    h->profiling = mask & ((1 << (LF_PROF_COUNTERS_BIT + 1)) - 1);
     return LF_OK;
 }
 
@@ -242,6 +253,44 @@ int lf_reset_profile(lf_handle *h)
     if (!h) return LF_EINVAL;
     memset(&h->prof, 0, sizeof h->prof);
     return LF_OK;
+}
+
+int lf_set_option(lf_handle *h, int option, int64_t value)
+{
+    if (!h) return LF_EINVAL;
+    switch (option) {
+    case LF_OPT_TRI_LDS_CAP:
+        if (value < 0 || value > (1 << 24)) break;
+        h->tri_lds_cap = (int)value;
+        return LF_OK;
+    case LF_OPT_HUB_BLOCKS:
+        if (value < 1 || value > 65536) break;
+        h->hub_blocks = (int)value;
+        return LF_OK;
+    case LF_OPT_REFRESH_BLOCKS:
+        if (value < 1 || value > 65536) break;
+        h->refresh_blocks = (int)value;
+        return LF_OK;
+    case LF_OPT_WAVE_TABLE:
+        if (value < 16 || value > 128 || (value & (value - 1))) break;
+        h->eval_wave_cap = (int)value;
+        return LF_OK;
+    default:
+        return lf_set_error(h, LF_EINVAL, "unknown option %d", option);
+    }
+    return lf_set_error(h, LF_EINVAL, "option %d: value %lld out of range", option, (long long)value);
+}
+
+int lf_get_option(lf_handle *h, int option, int64_t *value)
+{
+    if (!h || !value) return LF_EINVAL;
+    switch (option) {
+    case LF_OPT_TRI_LDS_CAP: *value = h->tri_lds_cap; return LF_OK;
+    case LF_OPT_HUB_BLOCKS: *value = h->hub_blocks; return LF_OK;
+    case LF_OPT_REFRESH_BLOCKS: *value = h->refresh_blocks; return LF_OK;
+    case LF_OPT_WAVE_TABLE: *value = h->eval_wave_cap; return LF_OK;
+    default: return lf_set_error(h, LF_EINVAL, "unknown option %d", option);
+    }
 }
 
 int lf_debug_exact_sum(lf_handle *h, const double *values_dev, int64_t n, double *out)

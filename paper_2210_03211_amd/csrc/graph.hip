@@ -616,7 +616,7 @@ int lf_node_stats(lf_handle *h)
     int maxdev = 0;
     LF_HIP(h, hipDeviceGetAttribute(&maxdev, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
 
-    LF_TRY(lf_prof_begin(h));
+    LF_TRY(lf_prof_begin(h, LF_K_TRIANGLES));
     int *od = nullptr;
     long long *oro = nullptr;
     int *orc = nullptr;
@@ -652,6 +652,7 @@ int lf_node_stats(lf_handle *h)
         // LDS: nbr, pre (+1), cnt
         int lds_cap = (maxdev - 1024) / (3 * (int)sizeof(int)) - 1;
         if (lds_cap > 65536) lds_cap = 65536;
+        if (h->tri_lds_cap > 0 && h->tri_lds_cap < lds_cap) lds_cap = h->tri_lds_cap;
         int blocks = ndefer < 1024 ? ndefer : 1024;
         int *gs = nullptr;
         long long gslice = 3ll * maxod + 2;
@@ -674,7 +675,7 @@ int lf_node_stats(lf_handle *h)
     lf_dev_free(h, defer);
 
     // local CC, cc, T
-    LF_TRY(lf_prof_begin(h));
+    LF_TRY(lf_prof_begin(h, LF_K_ORDER));
     LF_TRY(lf_dev_alloc(h, (void **)&h->ccl, sizeof(double) * (n > 0 ? n : 1)));
     int nb = (int)((n + RED_BLOCK - 1) / RED_BLOCK);
     if (nb > 1024) nb = 1024;
@@ -720,6 +721,7 @@ int lf_node_stats(lf_handle *h)
     LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
     LF_TRY(lf_prof_end(h, LF_K_ORDER, 7));
+    LF_TRY(lf_prof_flush(h));
     if (n == 0) h->cc = 0.0;
     h->T = (long long)(ht / 3);
     lf_dev_free(h, k1); lf_dev_free(h, k1b); lf_dev_free(h, v1); lf_dev_free(h, v1b);

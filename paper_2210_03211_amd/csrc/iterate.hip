@@ -1,0 +1,1029 @@
+// iterate.hip -- one LazyFox iteration on the GPU: queues of q nodes in node order, each
+// evaluated on the state at the start of the queue and then applied together
+// (Methods, "Node Changes", Algorithm 2, "Stopping Criteria").
+//
+// Per queue (all launches on the handle's stream, no host synchronisation):
+//   k_chunk_begin    reset the queue's counters
+//   k_eval           one wave per queued node: nodes whose neighbour memberships fit one
+//                    wave (<= 64 visits) are evaluated completely in LDS; the others are
+//                    registered as work items of the table path
+//   k_big_visits     table path, visit-parallel over all registered nodes: every
+//                    neighbour membership (y in C) adds its exact correction to the entry
+//                    (node, C) of a global open-addressing table; own memberships add the
+//                    leave candidates
+//   k_big_final      every occupied entry -> change of C's score; per node the largest
+//                    positive change (atomicMax on the bits of a positive double)
+//   k_big_tie        among the entries equal to that maximum the lowest community id
+//   k_apply_edit     membership edits, sizes, member-list appends, touched list
+//   k_apply_in       in-counts of the neighbours of moved nodes (neighbour blocks)
+//   k_refresh_plan   split every touched community's member list into parts
+//   k_refresh        exact re-sum per part; multi-part communities combine their parts
+//                    through carry-save counters and the last part finalises
+//
+// Every sum is exact (fixed point), so none of the launch shapes above can change a bit
+// of the result.
+#include "method.h"
+
+#define EW 4            // waves per block in the wave evaluation path
+#define ECAP 128        // table entries per wave (power of two)
+#define MXCAP 32        // own memberships kept in LDS (wave path)
+#define INB 512         // neighbours per in-count work item
+#define PART 512        // members per re-sum part
+#define MACC 19         // carry-save counters per multi-part community (3 x 6 digits + in-sum)
+#define GEMPTY (~0ull)
+
+static inline unsigned grid_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
+
+__global__ void k_chunk_begin(Ctx cx, int prev_start, int prev_len)
+{
+    long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j == 0) {
+        DevCounters *c = cx.ctr;
+        c->tcount = 0;
+        c->occ_cnt = 0;
+        c->in_items = 0;
+        c->parts_total = 0;
+        c->mslots = 0;
+    }
+    if (j < prev_len) cx.joined_to[cx.order[prev_start + j]] = -1;
+}
+
+// ------------------------------------------------------------------------------------
+// evaluation, wave path
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int lds_insert(int *key, int T, int lg, int C)
+{
+    unsigned hsh = hash_tab(C) >> (32 - lg);
+    while (true) {
+        int old = atomicCAS(&key[hsh], -1, C);
+        if (old == -1 || old == C) return (int)hsh;
+        hsh = (hsh + 1) & (T - 1);
+    }
+}
+
+__global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, int cstart, int clen, int wcap)
+{
+    __shared__ int s_key[EW][ECAP];
+    __shared__ int s_k[EW][ECAP];
+    __shared__ unsigned long long s_d[EW][4][ECAP];
+    __shared__ int s_mx[EW][MXCAP];
+    __shared__ int s_mxin[EW][MXCAP];
+    __shared__ long long s_vslot[EW][WAVE];
+    __shared__ int s_vdeg[EW][WAVE];
+    __shared__ int s_sz[EW][ECAP];
+    int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    int j = blockIdx.x * EW + wv;
+    if (j >= clen) return;                  // no block barriers in this kernel
+    int x = cx.order[cstart + j];
+    NodeHdr hx = cx.nh[x];
+    long long rb = cx.rowptr[x];
+    int d = hx.deg;
+    bool big = d > WAVE || hx.cnt > MXCAP;
+    int yc = 0, ydeg = 0, incl = 0, V = 0;
+    long long yoff = 0;
+    if (!big) {
+        if (lane < d) {
+            int y = cx.col[rb + lane];
+            NodeHdr hy = cx.nh[y];
+            yc = hy.cnt;
+            yoff = hy.off;
+            ydeg = hy.deg;
+        }
+        incl = yc;
+        for (int o = 1; o < WAVE; o <<= 1) {
+            int t = __shfl_up(incl, o, WAVE);
+            if (lane >= o) incl += t;
+        }
+        V = __shfl(incl, WAVE - 1, WAVE);
+        big = 2 * (V + hx.cnt) > wcap;
+    }
+    if (big) {
+        // table path: the node's work items are laid out statically for the iteration
+        if (lane == 0) {
+            cx.big_idx[j] = 1;
+            cx.big_bj[j] = 0;
+            cx.big_bl[j] = 0;
+            cx.big_cj[j] = 0x7fffffff;
+            cx.big_cl[j] = 0x7fffffff;
+        }
+        return;
+    }
+    if (lane == 0) cx.big_idx[j] = 0;
+    int T = 8;
+    while (T < 2 * (V + hx.cnt)) T <<= 1;
+    int lg = 31 - __clz(T);
+    int *key = s_key[wv], *kk = s_k[wv];
+    unsigned long long *d0 = s_d[wv][0], *d1 = s_d[wv][1], *d2 = s_d[wv][2], *d3 = s_d[wv][3];
+    for (int t = lane; t < T; t += WAVE) {
+        key[t] = -1; kk[t] = 0; d0[t] = 0; d1[t] = 0; d2[t] = 0; d3[t] = 0;
+    }
+    // flattened visit list: (slot index, neighbour degree)
+    for (int t = 0, base = incl - yc; t < yc; t++) {
+        s_vslot[wv][base + t] = yoff + t;
+        s_vdeg[wv][base + t] = ydeg;
+    }
+    int mcnt = hx.cnt;
+    if (lane < mcnt) {
+        Slot sl = cx.slot[hx.off + lane];
+        s_mx[wv][lane] = sl.comm;
+        s_mxin[wv][lane] = sl.in;
+    }
+    WAVE_SYNC();
+    // 1. candidates and neighbour counts: own communities are leave candidates even without
+    //    a neighbour in them; every neighbour membership counts towards its community
+    if (lane < mcnt) lds_insert(key, T, lg, s_mx[wv][lane]);
+    Slot sl = {0, 0};
+    int hsh = -1;
+    if (lane < V) {
+        sl = cx.slot[s_vslot[wv][lane]];
+        hsh = lds_insert(key, T, lg, sl.comm);
+        atomicAdd(&kk[hsh], 1);
+    }
+    WAVE_SYNC();
+    // 2. one community-record gather per candidate (its size feeds the visit terms)
+    for (int t = lane; t < T; t += WAVE) {
+        int C = key[t];
+        if (C >= 0) s_sz[wv][t] = cx.cr[C].s;
+    }
+    WAVE_SYNC();
+    // 3. exact correction of every visit, summed per candidate
+    int bad = 0;
+    if (lane < V) {
+        int C = sl.comm;
+        bool leave = false;
+        for (int a = 0; a < mcnt; a++) leave |= (s_mx[wv][a] == C);
+        X192 term = visit_term(leave, sl.in, s_vdeg[wv][lane], s_sz[wv][hsh], bad);
+        i64 t0, t1, t2, t3;
+        x192_digits(term, t0, t1, t2, t3);
+        atomicAdd(&d0[hsh], (unsigned long long)t0);
+        atomicAdd(&d1[hsh], (unsigned long long)t1);
+        atomicAdd(&d2[hsh], (unsigned long long)t2);
+        atomicAdd(&d3[hsh], (unsigned long long)t3);
+    }
+    WAVE_SYNC();
+    double bjd = 0.0, bld = 0.0;
+    int bj = -1, bl = -1, ncand = 0;
+    long long dx = hx.deg;
+    for (int t = lane; t < T; t += WAVE) {
+        int C = key[t];
+        if (C < 0) continue;
+        ncand++;
+        int k = kk[t];
+        int a = -1;
+        for (int q = 0; q < mcnt; q++)
+            if (s_mx[wv][q] == C) a = q;
+        bool leave = a >= 0;
+        if (leave && s_mxin[wv][a] != k) atomicOr(&cx.ctr->error, LF_DEVERR_INCOUNT);
+        X192 corr = x192_from_digits((i64)d0[t], (i64)d1[t], (i64)d2[t], (i64)d3[t]);
+        double dl = candidate_delta(cx, C, leave, k, dx, corr, bad);
+        if (leave) better(dl, C, bld, bl);
+        else better(dl, C, bjd, bj);
+    }
+    wave_best(bjd, bj);
+    wave_best(bld, bl);
+    ncand = wave_sum_int(ncand);
+    if (bad) atomicOr(&cx.ctr->error, LF_DEVERR_INEXACT);
+    if (lane == 0) {
+        cx.dj[j] = bj;
+        cx.djd[j] = bj >= 0 ? bjd : 0.0;
+        cx.dl[j] = bl;
+        cx.dld[j] = bl >= 0 ? bld : 0.0;
+        if (cx.stats) {
+            atomicAdd(&cx.ctr->visits, (unsigned long long)V);
+            atomicAdd(&cx.ctr->cands, (unsigned long long)ncand);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// evaluation, table path
+// ------------------------------------------------------------------------------------
+// slot of key (b, C) in the global table, claimed if absent (claimed = true then)
+__device__ __forceinline__ long long gfind(const Ctx &cx, int b, int C, bool &claimed)
+{
+    unsigned long long key = ((unsigned long long)(unsigned)b << 32) | (unsigned)C;
+    long long h = (long long)(hash64(key) & (unsigned long long)cx.gmask);
+    claimed = false;
+    for (long long probe = 0; probe <= cx.gmask; probe++) {
+        unsigned long long cur = __atomic_load_n(&cx.gt[h].key, __ATOMIC_RELAXED);
+        if (cur == key) return h;
+        if (cur == GEMPTY) {
+            unsigned long long old = atomicCAS(&cx.gt[h].key, GEMPTY, key);
+            if (old == GEMPTY) {
+                claimed = true;
+                return h;
+            }
+            if (old == key) return h;
+        }
+        h = (h + 1) & cx.gmask;
+    }
+    return -1;
+}
+
+// append the entries claimed by the lanes executing this call to the occupied list with
+// one atomic per wave
+__device__ __forceinline__ void occ_append(const Ctx &cx, bool claimed, long long h)
+{
+    unsigned long long m = __ballot(claimed);
+    if (!m) return;
+    int lane = threadIdx.x & (WAVE - 1);
+    int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&cx.ctr->occ_cnt, __popcll(m));
+    base = __shfl(base, leader, WAVE);
+    if (claimed) cx.occ[base + __popcll(m & ((1ull << lane) - 1))] = (int)h;
+}
+
+#define EWB 4           // waves per block in the table-path kernels
+
+// Table path, one wave per 64 consecutive work items (neighbours, then own memberships,
+// of the table-path nodes of this queue).  The wave flattens its items' neighbour
+// memberships and walks them 64 at a time with every lane converged.  The lane that
+// claims a key records its visit inline (no community gather, one atomic in total); every
+// other visit adds its exact correction, with lanes of one wave that hit the same entry
+// summed first so that a hot entry gets one set of atomics per wave.
+__global__ void __launch_bounds__(EWB * WAVE) k_big_visits(Ctx cx, int cstart, int clen)
+{
+    __shared__ long long s_sbase[EWB][WAVE];
+    __shared__ long long s_xoff[EWB][WAVE];
+    __shared__ int s_start[EWB][WAVE];
+    __shared__ int s_dy[EWB][WAVE];
+    __shared__ int s_j[EWB][WAVE];
+    __shared__ int s_xcnt[EWB][WAVE];
+    __shared__ int s_own[EWB][WAVE];
+    const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const long long ib0 = cx.item_base[cstart];
+    const long long count = cx.item_base[cstart + clen] - ib0;
+    const long long gw = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
+    const long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
+    int bad = 0, capfail = 0;
+    unsigned long long nvis = 0;
+    for (long long base = gw * WAVE; base < count; base += nw * WAVE) {
+        long long f = base + lane;
+        int vc = 0, dy = 0, jj = -1, own = 0, xcnt = 0;
+        long long sb = 0, xoff = 0;
+        if (f < count) {
+            int r = cx.item_node[ib0 + f];
+            int j = r - cstart;
+            if (j >= 0 && j < clen && cx.big_idx[j] > 0) {
+                int x = cx.order[r];
+                NodeHdr hx = cx.nh[x];
+                long long e = ib0 + f - cx.item_base[r];
+                if (e < hx.deg) {
+                    int y = cx.col[cx.rowptr[x] + e];
+                    NodeHdr hy = cx.nh[y];
+                    vc = hy.cnt;
+                    sb = hy.off;
+                    dy = hy.deg;
+                } else if (e < (long long)hx.deg + hx.cnt) {
+                    vc = 1;
+                    sb = hx.off + (e - hx.deg);
+                    own = 1;
+                }
+                jj = j;
+                xoff = hx.off;
+                xcnt = hx.cnt;
+            }
+        }
+        int incl = vc;
+        for (int o = 1; o < WAVE; o <<= 1) {
+            int t = __shfl_up(incl, o, WAVE);
+            if (lane >= o) incl += t;
+        }
+        const int Vw = __shfl(incl, WAVE - 1, WAVE);
+        s_start[wv][lane] = incl - vc;
+        s_sbase[wv][lane] = sb;
+        s_dy[wv][lane] = dy;
+        s_j[wv][lane] = jj;
+        s_xoff[wv][lane] = xoff;
+        s_xcnt[wv][lane] = xcnt;
+        s_own[wv][lane] = own;
+        WAVE_SYNC();
+        for (int v0 = 0; v0 < Vw; v0 += WAVE) {
+            const int v = v0 + lane;
+            const bool act = v < Vw;
+            int C = 0, iv = 0, dyv = 0, xc = 0;
+            long long hh = -1, xo = 0;
+            bool claimed = false, ownv = false;
+            if (act) {
+                int lo = 0, hi = WAVE - 1;          // owner: last lane whose range starts <= v
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (s_start[wv][mid] <= v) lo = mid; else hi = mid - 1;
+                }
+                int j = s_j[wv][lo];
+                ownv = s_own[wv][lo] != 0;
+                dyv = s_dy[wv][lo];
+                xo = s_xoff[wv][lo];
+                xc = s_xcnt[wv][lo];
+                Slot sl = cx.slot[s_sbase[wv][lo] + (v - s_start[wv][lo])];
+                C = sl.comm;
+                iv = sl.in;
+                hh = gfind(cx, j, C, claimed);
+                if (hh < 0) capfail = 1;
+            }
+            occ_append(cx, claimed, hh);
+            const bool vis = act && hh >= 0 && !ownv;
+            if (vis && claimed) {
+                cx.gt[hh].ii = iv;
+                cx.gt[hh].idy = dyv;
+            }
+            const bool extra = vis && !claimed;
+            i64 t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+            if (extra) {
+                long long s = cx.cr[C].s;
+                bool leave = find_slot(cx.slot, xo, xc, C) >= 0;
+                X192 term = visit_term(leave, iv, dyv, s, bad);
+                x192_digits(term, t0, t1, t2, t3);
+            }
+            bool pending = extra;
+            for (int attempt = 0; attempt < 3; attempt++) {
+                unsigned long long pm = __ballot(pending);
+                if (!pm) break;
+                int first = __ffsll((long long)pm) - 1;
+                long long h0 = __shfl(hh, first, WAVE);
+                bool in = pending && hh == h0;
+                unsigned long long gm = __ballot(in);
+                if (__popcll(gm) >= 4) {
+                    i64 a0 = wave_sum_i64(in ? t0 : 0), a1 = wave_sum_i64(in ? t1 : 0);
+                    i64 a2 = wave_sum_i64(in ? t2 : 0), a3 = wave_sum_i64(in ? t3 : 0);
+                    if (lane == first) {
+                        GEntry *g = &cx.gt[h0];
+                        atomicAdd(&g->cnt, __popcll(gm));
+                        atomicAdd((unsigned long long *)&g->d[0], (unsigned long long)a0);
+                        atomicAdd((unsigned long long *)&g->d[1], (unsigned long long)a1);
+                        atomicAdd((unsigned long long *)&g->d[2], (unsigned long long)a2);
+                        atomicAdd((unsigned long long *)&g->d[3], (unsigned long long)a3);
+                    }
+                    if (in) pending = false;
+                } else if (in) {
+                    GEntry *g = &cx.gt[hh];
+                    atomicAdd(&g->cnt, 1);
+                    atomicAdd((unsigned long long *)&g->d[0], (unsigned long long)t0);
+                    atomicAdd((unsigned long long *)&g->d[1], (unsigned long long)t1);
+                    atomicAdd((unsigned long long *)&g->d[2], (unsigned long long)t2);
+                    atomicAdd((unsigned long long *)&g->d[3], (unsigned long long)t3);
+                    pending = false;
+                }
+            }
+            if (pending) {
+                GEntry *g = &cx.gt[hh];
+                atomicAdd(&g->cnt, 1);
+                atomicAdd((unsigned long long *)&g->d[0], (unsigned long long)t0);
+                atomicAdd((unsigned long long *)&g->d[1], (unsigned long long)t1);
+                atomicAdd((unsigned long long *)&g->d[2], (unsigned long long)t2);
+                atomicAdd((unsigned long long *)&g->d[3], (unsigned long long)t3);
+            }
+            nvis += vis ? 1 : 0;
+        }
+        WAVE_SYNC();
+    }
+    if (cx.stats) {
+        nvis = (unsigned long long)wave_sum_i64((long long)nvis);
+        if (lane == 0 && nvis) atomicAdd(&cx.ctr->visits, nvis);
+    }
+    if (bad) atomicOr(&cx.ctr->error, LF_DEVERR_INEXACT);
+    if (capfail) atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
+}
+
+__global__ void __launch_bounds__(256) k_big_final(Ctx cx, int cstart, int clen)
+{
+    int count = __atomic_load_n(&cx.ctr->occ_cnt, __ATOMIC_RELAXED);
+    int bad = 0;
+    unsigned long long ncand = 0;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    // every lane of a wave runs the same number of trips (invalid lanes idle), so the
+    // per-wave reduction below sees all 64 lanes
+    for (long long base = blockIdx.x * (long long)blockDim.x; base < count; base += stride) {
+        long long e = base + threadIdx.x;
+        bool valid = e < count;
+        long long h = valid ? cx.occ[e] : 0;
+        GEntry ge;
+        ge.key = GEMPTY;
+        if (valid) ge = cx.gt[h];
+        unsigned long long key = ge.key;
+        int b = valid ? (int)(key >> 32) : -1, C = (int)(unsigned)key;
+        if (b >= clen) b = -1;
+        double dlt = 0.0;
+        bool leave = false;
+        if (b >= 0) {
+            {
+                int x = cx.order[cstart + b];
+                NodeHdr hx = cx.nh[x];
+                int k = ge.cnt + (ge.idy > 0 ? 1 : 0);
+                X192 corr = x192_from_digits(ge.d[0], ge.d[1], ge.d[2], ge.d[3]);
+                int a = find_slot(cx.slot, hx.off, hx.cnt, C);
+                leave = a >= 0;
+                if (ge.idy > 0) {
+                    X192 t = visit_term(leave, ge.ii, ge.idy, cx.cr[C].s, bad);
+                    x192_add(corr, t);
+                }
+                if (leave && cx.slot[hx.off + a].in != k) atomicOr(&cx.ctr->error, LF_DEVERR_INCOUNT);
+                dlt = candidate_delta(cx, C, leave, k, hx.deg, corr, bad);
+                ncand++;
+            }
+        }
+        // per-node maximum of the positive changes; one atomic per wave when every active
+        // lane works on the same node (the common case: a node's entries are contiguous)
+        {
+            unsigned long long bits = dlt > 0.0 ? (unsigned long long)__double_as_longlong(dlt) : 0ull;
+            unsigned long long jb = leave ? 0ull : bits, lb = leave ? bits : 0ull;
+            int lane = threadIdx.x & (WAVE - 1);
+            int b0 = __shfl(b, 0, WAVE);
+            bool uni = __ballot(b != b0) == 0 && b0 >= 0;
+            if (uni) {
+                for (int o = 32; o >= 1; o >>= 1) {
+                    unsigned long long oj = (unsigned long long)__shfl_xor((long long)jb, o, WAVE);
+                    unsigned long long ol = (unsigned long long)__shfl_xor((long long)lb, o, WAVE);
+                    if (oj > jb) jb = oj;
+                    if (ol > lb) lb = ol;
+                }
+                if (lane == 0) {
+                    if (jb) atomicMax(&cx.big_bj[b0], jb);
+                    if (lb) atomicMax(&cx.big_bl[b0], lb);
+                }
+            } else if (b >= 0) {
+                if (jb) atomicMax(&cx.big_bj[b], jb);
+                if (lb) atomicMax(&cx.big_bl[b], lb);
+            }
+        }
+        if (valid) {
+            cx.occ_key[e] = key | (leave ? (1ull << 63) : 0ull);
+            cx.occ_d[e] = dlt;
+            // leave the entry empty for the next queue
+            GEntry *gp = &cx.gt[h];
+            gp->key = GEMPTY;
+            gp->cnt = 0;
+            gp->ii = 0;
+            gp->idy = 0;
+            gp->d[0] = 0; gp->d[1] = 0; gp->d[2] = 0; gp->d[3] = 0;
+        }
+    }
+    if (cx.stats) {
+        ncand = (unsigned long long)wave_sum_i64((long long)ncand);
+        if ((threadIdx.x & (WAVE - 1)) == 0 && ncand) atomicAdd(&cx.ctr->cands, ncand);
+    }
+    if (bad) atomicOr(&cx.ctr->error, LF_DEVERR_INEXACT);
+}
+
+__global__ void __launch_bounds__(256) k_big_tie(Ctx cx)
+{
+    int count = __atomic_load_n(&cx.ctr->occ_cnt, __ATOMIC_RELAXED);
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count; e += stride) {
+        double dlt = cx.occ_d[e];
+        if (!(dlt > 0.0)) continue;
+        unsigned long long key = cx.occ_key[e];
+        bool leave = (key >> 63) != 0;
+        int b = (int)((key >> 32) & 0x7fffffffull), C = (int)(unsigned)key;
+        unsigned long long best = leave ? cx.big_bl[b] : cx.big_bj[b];
+        if ((unsigned long long)__double_as_longlong(dlt) == best) atomicMin(leave ? &cx.big_cl[b] : &cx.big_cj[b], C);
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// bulk apply
+// ------------------------------------------------------------------------------------
+// first touch of C in this queue appends it to the touched list
+__device__ __forceinline__ void touch(const Ctx &cx, int C, bool want)
+{
+    bool first = want && atomicExch(&cx.tflag[C], 1) == 0;
+    int pos = wave_reserve(&cx.ctr->tcount, first);
+    if (first) cx.tlist[pos] = C;
+}
+
+__global__ void k_apply_edit(Ctx cx, int cstart, int clen)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int lane = threadIdx.x & (WAVE - 1);
+    bool inq = j < clen;
+    int J = -1, L = -1;
+    if (inq) {
+        if (cx.big_idx[j] > 0) {
+            unsigned long long bj = cx.big_bj[j], bl = cx.big_bl[j];
+            J = bj ? cx.big_cj[j] : -1;
+            L = bl ? cx.big_cl[j] : -1;
+            cx.dj[j] = J;
+            cx.dl[j] = L;
+            cx.djd[j] = __longlong_as_double((long long)bj);
+            cx.dld[j] = __longlong_as_double((long long)bl);
+        } else {
+            J = cx.dj[j];
+            L = cx.dl[j];
+        }
+    }
+    unsigned long long ml = __ballot(L >= 0);
+    if (lane == 0 && ml) atomicAdd(&cx.ctr->leaves, (unsigned long long)__popcll(ml));
+    if (J < 0 && L < 0) return;
+    int x = cx.order[cstart + j];
+    NodeHdr hx = cx.nh[x];
+    int cnt = hx.cnt;
+    if (L >= 0) {
+        int t = find_slot(cx.slot, hx.off, cnt, L);
+        cx.slot[hx.off + t] = cx.slot[hx.off + cnt - 1];
+        cnt--;
+        atomicSub(&cx.cr[L].s, 1);
+    }
+    touch(cx, L, L >= 0);
+    bool joined = false;
+    if (J >= 0) {
+        long long capx = cx.nh[x + 1].off - hx.off;
+        if (cnt >= capx) {
+            atomicOr(&cx.ctr->error, LF_DEVERR_SLOTS);
+        } else {
+            Slot sn = {J, 0};
+            cx.slot[hx.off + cnt] = sn;
+            cnt++;
+            atomicAdd(&cx.cr[J].s, 1);
+            cx.joined_to[x] = J;
+            joined = true;
+            int p = atomicAdd(&cx.cm_len[J], 1);
+            long long cap = cx.cm_off[J + 1] - cx.cm_off[J];
+            if (p < cap) {
+                cx.cm_node[cx.cm_off[J] + p] = x;
+            } else {
+                int e = atomicAdd(&cx.ctr->ovf_cnt, 1);
+                cx.ovf_node[e] = x;
+                cx.ovf_comm[e] = J;
+                cx.ovf_flag[J] = 1;
+            }
+        }
+    }
+    touch(cx, J, joined);
+    unsigned long long mj = __ballot(joined);
+    if (mj && lane == __ffsll((long long)mj) - 1) atomicAdd(&cx.ctr->joins, (unsigned long long)__popcll(mj));
+    cx.nh[x].cnt = cnt;
+    int blocks = (hx.deg + INB - 1) / INB;
+    int p0 = wave_reserve(&cx.ctr->in_items, blocks == 1);
+    if (blocks > 1) p0 = atomicAdd(&cx.ctr->in_items, blocks);
+    if (blocks > 0) {
+        if (p0 + blocks > cx.in_cap) {
+            atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
+        } else {
+            cx.in_base[j] = p0;
+            for (int k = 0; k < blocks; k++) cx.in_item[p0 + k] = j;
+        }
+    }
+}
+
+// in-counts: a surviving member y of J (L) gains (loses) one per neighbour that joined
+// (left); a node that joined J in this queue gets its in-count counted afresh.  One wave
+// per block of INB neighbours of a moved node.
+__global__ void __launch_bounds__(256) k_apply_in(Ctx cx, int cstart, int clen)
+{
+    int count = __atomic_load_n(&cx.ctr->in_items, __ATOMIC_RELAXED);
+    if (count > cx.in_cap) count = cx.in_cap;
+    int lane = threadIdx.x & (WAVE - 1);
+    long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
+    for (long long p = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE; p < count; p += nw) {
+        int j = cx.in_item[p];
+        if (j < 0 || j >= clen) continue;          // only after a flagged overflow
+        int k = (int)p - cx.in_base[j];
+        if (k < 0) continue;
+        int J = cx.dj[j], L = cx.dl[j];
+        int x = cx.order[cstart + j];
+        if (J >= 0 && cx.joined_to[x] != J) J = -1;     // join did not fit (error flagged)
+        long long rb = cx.rowptr[x];
+        int d = cx.deg[x];
+        int lo = k * INB, hi = lo + INB < d ? lo + INB : d;
+        int fresh = 0;
+        for (int e = lo + lane; e < hi; e += WAVE) {
+            int y = cx.col[rb + e];
+            NodeHdr hy = cx.nh[y];
+            int jy = cx.joined_to[y];
+            for (int t = 0; t < hy.cnt; t++) {
+                int c = cx.slot[hy.off + t].comm;
+                if (c == J && J >= 0) {
+                    fresh++;
+                    if (jy != J) atomicAdd(&cx.slot[hy.off + t].in, 1);
+                } else if (c == L && L >= 0) {
+                    if (jy != L) atomicSub(&cx.slot[hy.off + t].in, 1);
+                }
+            }
+        }
+        fresh = wave_sum_int(fresh);
+        if (lane == 0 && J >= 0 && fresh) {
+            NodeHdr hx = cx.nh[x];
+            atomicAdd(&cx.slot[hx.off + hx.cnt - 1].in, fresh);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// exact re-sum of the touched communities
+// ------------------------------------------------------------------------------------
+__global__ void k_refresh_plan(Ctx cx)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int count = __atomic_load_n(&cx.ctr->tcount, __ATOMIC_RELAXED);
+    if (t >= count) return;
+    int C = cx.tlist[t];
+    long long cap = cx.cm_off[C + 1] - cx.cm_off[C];
+    long long len = cx.cm_len[C];
+    if (len > cap) len = cap;
+    int parts = (int)((len + PART - 1) / PART);
+    if (parts < 1) parts = 1;
+    int p0 = wave_reserve(&cx.ctr->parts_total, parts == 1);
+    if (parts > 1) p0 = atomicAdd(&cx.ctr->parts_total, parts);
+    if (p0 + parts > cx.part_cap) {
+        atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
+        return;
+    }
+    cx.part_base[C] = p0;
+    cx.part_cnt[C] = parts;
+    cx.part_done[C] = 0;
+    for (int k = 0; k < parts; k++) cx.part_comm[p0 + k] = C;
+    if (parts > 1) {
+        int ms = atomicAdd(&cx.ctr->mslots, 1);
+        if (ms >= cx.mslot_cap) {
+            atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
+            ms = 0;
+        }
+        cx.mslot[C] = ms;
+        for (int k = 0; k < MACC; k++) cx.macc[(long long)ms * MACC + k] = 0;
+    }
+}
+
+__device__ __forceinline__ void x192_to_digits6(const X192 &v, long long *dg)
+{
+    dg[0] = (long long)(v.w0 & 0xffffffffull);
+    dg[1] = (long long)(v.w0 >> 32);
+    dg[2] = (long long)(v.w1 & 0xffffffffull);
+    dg[3] = (long long)(v.w1 >> 32);
+    dg[4] = (long long)(v.w2 & 0xffffffffull);
+    dg[5] = (long long)(int)(unsigned)(v.w2 >> 32);
+}
+
+// sum_k D_k 2^(32k) for six signed 64-bit counters
+__device__ __forceinline__ X192 x192_from_digits6(const long long *D)
+{
+    X192 r = x192_zero();
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        long long v = D[k];
+        u64 sgn = v < 0 ? ~0ull : 0ull;
+        // v * 2^(32k) as a 192-bit two's complement value
+        u64 w[3] = {0, 0, 0};
+        int sh = 32 * k;
+        int li = sh >> 6, bi = sh & 63;
+        u64 lo = (u64)v << bi;
+        u64 hi = bi ? (((u64)v >> (64 - bi)) | (sgn << bi)) : sgn;
+        w[li] = lo;
+        if (li + 1 < 3) w[li + 1] = hi;
+        for (int q = li + 2; q < 3; q++) w[q] = sgn;
+        X192 t = {w[0], w[1], w[2]};
+        x192_add(r, t);
+    }
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_refresh(Ctx cx)
+{
+    int count = __atomic_load_n(&cx.ctr->parts_total, __ATOMIC_RELAXED);
+    if (count > cx.part_cap) count = cx.part_cap;
+    int lane = threadIdx.x & (WAVE - 1);
+    long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
+    int bad = 0;
+    for (long long p = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE; p < count; p += nw) {
+        int C = cx.part_comm[p];
+        if (C < 0 || C >= cx.K) continue;          // only after a flagged overflow
+        int k = (int)p - cx.part_base[C];
+        int parts = cx.part_cnt[C];
+        if (k < 0 || k >= parts) continue;
+        long long s = cx.cr[C].s;
+        long long base = cx.cm_off[C];
+        long long cap = cx.cm_off[C + 1] - base;
+        long long len = cx.cm_len[C];
+        if (len > cap) len = cap;
+        long long lo = (long long)k * PART, hi = lo + PART < len ? lo + PART : len;
+        X192 a0 = x192_zero(), ap = x192_zero(), am = x192_zero();
+        long long sumi = 0;
+        for (long long q = lo + lane; q < hi; q += WAVE)
+            member_terms(cx, cx.cm_node[base + q], C, s, a0, ap, am, sumi, bad);
+        if (k == 0 && cx.ovf_flag[C]) {
+            int no = __atomic_load_n(&cx.ctr->ovf_cnt, __ATOMIC_RELAXED);
+            for (int e = lane; e < no; e += WAVE)
+                if (cx.ovf_comm[e] == C) member_terms(cx, cx.ovf_node[e], C, s, a0, ap, am, sumi, bad);
+        }
+        a0 = wave_sum_x192(a0);
+        ap = wave_sum_x192(ap);
+        am = wave_sum_x192(am);
+        sumi = wave_sum_i64(sumi);
+        if (lane != 0) continue;
+        if (parts == 1) {
+            store_comm(cx, C, s, a0, ap, am, sumi, bad);
+            continue;
+        }
+        unsigned long long *acc = (unsigned long long *)&cx.macc[(long long)cx.mslot[C] * MACC];
+        long long dg[6];
+        x192_to_digits6(a0, dg);
+        for (int q = 0; q < 6; q++) atomicAdd(acc + q, (unsigned long long)dg[q]);
+        x192_to_digits6(ap, dg);
+        for (int q = 0; q < 6; q++) atomicAdd(acc + 6 + q, (unsigned long long)dg[q]);
+        x192_to_digits6(am, dg);
+        for (int q = 0; q < 6; q++) atomicAdd(acc + 12 + q, (unsigned long long)dg[q]);
+        atomicAdd(acc + 18, (unsigned long long)sumi);
+        __threadfence();
+        if (atomicAdd(&cx.part_done[C], 1) == parts - 1) {
+            // last part: every other part's counters are in (they fenced before counting)
+            __threadfence();
+            long long D[MACC];
+            for (int q = 0; q < MACC; q++) D[q] = (long long)__atomic_load_n(acc + q, __ATOMIC_RELAXED);
+            store_comm(cx, C, s, x192_from_digits6(D), x192_from_digits6(D + 6), x192_from_digits6(D + 12), D[18],
+                       bad);
+        }
+    }
+    if (bad) atomicOr(&cx.ctr->error, LF_DEVERR_INEXACT);
+}
+
+// ------------------------------------------------------------------------------------
+// per-iteration sizing of the queue buffers
+// ------------------------------------------------------------------------------------
+// vbound[x] = visits of x at the start of the iteration + deg + own memberships + 1:
+// an upper bound on the distinct table keys x can create in this iteration (each
+// neighbour gains at most one membership per iteration)
+__global__ void __launch_bounds__(256) k_node_bounds(Ctx cx, long long *vbound)
+{
+    long long x = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
+    int lane = threadIdx.x & (WAVE - 1);
+    if (x >= cx.n) return;
+    long long rb = cx.rowptr[x], re = cx.rowptr[x + 1];
+    long long v = 0;
+    for (long long e = rb + lane; e < re; e += WAVE) v += cx.nh[cx.col[e]].cnt;
+    v = wave_sum_i64(v);
+    if (lane == 0) {
+        NodeHdr hx = cx.nh[x];
+        vbound[x] = v + hx.deg + hx.cnt + 1;
+    }
+}
+
+// per queue: sum of (deg + cnt + 1) [work items], sum of vbound [table keys],
+// sum of ceil(deg / INB) [in-count items]; the maxima over queues go to out[0..2]
+__global__ void __launch_bounds__(256) k_chunk_bounds(Ctx cx, const long long *vbound, int q,
+                                                      unsigned long long *out)
+{
+    __shared__ long long s_a[256 / WAVE], s_b[256 / WAVE], s_c[256 / WAVE];
+    long long start = (long long)blockIdx.x * q;
+    long long end = start + q < cx.n ? start + q : cx.n;
+    long long a = 0, b = 0, c = 0;
+    for (long long r = start + threadIdx.x; r < end; r += blockDim.x) {
+        int x = cx.order[r];
+        NodeHdr hx = cx.nh[x];
+        a += hx.deg + hx.cnt + 1;
+        b += vbound[x];
+        c += (hx.deg + INB - 1) / INB;
+    }
+    a = wave_sum_i64(a);
+    b = wave_sum_i64(b);
+    c = wave_sum_i64(c);
+    int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    if (lane == 0) { s_a[wv] = a; s_b[wv] = b; s_c[wv] = c; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long ta = 0, tb = 0, tc = 0;
+        for (int k = 0; k < 256 / WAVE; k++) { ta += s_a[k]; tb += s_b[k]; tc += s_c[k]; }
+        atomicMax(&out[0], (unsigned long long)ta);
+        atomicMax(&out[1], (unsigned long long)tb);
+        atomicMax(&out[2], (unsigned long long)tc);
+    }
+}
+
+// per order position: work items reserved for this iteration (neighbours, own memberships
+// and the one membership the node may gain); written into `cnt` for the scan
+__global__ void k_item_counts(Ctx cx, long long *cnt)
+{
+    long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (r > cx.n) return;
+    if (r == cx.n) { cnt[r] = 0; return; }
+    NodeHdr hx = cx.nh[cx.order[r]];
+    cnt[r] = (long long)hx.deg + hx.cnt + 1;
+}
+
+__global__ void __launch_bounds__(256) k_item_fill(Ctx cx)
+{
+    long long r = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
+    int lane = threadIdx.x & (WAVE - 1);
+    if (r >= cx.n) return;
+    long long a = cx.item_base[r], b = cx.item_base[r + 1];
+    for (long long f = a + lane; f < b; f += WAVE) cx.item_node[f] = (int)r;
+}
+
+__global__ void k_empty_table(GEntry *t, long long n)
+{
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) t[i].key = GEMPTY;
+}
+
+// ------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------
+void lf_free_iteration_buffers(lf_handle *h)
+{
+    void **ptrs[] = {(void **)&h->dj, (void **)&h->dl, (void **)&h->djd, (void **)&h->dld,
+                     (void **)&h->big_idx,
+                     (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl,
+                     (void **)&h->in_base, (void **)&h->item_base, (void **)&h->item_node, (void **)&h->gt, (void **)&h->occ, (void **)&h->occ_key, (void **)&h->occ_d,
+                     (void **)&h->in_item, (void **)&h->part_comm, (void **)&h->macc};
+    for (void **p : ptrs) {
+        lf_dev_free(h, *p);
+        *p = nullptr;
+    }
+    h->q_cap = 0;
+    h->gT = 0;
+    h->item_cap = 0;
+    h->in_cap = 0;
+    h->part_cap = 0;
+    h->mslot_cap = 0;
+}
+
+static int size_queue_buffers(lf_handle *h, long long q)
+{
+    hipStream_t st = h->stream;
+    const int BS = 256;
+    long long n = h->n;
+    bool moved = false;
+    if (q > h->q_cap) {
+        void **ptrs[] = {(void **)&h->dj, (void **)&h->dl, (void **)&h->djd, (void **)&h->dld,
+                         (void **)&h->big_idx,
+                         (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl,
+                         (void **)&h->in_base};
+        for (void **p : ptrs) {
+            lf_dev_free(h, *p);
+            *p = nullptr;
+        }
+        LF_TRY(lf_dev_alloc(h, (void **)&h->dj, sizeof(int) * q));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->dl, sizeof(int) * q));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->djd, sizeof(double) * q));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->dld, sizeof(double) * q));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->big_idx, sizeof(int) * q));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->big_bj, sizeof(unsigned long long) * q));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->big_bl, sizeof(unsigned long long) * q));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->big_cj, sizeof(int) * q));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->big_cl, sizeof(int) * q));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->in_base, sizeof(int) * q));
+        h->q_cap = q;
+        moved = true;
+    }
+    // bounds for this iteration
+    unsigned long long *dout = nullptr;
+    LF_TRY(lf_dev_alloc(h, (void **)&dout, sizeof(unsigned long long) * 4));
+    LF_HIP(h, hipMemsetAsync(dout, 0, sizeof(unsigned long long) * 4, st));
+    Ctx cx = lf_ctx(h);
+    hipLaunchKernelGGL(k_node_bounds, dim3(grid_for(n * WAVE, BS)), dim3(BS), 0, st, cx, h->vbound);
+    long long nchunks = (n + q - 1) / q;
+    hipLaunchKernelGGL(k_chunk_bounds, dim3((unsigned)nchunks), dim3(BS), 0, st, cx, (const long long *)h->vbound,
+                       (int)q, dout);
+    unsigned long long hb[4];
+    LF_HIP(h, hipMemcpyAsync(hb, dout, sizeof(hb), hipMemcpyDeviceToHost, st));
+    LF_HIP(h, hipStreamSynchronize(st));
+    LF_HIP(h, hipGetLastError());
+    lf_dev_free(h, dout);
+    long long keys = (long long)hb[1] + 64;
+    long long initems = (long long)hb[2] + 64;
+    if (keys >= (1ll << 30) || initems >= (1ll << 31))
+        return lf_set_error(h, LF_EOVERFLOW, "queue of %lld nodes too large for the table path", q);
+    // static work-item layout of this iteration: order position r owns deg + cnt + 1 items
+    if (!h->item_base) LF_TRY(lf_dev_alloc(h, (void **)&h->item_base, sizeof(long long) * (n + 1)));
+    hipLaunchKernelGGL(k_item_counts, dim3(grid_for(n + 1, BS)), dim3(BS), 0, st, lf_ctx(h), h->vbound);
+    LF_TRY(lf_exclusive_scan_i64(h, h->vbound, h->item_base, n + 1));
+    long long items = 0;
+    LF_HIP(h, hipMemcpyAsync(&items, h->item_base + n, sizeof(long long), hipMemcpyDeviceToHost, st));
+    LF_HIP(h, hipStreamSynchronize(st));
+    if (items > h->item_cap) {
+        lf_dev_free(h, h->item_node);
+        h->item_node = nullptr;
+        long long want = items + items / 8 + 1024;
+        LF_TRY(lf_dev_alloc(h, (void **)&h->item_node, sizeof(int) * want));
+        h->item_cap = want;
+        moved = true;
+    }
+    hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n * WAVE, BS)), dim3(BS), 0, st, lf_ctx(h));
+    long long T = 1024;
+    while (T < 2 * keys) T <<= 1;
+    if (T > h->gT) {
+        void **ptrs[] = {(void **)&h->gt, (void **)&h->occ, (void **)&h->occ_key, (void **)&h->occ_d};
+        for (void **p : ptrs) {
+            lf_dev_free(h, *p);
+            *p = nullptr;
+        }
+        LF_TRY(lf_dev_alloc(h, (void **)&h->gt, sizeof(GEntry) * T));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->occ, sizeof(int) * T));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->occ_key, sizeof(unsigned long long) * T));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->occ_d, sizeof(double) * T));
+        LF_HIP(h, hipMemsetAsync(h->gt, 0, sizeof(GEntry) * T, st));
+        hipLaunchKernelGGL(k_empty_table, dim3(grid_for(T, BS)), dim3(BS), 0, st, h->gt, T);
+        h->gT = T;
+        moved = true;
+    }
+    if (initems > h->in_cap) {
+        lf_dev_free(h, h->in_item);
+        h->in_item = nullptr;
+        long long want = initems + initems / 4;
+        LF_TRY(lf_dev_alloc(h, (void **)&h->in_item, sizeof(int) * want));
+        h->in_cap = want;
+        moved = true;
+    }
+    long long pcap = 2 * q + (h->cm_cap + n) / PART + 64;
+    if (pcap > h->part_cap) {
+        lf_dev_free(h, h->part_comm);
+        h->part_comm = nullptr;
+        LF_TRY(lf_dev_alloc(h, (void **)&h->part_comm, sizeof(int) * pcap));
+        h->part_cap = pcap;
+        moved = true;
+    }
+    long long mcap = 2 * q + 64;
+    if (mcap > h->mslot_cap) {
+        lf_dev_free(h, h->macc);
+        h->macc = nullptr;
+        LF_TRY(lf_dev_alloc(h, (void **)&h->macc, sizeof(long long) * MACC * mcap));
+        h->mslot_cap = mcap;
+        moved = true;
+    }
+    if (moved) h->graph_version++;
+    LF_HIP(h, hipStreamSynchronize(st));
+    return LF_OK;
+}
+
+int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out)
+{
+    hipStream_t st = h->stream;
+    const int BS = 256;
+    long long n = h->n;
+    lf_run_info dummy;
+    memset(&dummy, 0, sizeof dummy);
+    if (!out) out = &dummy;
+    out->iterations = 0;
+    out->converged = 0;
+    out->hit_max = 0;
+    if (out->wtilde_hist) out->wtilde_hist[0] = h->Wt;
+    if (h->cc == 0.0) {
+        out->converged = 1;
+        out->wtilde = h->Wt;
+        out->wcc_hat = 0.0;
+        return LF_OK;
+    }
+    long long qq = q < n ? q : (n > 0 ? n : 1);
+    double prev = h->Wt;
+    for (int it = 0; it < max_iters; it++) {
+        LF_TRY(size_queue_buffers(h, qq));
+        LF_HIP(h, hipMemsetAsync(&h->ctr->joins, 0, sizeof(unsigned long long) * 2, st));
+        Ctx cx = lf_ctx(h);
+        int gb = h->hub_blocks, rbk = h->refresh_blocks;
+        int prev_start = 0, prev_len = 0;
+        for (long long start = 0; start < n; start += q) {
+            int clen = (int)((n - start) < q ? (n - start) : q);
+            int cstart = (int)start;
+            hipLaunchKernelGGL(k_chunk_begin, dim3(grid_for(prev_len > 0 ? prev_len : 1, BS)), dim3(BS), 0, st, cx,
+                               prev_start, prev_len);
+            LF_TRY(lf_prof_begin(h, LF_K_EVAL));
+            hipLaunchKernelGGL(k_eval, dim3(grid_for(clen, EW)), dim3(EW * WAVE), 0, st, cx, cstart, clen,
+                               h->eval_wave_cap);
+            LF_TRY(lf_prof_end(h, LF_K_EVAL, 1));
+            LF_TRY(lf_prof_begin(h, LF_K_EVAL_HUB));
+            hipLaunchKernelGGL(k_big_visits, dim3(gb), dim3(BS), 0, st, cx, cstart, clen);
+            hipLaunchKernelGGL(k_big_final, dim3(gb), dim3(BS), 0, st, cx, cstart, clen);
+            hipLaunchKernelGGL(k_big_tie, dim3(gb), dim3(BS), 0, st, cx);
+            LF_TRY(lf_prof_end(h, LF_K_EVAL_HUB, 3));
+            LF_TRY(lf_prof_begin(h, LF_K_APPLY));
+            hipLaunchKernelGGL(k_apply_edit, dim3(grid_for(clen, BS)), dim3(BS), 0, st, cx, cstart, clen);
+            hipLaunchKernelGGL(k_apply_in, dim3(rbk), dim3(BS), 0, st, cx, cstart, clen);
+            hipLaunchKernelGGL(k_refresh_plan, dim3(grid_for(2ll * clen, BS)), dim3(BS), 0, st, cx);
+            hipLaunchKernelGGL(k_refresh, dim3(rbk), dim3(BS), 0, st, cx);
+            LF_TRY(lf_prof_end(h, LF_K_APPLY, 4));
+            h->prof.chunks++;
+            h->prof.node_evals += clen;
+            prev_start = cstart;
+            prev_len = clen;
+        }
+        hipLaunchKernelGGL(k_chunk_begin, dim3(grid_for(prev_len > 0 ? prev_len : 1, BS)), dim3(BS), 0, st, cx,
+                           prev_start, prev_len);
+        LF_HIP(h, hipGetLastError());
+        LF_TRY(lf_prof_begin(h, LF_K_ITEREND));
+        long long joins = 0, leaves = 0, live = 0;
+        LF_TRY(lf_iteration_end(h, prev_start, prev_len, &joins, &leaves, &live));
+        LF_TRY(lf_prof_end(h, LF_K_ITEREND, 8));
+        LF_TRY(lf_check_dev_error(h));
+        out->iterations = it + 1;
+        if (out->wtilde_hist) out->wtilde_hist[it + 1] = h->Wt;
+        if (out->joins) out->joins[it] = joins;
+        if (out->leaves) out->leaves[it] = leaves;
+        if (out->communities) out->communities[it] = live;
+        bool stop = (prev == 0.0) || ((h->Wt - prev) / prev < theta);
+        prev = h->Wt;
+        if (stop) {
+            out->converged = 1;
+            break;
+        }
+    }
+    if (!out->converged && out->iterations == max_iters) out->hit_max = 1;
+    LF_TRY(lf_prof_flush(h));
+    {
+        unsigned long long vc[2];
+        LF_HIP(h, hipMemcpy(vc, &h->ctr->visits, sizeof(vc), hipMemcpyDeviceToHost));
+        h->prof.visits = (long long)vc[0];
+        h->prof.candidates = (long long)vc[1];
+    }
+    out->wtilde = h->Wt;
+    out->wcc_hat = h->Wt / h->cc;
+    return LF_OK;
+}

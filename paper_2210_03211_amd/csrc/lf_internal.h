@@ -23,29 +23,61 @@ struct Slot {
     int in;
 };
 
-// Device-side counters and flags (one struct in device memory).
+// One community, one 64-byte line: everything a candidate evaluation reads.  The exact
+// sums S+ / S- (sum of g over the members at size s+1 / s-1) are stored as 160-bit
+// non-negative fixed point (lowest bit 2^-120; every such sum is below 2^31).
+struct __align__(64) CommRec {
+    int s;                 // members
+    int pad;
+    long long m;           // internal edges
+    double W;              // cc-free score fl(p * R(sum g))
+    unsigned Sp[5];
+    unsigned Sm[5];
+};
+
+// One entry of the table path's global hash table, one 64-byte line: key (node, community),
+// neighbour count, the first visiting neighbour's (in-count, degree) kept inline (its
+// correction is computed when the entry is finalised), and four correction digits for
+// every later visit.
+struct __align__(64) GEntry {
+    unsigned long long key;
+    int cnt;
+    int ii;                // inline visit: in-count of the neighbour
+    int idy;               // inline visit: degree of the neighbour (0 = none)
+    int pad;
+    long long d[4];
+    long long pad2;
+};
+
+// Device-side counters and flags (one struct in device memory).  The per-queue counters
+// are reset by the first kernel of every queue.
 struct DevCounters {
     unsigned long long joins;      // per iteration
     unsigned long long leaves;     // per iteration
     unsigned long long visits;     // evaluation statistics (cumulative)
     unsigned long long cands;
-    int tcount;                    // touched communities in the current chunk
-    int hub_count;                 // nodes deferred to the workgroup evaluation path
-    int hub_next;                  // work counter of the workgroup evaluation kernel
-    int refresh_next;              // work counter of the community re-sum kernel
-    int ovf_cnt;                   // joiners that did not fit their community's member list
+    int tcount;                    // touched communities (queue)
+    int unused0;
+    int unused1;
+    int occ_cnt;                   // occupied entries of the global table (queue)
+    int in_items;                  // in-count work items (queue)
+    int parts_total;               // re-sum parts (queue)
+    int mslots;                    // multi-part re-sum accumulators in use (queue)
+    int refresh_next;              // work counter of the full re-sum at initialisation
+    int ovf_cnt;                   // joiners that did not fit their member list (iteration)
     int undecided;                 // initial clustering rounds
     int error;                     // bit flags, see LF_DEVERR_*
     int live;                      // communities with >= 2 members (iteration end)
     int max_mem;                   // largest membership count (iteration end)
     int pad[3];
-    X256 score;                    // exact partition score (iteration end)
+    X256 score;
 };
 
 #define LF_DEVERR_INEXACT 1        // a value did not fit the exact accumulator
 #define LF_DEVERR_INCOUNT 2        // in-count bookkeeping disagreed with a recount
 #define LF_DEVERR_ODD 4            // odd internal-degree sum
 #define LF_DEVERR_SLOTS 8          // a node ran out of membership slots
+#define LF_DEVERR_CAP 16           // a per-queue work buffer was sized too small
 
 // Everything a kernel needs, passed by value.
 struct Ctx {
@@ -57,24 +89,43 @@ struct Ctx {
     const int *order;
     NodeHdr *nh;
     Slot *slot;
-    int *cs;                 // community size
-    long long *cm;           // internal edges
-    double *cW;              // cc-free community score
-    X192 *cSp;               // exact sum of g at size s+1
-    X192 *cSm;               // exact sum of g at size s-1
+    CommRec *cr;             // community records
     long long *cm_off;       // member-list capacity offsets (K + 1)
     int *cm_len;             // member-list fill (may exceed capacity: overflow)
     int *cm_node;            // member lists
     int *tflag;              // touched flag per community
     int *tlist;              // touched list
-    int *joined_to;          // community joined in the current chunk (-1 otherwise)
+    int *joined_to;          // community joined in the current queue (-1 otherwise)
     int *ovf_node;           // overflow joiners (node, community)
     int *ovf_comm;
     int *ovf_flag;
-    int *dj, *dl;            // decisions of the current chunk
+    int *dj, *dl;            // decisions of the current queue
     double *djd, *dld;
-    int *hub_list;
     DevCounters *ctr;
+    // table path (nodes whose candidates do not fit one wave), indexed by queue position j
+    long long *item_base;    // [n + 1] first work item of order position r (static per iteration)
+    int *item_node;          // [items] order position owning each work item
+    int *big_idx;            // [q] 1 if queue index j takes the table path
+    unsigned long long *big_bj, *big_bl;   // [q] best join / leave change (bits; 0 = none)
+    int *big_cj, *big_cl;    // [q] lowest community id among the best
+    GEntry *gt;                // [gT] key (j << 32 | C), empty = ~0
+    int *occ;                  // [gT] occupied entries
+    unsigned long long *occ_key;  // [gT] key | leave << 63
+    double *occ_d;             // [gT] change of each occupied entry
+    long long gmask;           // gT - 1
+    // in-count work items
+    int *in_item;            // [in_cap] queue index of each item
+    int *in_base;            // [q] first item of queue index j
+    int in_cap;
+    // re-sum parts
+    int *part_comm;          // [part_cap]
+    int *part_base;          // [K]
+    int *part_cnt;           // [K]
+    int *part_done;          // [K]
+    int *mslot;              // [K]
+    long long *macc;         // [mslot_cap * 19] carry-save accumulators
+    int part_cap, mslot_cap;
+    int stats;               // collect work counters (visits, candidates)
 };
 
 struct lf_handle {
@@ -103,10 +154,7 @@ struct lf_handle {
     Slot *slot[2];
     int cur;
     long long slot_capb[2];  // capacity of each slot buffer
-    int *cs;
-    long long *cm;
-    double *cW;
-    X192 *cSp, *cSm;
+    CommRec *cr;
     long long *cm_off;
     int *cm_len;
     int *cm_node;
@@ -115,8 +163,26 @@ struct lf_handle {
     int *ovf_node, *ovf_comm, *ovf_flag;
     int *dj, *dl;
     double *djd, *dld;
-    int *hub_list;
-    long long q_cap;         // capacity of the decision / touched arrays
+    long long q_cap;         // capacity of the per-queue arrays
+    // table path and work lists (sized per iteration)
+    long long *item_base;
+    int *item_node;
+    int *big_idx;
+    unsigned long long *big_bj, *big_bl;
+    int *big_cj, *big_cl;
+    GEntry *gt;
+    int *occ;
+    unsigned long long *occ_key;
+    double *occ_d;
+    long long gT;
+    long long item_cap;      // capacity of item_node
+    int *in_item, *in_base;
+    long long in_cap;
+    int *part_comm, *part_base, *part_cnt, *part_done, *mslot;
+    long long *macc;
+    long long part_cap, mslot_cap;
+    long long *vbound;       // [n] per-node bounds used to size the per-queue buffers
+    int graph_version;       // bumped whenever a buffer used by captured launches moves
     DevCounters *ctr;
     double Wt;               // cc-free partition score
     // generic device scratch
@@ -124,13 +190,17 @@ struct lf_handle {
     size_t tmp_bytes;
     // tuning
     int eval_wave_cap;       // table entries per wave in the wave evaluation path
-    int hub_lds_entries;     // table entries of the workgroup evaluation path
-    int hub_blocks;          // resident workgroups of the workgroup evaluation path
-    int refresh_blocks;      // resident workgroups of the community re-sum kernel
+    int tri_lds_cap;         // 0 = auto
+    int hub_blocks;          // workgroups of the table-path evaluation kernels
+    int refresh_blocks;      // workgroups of the in-count and re-sum kernels
     // profiling
-    int profiling;
+    int profiling;           // bit mask of timed kernel classes (1 << LF_K_*)
     lf_profile prof;
     hipEvent_t ev0, ev1;
+    std::vector<hipEvent_t> *evpool;   // start/stop pairs recorded without host sync
+    std::vector<int> *evkind;          // kernel class of each recorded pair
+    std::vector<int> *evlaunch;        // launches bracketed by each pair
+    int evused;                        // pairs recorded and not yet folded into prof
     // allocation registry
     std::vector<void *> *allocs;
 };
@@ -157,9 +227,11 @@ void lf_dev_free(lf_handle *h, void *p);
 int lf_ensure_tmp(lf_handle *h, size_t bytes);
 Ctx lf_ctx(lf_handle *h);
 
-// profiling brackets around a launch sequence on the handle's stream
-int lf_prof_begin(lf_handle *h);
+// profiling brackets around a launch sequence on the handle's stream; events are only
+// resolved by lf_prof_flush (end of an API call), so timing never stalls the host
+int lf_prof_begin(lf_handle *h, int kind);
 int lf_prof_end(lf_handle *h, int kind, int launches);
+int lf_prof_flush(lf_handle *h);
 
 // ---- primitives (prims.hip) ------------------------------------------------------------
 int lf_sort_u64(lf_handle *h, unsigned long long *keys, unsigned long long *keys_alt, long long n,
@@ -181,6 +253,10 @@ int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out);
 // ---- community stages (communities.hip) ----------------------------------------------------
 int lf_initial_clustering(lf_handle *h);
 int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out);
+int lf_iteration_end(lf_handle *h, int last_start, int last_len, long long *joins, long long *leaves,
+                     long long *live);
+int lf_check_dev_error(lf_handle *h);
+void lf_free_iteration_buffers(lf_handle *h);
 int lf_fetch_memberships(lf_handle *h, long long *offsets, int *comm_ids, long long capacity,
                          long long *total, int *in_counts);
 void lf_free_partition(lf_handle *h);

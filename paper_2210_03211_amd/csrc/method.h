@@ -1,0 +1,177 @@
+// method.h -- device arithmetic of the LazyFox method (WCC-hat node terms, community
+// density, candidate changes), shared by the initialisation and the iteration kernels.
+//
+// WCC-hat (Methods, WCC-hat subsection): for a member x of community C with
+// d = deg(x,V), i = deg(x,C), s = |C| and density p,
+//     WCC-hat(x,C) = E[t(x,C)] / E[t(x,V)] * deg(x,V) / (|C\{x}| + deg(x,V\C))
+// with E[t(x,C)] = C(i,2) p and E[t(x,V)] = C(d,2) cc, i.e. p * g(i,d,s) / cc with
+//     g(i,d,s) = i(i-1) / ((d-1)(s-1+d-i)),   0 if i < 2 or d < 2 (E[t] = 0).
+// cc is a positive constant, so the method's comparisons use the cc-free score
+// W(C) = fl(p * R(sum_{y in C} g)), R = exact sum rounded once to nearest-even.
+#pragma once
+#include "lf_internal.h"
+
+#define WAVE 64
+
+#define WAVE_SYNC()                                                                        \
+    do {                                                                                   \
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");                             \
+        __builtin_amdgcn_wave_barrier();                                                   \
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");                             \
+    } while (0)
+
+__device__ __forceinline__ double g_term(long long i, long long d, long long s)
+{
+    if (d < 2 || i < 2) return 0.0;
+    long long num = i * (i - 1);
+    long long den = (d - 1) * (s - 1 + d - i);
+    return (double)num / (double)den;
+}
+
+// density of a community with s members and m internal edges
+__device__ __forceinline__ double density(long long s, long long m)
+{
+    if (s < 2) return 0.0;
+    return (double)(2 * m) / (double)(s * (s - 1));
+}
+
+__device__ __forceinline__ X192 rec_load(const unsigned *p)
+{
+    X192 r;
+    r.w0 = (u64)p[0] | ((u64)p[1] << 32);
+    r.w1 = (u64)p[2] | ((u64)p[3] << 32);
+    r.w2 = (u64)p[4];
+    return r;
+}
+
+__device__ __forceinline__ void rec_store(unsigned *p, const X192 &v, int &bad)
+{
+    p[0] = (unsigned)v.w0;
+    p[1] = (unsigned)(v.w0 >> 32);
+    p[2] = (unsigned)v.w1;
+    p[3] = (unsigned)(v.w1 >> 32);
+    p[4] = (unsigned)v.w2;
+    if (v.w2 >> 32) bad = 1;           // a stored sum is never negative nor >= 2^40
+}
+
+// write a re-summed community (members' exact sums at sizes s, s+1, s-1 and in-count sum)
+__device__ __forceinline__ void store_comm(const Ctx &cx, int C, long long s, X192 a0, X192 ap, X192 am,
+                                           long long sumi, int &bad)
+{
+    if (sumi & 1) atomicOr(&cx.ctr->error, LF_DEVERR_ODD);
+    long long m = sumi / 2;
+    CommRec *r = &cx.cr[C];
+    r->m = m;
+    r->W = density(s, m) * x192_round(a0);
+    rec_store(r->Sp, ap, bad);
+    rec_store(r->Sm, am, bad);
+    cx.tflag[C] = 0;
+}
+
+__device__ __forceinline__ int find_slot(const Slot *slot, long long off, int cnt, int c)
+{
+    for (int t = 0; t < cnt; t++)
+        if (slot[off + t].comm == c) return t;
+    return -1;
+}
+
+// correction of one neighbour y (in C with in-count i, degree dy) when x joins C (its
+// in-count rises by one, the size to s+1) or leaves C (falls by one, size s-1)
+__device__ __forceinline__ X192 visit_term(bool leave, long long i, long long dy, long long s, int &bad)
+{
+    double gn, go;
+    if (leave) { gn = g_term(i - 1, dy, s - 1); go = g_term(i, dy, s - 1); }
+    else { gn = g_term(i + 1, dy, s + 1); go = g_term(i, dy, s + 1); }
+    X192 t = x192_from_double(gn, bad);
+    X192 o = x192_from_double(go, bad);
+    x192_sub(t, o);
+    return t;
+}
+
+// change of C's cc-free score when x (degree dx, k neighbours in C) joins / leaves C;
+// corr = exact sum of the neighbours' corrections
+__device__ __forceinline__ double candidate_delta(const Ctx &cx, int C, bool leave, long long k, long long dx,
+                                                  X192 corr, int &bad)
+{
+    const CommRec *r = &cx.cr[C];
+    long long s = r->s;
+    long long m = r->m;
+    X192 S;
+    double p;
+    if (leave) {
+        S = rec_load(r->Sm);
+        x192_add(S, corr);
+        X192 own = x192_from_double(g_term(k, dx, s - 1), bad);
+        x192_sub(S, own);
+        p = density(s - 1, m - k);
+    } else {
+        S = rec_load(r->Sp);
+        x192_add(S, corr);
+        X192 own = x192_from_double(g_term(k, dx, s + 1), bad);
+        x192_add(S, own);
+        p = density(s + 1, m + k);
+    }
+    double pS = p * x192_round(S);
+    return pS - r->W;
+}
+
+// strictly positive changes only; larger wins; equal -> lower community id
+__device__ __forceinline__ void better(double d, int c, double &bd, int &bc)
+{
+    if (!(d > 0.0)) return;
+    if (bc < 0 || d > bd || (d == bd && c < bc)) { bd = d; bc = c; }
+}
+
+__device__ __forceinline__ void wave_best(double &bd, int &bc)
+{
+    for (int m = 32; m >= 1; m >>= 1) {
+        double od = __shfl_xor(bd, m, WAVE);
+        int oc = __shfl_xor(bc, m, WAVE);
+        if (oc >= 0 && (bc < 0 || od > bd || (od == bd && oc < bc))) { bd = od; bc = oc; }
+    }
+}
+
+// exact g-sums of one member y of C (at sizes s, s+1, s-1) if y is still in C
+__device__ __forceinline__ void member_terms(const Ctx &cx, int y, int C, long long s, X192 &a0, X192 &ap,
+                                             X192 &am, long long &sumi, int &bad)
+{
+    NodeHdr hy = cx.nh[y];
+    int t = find_slot(cx.slot, hy.off, hy.cnt, C);
+    if (t < 0) return;                       // left C earlier in this iteration
+    long long i = cx.slot[hy.off + t].in;
+    long long d = hy.deg;
+    sumi += i;
+    X192 v = x192_from_double(g_term(i, d, s), bad);
+    x192_add(a0, v);
+    v = x192_from_double(g_term(i, d, s + 1), bad);
+    x192_add(ap, v);
+    v = x192_from_double(g_term(i, d, s - 1), bad);
+    x192_add(am, v);
+}
+
+// The lanes executing this call with want = true receive consecutive indices from *ctr,
+// with a single atomic per wave (the leader is an active lane, so divergent callers are
+// fine); returns -1 for the others.
+__device__ __forceinline__ int wave_reserve(int *ctr, bool want)
+{
+    unsigned long long m = __ballot(want);
+    if (!m) return -1;
+    int lane = threadIdx.x & (WAVE - 1);
+    int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(ctr, __popcll(m));
+    base = __shfl(base, leader, WAVE);
+    return want ? base + __popcll(m & ((1ull << lane) - 1)) : -1;
+}
+
+__device__ __forceinline__ unsigned hash_tab(int c) { return (unsigned)c * 0x9E3779B1u; }
+
+__device__ __forceinline__ unsigned long long hash64(unsigned long long k)
+{
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}

@@ -57,22 +57,49 @@ int lf_ensure_tmp(lf_handle *h, size_t bytes)
     return LF_OK;
 }
 
-int lf_prof_begin(lf_handle *h)
+static bool prof_on(lf_handle *h, int kind) { return kind < LF_K_COUNT && ((h->profiling >> kind) & 1); }
+
+int lf_prof_begin(lf_handle *h, int kind)
 {
-    if (!h->profiling) return LF_OK;
-    LF_HIP(h, hipEventRecord(h->ev0, h->stream));
+    if (!prof_on(h, kind)) return LF_OK;
+    if (h->evused >= 4096) LF_TRY(lf_prof_flush(h));
+    size_t need = 2 * (size_t)(h->evused + 1);
+    while (h->evpool->size() < need) {
+        hipEvent_t e;
+        LF_HIP(h, hipEventCreate(&e));
+        h->evpool->push_back(e);
+    }
+    LF_HIP(h, hipEventRecord((*h->evpool)[2 * h->evused], h->stream));
     return LF_OK;
 }
 
 int lf_prof_end(lf_handle *h, int kind, int launches)
 {
-    if (!h->profiling) return LF_OK;
-    LF_HIP(h, hipEventRecord(h->ev1, h->stream));
-    LF_HIP(h, hipEventSynchronize(h->ev1));
-    float ms = 0.f;
-    LF_HIP(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
-    h->prof.ms[kind] += ms;
-    h->prof.launches[kind] += launches;
+    if (!prof_on(h, kind)) return LF_OK;
+    LF_HIP(h, hipEventRecord((*h->evpool)[2 * h->evused + 1], h->stream));
+    if ((int)h->evkind->size() <= h->evused) {
+        h->evkind->push_back(kind);
+        h->evlaunch->push_back(launches);
+    } else {
+        (*h->evkind)[h->evused] = kind;
+        (*h->evlaunch)[h->evused] = launches;
+    }
+    h->evused++;
+    return LF_OK;
+}
+
+int lf_prof_flush(lf_handle *h)
+{
+    if (h->evused == 0) return LF_OK;
+    LF_HIP(h, hipEventSynchronize((*h->evpool)[2 * h->evused - 1]));
+    for (int k = 0; k < h->evused; k++) {
+        float ms = 0.f;
+        LF_HIP(h, hipEventElapsedTime(&ms, (*h->evpool)[2 * k], (*h->evpool)[2 * k + 1]));
+        int kind = (*h->evkind)[k];
+        h->prof.ms[kind] += ms;
+        h->prof.launches[kind] += (*h->evlaunch)[k];
+    }
+    h->evused = 0;
     return LF_OK;
 }
 

@@ -74,6 +74,7 @@ SMALL = {
     "cliques": lambda: cliques([3, 7, 4, 12]),
     "path": lambda: path(9),
     "social_0.2pct": lambda: G.named_config("social", scale=0.002),
+    "dense300": lambda: G.random_gnp(300, 0.9, 4),
 }
 
 
@@ -221,8 +222,8 @@ def test_run_parity_copurchase_full(lf, orc):
 
 
 def test_hub_path_parity(lf, orc):
-    """Nodes of high degree go through the workgroup evaluation path; a star-of-cliques
-    graph forces candidate tables far beyond one wave's."""
+    """Nodes of high degree go through the global-table path; a star-of-cliques graph
+    gives one node hundreds of distinct candidates."""
     say("hub path")
     rng = np.random.default_rng(9)
     src, dst = [], []
@@ -294,3 +295,51 @@ def test_reinit_restarts(lf):
     h.init_communities()
     off1, ids1 = h.memberships()
     assert np.array_equal(off0, off1) and np.array_equal(ids0, ids1)
+
+
+# ------------------------------------------------------------------ forced code paths
+def test_triangle_group_paths(lf, orc):
+    """Out-lists longer than one wave's LDS go to the workgroup triangle kernel; with a
+    small LDS cap that kernel keeps them in global scratch instead."""
+    g = G.random_gnp(600, 0.9, 5)          # out-degrees well above 256
+    o = oracle_graph(orc, g).init_communities()
+    otri, occl, oorder = o.node_stats()
+    for cap in (0, 16):
+        say("triangle group path, lds cap", cap)
+        h = lf.Handle(0)
+        h.lf_set_option("tri_lds_cap", cap)
+        import torch
+        h.load_graph(g.n, torch.from_numpy(g.src).cuda(), torch.from_numpy(g.dst).cuda()).init_communities()
+        tri, ccl, order = h.node_stats()
+        assert np.array_equal(tri, otri) and np.array_equal(order, oorder)
+        assert np.array_equal(ccl.view(np.int64), occl.view(np.int64))
+
+
+@pytest.mark.parametrize("name,q", [("sbm2000", 64), ("copurchase_1pct", 16), ("social_0.2pct", 512)])
+def test_small_tables_and_single_workgroups(lf, orc, name, q):
+    """A tiny wave table pushes nearly every node onto the global-table path; single
+    workgroups make every grid-stride loop run long."""
+    import torch
+    say("forced hub path", name, q)
+    g = SMALL[name]()
+    o = oracle_graph(orc, g).init_communities()
+    oinfo = o.run_iterations(q, 0.01, 50)
+    for opts in ({"wave_table": 16}, {"hub_blocks": 1, "refresh_blocks": 1}, {"wave_table": 16, "hub_blocks": 3}):
+        h = lf.Handle(0)
+        for k, v in opts.items():
+            h.lf_set_option(k, v)
+            assert h.lf_get_option(k) == v
+        h.load_graph(g.n, torch.from_numpy(g.src).cuda(), torch.from_numpy(g.dst).cuda()).init_communities()
+        info = h.run_iterations(q, 0.01, 50)
+        assert info["iterations"] == oinfo["iterations"]
+        off, ids = h.memberships()
+        ooff, oids = o.memberships()
+        assert np.array_equal(off, ooff) and np.array_equal(ids, oids)
+        assert np.array_equal(info["wtilde_hist"], oinfo["wtilde_hist"])
+
+
+def test_option_validation(lf):
+    h = lf.Handle(0)
+    for name, bad in (("wave_table", 100), ("wave_table", 256), ("hub_blocks", 0)):
+        with pytest.raises(lf.LazyFoxError):
+            h.lf_set_option(name, bad)
