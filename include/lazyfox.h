@@ -182,7 +182,10 @@ int lf_reset_profile(lf_handle *h);
 #define LF_OPT_REFRESH_BLOCKS 4    /* workgroups of the in-count and re-sum kernels */
 #define LF_OPT_WAVE_TABLE 5        /* candidate-table entries per wave in the wave path
                                       (power of two, 16 .. 128); nodes needing more go to
-                                      the table path */
+                                      the medium wave path */
+#define LF_OPT_MED_TABLE 6         /* candidate-table entries per wave in the medium wave
+                                      path (power of two, 16 .. 512); nodes needing more
+                                      go to the global-table path */
 int lf_set_option(lf_handle *h, int option, int64_t value);
 int lf_get_option(lf_handle *h, int option, int64_t *value);
 

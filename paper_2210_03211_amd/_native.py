@@ -13,7 +13,7 @@ LF_OK, LF_EINVAL, LF_ESTATE, LF_ENOMEM, LF_EDEVICE, LF_ERANGE, LF_EOVERFLOW = 0,
 LF_EINTERNAL = -8
 LF_RELABEL = 1
 LF_DEVICE_PTR = 2
-OPTIONS = {"tri_lds_cap": 1, "hub_blocks": 3, "refresh_blocks": 4, "wave_table": 5}
+OPTIONS = {"tri_lds_cap": 1, "hub_blocks": 3, "refresh_blocks": 4, "wave_table": 5, "med_table": 6}
 KERNEL_CLASSES = ["build", "triangles", "order", "init_clustering", "eval", "eval_hub", "apply",
                   "iteration_end"]
 

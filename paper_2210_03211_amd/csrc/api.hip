@@ -49,6 +49,7 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     h->eval_wave_cap = 128;
+    h->eval_med_cap = 512;
     h->hub_blocks = 2 * cus;
     h->refresh_blocks = 2 * cus;
     h->K = -1;
@@ -275,6 +276,10 @@ int lf_set_option(lf_handle *h, int option, int64_t value)
         if (value < 16 || value > 128 || (value & (value - 1))) break;
         h->eval_wave_cap = (int)value;
         return LF_OK;
+    case LF_OPT_MED_TABLE:
+        if (value < 16 || value > 512 || (value & (value - 1))) break;
+        h->eval_med_cap = (int)value;
+        return LF_OK;
     default:
         return lf_set_error(h, LF_EINVAL, "unknown option %d", option);
     }
@@ -289,6 +294,7 @@ int lf_get_option(lf_handle *h, int option, int64_t *value)
     case LF_OPT_HUB_BLOCKS: *value = h->hub_blocks; return LF_OK;
     case LF_OPT_REFRESH_BLOCKS: *value = h->refresh_blocks; return LF_OK;
     case LF_OPT_WAVE_TABLE: *value = h->eval_wave_cap; return LF_OK;
+    case LF_OPT_MED_TABLE: *value = h->eval_med_cap; return LF_OK;
     default: return lf_set_error(h, LF_EINVAL, "unknown option %d", option);
     }
 }

@@ -61,121 +61,127 @@ __device__ __forceinline__ int lds_insert(int *key, int T, int lg, int C)
     }
 }
 
-__global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, int cstart, int clen, int wcap)
+// Per-wave LDS of the wave paths: a candidate table of 2*VCAP entries and a visit list of
+// VCAP entries.
+template <int VCAP>
+struct WaveLds {
+    int key[2 * VCAP];
+    int kk[2 * VCAP];
+    int sz[2 * VCAP];
+    unsigned long long d[4][2 * VCAP];
+    long long vslot[VCAP];
+    int vdeg[VCAP];
+    int vhash[VCAP];
+    int vin[VCAP];
+    int vcomm[VCAP];
+    int mx[MXCAP];
+    int mxin[MXCAP];
+};
+
+// big_idx states of a queue index
+#define Q_DONE 0        // evaluated by a wave path
+#define Q_TABLE 1       // goes to the table path
+#define Q_MEDIUM 2      // too large for the small wave path, try the medium one
+
+// Evaluate queued node j with one wave if its neighbours (<= VCAP), visits and own
+// memberships fit (2 * (visits + own) <= table, <= VCAP visits).  Returns false (decision
+// not written) otherwise.
+template <int VCAP>
+__device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int lane, WaveLds<VCAP> &L,
+                                          int wcap)
 {
-    __shared__ int s_key[EW][ECAP];
-    __shared__ int s_k[EW][ECAP];
-    __shared__ unsigned long long s_d[EW][4][ECAP];
-    __shared__ int s_mx[EW][MXCAP];
-    __shared__ int s_mxin[EW][MXCAP];
-    __shared__ long long s_vslot[EW][WAVE];
-    __shared__ int s_vdeg[EW][WAVE];
-    __shared__ int s_sz[EW][ECAP];
-    int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    int j = blockIdx.x * EW + wv;
-    if (j >= clen) return;                  // no block barriers in this kernel
-    int x = cx.order[cstart + j];
-    NodeHdr hx = cx.nh[x];
-    long long rb = cx.rowptr[x];
-    int d = hx.deg;
-    bool big = d > WAVE || hx.cnt > MXCAP;
-    int yc = 0, ydeg = 0, incl = 0, V = 0;
-    long long yoff = 0;
-    if (!big) {
-        if (lane < d) {
-            int y = cx.col[rb + lane];
+    const int x = cx.order[cstart + j];
+    const NodeHdr hx = cx.nh[x];
+    const long long rb = cx.rowptr[x];
+    const int d = hx.deg, mcnt = hx.cnt;
+    if (d > VCAP || mcnt > MXCAP) return false;
+    // neighbour headers in batches of 64, flattened into the visit list
+    int V = 0;
+    for (int base = 0; base < d; base += WAVE) {
+        int e = base + lane;
+        int yc = 0, ydeg = 0;
+        long long yoff = 0;
+        if (e < d) {
+            int y = cx.col[rb + e];
             NodeHdr hy = cx.nh[y];
             yc = hy.cnt;
             yoff = hy.off;
             ydeg = hy.deg;
         }
-        incl = yc;
+        int incl = yc;
         for (int o = 1; o < WAVE; o <<= 1) {
             int t = __shfl_up(incl, o, WAVE);
             if (lane >= o) incl += t;
         }
-        V = __shfl(incl, WAVE - 1, WAVE);
-        big = 2 * (V + hx.cnt) > wcap;
-    }
-    if (big) {
-        // table path: the node's work items are laid out statically for the iteration
-        if (lane == 0) {
-            cx.big_idx[j] = 1;
-            cx.big_bj[j] = 0;
-            cx.big_bl[j] = 0;
-            cx.big_cj[j] = 0x7fffffff;
-            cx.big_cl[j] = 0x7fffffff;
+        int p0 = V + incl - yc;
+        V += __shfl(incl, WAVE - 1, WAVE);
+        if (V + mcnt > VCAP || 2 * (V + mcnt) > wcap) return false;   // wave-uniform
+        for (int t = 0; t < yc; t++) {
+            L.vslot[p0 + t] = yoff + t;
+            L.vdeg[p0 + t] = ydeg;
         }
-        return;
     }
-    if (lane == 0) cx.big_idx[j] = 0;
     int T = 8;
-    while (T < 2 * (V + hx.cnt)) T <<= 1;
-    int lg = 31 - __clz(T);
-    int *key = s_key[wv], *kk = s_k[wv];
-    unsigned long long *d0 = s_d[wv][0], *d1 = s_d[wv][1], *d2 = s_d[wv][2], *d3 = s_d[wv][3];
+    while (T < 2 * (V + mcnt)) T <<= 1;
+    const int lg = 31 - __clz(T);
     for (int t = lane; t < T; t += WAVE) {
-        key[t] = -1; kk[t] = 0; d0[t] = 0; d1[t] = 0; d2[t] = 0; d3[t] = 0;
+        L.key[t] = -1; L.kk[t] = 0;
+        L.d[0][t] = 0; L.d[1][t] = 0; L.d[2][t] = 0; L.d[3][t] = 0;
     }
-    // flattened visit list: (slot index, neighbour degree)
-    for (int t = 0, base = incl - yc; t < yc; t++) {
-        s_vslot[wv][base + t] = yoff + t;
-        s_vdeg[wv][base + t] = ydeg;
-    }
-    int mcnt = hx.cnt;
     if (lane < mcnt) {
         Slot sl = cx.slot[hx.off + lane];
-        s_mx[wv][lane] = sl.comm;
-        s_mxin[wv][lane] = sl.in;
+        L.mx[lane] = sl.comm;
+        L.mxin[lane] = sl.in;
     }
     WAVE_SYNC();
     // 1. candidates and neighbour counts: own communities are leave candidates even without
     //    a neighbour in them; every neighbour membership counts towards its community
-    if (lane < mcnt) lds_insert(key, T, lg, s_mx[wv][lane]);
-    Slot sl = {0, 0};
-    int hsh = -1;
-    if (lane < V) {
-        sl = cx.slot[s_vslot[wv][lane]];
-        hsh = lds_insert(key, T, lg, sl.comm);
-        atomicAdd(&kk[hsh], 1);
+    if (lane < mcnt) lds_insert(L.key, T, lg, L.mx[lane]);
+    for (int v = lane; v < V; v += WAVE) {
+        Slot sl = cx.slot[L.vslot[v]];
+        int h = lds_insert(L.key, T, lg, sl.comm);
+        atomicAdd(&L.kk[h], 1);
+        L.vhash[v] = h;
+        L.vin[v] = sl.in;
+        L.vcomm[v] = sl.comm;
     }
     WAVE_SYNC();
     // 2. one community-record gather per candidate (its size feeds the visit terms)
     for (int t = lane; t < T; t += WAVE) {
-        int C = key[t];
-        if (C >= 0) s_sz[wv][t] = cx.cr[C].s;
+        int C = L.key[t];
+        if (C >= 0) L.sz[t] = cx.cr[C].s;
     }
     WAVE_SYNC();
     // 3. exact correction of every visit, summed per candidate
     int bad = 0;
-    if (lane < V) {
-        int C = sl.comm;
+    for (int v = lane; v < V; v += WAVE) {
+        int C = L.vcomm[v], h = L.vhash[v];
         bool leave = false;
-        for (int a = 0; a < mcnt; a++) leave |= (s_mx[wv][a] == C);
-        X192 term = visit_term(leave, sl.in, s_vdeg[wv][lane], s_sz[wv][hsh], bad);
+        for (int a = 0; a < mcnt; a++) leave |= (L.mx[a] == C);
+        X192 term = visit_term(leave, L.vin[v], L.vdeg[v], L.sz[h], bad);
         i64 t0, t1, t2, t3;
         x192_digits(term, t0, t1, t2, t3);
-        atomicAdd(&d0[hsh], (unsigned long long)t0);
-        atomicAdd(&d1[hsh], (unsigned long long)t1);
-        atomicAdd(&d2[hsh], (unsigned long long)t2);
-        atomicAdd(&d3[hsh], (unsigned long long)t3);
+        atomicAdd(&L.d[0][h], (unsigned long long)t0);
+        atomicAdd(&L.d[1][h], (unsigned long long)t1);
+        atomicAdd(&L.d[2][h], (unsigned long long)t2);
+        atomicAdd(&L.d[3][h], (unsigned long long)t3);
     }
     WAVE_SYNC();
+    // 4. change of every candidate's score, best join and best leave
     double bjd = 0.0, bld = 0.0;
     int bj = -1, bl = -1, ncand = 0;
-    long long dx = hx.deg;
     for (int t = lane; t < T; t += WAVE) {
-        int C = key[t];
+        int C = L.key[t];
         if (C < 0) continue;
         ncand++;
-        int k = kk[t];
+        int k = L.kk[t];
         int a = -1;
         for (int q = 0; q < mcnt; q++)
-            if (s_mx[wv][q] == C) a = q;
+            if (L.mx[q] == C) a = q;
         bool leave = a >= 0;
-        if (leave && s_mxin[wv][a] != k) atomicOr(&cx.ctr->error, LF_DEVERR_INCOUNT);
-        X192 corr = x192_from_digits((i64)d0[t], (i64)d1[t], (i64)d2[t], (i64)d3[t]);
-        double dl = candidate_delta(cx, C, leave, k, dx, corr, bad);
+        if (leave && L.mxin[a] != k) atomicOr(&cx.ctr->error, LF_DEVERR_INCOUNT);
+        X192 corr = x192_from_digits((i64)L.d[0][t], (i64)L.d[1][t], (i64)L.d[2][t], (i64)L.d[3][t]);
+        double dl = candidate_delta(cx, C, leave, k, d, corr, bad);
         if (leave) better(dl, C, bld, bl);
         else better(dl, C, bjd, bj);
     }
@@ -188,11 +194,62 @@ __global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, int cstart, int clen
         cx.djd[j] = bj >= 0 ? bjd : 0.0;
         cx.dl[j] = bl;
         cx.dld[j] = bl >= 0 ? bld : 0.0;
+        cx.big_idx[j] = Q_DONE;
         if (cx.stats) {
             atomicAdd(&cx.ctr->visits, (unsigned long long)V);
             atomicAdd(&cx.ctr->cands, (unsigned long long)ncand);
         }
     }
+    return true;
+}
+
+__device__ __forceinline__ void mark_table(const Ctx &cx, int j)
+{
+    cx.big_idx[j] = Q_TABLE;
+    cx.big_bj[j] = 0;
+    cx.big_bl[j] = 0;
+    cx.big_cj[j] = 0x7fffffff;
+    cx.big_cl[j] = 0x7fffffff;
+}
+
+#define VSMALL 64       // visits of the small wave path
+#define VMED 256        // visits of the medium wave path
+#define EWM 2           // waves per block in the medium path
+
+// small wave path: every queued node; nodes that do not fit are passed on
+__global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, int cstart, int clen, int wcap, int prev_start,
+                                                   int prev_len)
+{
+    __shared__ WaveLds<VSMALL> s_l[EW];
+    const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int j = blockIdx.x * EW + wv;
+    // start of a queue: reset its counters (no kernel of this launch uses them) and clear
+    // the previous queue's join marks
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        DevCounters *c = cx.ctr;
+        c->tcount = 0;
+        c->occ_cnt = 0;
+        c->in_items = 0;
+        c->parts_total = 0;
+        c->mslots = 0;
+    }
+    if (lane == 0)
+        for (int p = j; p < prev_len; p += clen) cx.joined_to[cx.order[prev_start + p]] = -1;
+    if (j >= clen) return;                  // no block barriers in this kernel
+    if (eval_wave<VSMALL>(cx, cstart, j, lane, s_l[wv], wcap < 2 * VSMALL ? wcap : 2 * VSMALL)) return;
+    if (lane == 0) cx.big_idx[j] = Q_MEDIUM;
+}
+
+// medium wave path: nodes passed on by the small path; those still too large go to the
+// table path
+__global__ void __launch_bounds__(EWM * WAVE) k_eval_med(Ctx cx, int cstart, int clen, int mcap)
+{
+    __shared__ WaveLds<VMED> s_l[EWM];
+    const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int j = blockIdx.x * EWM + wv;
+    if (j >= clen || cx.big_idx[j] != Q_MEDIUM) return;
+    if (eval_wave<VMED>(cx, cstart, j, lane, s_l[wv], mcap)) return;
+    if (lane == 0) mark_table(cx, j);
 }
 
 // ------------------------------------------------------------------------------------
@@ -265,7 +322,7 @@ __global__ void __launch_bounds__(EWB * WAVE) k_big_visits(Ctx cx, int cstart, i
         if (f < count) {
             int r = cx.item_node[ib0 + f];
             int j = r - cstart;
-            if (j >= 0 && j < clen && cx.big_idx[j] > 0) {
+            if (j >= 0 && j < clen && cx.big_idx[j] == Q_TABLE) {
                 int x = cx.order[r];
                 NodeHdr hx = cx.nh[x];
                 long long e = ib0 + f - cx.item_base[r];
@@ -499,7 +556,7 @@ __global__ void k_apply_edit(Ctx cx, int cstart, int clen)
     bool inq = j < clen;
     int J = -1, L = -1;
     if (inq) {
-        if (cx.big_idx[j] > 0) {
+        if (cx.big_idx[j] == Q_TABLE) {
             unsigned long long bj = cx.big_bj[j], bl = cx.big_bl[j];
             J = bj ? cx.big_cj[j] : -1;
             L = bl ? cx.big_cl[j] : -1;
@@ -569,13 +626,22 @@ __global__ void k_apply_edit(Ctx cx, int cstart, int clen)
 // in-counts: a surviving member y of J (L) gains (loses) one per neighbour that joined
 // (left); a node that joined J in this queue gets its in-count counted afresh.  One wave
 // per block of INB neighbours of a moved node.
-__global__ void __launch_bounds__(256) k_apply_in(Ctx cx, int cstart, int clen)
+__device__ void refresh_plan(const Ctx &cx, int t);
+
+// Blocks [0, plan_blocks) split the touched communities into re-sum parts (one thread
+// each); the other blocks apply the in-count changes.  Both only need the edits.
+__global__ void __launch_bounds__(256) k_apply_in(Ctx cx, int cstart, int clen, int plan_blocks)
 {
+    if ((int)blockIdx.x < plan_blocks) {
+        refresh_plan(cx, blockIdx.x * blockDim.x + threadIdx.x);
+        return;
+    }
     int count = __atomic_load_n(&cx.ctr->in_items, __ATOMIC_RELAXED);
     if (count > cx.in_cap) count = cx.in_cap;
     int lane = threadIdx.x & (WAVE - 1);
-    long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
-    for (long long p = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE; p < count; p += nw) {
+    long long nw = (long long)(gridDim.x - plan_blocks) * (blockDim.x / WAVE);
+    for (long long p = ((blockIdx.x - plan_blocks) * (long long)blockDim.x + threadIdx.x) / WAVE; p < count;
+         p += nw) {
         int j = cx.in_item[p];
         if (j < 0 || j >= clen) continue;          // only after a flagged overflow
         int k = (int)p - cx.in_base[j];
@@ -612,9 +678,8 @@ __global__ void __launch_bounds__(256) k_apply_in(Ctx cx, int cstart, int clen)
 // ------------------------------------------------------------------------------------
 // exact re-sum of the touched communities
 // ------------------------------------------------------------------------------------
-__global__ void k_refresh_plan(Ctx cx)
+__device__ void refresh_plan(const Ctx &cx, int t)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
     int count = __atomic_load_n(&cx.ctr->tcount, __ATOMIC_RELAXED);
     if (t >= count) return;
     int C = cx.tlist[t];
@@ -973,11 +1038,11 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
         for (long long start = 0; start < n; start += q) {
             int clen = (int)((n - start) < q ? (n - start) : q);
             int cstart = (int)start;
-            hipLaunchKernelGGL(k_chunk_begin, dim3(grid_for(prev_len > 0 ? prev_len : 1, BS)), dim3(BS), 0, st, cx,
-                               prev_start, prev_len);
             LF_TRY(lf_prof_begin(h, LF_K_EVAL));
             hipLaunchKernelGGL(k_eval, dim3(grid_for(clen, EW)), dim3(EW * WAVE), 0, st, cx, cstart, clen,
-                               h->eval_wave_cap);
+                               h->eval_wave_cap, prev_start, prev_len);
+            hipLaunchKernelGGL(k_eval_med, dim3(grid_for(clen, EWM)), dim3(EWM * WAVE), 0, st, cx, cstart, clen,
+                               h->eval_med_cap);
             LF_TRY(lf_prof_end(h, LF_K_EVAL, 1));
             LF_TRY(lf_prof_begin(h, LF_K_EVAL_HUB));
             hipLaunchKernelGGL(k_big_visits, dim3(gb), dim3(BS), 0, st, cx, cstart, clen);
@@ -986,10 +1051,10 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
             LF_TRY(lf_prof_end(h, LF_K_EVAL_HUB, 3));
             LF_TRY(lf_prof_begin(h, LF_K_APPLY));
             hipLaunchKernelGGL(k_apply_edit, dim3(grid_for(clen, BS)), dim3(BS), 0, st, cx, cstart, clen);
-            hipLaunchKernelGGL(k_apply_in, dim3(rbk), dim3(BS), 0, st, cx, cstart, clen);
-            hipLaunchKernelGGL(k_refresh_plan, dim3(grid_for(2ll * clen, BS)), dim3(BS), 0, st, cx);
+            int pb = (int)grid_for(2ll * clen, BS);
+            hipLaunchKernelGGL(k_apply_in, dim3(pb + rbk), dim3(BS), 0, st, cx, cstart, clen, pb);
             hipLaunchKernelGGL(k_refresh, dim3(rbk), dim3(BS), 0, st, cx);
-            LF_TRY(lf_prof_end(h, LF_K_APPLY, 4));
+            LF_TRY(lf_prof_end(h, LF_K_APPLY, 3));
             h->prof.chunks++;
             h->prof.node_evals += clen;
             prev_start = cstart;

@@ -189,7 +189,8 @@ struct lf_handle {
     void *tmp;
     size_t tmp_bytes;
     // tuning
-    int eval_wave_cap;       // table entries per wave in the wave evaluation path
+    int eval_wave_cap;       // table entries per wave in the small wave path
+    int eval_med_cap;        // table entries per wave in the medium wave path
     int tri_lds_cap;         // 0 = auto
     int hub_blocks;          // workgroups of the table-path evaluation kernels
     int refresh_blocks;      // workgroups of the in-count and re-sum kernels

@@ -317,14 +317,15 @@ def test_triangle_group_paths(lf, orc):
 
 @pytest.mark.parametrize("name,q", [("sbm2000", 64), ("copurchase_1pct", 16), ("social_0.2pct", 512)])
 def test_small_tables_and_single_workgroups(lf, orc, name, q):
-    """A tiny wave table pushes nearly every node onto the global-table path; single
-    workgroups make every grid-stride loop run long."""
+    """Tiny wave tables push nearly every node onto the medium wave path or the
+    global-table path; single workgroups make every grid-stride loop run long."""
     import torch
     say("forced hub path", name, q)
     g = SMALL[name]()
     o = oracle_graph(orc, g).init_communities()
     oinfo = o.run_iterations(q, 0.01, 50)
-    for opts in ({"wave_table": 16}, {"hub_blocks": 1, "refresh_blocks": 1}, {"wave_table": 16, "hub_blocks": 3}):
+    for opts in ({"wave_table": 16}, {"wave_table": 16, "med_table": 16}, {"med_table": 32, "hub_blocks": 3},
+                 {"hub_blocks": 1, "refresh_blocks": 1}):
         h = lf.Handle(0)
         for k, v in opts.items():
             h.lf_set_option(k, v)
@@ -340,6 +341,45 @@ def test_small_tables_and_single_workgroups(lf, orc, name, q):
 
 def test_option_validation(lf):
     h = lf.Handle(0)
-    for name, bad in (("wave_table", 100), ("wave_table", 256), ("hub_blocks", 0)):
+    for name, bad in (("wave_table", 100), ("wave_table", 256), ("med_table", 1024), ("hub_blocks", 0)):
         with pytest.raises(lf.LazyFoxError):
             h.lf_set_option(name, bad)
+
+
+def _sha(*arrays):
+    import hashlib
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.parametrize("golden", ["social_q4096_seed0.json"])
+def test_full_size_against_stored_oracle(lf, golden):
+    """The full-size workload (4,000,000 nodes, ~34.9M edges, queue 4096) in the same
+    launch configuration the benchmark times, against the oracle's stored results
+    (tests/golden/make_golden.py, CPU oracle only): node statistics, every cc-free score
+    of the history bit for bit, join/leave/community counts per iteration, and the final
+    memberships (hash of the offset and id arrays)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", golden)) as f:
+        gd = json.load(f)
+    say("full size", gd["workload"], "q", gd["queue"])
+    g = G.named_config(gd["workload"], seed=gd["seed"])
+    h = gpu_graph(lf, g).init_communities()
+    assert h.n == gd["nodes"] and h.nedges == gd["edges"]
+    sc = h.scores()
+    assert sc["triangles"] == gd["triangles"] and sc["cc"].hex() == gd["cc"]
+    tri, ccl, order = h.node_stats()
+    assert _sha(tri) == gd["tri_sha256"]
+    assert _sha(ccl) == gd["ccl_sha256"]
+    assert _sha(order) == gd["order_sha256"]
+    info = h.run_iterations(gd["queue"], gd["threshold"], gd["max_iters"])
+    assert info["iterations"] == gd["iterations"] and info["converged"] == gd["converged"]
+    assert [float(w).hex() for w in info["wtilde_hist"]] == gd["wtilde_hist"]
+    assert info["joins"].tolist() == gd["joins"] and info["leaves"].tolist() == gd["leaves"]
+    assert info["communities"].tolist() == gd["communities"]
+    off, ids = h.memberships()
+    assert ids.size == gd["memberships"]
+    assert _sha(off.astype("<i8"), ids.astype("<i4")) == gd["memberships_sha256"]
