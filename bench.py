@@ -43,19 +43,67 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-scale", type=float, default=0.05)
+    ap.add_argument("--cpu-sample-scale", type=float, default=0.2)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run a device copy of this many MiB (for HBM counter scaling)")
     ap.add_argument("--sweep", default="", help="comma-separated queue sizes: extra untimed-line runs")
     return ap.parse_args()
 
 
-def eval_bytes(prof, nedges_directed_per_iter, iterations):
-    """Algorithmic bytes of the evaluation kernels (both paths), per the layout:
-    per queued node 60 B (order 4, node header 16, row offsets 16, decision 24);
-    per neighbour 20 B (column index 4, node header 16); per neighbour membership
-    12 B (slot 8, community size 4); per candidate 44 B (size 4, internal edges 8,
-    score 8, exact sum 24)."""
-    return (60.0 * prof["node_evals"] + 20.0 * nedges_directed_per_iter * iterations
-            + 12.0 * prof["visits"] + 44.0 * prof["candidates"])
+# Algorithmic bytes per unit of evaluation work, from the data layout: per decided node
+# 60 B (order 4, node header 16, row offsets 16, decision 24); per neighbour 20 B (column
+# index 4, node header 16); per neighbour membership visited 12 B (slot 8, community size
+# 4); per candidate scored 44 B (size 4, internal edges 8, score 8, one exact sum 24).
+B_NODE, B_NEIGHBOUR, B_VISIT, B_CAND = 60.0, 20.0, 12.0, 44.0
+
+
+def kernel_bytes(kernel, paths):
+    """Algorithmic bytes one pass moves through `kernel` (None if no model for it)."""
+    def full(p):
+        w = paths[p]
+        return (B_NODE * w["nodes"] + B_NEIGHBOUR * w["neighbours"] + B_VISIT * w["visits"]
+                + B_CAND * w["candidates"])
+    t = paths["table"]
+    return {
+        "k_eval": lambda: full("small"),
+        "k_eval_med": lambda: full("medium"),
+        "k_big_visits": lambda: B_NODE * t["nodes"] + B_NEIGHBOUR * t["neighbours"] + B_VISIT * t["visits"],
+        "k_big_final": lambda: B_CAND * t["candidates"],
+    }.get(kernel, lambda: None)()
+
+
+def kernel_sources_sha():
+    """Hash of the HIP sources and headers the kernels are built from."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2210_03211_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(ROOT, "include", "lazyfox.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by the same counters on a copy of known
+    size), or None if there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(args, wl):
@@ -111,13 +159,29 @@ def main():
     for w in range(args.warmup):
         info, off, ids = step()
         print("[bench] warmup %d: %d iterations" % (w, info["iterations"]), file=sys.stderr, flush=True)
-    # untimed profiled pass: which kernel class dominates
+    # untimed pass with every kernel timed on its own: which kernel dominates
     h.lf_reset_profile()
-    step(0x1FF)
-    cls_prof = h.lf_get_profile()
-    dom = max(("eval", "eval_hub", "apply", "triangles"), key=lambda k: cls_prof["ms"][k])
+    step(True)
+    timing = h.lf_get_profile()
+    dom = max(timing["ms"], key=lambda k: timing["ms"][k] if k.startswith("k_") else -1.0)
     dom_bit = 1 << lf.KERNEL_CLASSES.index(dom)
-    print("[bench] per-class ms (profiled pass): %s" % json.dumps(cls_prof["ms"]), file=sys.stderr, flush=True)
+    print("[bench] per-kernel ms (timing pass): %s" % json.dumps(timing["ms"]), file=sys.stderr, flush=True)
+    # untimed pass with the per-path work counters (their atomics would disturb timing)
+    h.lf_reset_profile()
+    step(1 << lf.PROF_COUNTERS_BIT)
+    work = h.lf_get_profile()
+    print("[bench] work per step: %s" % json.dumps(work["paths"]), file=sys.stderr, flush=True)
+    if args.calibrate_copy_mib:
+        # a plain device copy of known size, for scaling the HBM byte counters
+        nb = args.calibrate_copy_mib << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        b = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print("[bench] copy calibration: %d bytes read, %d written" % (nb, nb), file=sys.stderr, flush=True)
+        del a, b
 
     h.lf_reset_profile()
     hashes = set()
@@ -139,25 +203,18 @@ def main():
     evals_per_step = n * iters[0]
     value = evals_per_step / (ms_per_step / 1000.0)
 
-    # roofline of the dominant kernel class over the timed region
+    # roofline of the dominant kernel: algorithmic bytes per launch (work counters of one
+    # pass / launches per pass) over its average launch time in the timed steps
     launches = prof["launches"][dom]
-    kms = prof["ms"][dom]
-    if dom in ("eval", "eval_hub"):
-        # bytes of both evaluation paths, attributed by launch to the dominant one
-        # work counters come from the profiled pass (same deterministic run), per step
-        per_step = dict(node_evals=cls_prof["node_evals"], visits=cls_prof["visits"],
-                        candidates=cls_prof["candidates"])
-        total_b = eval_bytes(per_step, 2 * ne, iters[0])
-        per_launch = total_b / max(1, cls_prof["chunks"])
-        avg_ms = kms / max(1, launches)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    else:
-        per_launch = None
-        avg_ms = kms / max(1, launches)
-        achieved = None
-    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-            "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches": launches}
+    avg_ms = prof["ms"][dom] / max(1, launches)
+    pass_bytes = kernel_bytes(dom, work["paths"])
+    per_launch = pass_bytes / max(1, timing["launches"][dom]) if pass_bytes is not None else None
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if per_launch is not None else None
+    traffic = stored_traffic(dom, args.workload)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+            "kernel": dom, "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches": launches}
+    eval_kernels = ("k_eval", "k_eval_med", "k_big_visits", "k_big_final", "k_big_tie")
     out = {
         "metric": "dWCC-hat node-evals/s (whole hot path, end-to-end)",
         "value": value, "unit": "node-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -167,10 +224,9 @@ def main():
                    "threshold": args.threshold, "iterations": iters[0], "seed": args.seed,
                    "communities_created": K, "memberships_sha256": next(iter(hashes))[:16]},
         "end_to_end_s": ms_per_step / 1000.0,
-        "kernel_node_evals_per_s": cls_prof["node_evals"] / max(1e-9, (cls_prof["ms"]["eval"] + cls_prof["ms"]["eval_hub"]) * 1e-3),
-        "work_per_step": {"node_evals": cls_prof["node_evals"], "visits": cls_prof["visits"],
-                          "candidates": cls_prof["candidates"], "chunks": cls_prof["chunks"]},
-        "class_ms_profiled_pass": cls_prof["ms"],
+        "kernel_node_evals_per_s": timing["node_evals"] / max(1e-9, sum(timing["ms"][k] for k in eval_kernels) * 1e-3),
+        "work_per_step": {"node_evals": work["node_evals"], "chunks": work["chunks"], "paths": work["paths"]},
+        "kernel_ms_timing_pass": {k: round(v, 3) for k, v in timing["ms"].items()},
         "roofline": roof,
     }
     if args.sweep:

@@ -60,19 +60,28 @@ typedef struct {
     int64_t *communities;   /* communities with >= 2 members after each iteration */
 } lf_run_info;
 
-/* Per-kernel-class timing, collected with HIP events on the handle's stream when
-   profiling is enabled (lf_set_profiling). */
+/* Per-kernel timing, collected with HIP events on the handle's stream when profiling is
+   enabled (lf_set_profiling).  The set-up phases are timed as a whole; every kernel of a
+   queue (chunk) is timed on its own, so one event pair brackets exactly one launch. */
 #define LF_K_BUILD 0        /* graph build (sorts, CSR) */
 #define LF_K_TRIANGLES 1    /* triangle counting (all launches) */
 #define LF_K_ORDER 2        /* CC, cc reduction, node order */
 #define LF_K_INITCLUST 3    /* initial clustering and state set-up */
-#define LF_K_EVAL 4         /* join/leave evaluation (wave path) */
-#define LF_K_EVAL_HUB 5     /* join/leave evaluation (workgroup path) */
-#define LF_K_APPLY 6        /* bulk apply: membership edits, in-counts, community re-sums */
-#define LF_K_ITEREND 7      /* iteration end: degenerate removal, compaction, score */
-#define LF_K_COUNT 8
-#define LF_PROF_COUNTERS_BIT 8  /* profiling mask bit: also count visits and candidates
-                                   (adds a few global atomics to the evaluation kernels) */
+#define LF_K_EVAL 4         /* k_eval: small wave evaluation path (<= 64 visits per node) */
+#define LF_K_EVAL_MED 5     /* k_eval_med: medium wave evaluation path (<= 256 visits) */
+#define LF_K_TAB_VISITS 6   /* k_big_visits: table path, neighbour-membership visits */
+#define LF_K_TAB_FINAL 7    /* k_big_final: table path, candidate changes and maxima */
+#define LF_K_TAB_TIE 8      /* k_big_tie: table path, lowest id among equal maxima */
+#define LF_K_APPLY_EDIT 9   /* k_apply_edit: membership edits, sizes, member lists */
+#define LF_K_APPLY_IN 10    /* k_apply_in: neighbours' in-counts and re-sum planning */
+#define LF_K_REFRESH 11     /* k_refresh: exact re-sums of the touched communities */
+#define LF_K_ITEREND 12     /* iteration end: degenerate removal, compaction, score */
+#define LF_K_COUNT 13
+#define LF_PROF_COUNTERS_BIT 16 /* profiling mask bit: also count the evaluation work per
+                                   path (adds a few global atomics to those kernels) */
+#define LF_PATH_SMALL 0     /* evaluation paths for the per-path work counters */
+#define LF_PATH_MED 1
+#define LF_PATH_TABLE 2
 typedef struct {
     int64_t launches[LF_K_COUNT];
     double ms[LF_K_COUNT];
@@ -80,6 +89,12 @@ typedef struct {
     int64_t node_evals;      /* queued-node evaluations */
     int64_t visits;          /* neighbour-membership visits in the evaluation kernels */
     int64_t candidates;      /* candidate communities evaluated */
+    /* per evaluation path (LF_PATH_*): nodes it decided, their neighbours, the
+       neighbour memberships it visited and the candidates it scored */
+    int64_t path_nodes[3];
+    int64_t path_neighbours[3];
+    int64_t path_visits[3];
+    int64_t path_candidates[3];
 } lf_profile;
 
 /* Create a handle on HIP device `device`.  `hip_stream` is a hipStream_t (for example
@@ -166,10 +181,10 @@ int lf_get_communities(lf_handle *h, int32_t *size, int64_t *internal_edges, dou
 /* in[j] = |N(x) ∩ C| for the j-th membership in the lf_get_memberships listing. */
 int lf_get_in_counts(lf_handle *h, int32_t *in, int64_t capacity);
 
-/* Kernel timing: `mask` selects the kernel classes to time (bit 1 << LF_K_*; 0 = off).
+/* Kernel timing: `mask` selects the kernels to time (bit 1 << LF_K_*; 0 = off).
    HIP events are recorded around each timed launch on the handle's stream and resolved at
    the end of the API call, so timing does not stall the host.  chunks and node_evals are
-   always counted; visits and candidates only with bit 1 << LF_PROF_COUNTERS_BIT. */
+   always counted; the work counters only with bit 1 << LF_PROF_COUNTERS_BIT. */
 int lf_set_profiling(lf_handle *h, int mask);
 int lf_get_profile(lf_handle *h, lf_profile *out);
 int lf_reset_profile(lf_handle *h);

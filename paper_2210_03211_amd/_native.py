@@ -14,8 +14,10 @@ LF_EINTERNAL = -8
 LF_RELABEL = 1
 LF_DEVICE_PTR = 2
 OPTIONS = {"tri_lds_cap": 1, "hub_blocks": 3, "refresh_blocks": 4, "wave_table": 5, "med_table": 6}
-KERNEL_CLASSES = ["build", "triangles", "order", "init_clustering", "eval", "eval_hub", "apply",
-                  "iteration_end"]
+KERNEL_CLASSES = ["build", "triangles", "order", "init_clustering", "k_eval", "k_eval_med", "k_big_visits",
+                  "k_big_final", "k_big_tie", "k_apply_edit", "k_apply_in", "k_refresh", "iteration_end"]
+PROF_COUNTERS_BIT = 16
+PATHS = ["small", "medium", "table"]
 
 
 class LazyFoxError(RuntimeError):
@@ -32,8 +34,10 @@ class RunInfo(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8), ("chunks", C.c_int64),
-                ("node_evals", C.c_int64), ("visits", C.c_int64), ("candidates", C.c_int64)]
+    _fields_ = [("launches", C.c_int64 * 13), ("ms", C.c_double * 13), ("chunks", C.c_int64),
+                ("node_evals", C.c_int64), ("visits", C.c_int64), ("candidates", C.c_int64),
+                ("path_nodes", C.c_int64 * 3), ("path_neighbours", C.c_int64 * 3),
+                ("path_visits", C.c_int64 * 3), ("path_candidates", C.c_int64 * 3)]
 
 
 _lib = None
@@ -266,10 +270,11 @@ class Handle:
 
     communities = lf_get_communities
 
-    def lf_set_profiling(self, mask=0xFF):
-        """mask: kernel classes to time (bit i = KERNEL_CLASSES[i]); True = all, 0 = off."""
+    def lf_set_profiling(self, mask=True):
+        """mask: kernels to time (bit i = KERNEL_CLASSES[i]; bit PROF_COUNTERS_BIT adds the
+        per-path work counters); True = every kernel without the counters, 0 = off."""
         if mask is True:
-            mask = 0xFF
+            mask = (1 << len(KERNEL_CLASSES)) - 1
         self._check(self.L.lf_set_profiling(self.h, int(mask)), "lf_set_profiling")
 
     def lf_reset_profile(self):
@@ -281,7 +286,10 @@ class Handle:
         return dict(launches={k: int(p.launches[i]) for i, k in enumerate(KERNEL_CLASSES)},
                     ms={k: float(p.ms[i]) for i, k in enumerate(KERNEL_CLASSES)},
                     chunks=int(p.chunks), node_evals=int(p.node_evals), visits=int(p.visits),
-                    candidates=int(p.candidates))
+                    candidates=int(p.candidates),
+                    paths={name: dict(nodes=int(p.path_nodes[i]), neighbours=int(p.path_neighbours[i]),
+                                      visits=int(p.path_visits[i]), candidates=int(p.path_candidates[i]))
+                           for i, name in enumerate(PATHS)})
 
     def lf_set_option(self, name, value):
         self._check(self.L.lf_set_option(self.h, OPTIONS[name], int(value)), "lf_set_option")

@@ -3,10 +3,12 @@
 // (Methods, "Node Changes", Algorithm 2, "Stopping Criteria").
 //
 // Per queue (all launches on the handle's stream, no host synchronisation):
-//   k_chunk_begin    reset the queue's counters
 //   k_eval           one wave per queued node: nodes whose neighbour memberships fit one
-//                    wave (<= 64 visits) are evaluated completely in LDS; the others are
-//                    registered as work items of the table path
+//                    wave (<= 64 visits) are evaluated completely in LDS, the others are
+//                    passed on; block 0 also resets the queue's counters and the previous
+//                    queue's join marks
+//   k_eval_med       the same with tables for <= 256 visits; nodes that still do not fit
+//                    are registered for the table path
 //   k_big_visits     table path, visit-parallel over all registered nodes: every
 //                    neighbour membership (y in C) adds its exact correction to the entry
 //                    (node, C) of a global open-addressing table; own memberships add the
@@ -15,10 +17,11 @@
 //                    positive change (atomicMax on the bits of a positive double)
 //   k_big_tie        among the entries equal to that maximum the lowest community id
 //   k_apply_edit     membership edits, sizes, member-list appends, touched list
-//   k_apply_in       in-counts of the neighbours of moved nodes (neighbour blocks)
-//   k_refresh_plan   split every touched community's member list into parts
+//   k_apply_in       in-counts of the neighbours of moved nodes (neighbour blocks); its
+//                    first blocks split every touched community's member list into parts
 //   k_refresh        exact re-sum per part; multi-part communities combine their parts
 //                    through carry-save counters and the last part finalises
+// At the end of an iteration k_chunk_begin does the reset for the last queue.
 //
 // Every sum is exact (fixed point), so none of the launch shapes above can change a bit
 // of the result.
@@ -82,6 +85,8 @@ struct WaveLds {
 #define Q_DONE 0        // evaluated by a wave path
 #define Q_TABLE 1       // goes to the table path
 #define Q_MEDIUM 2      // too large for the small wave path, try the medium one
+#define VSMALL 64       // visits of the small wave path
+#define VMED 256        // visits of the medium wave path
 
 // Evaluate queued node j with one wave if its neighbours (<= VCAP), visits and own
 // memberships fit (2 * (visits + own) <= table, <= VCAP visits).  Returns false (decision
@@ -196,15 +201,22 @@ __device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int 
         cx.dld[j] = bl >= 0 ? bld : 0.0;
         cx.big_idx[j] = Q_DONE;
         if (cx.stats) {
-            atomicAdd(&cx.ctr->visits, (unsigned long long)V);
-            atomicAdd(&cx.ctr->cands, (unsigned long long)ncand);
+            unsigned long long *w = cx.ctr->work[VCAP == VSMALL ? LF_PATH_SMALL : LF_PATH_MED];
+            atomicAdd(&w[0], 1ull);
+            atomicAdd(&w[1], (unsigned long long)d);
+            atomicAdd(&w[2], (unsigned long long)V);
+            atomicAdd(&w[3], (unsigned long long)ncand);
         }
     }
     return true;
 }
 
-__device__ __forceinline__ void mark_table(const Ctx &cx, int j)
+__device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg)
 {
+    if (cx.stats) {
+        atomicAdd(&cx.ctr->work[LF_PATH_TABLE][0], 1ull);
+        atomicAdd(&cx.ctr->work[LF_PATH_TABLE][1], (unsigned long long)deg);
+    }
     cx.big_idx[j] = Q_TABLE;
     cx.big_bj[j] = 0;
     cx.big_bl[j] = 0;
@@ -212,8 +224,6 @@ __device__ __forceinline__ void mark_table(const Ctx &cx, int j)
     cx.big_cl[j] = 0x7fffffff;
 }
 
-#define VSMALL 64       // visits of the small wave path
-#define VMED 256        // visits of the medium wave path
 #define EWM 2           // waves per block in the medium path
 
 // small wave path: every queued node; nodes that do not fit are passed on
@@ -249,7 +259,7 @@ __global__ void __launch_bounds__(EWM * WAVE) k_eval_med(Ctx cx, int cstart, int
     const int j = blockIdx.x * EWM + wv;
     if (j >= clen || cx.big_idx[j] != Q_MEDIUM) return;
     if (eval_wave<VMED>(cx, cstart, j, lane, s_l[wv], mcap)) return;
-    if (lane == 0) mark_table(cx, j);
+    if (lane == 0) mark_table(cx, j, cx.nh[cx.order[cstart + j]].deg);
 }
 
 // ------------------------------------------------------------------------------------
@@ -437,7 +447,7 @@ __global__ void __launch_bounds__(EWB * WAVE) k_big_visits(Ctx cx, int cstart, i
     }
     if (cx.stats) {
         nvis = (unsigned long long)wave_sum_i64((long long)nvis);
-        if (lane == 0 && nvis) atomicAdd(&cx.ctr->visits, nvis);
+        if (lane == 0 && nvis) atomicAdd(&cx.ctr->work[LF_PATH_TABLE][2], nvis);
     }
     if (bad) atomicOr(&cx.ctr->error, LF_DEVERR_INEXACT);
     if (capfail) atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
@@ -518,7 +528,7 @@ __global__ void __launch_bounds__(256) k_big_final(Ctx cx, int cstart, int clen)
     }
     if (cx.stats) {
         ncand = (unsigned long long)wave_sum_i64((long long)ncand);
-        if ((threadIdx.x & (WAVE - 1)) == 0 && ncand) atomicAdd(&cx.ctr->cands, ncand);
+        if ((threadIdx.x & (WAVE - 1)) == 0 && ncand) atomicAdd(&cx.ctr->work[LF_PATH_TABLE][3], ncand);
     }
     if (bad) atomicOr(&cx.ctr->error, LF_DEVERR_INEXACT);
 }
@@ -1041,20 +1051,30 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
             LF_TRY(lf_prof_begin(h, LF_K_EVAL));
             hipLaunchKernelGGL(k_eval, dim3(grid_for(clen, EW)), dim3(EW * WAVE), 0, st, cx, cstart, clen,
                                h->eval_wave_cap, prev_start, prev_len);
+            LF_TRY(lf_prof_end(h, LF_K_EVAL, 1));
+            LF_TRY(lf_prof_begin(h, LF_K_EVAL_MED));
             hipLaunchKernelGGL(k_eval_med, dim3(grid_for(clen, EWM)), dim3(EWM * WAVE), 0, st, cx, cstart, clen,
                                h->eval_med_cap);
-            LF_TRY(lf_prof_end(h, LF_K_EVAL, 1));
-            LF_TRY(lf_prof_begin(h, LF_K_EVAL_HUB));
+            LF_TRY(lf_prof_end(h, LF_K_EVAL_MED, 1));
+            LF_TRY(lf_prof_begin(h, LF_K_TAB_VISITS));
             hipLaunchKernelGGL(k_big_visits, dim3(gb), dim3(BS), 0, st, cx, cstart, clen);
+            LF_TRY(lf_prof_end(h, LF_K_TAB_VISITS, 1));
+            LF_TRY(lf_prof_begin(h, LF_K_TAB_FINAL));
             hipLaunchKernelGGL(k_big_final, dim3(gb), dim3(BS), 0, st, cx, cstart, clen);
+            LF_TRY(lf_prof_end(h, LF_K_TAB_FINAL, 1));
+            LF_TRY(lf_prof_begin(h, LF_K_TAB_TIE));
             hipLaunchKernelGGL(k_big_tie, dim3(gb), dim3(BS), 0, st, cx);
-            LF_TRY(lf_prof_end(h, LF_K_EVAL_HUB, 3));
-            LF_TRY(lf_prof_begin(h, LF_K_APPLY));
+            LF_TRY(lf_prof_end(h, LF_K_TAB_TIE, 1));
+            LF_TRY(lf_prof_begin(h, LF_K_APPLY_EDIT));
             hipLaunchKernelGGL(k_apply_edit, dim3(grid_for(clen, BS)), dim3(BS), 0, st, cx, cstart, clen);
+            LF_TRY(lf_prof_end(h, LF_K_APPLY_EDIT, 1));
             int pb = (int)grid_for(2ll * clen, BS);
+            LF_TRY(lf_prof_begin(h, LF_K_APPLY_IN));
             hipLaunchKernelGGL(k_apply_in, dim3(pb + rbk), dim3(BS), 0, st, cx, cstart, clen, pb);
+            LF_TRY(lf_prof_end(h, LF_K_APPLY_IN, 1));
+            LF_TRY(lf_prof_begin(h, LF_K_REFRESH));
             hipLaunchKernelGGL(k_refresh, dim3(rbk), dim3(BS), 0, st, cx);
-            LF_TRY(lf_prof_end(h, LF_K_APPLY, 3));
+            LF_TRY(lf_prof_end(h, LF_K_REFRESH, 1));
             h->prof.chunks++;
             h->prof.node_evals += clen;
             prev_start = cstart;
@@ -1083,10 +1103,18 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
     if (!out->converged && out->iterations == max_iters) out->hit_max = 1;
     LF_TRY(lf_prof_flush(h));
     {
-        unsigned long long vc[2];
-        LF_HIP(h, hipMemcpy(vc, &h->ctr->visits, sizeof(vc), hipMemcpyDeviceToHost));
-        h->prof.visits = (long long)vc[0];
-        h->prof.candidates = (long long)vc[1];
+        unsigned long long w[3][4];
+        LF_HIP(h, hipMemcpy(w, h->ctr->work, sizeof(w), hipMemcpyDeviceToHost));
+        h->prof.visits = 0;
+        h->prof.candidates = 0;
+        for (int p = 0; p < 3; p++) {
+            h->prof.path_nodes[p] = (long long)w[p][0];
+            h->prof.path_neighbours[p] = (long long)w[p][1];
+            h->prof.path_visits[p] = (long long)w[p][2];
+            h->prof.path_candidates[p] = (long long)w[p][3];
+            h->prof.visits += (long long)w[p][2];
+            h->prof.candidates += (long long)w[p][3];
+        }
     }
     out->wtilde = h->Wt;
     out->wcc_hat = h->Wt / h->cc;

@@ -54,8 +54,8 @@ struct __align__(64) GEntry {
 struct DevCounters {
     unsigned long long joins;      // per iteration
     unsigned long long leaves;     // per iteration
-    unsigned long long visits;     // evaluation statistics (cumulative)
-    unsigned long long cands;
+    unsigned long long work[3][4]; // evaluation work per path (cumulative): nodes,
+                                   // neighbours, visits, candidates
     int tcount;                    // touched communities (queue)
     int unused0;
     int unused1;
@@ -125,7 +125,7 @@ struct Ctx {
     int *mslot;              // [K]
     long long *macc;         // [mslot_cap * 19] carry-save accumulators
     int part_cap, mslot_cap;
-    int stats;               // collect work counters (visits, candidates)
+    int stats;               // collect the per-path work counters
 };
 
 struct lf_handle {
