@@ -64,19 +64,24 @@ __device__ __forceinline__ int lds_insert(int *key, int T, int lg, int C)
     }
 }
 
-// Per-wave LDS of the wave paths: a candidate table of 2*VCAP entries and a visit list of
-// VCAP entries.
+// Per-wave LDS of the wave paths: a candidate hash table of 2*VCAP entries, per candidate
+// (compact index, at most VCAP) its size and four correction digits, and per visit its
+// degree, table entry and in-count.  The visit-slot list is only needed before the digits
+// are cleared and shares their storage.
 template <int VCAP>
 struct WaveLds {
     int key[2 * VCAP];
     int kk[2 * VCAP];
-    int sz[2 * VCAP];
-    unsigned long long d[4][2 * VCAP];
-    long long vslot[VCAP];
+    int ci[2 * VCAP];
+    int sz[VCAP];
+    int cl[VCAP];
+    union {
+        unsigned long long d[4][VCAP];
+        long long vslot[VCAP];
+    };
     int vdeg[VCAP];
     int vhash[VCAP];
     int vin[VCAP];
-    int vcomm[VCAP];
     int mx[MXCAP];
     int mxin[MXCAP];
 };
@@ -90,109 +95,168 @@ struct WaveLds {
 
 // Evaluate queued node j with one wave if its neighbours (<= VCAP), visits and own
 // memberships fit (2 * (visits + own) <= table, <= VCAP visits).  Returns false (decision
-// not written) otherwise.
+// not written) otherwise.  Every phase issues all of a lane's global gathers (at most
+// VCAP / 64 of them) before it uses any, so a node costs a handful of memory round trips
+// whatever its size: own slots + column indices, neighbour headers, neighbour slots, and
+// one record per candidate.
 template <int VCAP>
 __device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int lane, WaveLds<VCAP> &L,
                                           int wcap)
 {
+    constexpr int NB = VCAP / WAVE;
     const int x = cx.order[cstart + j];
     const NodeHdr hx = cx.nh[x];
     const long long rb = cx.rowptr[x];
     const int d = hx.deg, mcnt = hx.cnt;
     if (d > VCAP || mcnt > MXCAP) return false;
-    // neighbour headers in batches of 64, flattened into the visit list
+    Slot own = {-1, 0};
+    if (lane < mcnt) own = cx.slot[hx.off + lane];
+    int yv[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        int e = b * WAVE + lane;
+        yv[b] = e < d ? cx.col[rb + e] : -1;
+    }
+    NodeHdr hy[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        hy[b].off = 0;
+        hy[b].cnt = 0;
+        hy[b].deg = 0;
+        if (yv[b] >= 0) hy[b] = cx.nh[yv[b]];
+    }
+    // neighbour memberships flattened into the visit list
     int V = 0;
-    for (int base = 0; base < d; base += WAVE) {
-        int e = base + lane;
-        int yc = 0, ydeg = 0;
-        long long yoff = 0;
-        if (e < d) {
-            int y = cx.col[rb + e];
-            NodeHdr hy = cx.nh[y];
-            yc = hy.cnt;
-            yoff = hy.off;
-            ydeg = hy.deg;
-        }
-        int incl = yc;
-        for (int o = 1; o < WAVE; o <<= 1) {
-            int t = __shfl_up(incl, o, WAVE);
-            if (lane >= o) incl += t;
-        }
-        int p0 = V + incl - yc;
-        V += __shfl(incl, WAVE - 1, WAVE);
-        if (V + mcnt > VCAP || 2 * (V + mcnt) > wcap) return false;   // wave-uniform
-        for (int t = 0; t < yc; t++) {
-            L.vslot[p0 + t] = yoff + t;
-            L.vdeg[p0 + t] = ydeg;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        if (b * WAVE < d) {                 // wave-uniform
+            int yc = hy[b].cnt;
+            int incl = yc;
+            for (int o = 1; o < WAVE; o <<= 1) {
+                int t = __shfl_up(incl, o, WAVE);
+                if (lane >= o) incl += t;
+            }
+            int p0 = V + incl - yc;
+            V += __shfl(incl, WAVE - 1, WAVE);
+            if (V + mcnt > VCAP || 2 * (V + mcnt) > wcap) return false;   // wave-uniform
+            for (int t = 0; t < yc; t++) {
+                L.vslot[p0 + t] = hy[b].off + t;
+                L.vdeg[p0 + t] = hy[b].deg;
+            }
         }
     }
     int T = 8;
     while (T < 2 * (V + mcnt)) T <<= 1;
     const int lg = 31 - __clz(T);
     for (int t = lane; t < T; t += WAVE) {
-        L.key[t] = -1; L.kk[t] = 0;
-        L.d[0][t] = 0; L.d[1][t] = 0; L.d[2][t] = 0; L.d[3][t] = 0;
+        L.key[t] = -1;
+        L.kk[t] = 0;
     }
     if (lane < mcnt) {
-        Slot sl = cx.slot[hx.off + lane];
-        L.mx[lane] = sl.comm;
-        L.mxin[lane] = sl.in;
+        L.mx[lane] = own.comm;
+        L.mxin[lane] = own.in;
     }
     WAVE_SYNC();
     // 1. candidates and neighbour counts: own communities are leave candidates even without
     //    a neighbour in them; every neighbour membership counts towards its community
-    if (lane < mcnt) lds_insert(L.key, T, lg, L.mx[lane]);
-    for (int v = lane; v < V; v += WAVE) {
-        Slot sl = cx.slot[L.vslot[v]];
-        int h = lds_insert(L.key, T, lg, sl.comm);
-        atomicAdd(&L.kk[h], 1);
-        L.vhash[v] = h;
-        L.vin[v] = sl.in;
-        L.vcomm[v] = sl.comm;
+    if (lane < mcnt) lds_insert(L.key, T, lg, own.comm);
+    Slot sv[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        int v = b * WAVE + lane;
+        sv[b].comm = -1;
+        sv[b].in = 0;
+        if (v < V) sv[b] = cx.slot[L.vslot[v]];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        int v = b * WAVE + lane;
+        if (v < V) {
+            int h = lds_insert(L.key, T, lg, sv[b].comm);
+            atomicAdd(&L.kk[h], 1);
+            L.vhash[v] = h;
+            L.vin[v] = sv[b].in;
+        }
     }
     WAVE_SYNC();
-    // 2. one community-record gather per candidate (its size feeds the visit terms)
-    for (int t = lane; t < T; t += WAVE) {
-        int C = L.key[t];
-        if (C >= 0) L.sz[t] = cx.cr[C].s;
+    // compact list of the occupied entries (at most V + mcnt <= VCAP); the visit slots are
+    // consumed, so their storage becomes the candidates' digits
+    int NC = 0;
+    for (int t0 = 0; t0 < T; t0 += WAVE) {
+        int t = t0 + lane;
+        bool occ = t < T && L.key[t] >= 0;
+        unsigned long long m = __ballot(occ);
+        int c = NC + __popcll(m & ((1ull << lane) - 1));
+        if (occ) {
+            L.cl[c] = t;
+            L.ci[t] = c;
+        }
+        NC += __popcll(m);
+    }
+    for (int c = lane; c < NC; c += WAVE) {
+        L.d[0][c] = 0; L.d[1][c] = 0; L.d[2][c] = 0; L.d[3][c] = 0;
+    }
+    WAVE_SYNC();
+    // 2. one community-record gather per candidate; its size feeds the visit terms
+    int ct[NB];
+    bool lv[NB];
+    CandRec rc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        int c = b * WAVE + lane;
+        ct[b] = c < NC ? L.cl[c] : -1;
+        lv[b] = false;
+        if (ct[b] >= 0) {
+            int C = L.key[ct[b]];
+            for (int q = 0; q < mcnt; q++) lv[b] |= (L.mx[q] == C);
+            load_cand(cx, C, lv[b], rc[b]);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        int c = b * WAVE + lane;
+        if (ct[b] >= 0) L.sz[c] = rc[b].s;
     }
     WAVE_SYNC();
     // 3. exact correction of every visit, summed per candidate
     int bad = 0;
     for (int v = lane; v < V; v += WAVE) {
-        int C = L.vcomm[v], h = L.vhash[v];
+        int h = L.vhash[v];
+        int C = L.key[h], c = L.ci[h];
         bool leave = false;
         for (int a = 0; a < mcnt; a++) leave |= (L.mx[a] == C);
-        X192 term = visit_term(leave, L.vin[v], L.vdeg[v], L.sz[h], bad);
+        X192 term = visit_term(leave, L.vin[v], L.vdeg[v], L.sz[c], bad);
         i64 t0, t1, t2, t3;
         x192_digits(term, t0, t1, t2, t3);
-        atomicAdd(&L.d[0][h], (unsigned long long)t0);
-        atomicAdd(&L.d[1][h], (unsigned long long)t1);
-        atomicAdd(&L.d[2][h], (unsigned long long)t2);
-        atomicAdd(&L.d[3][h], (unsigned long long)t3);
+        atomicAdd(&L.d[0][c], (unsigned long long)t0);
+        atomicAdd(&L.d[1][c], (unsigned long long)t1);
+        atomicAdd(&L.d[2][c], (unsigned long long)t2);
+        atomicAdd(&L.d[3][c], (unsigned long long)t3);
     }
     WAVE_SYNC();
     // 4. change of every candidate's score, best join and best leave
     double bjd = 0.0, bld = 0.0;
-    int bj = -1, bl = -1, ncand = 0;
-    for (int t = lane; t < T; t += WAVE) {
+    int bj = -1, bl = -1;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        int t = ct[b];
+        if (t < 0) continue;
+        int c = b * WAVE + lane;
         int C = L.key[t];
-        if (C < 0) continue;
-        ncand++;
         int k = L.kk[t];
-        int a = -1;
-        for (int q = 0; q < mcnt; q++)
-            if (L.mx[q] == C) a = q;
-        bool leave = a >= 0;
-        if (leave && L.mxin[a] != k) atomicOr(&cx.ctr->error, LF_DEVERR_INCOUNT);
-        X192 corr = x192_from_digits((i64)L.d[0][t], (i64)L.d[1][t], (i64)L.d[2][t], (i64)L.d[3][t]);
-        double dl = candidate_delta(cx, C, leave, k, d, corr, bad);
-        if (leave) better(dl, C, bld, bl);
+        if (lv[b]) {
+            int a = -1;
+            for (int q = 0; q < mcnt; q++)
+                if (L.mx[q] == C) a = q;
+            if (L.mxin[a] != k) atomicOr(&cx.ctr->error, LF_DEVERR_INCOUNT);
+        }
+        X192 corr = x192_from_digits((i64)L.d[0][c], (i64)L.d[1][c], (i64)L.d[2][c], (i64)L.d[3][c]);
+        double dl = cand_delta(rc[b], lv[b], k, d, corr, bad);
+        if (lv[b]) better(dl, C, bld, bl);
         else better(dl, C, bjd, bj);
     }
     wave_best(bjd, bj);
     wave_best(bld, bl);
-    ncand = wave_sum_int(ncand);
     if (bad) atomicOr(&cx.ctr->error, LF_DEVERR_INEXACT);
     if (lane == 0) {
         cx.dj[j] = bj;
@@ -205,7 +269,7 @@ __device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int 
             atomicAdd(&w[0], 1ull);
             atomicAdd(&w[1], (unsigned long long)d);
             atomicAdd(&w[2], (unsigned long long)V);
-            atomicAdd(&w[3], (unsigned long long)ncand);
+            atomicAdd(&w[3], (unsigned long long)NC);
         }
     }
     return true;

@@ -88,31 +88,54 @@ __device__ __forceinline__ X192 visit_term(bool leave, long long i, long long dy
     return t;
 }
 
+// the fields of C's record a candidate evaluation needs (S = S- for a leave, S+ for a join)
+struct CandRec {
+    long long m;
+    double W;
+    unsigned S[5];
+    int s;
+};
+
+__device__ __forceinline__ void load_cand(const Ctx &cx, int C, bool leave, CandRec &r)
+{
+    const CommRec *p = &cx.cr[C];
+    r.s = p->s;
+    r.m = p->m;
+    r.W = p->W;
+    const unsigned *S = leave ? p->Sm : p->Sp;
+#pragma unroll
+    for (int k = 0; k < 5; k++) r.S[k] = S[k];
+}
+
 // change of C's cc-free score when x (degree dx, k neighbours in C) joins / leaves C;
 // corr = exact sum of the neighbours' corrections
-__device__ __forceinline__ double candidate_delta(const Ctx &cx, int C, bool leave, long long k, long long dx,
-                                                  X192 corr, int &bad)
+__device__ __forceinline__ double cand_delta(const CandRec &r, bool leave, long long k, long long dx, X192 corr,
+                                             int &bad)
 {
-    const CommRec *r = &cx.cr[C];
-    long long s = r->s;
-    long long m = r->m;
-    X192 S;
+    long long s = r.s;
+    long long m = r.m;
+    X192 S = rec_load(r.S);
+    x192_add(S, corr);
     double p;
     if (leave) {
-        S = rec_load(r->Sm);
-        x192_add(S, corr);
         X192 own = x192_from_double(g_term(k, dx, s - 1), bad);
         x192_sub(S, own);
         p = density(s - 1, m - k);
     } else {
-        S = rec_load(r->Sp);
-        x192_add(S, corr);
         X192 own = x192_from_double(g_term(k, dx, s + 1), bad);
         x192_add(S, own);
         p = density(s + 1, m + k);
     }
     double pS = p * x192_round(S);
-    return pS - r->W;
+    return pS - r.W;
+}
+
+__device__ __forceinline__ double candidate_delta(const Ctx &cx, int C, bool leave, long long k, long long dx,
+                                                  X192 corr, int &bad)
+{
+    CandRec r;
+    load_cand(cx, C, leave, r);
+    return cand_delta(r, leave, k, dx, corr, bad);
 }
 
 // strictly positive changes only; larger wins; equal -> lower community id
