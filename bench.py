@@ -66,8 +66,8 @@ def kernel_bytes(kernel, paths):
     t = paths["table"]
     return {
         "k_eval": lambda: full("small"),
-        "k_eval_med": lambda: full("medium"),
-        "k_big_visits": lambda: B_NODE * t["nodes"] + B_NEIGHBOUR * t["neighbours"] + B_VISIT * t["visits"],
+        "k_eval_big": lambda: (full("medium") + full("group") + B_NODE * t["nodes"]
+                               + B_NEIGHBOUR * t["neighbours"] + B_VISIT * t["visits"]),
         "k_big_final": lambda: B_CAND * t["candidates"],
     }.get(kernel, lambda: None)()
 
@@ -214,7 +214,7 @@ def main():
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
             "kernel": dom, "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches": launches}
-    eval_kernels = ("k_eval", "k_eval_med", "k_big_visits", "k_big_final", "k_big_tie")
+    eval_kernels = ("k_eval", "k_eval_big", "k_big_final", "k_big_tie")
     out = {
         "metric": "dWCC-hat node-evals/s (whole hot path, end-to-end)",
         "value": value, "unit": "node-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

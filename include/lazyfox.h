@@ -68,20 +68,22 @@ typedef struct {
 #define LF_K_ORDER 2        /* CC, cc reduction, node order */
 #define LF_K_INITCLUST 3    /* initial clustering and state set-up */
 #define LF_K_EVAL 4         /* k_eval: small wave evaluation path (<= 64 visits per node) */
-#define LF_K_EVAL_MED 5     /* k_eval_med: medium wave evaluation path (<= 256 visits) */
-#define LF_K_TAB_VISITS 6   /* k_big_visits: table path, neighbour-membership visits */
-#define LF_K_TAB_FINAL 7    /* k_big_final: table path, candidate changes and maxima */
-#define LF_K_TAB_TIE 8      /* k_big_tie: table path, lowest id among equal maxima */
-#define LF_K_APPLY_EDIT 9   /* k_apply_edit: membership edits, sizes, member lists */
-#define LF_K_APPLY_IN 10    /* k_apply_in: neighbours' in-counts and re-sum planning */
-#define LF_K_REFRESH 11     /* k_refresh: exact re-sums of the touched communities */
-#define LF_K_ITEREND 12     /* iteration end: degenerate removal, compaction, score */
-#define LF_K_COUNT 13
+#define LF_K_EVAL_BIG 5     /* k_eval_big: medium wave path (<= 256 visits), workgroup path
+                               (<= 1024 visits) and the table path's neighbour visits */
+#define LF_K_TAB_FINAL 6    /* k_big_final: table path, candidate changes and maxima */
+#define LF_K_TAB_TIE 7      /* k_big_tie: table path, lowest id among equal maxima */
+#define LF_K_APPLY_EDIT 8   /* k_apply_edit: membership edits, sizes, member lists */
+#define LF_K_APPLY_IN 9     /* k_apply_in: neighbours' in-counts and re-sum planning */
+#define LF_K_REFRESH 10     /* k_refresh: exact re-sums of the touched communities */
+#define LF_K_ITEREND 11     /* iteration end: degenerate removal, compaction, score */
+#define LF_K_COUNT 12
 #define LF_PROF_COUNTERS_BIT 16 /* profiling mask bit: also count the evaluation work per
                                    path (adds a few global atomics to those kernels) */
 #define LF_PATH_SMALL 0     /* evaluation paths for the per-path work counters */
 #define LF_PATH_MED 1
-#define LF_PATH_TABLE 2
+#define LF_PATH_GROUP 2
+#define LF_PATH_TABLE 3
+#define LF_PATH_COUNT 4
 typedef struct {
     int64_t launches[LF_K_COUNT];
     double ms[LF_K_COUNT];
@@ -91,10 +93,10 @@ typedef struct {
     int64_t candidates;      /* candidate communities evaluated */
     /* per evaluation path (LF_PATH_*): nodes it decided, their neighbours, the
        neighbour memberships it visited and the candidates it scored */
-    int64_t path_nodes[3];
-    int64_t path_neighbours[3];
-    int64_t path_visits[3];
-    int64_t path_candidates[3];
+    int64_t path_nodes[LF_PATH_COUNT];
+    int64_t path_neighbours[LF_PATH_COUNT];
+    int64_t path_visits[LF_PATH_COUNT];
+    int64_t path_candidates[LF_PATH_COUNT];
 } lf_profile;
 
 /* Create a handle on HIP device `device`.  `hip_stream` is a hipStream_t (for example
@@ -200,7 +202,10 @@ int lf_reset_profile(lf_handle *h);
                                       the medium wave path */
 #define LF_OPT_MED_TABLE 6         /* candidate-table entries per wave in the medium wave
                                       path (power of two, 16 .. 512); nodes needing more
-                                      go to the global-table path */
+                                      go to the workgroup path */
+#define LF_OPT_GRP_TABLE 7         /* candidate-table entries per workgroup in the
+                                      workgroup path (power of two, 16 .. 2048); nodes
+                                      needing more go to the global-table path */
 int lf_set_option(lf_handle *h, int option, int64_t value);
 int lf_get_option(lf_handle *h, int option, int64_t *value);
 

@@ -13,11 +13,12 @@ LF_OK, LF_EINVAL, LF_ESTATE, LF_ENOMEM, LF_EDEVICE, LF_ERANGE, LF_EOVERFLOW = 0,
 LF_EINTERNAL = -8
 LF_RELABEL = 1
 LF_DEVICE_PTR = 2
-OPTIONS = {"tri_lds_cap": 1, "hub_blocks": 3, "refresh_blocks": 4, "wave_table": 5, "med_table": 6}
-KERNEL_CLASSES = ["build", "triangles", "order", "init_clustering", "k_eval", "k_eval_med", "k_big_visits",
-                  "k_big_final", "k_big_tie", "k_apply_edit", "k_apply_in", "k_refresh", "iteration_end"]
+OPTIONS = {"tri_lds_cap": 1, "hub_blocks": 3, "refresh_blocks": 4, "wave_table": 5, "med_table": 6,
+           "grp_table": 7}
+KERNEL_CLASSES = ["build", "triangles", "order", "init_clustering", "k_eval", "k_eval_big", "k_big_final",
+                  "k_big_tie", "k_apply_edit", "k_apply_in", "k_refresh", "iteration_end"]
 PROF_COUNTERS_BIT = 16
-PATHS = ["small", "medium", "table"]
+PATHS = ["small", "medium", "group", "table"]
 
 
 class LazyFoxError(RuntimeError):
@@ -34,10 +35,10 @@ class RunInfo(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 13), ("ms", C.c_double * 13), ("chunks", C.c_int64),
+    _fields_ = [("launches", C.c_int64 * 12), ("ms", C.c_double * 12), ("chunks", C.c_int64),
                 ("node_evals", C.c_int64), ("visits", C.c_int64), ("candidates", C.c_int64),
-                ("path_nodes", C.c_int64 * 3), ("path_neighbours", C.c_int64 * 3),
-                ("path_visits", C.c_int64 * 3), ("path_candidates", C.c_int64 * 3)]
+                ("path_nodes", C.c_int64 * 4), ("path_neighbours", C.c_int64 * 4),
+                ("path_visits", C.c_int64 * 4), ("path_candidates", C.c_int64 * 4)]
 
 
 _lib = None

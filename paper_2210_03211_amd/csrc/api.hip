@@ -50,6 +50,7 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     h->eval_wave_cap = 128;
     h->eval_med_cap = 512;
+    h->eval_grp_cap = 2048;
     h->hub_blocks = 2 * cus;
     h->refresh_blocks = 2 * cus;
     h->K = -1;
@@ -71,6 +72,7 @@ int lf_destroy(lf_handle *h)
     (void)hipEventDestroy(h->ev0);
     (void)hipEventDestroy(h->ev1);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    free(h->hqoff);
     free(h);
     return LF_OK;
 }
@@ -280,6 +282,10 @@ int lf_set_option(lf_handle *h, int option, int64_t value)
         if (value < 16 || value > 512 || (value & (value - 1))) break;
         h->eval_med_cap = (int)value;
         return LF_OK;
+    case LF_OPT_GRP_TABLE:
+        if (value < 16 || value > 2048 || (value & (value - 1))) break;
+        h->eval_grp_cap = (int)value;
+        return LF_OK;
     default:
         return lf_set_error(h, LF_EINVAL, "unknown option %d", option);
     }
@@ -295,6 +301,7 @@ int lf_get_option(lf_handle *h, int option, int64_t *value)
     case LF_OPT_REFRESH_BLOCKS: *value = h->refresh_blocks; return LF_OK;
     case LF_OPT_WAVE_TABLE: *value = h->eval_wave_cap; return LF_OK;
     case LF_OPT_MED_TABLE: *value = h->eval_med_cap; return LF_OK;
+    case LF_OPT_GRP_TABLE: *value = h->eval_grp_cap; return LF_OK;
     default: return lf_set_error(h, LF_EINVAL, "unknown option %d", option);
     }
 }

@@ -331,9 +331,11 @@ Ctx lf_ctx(lf_handle *h)
     c.djd = h->djd;
     c.dld = h->dld;
     c.ctr = h->ctr;
-    c.item_base = h->item_base;
-    c.item_node = h->item_node;
     c.big_idx = h->big_idx;
+    for (int k = 0; k < LF_PATH_COUNT; k++) c.plist[k] = h->plist[k];
+    c.rank = h->rank;
+    c.titem_base = h->titem_base;
+    c.titem_node = h->titem_node;
     c.big_bj = h->big_bj;
     c.big_bl = h->big_bl;
     c.big_cj = h->big_cj;
@@ -364,7 +366,9 @@ void lf_free_partition(lf_handle *h)
                      (void **)&h->cm_off, (void **)&h->cm_len, (void **)&h->cm_node, (void **)&h->tflag,
                      (void **)&h->tlist, (void **)&h->joined_to, (void **)&h->ovf_node,
                      (void **)&h->ovf_comm, (void **)&h->ovf_flag, (void **)&h->ctr, (void **)&h->part_base,
-                     (void **)&h->part_cnt, (void **)&h->part_done, (void **)&h->mslot, (void **)&h->vbound};
+                     (void **)&h->part_cnt, (void **)&h->part_done, (void **)&h->mslot, (void **)&h->vbound,
+                     (void **)&h->cls, (void **)&h->cscan, (void **)&h->plist[0], (void **)&h->plist[1],
+                     (void **)&h->plist[2], (void **)&h->plist[3]};
     for (void **p : ptrs) {
         lf_dev_free(h, *p);
         *p = nullptr;
@@ -515,6 +519,9 @@ int lf_initial_clustering(lf_handle *h)
     LF_TRY(lf_dev_alloc(h, (void **)&h->part_done, sizeof(int) * KK));
     LF_TRY(lf_dev_alloc(h, (void **)&h->mslot, sizeof(int) * KK));
     LF_TRY(lf_dev_alloc(h, (void **)&h->vbound, sizeof(long long) * (nn + 1)));
+    LF_TRY(lf_dev_alloc(h, (void **)&h->cls, sizeof(int) * nn));
+    LF_TRY(lf_dev_alloc(h, (void **)&h->cscan, sizeof(long long) * (nn + 1)));
+    for (int k = 0; k < LF_PATH_COUNT; k++) LF_TRY(lf_dev_alloc(h, (void **)&h->plist[k], sizeof(int) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->joined_to, sizeof(int) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->ovf_node, sizeof(int) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->ovf_comm, sizeof(int) * nn));

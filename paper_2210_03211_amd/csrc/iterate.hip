@@ -2,19 +2,21 @@
 // evaluated on the state at the start of the queue and then applied together
 // (Methods, "Node Changes", Algorithm 2, "Stopping Criteria").
 //
-// Per queue (all launches on the handle's stream, no host synchronisation):
-//   k_eval           one wave per queued node: nodes whose neighbour memberships fit one
-//                    wave (<= 64 visits) are evaluated completely in LDS, the others are
-//                    passed on; block 0 also resets the queue's counters and the previous
-//                    queue's join marks
-//   k_eval_med       the same with tables for <= 256 visits; nodes that still do not fit
-//                    are registered for the table path
-//   k_big_visits     table path, visit-parallel over all registered nodes: every
+// At the start of an iteration every node is given an evaluation path from a bound on
+// its visits that holds for the whole iteration (k_node_bounds), and each path gets the
+// list of its nodes in order.  Per queue (all launches on the handle's stream, no host
+// synchronisation):
+//   k_eval           small path: one wave per node with <= 64 visits, decided entirely
+//                    in an LDS hash table; block 0 also resets the queue's counters and
+//                    the previous queue's join marks
+//   k_eval_big       by block role: the table path's visits (largest nodes): every
 //                    neighbour membership (y in C) adds its exact correction to the entry
-//                    (node, C) of a global open-addressing table; own memberships add the
-//                    leave candidates
-//   k_big_final      every occupied entry -> change of C's score; per node the largest
-//                    positive change (atomicMax on the bits of a positive double)
+//                    (node, C) of a global open-addressing table, own memberships add the
+//                    leave candidates; the workgroup path (one workgroup per node with
+//                    <= 1024 visits, LDS tables); the medium path (one wave per node with
+//                    <= 256 visits)
+//   k_big_final      every occupied table entry -> change of C's score; per node the
+//                    largest positive change (atomicMax on the bits of a positive double)
 //   k_big_tie        among the entries equal to that maximum the lowest community id
 //   k_apply_edit     membership edits, sizes, member-list appends, touched list
 //   k_apply_in       in-counts of the neighbours of moved nodes (neighbour blocks); its
@@ -64,12 +66,13 @@ __device__ __forceinline__ int lds_insert(int *key, int T, int lg, int C)
     }
 }
 
-// Per-wave LDS of the wave paths: a candidate hash table of 2*VCAP entries, per candidate
+// LDS of one node evaluation: a candidate hash table of 2*VCAP entries, per candidate
 // (compact index, at most VCAP) its size and four correction digits, and per visit its
 // degree, table entry and in-count.  The visit-slot list is only needed before the digits
-// are cleared and shares their storage.
+// are cleared and shares their storage.  The last fields exchange values between the
+// waves of a workgroup evaluation.
 template <int VCAP>
-struct WaveLds {
+struct NodeLds {
     int key[2 * VCAP];
     int kk[2 * VCAP];
     int ci[2 * VCAP];
@@ -84,37 +87,82 @@ struct WaveLds {
     int vin[VCAP];
     int mx[MXCAP];
     int mxin[MXCAP];
+    int wtot[4];
+    int nc;
+    double bjd[4], bld[4];
+    int bj[4], bl[4];
 };
 
 // big_idx states of a queue index
-#define Q_DONE 0        // evaluated by a wave path
-#define Q_TABLE 1       // goes to the table path
-#define Q_MEDIUM 2      // too large for the small wave path, try the medium one
+#define Q_DONE 0        // decided by a wave or workgroup path
+#define Q_TABLE 1       // decided by the table path
 #define VSMALL 64       // visits of the small wave path
 #define VMED 256        // visits of the medium wave path
+#define VGRP 1024       // visits of the workgroup path
+#define GT 256          // threads of the workgroup path
 
-// Evaluate queued node j with one wave if its neighbours (<= VCAP), visits and own
-// memberships fit (2 * (visits + own) <= table, <= VCAP visits).  Returns false (decision
-// not written) otherwise.  Every phase issues all of a lane's global gathers (at most
-// VCAP / 64 of them) before it uses any, so a node costs a handful of memory round trips
-// whatever its size: own slots + column indices, neighbour headers, neighbour slots, and
-// one record per candidate.
-template <int VCAP>
-__device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int lane, WaveLds<VCAP> &L,
-                                          int wcap)
+// barrier over the NT threads that evaluate one node (one wave or the whole workgroup)
+template <int NT>
+__device__ __forceinline__ void node_sync()
 {
-    constexpr int NB = VCAP / WAVE;
+    if constexpr (NT == WAVE) WAVE_SYNC();
+    else __syncthreads();
+}
+
+// inclusive prefix sum of v over the NT threads (wave shuffles, then the waves' totals
+// through LDS); *total receives the sum over all NT threads
+template <int NT, int VCAP>
+__device__ __forceinline__ int node_incl_scan(int v, int tid, NodeLds<VCAP> &L, int *total)
+{
+    const int lane = tid & (WAVE - 1);
+    int incl = v;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int t = __shfl_up(incl, o, WAVE);
+        if (lane >= o) incl += t;
+    }
+    if constexpr (NT == WAVE) {
+        *total = __shfl(incl, WAVE - 1, WAVE);
+        return incl;
+    } else {
+        const int wv = tid / WAVE;
+        if (lane == WAVE - 1) L.wtot[wv] = incl;
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < NT / WAVE; w++) {
+            int t = L.wtot[w];
+            if (w < wv) off += t;
+            tot += t;
+        }
+        __syncthreads();
+        *total = tot;
+        return incl + off;
+    }
+}
+
+// Evaluate queued node j with NT threads (one wave, or a workgroup of GT threads) if its
+// neighbours (<= VCAP), visits and own memberships fit (2 * (visits + own) <= table,
+// <= VCAP visits, <= MXCAP own).  Returns false (decision not written) otherwise; the
+// decision to return is the same for all NT threads.  Every phase issues all of a
+// thread's global gathers (at most VCAP / NT of them) before it uses any, so a node costs
+// a handful of memory round trips whatever its size: own slots + column indices,
+// neighbour headers, neighbour slots, and one record per candidate.
+template <int NT, int VCAP>
+__device__ __forceinline__ bool eval_node(const Ctx &cx, int cstart, int j, int tid, NodeLds<VCAP> &L, int wcap,
+                                          int path)
+{
+    constexpr int NB = VCAP / NT;
+    const int lane = tid & (WAVE - 1);
     const int x = cx.order[cstart + j];
     const NodeHdr hx = cx.nh[x];
     const long long rb = cx.rowptr[x];
     const int d = hx.deg, mcnt = hx.cnt;
     if (d > VCAP || mcnt > MXCAP) return false;
     Slot own = {-1, 0};
-    if (lane < mcnt) own = cx.slot[hx.off + lane];
+    if (tid < mcnt) own = cx.slot[hx.off + tid];
     int yv[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        int e = b * WAVE + lane;
+        int e = b * NT + tid;
         yv[b] = e < d ? cx.col[rb + e] : -1;
     }
     NodeHdr hy[NB];
@@ -129,16 +177,12 @@ __device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int 
     int V = 0;
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        if (b * WAVE < d) {                 // wave-uniform
-            int yc = hy[b].cnt;
-            int incl = yc;
-            for (int o = 1; o < WAVE; o <<= 1) {
-                int t = __shfl_up(incl, o, WAVE);
-                if (lane >= o) incl += t;
-            }
+        if (b * NT < d) {                   // uniform over the NT threads
+            int yc = hy[b].cnt, tot;
+            int incl = node_incl_scan<NT>(yc, tid, L, &tot);
             int p0 = V + incl - yc;
-            V += __shfl(incl, WAVE - 1, WAVE);
-            if (V + mcnt > VCAP || 2 * (V + mcnt) > wcap) return false;   // wave-uniform
+            V += tot;
+            if (V + mcnt > VCAP || 2 * (V + mcnt) > wcap) return false;   // uniform
             for (int t = 0; t < yc; t++) {
                 L.vslot[p0 + t] = hy[b].off + t;
                 L.vdeg[p0 + t] = hy[b].deg;
@@ -148,29 +192,30 @@ __device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int 
     int T = 8;
     while (T < 2 * (V + mcnt)) T <<= 1;
     const int lg = 31 - __clz(T);
-    for (int t = lane; t < T; t += WAVE) {
+    for (int t = tid; t < T; t += NT) {
         L.key[t] = -1;
         L.kk[t] = 0;
     }
-    if (lane < mcnt) {
-        L.mx[lane] = own.comm;
-        L.mxin[lane] = own.in;
+    if (tid < mcnt) {
+        L.mx[tid] = own.comm;
+        L.mxin[tid] = own.in;
     }
-    WAVE_SYNC();
+    if (tid == 0) L.nc = 0;
+    node_sync<NT>();
     // 1. candidates and neighbour counts: own communities are leave candidates even without
     //    a neighbour in them; every neighbour membership counts towards its community
-    if (lane < mcnt) lds_insert(L.key, T, lg, own.comm);
+    if (tid < mcnt) lds_insert(L.key, T, lg, own.comm);
     Slot sv[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        int v = b * WAVE + lane;
+        int v = b * NT + tid;
         sv[b].comm = -1;
         sv[b].in = 0;
         if (v < V) sv[b] = cx.slot[L.vslot[v]];
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        int v = b * WAVE + lane;
+        int v = b * NT + tid;
         if (v < V) {
             int h = lds_insert(L.key, T, lg, sv[b].comm);
             atomicAdd(&L.kk[h], 1);
@@ -178,32 +223,35 @@ __device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int 
             L.vin[v] = sv[b].in;
         }
     }
-    WAVE_SYNC();
-    // compact list of the occupied entries (at most V + mcnt <= VCAP); the visit slots are
-    // consumed, so their storage becomes the candidates' digits
-    int NC = 0;
-    for (int t0 = 0; t0 < T; t0 += WAVE) {
-        int t = t0 + lane;
+    node_sync<NT>();
+    // compact list of the occupied entries (at most V + mcnt <= VCAP; the order within the
+    // list does not matter); the visit slots are consumed, so their storage becomes the
+    // candidates' digits
+    for (int t0 = 0; t0 < T; t0 += NT) {
+        int t = t0 + tid;
         bool occ = t < T && L.key[t] >= 0;
         unsigned long long m = __ballot(occ);
-        int c = NC + __popcll(m & ((1ull << lane) - 1));
+        int base = 0;
+        if (lane == 0 && m) base = atomicAdd(&L.nc, __popcll(m));
+        base = __shfl(base, 0, WAVE);
+        int c = base + __popcll(m & ((1ull << lane) - 1));
         if (occ) {
             L.cl[c] = t;
             L.ci[t] = c;
         }
-        NC += __popcll(m);
     }
-    for (int c = lane; c < NC; c += WAVE) {
+    node_sync<NT>();
+    const int NC = L.nc;
+    for (int c = tid; c < NC; c += NT) {
         L.d[0][c] = 0; L.d[1][c] = 0; L.d[2][c] = 0; L.d[3][c] = 0;
     }
-    WAVE_SYNC();
     // 2. one community-record gather per candidate; its size feeds the visit terms
     int ct[NB];
     bool lv[NB];
     CandRec rc[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        int c = b * WAVE + lane;
+        int c = b * NT + tid;
         ct[b] = c < NC ? L.cl[c] : -1;
         lv[b] = false;
         if (ct[b] >= 0) {
@@ -214,13 +262,13 @@ __device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int 
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        int c = b * WAVE + lane;
+        int c = b * NT + tid;
         if (ct[b] >= 0) L.sz[c] = rc[b].s;
     }
-    WAVE_SYNC();
+    node_sync<NT>();
     // 3. exact correction of every visit, summed per candidate
     int bad = 0;
-    for (int v = lane; v < V; v += WAVE) {
+    for (int v = tid; v < V; v += NT) {
         int h = L.vhash[v];
         int C = L.key[h], c = L.ci[h];
         bool leave = false;
@@ -233,7 +281,7 @@ __device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int 
         atomicAdd(&L.d[2][c], (unsigned long long)t2);
         atomicAdd(&L.d[3][c], (unsigned long long)t3);
     }
-    WAVE_SYNC();
+    node_sync<NT>();
     // 4. change of every candidate's score, best join and best leave
     double bjd = 0.0, bld = 0.0;
     int bj = -1, bl = -1;
@@ -241,7 +289,7 @@ __device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int 
     for (int b = 0; b < NB; b++) {
         int t = ct[b];
         if (t < 0) continue;
-        int c = b * WAVE + lane;
+        int c = b * NT + tid;
         int C = L.key[t];
         int k = L.kk[t];
         if (lv[b]) {
@@ -257,15 +305,33 @@ __device__ __forceinline__ bool eval_wave(const Ctx &cx, int cstart, int j, int 
     }
     wave_best(bjd, bj);
     wave_best(bld, bl);
+    if constexpr (NT > WAVE) {
+        const int wv = tid / WAVE;
+        if (lane == 0) {
+            L.bjd[wv] = bjd; L.bj[wv] = bj;
+            L.bld[wv] = bld; L.bl[wv] = bl;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < NT / WAVE; w++) {
+                int oc = L.bj[w];
+                double od = L.bjd[w];
+                if (oc >= 0 && (bj < 0 || od > bjd || (od == bjd && oc < bj))) { bjd = od; bj = oc; }
+                oc = L.bl[w];
+                od = L.bld[w];
+                if (oc >= 0 && (bl < 0 || od > bld || (od == bld && oc < bl))) { bld = od; bl = oc; }
+            }
+        }
+    }
     if (bad) atomicOr(&cx.ctr->error, LF_DEVERR_INEXACT);
-    if (lane == 0) {
+    if (tid == 0) {
         cx.dj[j] = bj;
         cx.djd[j] = bj >= 0 ? bjd : 0.0;
         cx.dl[j] = bl;
         cx.dld[j] = bl >= 0 ? bld : 0.0;
         cx.big_idx[j] = Q_DONE;
         if (cx.stats) {
-            unsigned long long *w = cx.ctr->work[VCAP == VSMALL ? LF_PATH_SMALL : LF_PATH_MED];
+            unsigned long long *w = cx.ctr->work[path];
             atomicAdd(&w[0], 1ull);
             atomicAdd(&w[1], (unsigned long long)d);
             atomicAdd(&w[2], (unsigned long long)V);
@@ -288,42 +354,33 @@ __device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg)
     cx.big_cl[j] = 0x7fffffff;
 }
 
-#define EWM 2           // waves per block in the medium path
 
-// small wave path: every queued node; nodes that do not fit are passed on
-__global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, int cstart, int clen, int wcap, int prev_start,
+// The three in-LDS evaluation paths.  Each takes its queue's nodes from its path list
+// (list positions [ls, ls + ln)); the path was chosen so that the node fits, and a node
+// that does not is an internal error.
+
+// small wave path, one wave per node; block 0 also resets the queue's apply counters (no
+// kernel that runs beside this one uses them) and every wave clears join marks of the
+// previous queue
+__global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, int cstart, int wcap, int ls, int ln, int prev_start,
                                                    int prev_len)
 {
-    __shared__ WaveLds<VSMALL> s_l[EW];
+    __shared__ NodeLds<VSMALL> s_l[EW];
     const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    const int j = blockIdx.x * EW + wv;
-    // start of a queue: reset its counters (no kernel of this launch uses them) and clear
-    // the previous queue's join marks
+    const int p = blockIdx.x * EW + wv;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         DevCounters *c = cx.ctr;
         c->tcount = 0;
-        c->occ_cnt = 0;
         c->in_items = 0;
         c->parts_total = 0;
         c->mslots = 0;
     }
     if (lane == 0)
-        for (int p = j; p < prev_len; p += clen) cx.joined_to[cx.order[prev_start + p]] = -1;
-    if (j >= clen) return;                  // no block barriers in this kernel
-    if (eval_wave<VSMALL>(cx, cstart, j, lane, s_l[wv], wcap < 2 * VSMALL ? wcap : 2 * VSMALL)) return;
-    if (lane == 0) cx.big_idx[j] = Q_MEDIUM;
-}
-
-// medium wave path: nodes passed on by the small path; those still too large go to the
-// table path
-__global__ void __launch_bounds__(EWM * WAVE) k_eval_med(Ctx cx, int cstart, int clen, int mcap)
-{
-    __shared__ WaveLds<VMED> s_l[EWM];
-    const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    const int j = blockIdx.x * EWM + wv;
-    if (j >= clen || cx.big_idx[j] != Q_MEDIUM) return;
-    if (eval_wave<VMED>(cx, cstart, j, lane, s_l[wv], mcap)) return;
-    if (lane == 0) mark_table(cx, j, cx.nh[cx.order[cstart + j]].deg);
+        for (int k = p; k < prev_len; k += gridDim.x * EW) cx.joined_to[cx.order[prev_start + k]] = -1;
+    if (p >= ln) return;                    // no block barriers in this kernel
+    const int j = cx.plist[LF_PATH_SMALL][ls + p] - cstart;
+    if (!eval_node<WAVE, VSMALL>(cx, cstart, j, lane, s_l[wv], wcap, LF_PATH_SMALL) && lane == 0)
+        atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
 }
 
 // ------------------------------------------------------------------------------------
@@ -373,20 +430,33 @@ __device__ __forceinline__ void occ_append(const Ctx &cx, bool claimed, long lon
 // claims a key records its visit inline (no community gather, one atomic in total); every
 // other visit adds its exact correction, with lanes of one wave that hit the same entry
 // summed first so that a hot entry gets one set of atomics per wave.
-__global__ void __launch_bounds__(EWB * WAVE) k_big_visits(Ctx cx, int cstart, int clen)
+struct TabLds {
+    long long sbase[EWB][WAVE];
+    long long xoff[EWB][WAVE];
+    int start[EWB][WAVE];
+    int dy[EWB][WAVE];
+    int j[EWB][WAVE];
+    int xcnt[EWB][WAVE];
+    int own[EWB][WAVE];
+};
+
+// blocks blk of nblk (EWB waves each) walk the work items of the queue's table-path
+// nodes (list positions [ls, ls + ln))
+__device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, int ln, int blk, int nblk,
+                                             TabLds &S)
 {
-    __shared__ long long s_sbase[EWB][WAVE];
-    __shared__ long long s_xoff[EWB][WAVE];
-    __shared__ int s_start[EWB][WAVE];
-    __shared__ int s_dy[EWB][WAVE];
-    __shared__ int s_j[EWB][WAVE];
-    __shared__ int s_xcnt[EWB][WAVE];
-    __shared__ int s_own[EWB][WAVE];
+    auto &s_sbase = S.sbase;
+    auto &s_xoff = S.xoff;
+    auto &s_start = S.start;
+    auto &s_dy = S.dy;
+    auto &s_j = S.j;
+    auto &s_xcnt = S.xcnt;
+    auto &s_own = S.own;
     const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    const long long ib0 = cx.item_base[cstart];
-    const long long count = cx.item_base[cstart + clen] - ib0;
-    const long long gw = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
-    const long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
+    const long long ib0 = cx.titem_base[ls];
+    const long long count = cx.titem_base[ls + ln] - ib0;
+    const long long gw = (blk * (long long)(EWB * WAVE) + threadIdx.x) / WAVE;
+    const long long nw = (long long)nblk * EWB;
     int bad = 0, capfail = 0;
     unsigned long long nvis = 0;
     for (long long base = gw * WAVE; base < count; base += nw * WAVE) {
@@ -394,12 +464,14 @@ __global__ void __launch_bounds__(EWB * WAVE) k_big_visits(Ctx cx, int cstart, i
         int vc = 0, dy = 0, jj = -1, own = 0, xcnt = 0;
         long long sb = 0, xoff = 0;
         if (f < count) {
-            int r = cx.item_node[ib0 + f];
+            int p = cx.titem_node[ib0 + f];
+            int r = cx.plist[LF_PATH_TABLE][p];
             int j = r - cstart;
-            if (j >= 0 && j < clen && cx.big_idx[j] == Q_TABLE) {
+            {
                 int x = cx.order[r];
                 NodeHdr hx = cx.nh[x];
-                long long e = ib0 + f - cx.item_base[r];
+                long long e = ib0 + f - cx.titem_base[p];
+                if (e == 0) mark_table(cx, j, hx.deg);   // k_big_final reads it after this launch
                 if (e < hx.deg) {
                     int y = cx.col[cx.rowptr[x] + e];
                     NodeHdr hy = cx.nh[y];
@@ -517,6 +589,50 @@ __global__ void __launch_bounds__(EWB * WAVE) k_big_visits(Ctx cx, int cstart, i
     if (capfail) atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
 }
 
+// The larger nodes of a queue in one launch, blocks by role: [0, bt) walk the table-path
+// work items, the next bg blocks evaluate workgroup-path nodes (one node per block at a
+// time), the last bm blocks medium-path nodes (one node per wave).  All read the state
+// at the queue's start, so the roles are independent.
+struct BigRoles {
+    int bt, bg, bm;          // blocks per role
+    int lt, nt;              // table-path list positions of the queue
+    int lg, ng;              // workgroup-path list positions
+    int lm, nm;              // medium-path list positions
+};
+
+union BigLds {
+    TabLds t;
+    NodeLds<VGRP> g;
+    NodeLds<VMED> m[GT / WAVE];
+};
+
+__global__ void __launch_bounds__(GT) k_eval_big(Ctx cx, int cstart, int mcap, int gcap, BigRoles r)
+{
+    __shared__ BigLds L;
+    int b = blockIdx.x;
+    if (b < r.bt) {
+        table_visits(cx, cstart, r.lt, r.nt, b, r.bt, L.t);
+        return;
+    }
+    b -= r.bt;
+    if (b < r.bg) {
+        for (int p = b; p < r.ng; p += r.bg) {
+            const int j = cx.plist[LF_PATH_GROUP][r.lg + p] - cstart;
+            if (!eval_node<GT, VGRP>(cx, cstart, j, threadIdx.x, L.g, gcap, LF_PATH_GROUP) && threadIdx.x == 0)
+                atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
+            __syncthreads();                // the next node reuses the LDS
+        }
+        return;
+    }
+    b -= r.bg;
+    const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    for (int p = b * (GT / WAVE) + wv; p < r.nm; p += r.bm * (GT / WAVE)) {   // no block barriers
+        const int j = cx.plist[LF_PATH_MED][r.lm + p] - cstart;
+        if (!eval_node<WAVE, VMED>(cx, cstart, j, lane, L.m[wv], mcap, LF_PATH_MED) && lane == 0)
+            atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_big_final(Ctx cx, int cstart, int clen)
 {
     int count = __atomic_load_n(&cx.ctr->occ_cnt, __ATOMIC_RELAXED);
@@ -627,6 +743,8 @@ __global__ void k_apply_edit(Ctx cx, int cstart, int clen)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     int lane = threadIdx.x & (WAVE - 1);
+    if (j == 0) cx.ctr->occ_cnt = 0;        // the table path of this queue is done
+
     bool inq = j < clen;
     int J = -1, L = -1;
     if (inq) {
@@ -878,27 +996,45 @@ __global__ void __launch_bounds__(256) k_refresh(Ctx cx)
 // ------------------------------------------------------------------------------------
 // per-iteration sizing of the queue buffers
 // ------------------------------------------------------------------------------------
-// vbound[x] = visits of x at the start of the iteration + deg + own memberships + 1:
-// an upper bound on the distinct table keys x can create in this iteration (each
-// neighbour gains at most one membership per iteration)
-__global__ void __launch_bounds__(256) k_node_bounds(Ctx cx, long long *vbound)
+// Evaluation path of every node for this iteration.  A node's own memberships do not
+// change before it is evaluated, and each neighbour gains at most one membership per
+// iteration, only if it is evaluated earlier (a smaller order position: the neighbours
+// in the same queue are read at the queue's start).  So visits at evaluation <=
+// B = visits at the iteration start + neighbours earlier in the order, and the path
+// chosen from B always fits.  vbound[x] = B + own + 1 bounds x's distinct table keys.
+__global__ void __launch_bounds__(256) k_node_bounds(Ctx cx, long long *vbound, int *cls, int wcap, int mcap,
+                                                     int gcap)
 {
     long long x = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
     int lane = threadIdx.x & (WAVE - 1);
     if (x >= cx.n) return;
-    long long rb = cx.rowptr[x], re = cx.rowptr[x + 1];
-    long long v = 0;
-    for (long long e = rb + lane; e < re; e += WAVE) v += cx.nh[cx.col[e]].cnt;
+    const long long rb = cx.rowptr[x], re = cx.rowptr[x + 1];
+    const int rx = cx.rank[x];
+    long long v = 0, pre = 0;
+    for (long long e = rb + lane; e < re; e += WAVE) {
+        int y = cx.col[e];
+        v += cx.nh[y].cnt;
+        pre += cx.rank[y] < rx ? 1 : 0;
+    }
     v = wave_sum_i64(v);
+    pre = wave_sum_i64(pre);
     if (lane == 0) {
         NodeHdr hx = cx.nh[x];
-        vbound[x] = v + hx.deg + hx.cnt + 1;
+        const long long B = v + pre, M = hx.cnt, d = hx.deg;
+        vbound[x] = B + M + 1;
+        int c = LF_PATH_TABLE;
+        if (M <= MXCAP) {
+            if (d <= VSMALL && B + M <= VSMALL && 2 * (B + M) <= wcap) c = LF_PATH_SMALL;
+            else if (d <= VMED && B + M <= VMED && 2 * (B + M) <= mcap) c = LF_PATH_MED;
+            else if (d <= VGRP && B + M <= VGRP && 2 * (B + M) <= gcap) c = LF_PATH_GROUP;
+        }
+        cls[rx] = c;
     }
 }
 
-// per queue: sum of (deg + cnt + 1) [work items], sum of vbound [table keys],
-// sum of ceil(deg / INB) [in-count items]; the maxima over queues go to out[0..2]
-__global__ void __launch_bounds__(256) k_chunk_bounds(Ctx cx, const long long *vbound, int q,
+// per queue: work items and table keys of its table-path nodes, and in-count items of
+// all its nodes; the maxima over queues go to out[0..2]
+__global__ void __launch_bounds__(256) k_chunk_bounds(Ctx cx, const long long *vbound, const int *cls, int q,
                                                       unsigned long long *out)
 {
     __shared__ long long s_a[256 / WAVE], s_b[256 / WAVE], s_c[256 / WAVE];
@@ -908,8 +1044,10 @@ __global__ void __launch_bounds__(256) k_chunk_bounds(Ctx cx, const long long *v
     for (long long r = start + threadIdx.x; r < end; r += blockDim.x) {
         int x = cx.order[r];
         NodeHdr hx = cx.nh[x];
-        a += hx.deg + hx.cnt + 1;
-        b += vbound[x];
+        if (cls[r] == LF_PATH_TABLE) {
+            a += hx.deg + hx.cnt + 1;
+            b += vbound[x];
+        }
         c += (hx.deg + INB - 1) / INB;
     }
     a = wave_sum_i64(a);
@@ -927,24 +1065,49 @@ __global__ void __launch_bounds__(256) k_chunk_bounds(Ctx cx, const long long *v
     }
 }
 
-// per order position: work items reserved for this iteration (neighbours, own memberships
-// and the one membership the node may gain); written into `cnt` for the scan
-__global__ void k_item_counts(Ctx cx, long long *cnt)
+// flags[r] = (cls[r] == c) for the scan that places path c's nodes; flags[n] = 0
+__global__ void k_class_flags(const int *cls, int c, long long *flags, long long n)
 {
     long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (r > cx.n) return;
-    if (r == cx.n) { cnt[r] = 0; return; }
-    NodeHdr hx = cx.nh[cx.order[r]];
-    cnt[r] = (long long)hx.deg + hx.cnt + 1;
+    if (r < n) flags[r] = cls[r] == c ? 1 : 0;
+    else if (r == n) flags[r] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_item_fill(Ctx cx)
+// path c's list (ascending order positions) and its first list position per queue
+__global__ void k_class_scatter(const int *cls, int c, const long long *scan, int *list, long long n, int q,
+                                long long nq, long long *qoff)
 {
-    long long r = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
+    long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (r < n && cls[r] == c) list[scan[r]] = (int)r;
+    if (r <= nq) {
+        long long p = r * q < n ? r * q : n;
+        qoff[r] = scan[p];
+    }
+}
+
+// work items of every table-path node: its neighbours, its own memberships and one spare
+__global__ void k_titem_counts(Ctx cx, long long nt, long long *cnt)
+{
+    long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (p > nt) return;
+    if (p == nt) { cnt[p] = 0; return; }
+    NodeHdr hx = cx.nh[cx.order[cx.plist[LF_PATH_TABLE][p]]];
+    cnt[p] = (long long)hx.deg + hx.cnt + 1;
+}
+
+__global__ void k_queue_items(const long long *titem_base, const long long *qoff_t, long long nq, long long *out)
+{
+    long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (k <= nq) out[k] = titem_base[qoff_t[k]];
+}
+
+__global__ void __launch_bounds__(256) k_titem_fill(Ctx cx, long long nt)
+{
+    long long p = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
     int lane = threadIdx.x & (WAVE - 1);
-    if (r >= cx.n) return;
-    long long a = cx.item_base[r], b = cx.item_base[r + 1];
-    for (long long f = a + lane; f < b; f += WAVE) cx.item_node[f] = (int)r;
+    if (p >= nt) return;
+    long long a = cx.titem_base[p], b = cx.titem_base[p + 1];
+    for (long long f = a + lane; f < b; f += WAVE) cx.titem_node[f] = (int)p;
 }
 
 __global__ void k_empty_table(GEntry *t, long long n)
@@ -961,18 +1124,19 @@ void lf_free_iteration_buffers(lf_handle *h)
     void **ptrs[] = {(void **)&h->dj, (void **)&h->dl, (void **)&h->djd, (void **)&h->dld,
                      (void **)&h->big_idx,
                      (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl,
-                     (void **)&h->in_base, (void **)&h->item_base, (void **)&h->item_node, (void **)&h->gt, (void **)&h->occ, (void **)&h->occ_key, (void **)&h->occ_d,
-                     (void **)&h->in_item, (void **)&h->part_comm, (void **)&h->macc};
+                     (void **)&h->in_base, (void **)&h->gt, (void **)&h->occ, (void **)&h->occ_key, (void **)&h->occ_d,
+                     (void **)&h->in_item, (void **)&h->part_comm, (void **)&h->macc,
+                     (void **)&h->titem_base, (void **)&h->titem_node};
     for (void **p : ptrs) {
         lf_dev_free(h, *p);
         *p = nullptr;
     }
     h->q_cap = 0;
     h->gT = 0;
-    h->item_cap = 0;
     h->in_cap = 0;
     h->part_cap = 0;
     h->mslot_cap = 0;
+    h->titem_cap = 0;
 }
 
 static int size_queue_buffers(lf_handle *h, long long q)
@@ -1003,15 +1167,40 @@ static int size_queue_buffers(lf_handle *h, long long q)
         h->q_cap = q;
         moved = true;
     }
-    // bounds for this iteration
+    // paths of this iteration, then bounds of the table path and in-count items
+    const long long nq = (n + q - 1) / q;
+    Ctx cx = lf_ctx(h);
+    hipLaunchKernelGGL(k_node_bounds, dim3(grid_for(n * WAVE, BS)), dim3(BS), 0, st, cx, h->vbound, h->cls,
+                       h->eval_wave_cap < 2 * VSMALL ? h->eval_wave_cap : 2 * VSMALL, h->eval_med_cap,
+                       h->eval_grp_cap);
+    if (h->hqoff_cap < nq + 1) {
+        free(h->hqoff);
+        h->hqoff = (long long *)malloc(sizeof(long long) * (LF_PATH_COUNT + 1) * (nq + 1));
+        if (!h->hqoff) return lf_set_error(h, LF_ENOMEM, "host queue offsets");
+        h->hqoff_cap = nq + 1;
+    }
+    long long *dq = nullptr;
+    LF_TRY(lf_dev_alloc(h, (void **)&dq, sizeof(long long) * (LF_PATH_COUNT + 1) * (nq + 1)));
+    if (!h->titem_base) {
+        LF_TRY(lf_dev_alloc(h, (void **)&h->titem_base, sizeof(long long) * (n + 1)));
+        moved = true;
+    }
+    for (int c = 0; c < LF_PATH_COUNT; c++) {
+        // titem_base serves as the flag array until the table-path items are laid out
+        hipLaunchKernelGGL(k_class_flags, dim3(grid_for(n + 1, BS)), dim3(BS), 0, st, (const int *)h->cls, c,
+                           h->titem_base, n);
+        LF_TRY(lf_exclusive_scan_i64(h, h->titem_base, h->cscan, n + 1));
+        long long m = (n > nq ? n : nq) + 1;
+        hipLaunchKernelGGL(k_class_scatter, dim3(grid_for(m, BS)), dim3(BS), 0, st, (const int *)h->cls, c,
+                           (const long long *)h->cscan, h->plist[c], n, (int)q, nq, dq + c * (nq + 1));
+    }
+    LF_HIP(h, hipMemcpyAsync(h->hqoff, dq, sizeof(long long) * LF_PATH_COUNT * (nq + 1), hipMemcpyDeviceToHost,
+                             st));
     unsigned long long *dout = nullptr;
     LF_TRY(lf_dev_alloc(h, (void **)&dout, sizeof(unsigned long long) * 4));
     LF_HIP(h, hipMemsetAsync(dout, 0, sizeof(unsigned long long) * 4, st));
-    Ctx cx = lf_ctx(h);
-    hipLaunchKernelGGL(k_node_bounds, dim3(grid_for(n * WAVE, BS)), dim3(BS), 0, st, cx, h->vbound);
-    long long nchunks = (n + q - 1) / q;
-    hipLaunchKernelGGL(k_chunk_bounds, dim3((unsigned)nchunks), dim3(BS), 0, st, cx, (const long long *)h->vbound,
-                       (int)q, dout);
+    hipLaunchKernelGGL(k_chunk_bounds, dim3((unsigned)nq), dim3(BS), 0, st, cx, (const long long *)h->vbound,
+                       (const int *)h->cls, (int)q, dout);
     unsigned long long hb[4];
     LF_HIP(h, hipMemcpyAsync(hb, dout, sizeof(hb), hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
@@ -1021,22 +1210,30 @@ static int size_queue_buffers(lf_handle *h, long long q)
     long long initems = (long long)hb[2] + 64;
     if (keys >= (1ll << 30) || initems >= (1ll << 31))
         return lf_set_error(h, LF_EOVERFLOW, "queue of %lld nodes too large for the table path", q);
-    // static work-item layout of this iteration: order position r owns deg + cnt + 1 items
-    if (!h->item_base) LF_TRY(lf_dev_alloc(h, (void **)&h->item_base, sizeof(long long) * (n + 1)));
-    hipLaunchKernelGGL(k_item_counts, dim3(grid_for(n + 1, BS)), dim3(BS), 0, st, lf_ctx(h), h->vbound);
-    LF_TRY(lf_exclusive_scan_i64(h, h->vbound, h->item_base, n + 1));
+    // static work-item layout of the table-path nodes: list position p owns deg + cnt + 1
+    const long long nt = h->hqoff[LF_PATH_TABLE * (nq + 1) + nq];
+    hipLaunchKernelGGL(k_titem_counts, dim3(grid_for(nt + 1, BS)), dim3(BS), 0, st, lf_ctx(h), nt, h->cscan);
+    LF_TRY(lf_exclusive_scan_i64(h, h->cscan, h->titem_base, nt + 1));
     long long items = 0;
-    LF_HIP(h, hipMemcpyAsync(&items, h->item_base + n, sizeof(long long), hipMemcpyDeviceToHost, st));
+    LF_HIP(h, hipMemcpyAsync(&items, h->titem_base + nt, sizeof(long long), hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
-    if (items > h->item_cap) {
-        lf_dev_free(h, h->item_node);
-        h->item_node = nullptr;
+    if (items > h->titem_cap || !h->titem_node) {
+        lf_dev_free(h, h->titem_node);
+        h->titem_node = nullptr;
         long long want = items + items / 8 + 1024;
-        LF_TRY(lf_dev_alloc(h, (void **)&h->item_node, sizeof(int) * want));
-        h->item_cap = want;
+        LF_TRY(lf_dev_alloc(h, (void **)&h->titem_node, sizeof(int) * want));
+        h->titem_cap = want;
         moved = true;
     }
-    hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n * WAVE, BS)), dim3(BS), 0, st, lf_ctx(h));
+    if (nt > 0)
+        hipLaunchKernelGGL(k_titem_fill, dim3(grid_for(nt * WAVE, BS)), dim3(BS), 0, st, lf_ctx(h), nt);
+    // first table-path work item of every queue (sizes the table-visit role)
+    hipLaunchKernelGGL(k_queue_items, dim3(grid_for(nq + 1, BS)), dim3(BS), 0, st, (const long long *)h->titem_base,
+                       (const long long *)(dq + LF_PATH_TABLE * (nq + 1)), nq, dq + LF_PATH_COUNT * (nq + 1));
+    LF_HIP(h, hipMemcpyAsync(h->hqoff + LF_PATH_COUNT * (nq + 1), dq + LF_PATH_COUNT * (nq + 1),
+                             sizeof(long long) * (nq + 1), hipMemcpyDeviceToHost, st));
+    LF_HIP(h, hipStreamSynchronize(st));
+    lf_dev_free(h, dq);
     long long T = 1024;
     while (T < 2 * keys) T <<= 1;
     if (T > h->gT) {
@@ -1105,30 +1302,54 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
     double prev = h->Wt;
     for (int it = 0; it < max_iters; it++) {
         LF_TRY(size_queue_buffers(h, qq));
+        const long long nq = (n + qq - 1) / qq;
+        const long long *qo = h->hqoff;     // [path][nq + 1]
+        const long long *hit = h->hqoff + LF_PATH_COUNT * (nq + 1);   // first table item per queue
         LF_HIP(h, hipMemsetAsync(&h->ctr->joins, 0, sizeof(unsigned long long) * 2, st));
         Ctx cx = lf_ctx(h);
+        hipLaunchKernelGGL(k_chunk_begin, dim3(1), dim3(BS), 0, st, cx, 0, 0);
         int gb = h->hub_blocks, rbk = h->refresh_blocks;
         int prev_start = 0, prev_len = 0;
-        for (long long start = 0; start < n; start += q) {
-            int clen = (int)((n - start) < q ? (n - start) : q);
+        for (long long k = 0; k < nq; k++) {
+            const long long start = k * qq;
+            int clen = (int)((n - start) < qq ? (n - start) : qq);
             int cstart = (int)start;
+            int ls[LF_PATH_COUNT], ln[LF_PATH_COUNT];
+            for (int c = 0; c < LF_PATH_COUNT; c++) {
+                ls[c] = (int)qo[c * (nq + 1) + k];
+                ln[c] = (int)(qo[c * (nq + 1) + k + 1] - ls[c]);
+            }
             LF_TRY(lf_prof_begin(h, LF_K_EVAL));
-            hipLaunchKernelGGL(k_eval, dim3(grid_for(clen, EW)), dim3(EW * WAVE), 0, st, cx, cstart, clen,
-                               h->eval_wave_cap, prev_start, prev_len);
+            hipLaunchKernelGGL(k_eval, dim3(ln[0] > 0 ? grid_for(ln[0], EW) : 1), dim3(EW * WAVE), 0, st, cx,
+                               cstart, h->eval_wave_cap < 2 * VSMALL ? h->eval_wave_cap : 2 * VSMALL, ls[0], ln[0],
+                               prev_start, prev_len);
             LF_TRY(lf_prof_end(h, LF_K_EVAL, 1));
-            LF_TRY(lf_prof_begin(h, LF_K_EVAL_MED));
-            hipLaunchKernelGGL(k_eval_med, dim3(grid_for(clen, EWM)), dim3(EWM * WAVE), 0, st, cx, cstart, clen,
-                               h->eval_med_cap);
-            LF_TRY(lf_prof_end(h, LF_K_EVAL_MED, 1));
-            LF_TRY(lf_prof_begin(h, LF_K_TAB_VISITS));
-            hipLaunchKernelGGL(k_big_visits, dim3(gb), dim3(BS), 0, st, cx, cstart, clen);
-            LF_TRY(lf_prof_end(h, LF_K_TAB_VISITS, 1));
-            LF_TRY(lf_prof_begin(h, LF_K_TAB_FINAL));
-            hipLaunchKernelGGL(k_big_final, dim3(gb), dim3(BS), 0, st, cx, cstart, clen);
-            LF_TRY(lf_prof_end(h, LF_K_TAB_FINAL, 1));
-            LF_TRY(lf_prof_begin(h, LF_K_TAB_TIE));
-            hipLaunchKernelGGL(k_big_tie, dim3(gb), dim3(BS), 0, st, cx);
-            LF_TRY(lf_prof_end(h, LF_K_TAB_TIE, 1));
+            BigRoles br;
+            const long long titems = hit[k + 1] - hit[k];
+            br.bt = ln[LF_PATH_TABLE] > 0 ? (int)grid_for(titems, 2 * EWB * WAVE) : 0;
+            if (br.bt > gb) br.bt = gb;
+            br.bg = ln[LF_PATH_GROUP] < gb ? ln[LF_PATH_GROUP] : gb;
+            br.bm = (int)grid_for(ln[LF_PATH_MED], GT / WAVE);
+            br.lt = ls[LF_PATH_TABLE];
+            br.nt = ln[LF_PATH_TABLE];
+            br.lg = ls[LF_PATH_GROUP];
+            br.ng = ln[LF_PATH_GROUP];
+            br.lm = ls[LF_PATH_MED];
+            br.nm = ln[LF_PATH_MED];
+            if (br.bt + br.bg + br.bm > 0) {
+                LF_TRY(lf_prof_begin(h, LF_K_EVAL_BIG));
+                hipLaunchKernelGGL(k_eval_big, dim3(br.bt + br.bg + br.bm), dim3(GT), 0, st, cx, cstart,
+                                   h->eval_med_cap, h->eval_grp_cap, br);
+                LF_TRY(lf_prof_end(h, LF_K_EVAL_BIG, 1));
+            }
+            if (ln[LF_PATH_TABLE] > 0) {
+                LF_TRY(lf_prof_begin(h, LF_K_TAB_FINAL));
+                hipLaunchKernelGGL(k_big_final, dim3(gb), dim3(BS), 0, st, cx, cstart, clen);
+                LF_TRY(lf_prof_end(h, LF_K_TAB_FINAL, 1));
+                LF_TRY(lf_prof_begin(h, LF_K_TAB_TIE));
+                hipLaunchKernelGGL(k_big_tie, dim3(gb), dim3(BS), 0, st, cx);
+                LF_TRY(lf_prof_end(h, LF_K_TAB_TIE, 1));
+            }
             LF_TRY(lf_prof_begin(h, LF_K_APPLY_EDIT));
             hipLaunchKernelGGL(k_apply_edit, dim3(grid_for(clen, BS)), dim3(BS), 0, st, cx, cstart, clen);
             LF_TRY(lf_prof_end(h, LF_K_APPLY_EDIT, 1));
@@ -1167,11 +1388,11 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
     if (!out->converged && out->iterations == max_iters) out->hit_max = 1;
     LF_TRY(lf_prof_flush(h));
     {
-        unsigned long long w[3][4];
+        unsigned long long w[LF_PATH_COUNT][4];
         LF_HIP(h, hipMemcpy(w, h->ctr->work, sizeof(w), hipMemcpyDeviceToHost));
         h->prof.visits = 0;
         h->prof.candidates = 0;
-        for (int p = 0; p < 3; p++) {
+        for (int p = 0; p < LF_PATH_COUNT; p++) {
             h->prof.path_nodes[p] = (long long)w[p][0];
             h->prof.path_neighbours[p] = (long long)w[p][1];
             h->prof.path_visits[p] = (long long)w[p][2];

@@ -54,7 +54,7 @@ struct __align__(64) GEntry {
 struct DevCounters {
     unsigned long long joins;      // per iteration
     unsigned long long leaves;     // per iteration
-    unsigned long long work[3][4]; // evaluation work per path (cumulative): nodes,
+    unsigned long long work[LF_PATH_COUNT][4]; // evaluation work per path (cumulative): nodes,
                                    // neighbours, visits, candidates
     int tcount;                    // touched communities (queue)
     int unused0;
@@ -103,9 +103,13 @@ struct Ctx {
     double *djd, *dld;
     DevCounters *ctr;
     // table path (nodes whose candidates do not fit one wave), indexed by queue position j
-    long long *item_base;    // [n + 1] first work item of order position r (static per iteration)
-    int *item_node;          // [items] order position owning each work item
-    int *big_idx;            // [q] 1 if queue index j takes the table path
+    int *big_idx;            // [q] evaluation state of queue index j (Q_* in iterate.hip)
+    // evaluation path of every node for the current iteration: per path the order
+    // positions of its nodes, ascending (a queue's nodes of a path are contiguous)
+    int *plist[LF_PATH_COUNT];
+    const int *rank;         // [n] order position of each node
+    long long *titem_base;   // [table-path nodes + 1] first work item of each
+    int *titem_node;         // [items] table-path list position owning each item
     unsigned long long *big_bj, *big_bl;   // [q] best join / leave change (bits; 0 = none)
     int *big_cj, *big_cl;    // [q] lowest community id among the best
     GEntry *gt;                // [gT] key (j << 32 | C), empty = ~0
@@ -165,9 +169,16 @@ struct lf_handle {
     double *djd, *dld;
     long long q_cap;         // capacity of the per-queue arrays
     // table path and work lists (sized per iteration)
-    long long *item_base;
-    int *item_node;
     int *big_idx;
+    int *cls;                // [n] evaluation path per order position (this iteration)
+    long long *cscan;        // [n + 1] scan scratch of the path lists
+    int *plist[LF_PATH_COUNT];
+    long long *titem_base;
+    int *titem_node;
+    long long titem_cap;
+    long long *hqoff;        // host: [LF_PATH_COUNT][nq + 1] first list position per queue,
+                             // then [nq + 1] first table-path work item per queue
+    long long hqoff_cap;
     unsigned long long *big_bj, *big_bl;
     int *big_cj, *big_cl;
     GEntry *gt;
@@ -175,7 +186,6 @@ struct lf_handle {
     unsigned long long *occ_key;
     double *occ_d;
     long long gT;
-    long long item_cap;      // capacity of item_node
     int *in_item, *in_base;
     long long in_cap;
     int *part_comm, *part_base, *part_cnt, *part_done, *mslot;
@@ -191,6 +201,7 @@ struct lf_handle {
     // tuning
     int eval_wave_cap;       // table entries per wave in the small wave path
     int eval_med_cap;        // table entries per wave in the medium wave path
+    int eval_grp_cap;        // table entries per workgroup in the workgroup path
     int tri_lds_cap;         // 0 = auto
     int hub_blocks;          // workgroups of the table-path evaluation kernels
     int refresh_blocks;      // workgroups of the in-count and re-sum kernels
@@ -232,6 +243,8 @@ Ctx lf_ctx(lf_handle *h);
 // resolved by lf_prof_flush (end of an API call), so timing never stalls the host
 int lf_prof_begin(lf_handle *h, int kind);
 int lf_prof_end(lf_handle *h, int kind, int launches);
+int lf_prof_begin_on(lf_handle *h, int kind, hipStream_t st);
+int lf_prof_end_on(lf_handle *h, int kind, int launches, hipStream_t st);
 int lf_prof_flush(lf_handle *h);
 
 // ---- primitives (prims.hip) ------------------------------------------------------------

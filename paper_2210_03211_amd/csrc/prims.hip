@@ -59,7 +59,10 @@ int lf_ensure_tmp(lf_handle *h, size_t bytes)
 
 static bool prof_on(lf_handle *h, int kind) { return kind < LF_K_COUNT && ((h->profiling >> kind) & 1); }
 
-int lf_prof_begin(lf_handle *h, int kind)
+int lf_prof_begin(lf_handle *h, int kind) { return lf_prof_begin_on(h, kind, h->stream); }
+int lf_prof_end(lf_handle *h, int kind, int launches) { return lf_prof_end_on(h, kind, launches, h->stream); }
+
+int lf_prof_begin_on(lf_handle *h, int kind, hipStream_t st)
 {
     if (!prof_on(h, kind)) return LF_OK;
     if (h->evused >= 4096) LF_TRY(lf_prof_flush(h));
@@ -69,14 +72,14 @@ int lf_prof_begin(lf_handle *h, int kind)
         LF_HIP(h, hipEventCreate(&e));
         h->evpool->push_back(e);
     }
-    LF_HIP(h, hipEventRecord((*h->evpool)[2 * h->evused], h->stream));
+    LF_HIP(h, hipEventRecord((*h->evpool)[2 * h->evused], st));
     return LF_OK;
 }
 
-int lf_prof_end(lf_handle *h, int kind, int launches)
+int lf_prof_end_on(lf_handle *h, int kind, int launches, hipStream_t st)
 {
     if (!prof_on(h, kind)) return LF_OK;
-    LF_HIP(h, hipEventRecord((*h->evpool)[2 * h->evused + 1], h->stream));
+    LF_HIP(h, hipEventRecord((*h->evpool)[2 * h->evused + 1], st));
     if ((int)h->evkind->size() <= h->evused) {
         h->evkind->push_back(kind);
         h->evlaunch->push_back(launches);
@@ -91,9 +94,9 @@ int lf_prof_end(lf_handle *h, int kind, int launches)
 int lf_prof_flush(lf_handle *h)
 {
     if (h->evused == 0) return LF_OK;
-    LF_HIP(h, hipEventSynchronize((*h->evpool)[2 * h->evused - 1]));
-    for (int k = 0; k < h->evused; k++) {
+    for (int k = 0; k < h->evused; k++) {       // pairs may sit on different streams
         float ms = 0.f;
+        LF_HIP(h, hipEventSynchronize((*h->evpool)[2 * k + 1]));
         LF_HIP(h, hipEventElapsedTime(&ms, (*h->evpool)[2 * k], (*h->evpool)[2 * k + 1]));
         int kind = (*h->evkind)[k];
         h->prof.ms[kind] += ms;

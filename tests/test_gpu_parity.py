@@ -317,14 +317,16 @@ def test_triangle_group_paths(lf, orc):
 
 @pytest.mark.parametrize("name,q", [("sbm2000", 64), ("copurchase_1pct", 16), ("social_0.2pct", 512)])
 def test_small_tables_and_single_workgroups(lf, orc, name, q):
-    """Tiny wave tables push nearly every node onto the medium wave path or the
-    global-table path; single workgroups make every grid-stride loop run long."""
+    """Tiny wave and workgroup tables push nearly every node onto the medium wave path,
+    the workgroup path or the global-table path; single workgroups make every
+    grid-stride loop run long."""
     import torch
     say("forced hub path", name, q)
     g = SMALL[name]()
     o = oracle_graph(orc, g).init_communities()
     oinfo = o.run_iterations(q, 0.01, 50)
     for opts in ({"wave_table": 16}, {"wave_table": 16, "med_table": 16}, {"med_table": 32, "hub_blocks": 3},
+                 {"wave_table": 16, "med_table": 16, "grp_table": 64}, {"med_table": 16, "grp_table": 16},
                  {"hub_blocks": 1, "refresh_blocks": 1}):
         h = lf.Handle(0)
         for k, v in opts.items():
@@ -341,7 +343,8 @@ def test_small_tables_and_single_workgroups(lf, orc, name, q):
 
 def test_option_validation(lf):
     h = lf.Handle(0)
-    for name, bad in (("wave_table", 100), ("wave_table", 256), ("med_table", 1024), ("hub_blocks", 0)):
+    for name, bad in (("wave_table", 100), ("wave_table", 256), ("med_table", 1024), ("grp_table", 4096),
+                      ("grp_table", 100), ("hub_blocks", 0)):
         with pytest.raises(lf.LazyFoxError):
             h.lf_set_option(name, bad)
 
