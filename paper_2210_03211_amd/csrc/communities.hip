@@ -522,13 +522,14 @@ int lf_initial_clustering(lf_handle *h)
     LF_TRY(lf_dev_alloc(h, (void **)&h->cls, sizeof(int) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->cscan, sizeof(long long) * (nn + 1)));
     for (int k = 0; k < LF_PATH_COUNT; k++) LF_TRY(lf_dev_alloc(h, (void **)&h->plist[k], sizeof(int) * nn));
-    LF_TRY(lf_dev_alloc(h, (void **)&h->joined_to, sizeof(int) * nn));
+    LF_TRY(lf_dev_alloc(h, (void **)&h->joined_to, sizeof(unsigned long long) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->ovf_node, sizeof(int) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->ovf_comm, sizeof(int) * nn));
     LF_HIP(h, hipMemsetAsync(h->cr, 0, sizeof(CommRec) * KK, st));
     LF_HIP(h, hipMemsetAsync(h->tflag, 0, sizeof(int) * KK, st));
     LF_HIP(h, hipMemsetAsync(h->ovf_flag, 0, sizeof(int) * KK, st));
-    LF_HIP(h, hipMemsetAsync(h->joined_to, 0xff, sizeof(int) * nn, st));
+    LF_HIP(h, hipMemsetAsync(h->joined_to, 0xff, sizeof(unsigned long long) * nn, st));
+    h->qtag = 0;
     if (n >= 0)
         hipLaunchKernelGGL(k_init_slots, dim3(grid_for((n + 1) * WAVE, BS)), dim3(BS), 0, st, h->rowptr, h->col,
                            h->deg, comm_of, n, h->nh, h->slot[0], h->cr);
@@ -555,15 +556,13 @@ int lf_initial_clustering(lf_handle *h)
     return LF_OK;
 }
 
-int lf_iteration_end(lf_handle *h, int last_start, int last_len, long long *joins, long long *leaves,
+int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
                      long long *live)
 {
     hipStream_t st = h->stream;
     const int BS = 256;
     long long n = h->n;
     int K = h->K;
-    (void)last_start;
-    (void)last_len;
     Ctx cx = lf_ctx(h);
     LF_HIP(h, hipMemsetAsync(&h->ctr->live, 0, sizeof(int) * 2, st));   // live, max_mem
     LF_HIP(h, hipMemsetAsync(&h->ctr->ovf_cnt, 0, sizeof(int), st));

@@ -7,8 +7,7 @@
 // list of its nodes in order.  Per queue (all launches on the handle's stream, no host
 // synchronisation):
 //   k_eval           small path: one wave per node with <= 64 visits, decided entirely
-//                    in an LDS hash table; block 0 also resets the queue's counters and
-//                    the previous queue's join marks
+//                    in an LDS hash table; block 0 also resets the queue's counters
 //   k_eval_big       by block role: the table path's visits (largest nodes): every
 //                    neighbour membership (y in C) adds its exact correction to the entry
 //                    (node, C) of a global open-addressing table, own memberships add the
@@ -23,7 +22,7 @@
 //                    first blocks split every touched community's member list into parts
 //   k_refresh        exact re-sum per part; multi-part communities combine their parts
 //                    through carry-save counters and the last part finalises
-// At the end of an iteration k_chunk_begin does the reset for the last queue.
+// k_queue_reset clears the queue counters at the start and the end of an iteration.
 //
 // Every sum is exact (fixed point), so none of the launch shapes above can change a bit
 // of the result.
@@ -39,10 +38,10 @@
 
 static inline unsigned grid_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
 
-__global__ void k_chunk_begin(Ctx cx, int prev_start, int prev_len)
+// reset the counters of a queue (at the start and the end of an iteration)
+__global__ void k_queue_reset(Ctx cx)
 {
-    long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (j == 0) {
+    if (threadIdx.x == 0) {
         DevCounters *c = cx.ctr;
         c->tcount = 0;
         c->occ_cnt = 0;
@@ -50,7 +49,6 @@ __global__ void k_chunk_begin(Ctx cx, int prev_start, int prev_len)
         c->parts_total = 0;
         c->mslots = 0;
     }
-    if (j < prev_len) cx.joined_to[cx.order[prev_start + j]] = -1;
 }
 
 // ------------------------------------------------------------------------------------
@@ -215,10 +213,36 @@ __device__ __forceinline__ bool eval_node(const Ctx &cx, int cstart, int j, int 
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        int v = b * NT + tid;
-        if (v < V) {
-            int h = lds_insert(L.key, T, lg, sv[b].comm);
+        // lanes of a wave that share the first pending community (a node's own
+        // communities often hold most of its neighbours) insert and count it once
+        const int v = b * NT + tid;
+        const int C = sv[b].comm;
+        bool pend = v < V;
+        int h = -1;
+        for (int att = 0; att < 2; att++) {
+            const unsigned long long pm = __ballot(pend);
+            if (!pm) break;
+            const int first = __ffsll((long long)pm) - 1;
+            const int c0 = __shfl(C, first, WAVE);
+            const bool in = pend && C == c0;
+            const unsigned long long gm = __ballot(in);
+            if (__popcll(gm) < 4) break;    // uniform over the wave
+            int h0 = 0;
+            if (lane == first) {
+                h0 = lds_insert(L.key, T, lg, c0);
+                atomicAdd(&L.kk[h0], __popcll(gm));
+            }
+            h0 = __shfl(h0, first, WAVE);
+            if (in) {
+                h = h0;
+                pend = false;
+            }
+        }
+        if (pend) {
+            h = lds_insert(L.key, T, lg, C);
             atomicAdd(&L.kk[h], 1);
+        }
+        if (v < V) {
             L.vhash[v] = h;
             L.vin[v] = sv[b].in;
         }
@@ -266,20 +290,48 @@ __device__ __forceinline__ bool eval_node(const Ctx &cx, int cstart, int j, int 
         if (ct[b] >= 0) L.sz[c] = rc[b].s;
     }
     node_sync<NT>();
-    // 3. exact correction of every visit, summed per candidate
+    // 3. exact correction of every visit, summed per candidate; as in phase 1, lanes of a
+    //    wave that share the first pending candidate add one wave-summed set of digits
     int bad = 0;
-    for (int v = tid; v < V; v += NT) {
-        int h = L.vhash[v];
-        int C = L.key[h], c = L.ci[h];
-        bool leave = false;
-        for (int a = 0; a < mcnt; a++) leave |= (L.mx[a] == C);
-        X192 term = visit_term(leave, L.vin[v], L.vdeg[v], L.sz[c], bad);
-        i64 t0, t1, t2, t3;
-        x192_digits(term, t0, t1, t2, t3);
-        atomicAdd(&L.d[0][c], (unsigned long long)t0);
-        atomicAdd(&L.d[1][c], (unsigned long long)t1);
-        atomicAdd(&L.d[2][c], (unsigned long long)t2);
-        atomicAdd(&L.d[3][c], (unsigned long long)t3);
+    for (int v0 = 0; v0 < V; v0 += NT) {    // same trip count on every lane of a wave
+        const int v = v0 + tid;
+        const bool act = v < V;
+        int c = 0;
+        i64 t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+        if (act) {
+            int h = L.vhash[v];
+            int C = L.key[h];
+            c = L.ci[h];
+            bool leave = false;
+            for (int a = 0; a < mcnt; a++) leave |= (L.mx[a] == C);
+            X192 term = visit_term(leave, L.vin[v], L.vdeg[v], L.sz[c], bad);
+            x192_digits(term, t0, t1, t2, t3);
+        }
+        bool pend = act;
+        for (int att = 0; att < 2; att++) {
+            const unsigned long long pm = __ballot(pend);
+            if (!pm) break;
+            const int first = __ffsll((long long)pm) - 1;
+            const int c0 = __shfl(c, first, WAVE);
+            const bool in = pend && c == c0;
+            const unsigned long long gm = __ballot(in);
+            if (__popcll(gm) < 4) break;    // uniform over the wave
+            const i64 a0 = wave_sum_i64(in ? t0 : 0), a1 = wave_sum_i64(in ? t1 : 0);
+            const i64 a2 = wave_sum_i64(in ? t2 : 0), a3 = wave_sum_i64(in ? t3 : 0);
+            if (lane == first) {
+                atomicAdd(&L.d[0][c0], (unsigned long long)a0);
+                atomicAdd(&L.d[1][c0], (unsigned long long)a1);
+                atomicAdd(&L.d[2][c0], (unsigned long long)a2);
+                atomicAdd(&L.d[3][c0], (unsigned long long)a3);
+            }
+            if (in) pend = false;
+        }
+        if (pend) {
+            atomicAdd(&L.d[0][c], (unsigned long long)t0);
+            atomicAdd(&L.d[1][c], (unsigned long long)t1);
+            atomicAdd(&L.d[2][c], (unsigned long long)t2);
+            atomicAdd(&L.d[3][c], (unsigned long long)t3);
+        }
     }
     node_sync<NT>();
     // 4. change of every candidate's score, best join and best leave
@@ -359,11 +411,8 @@ __device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg)
 // (list positions [ls, ls + ln)); the path was chosen so that the node fits, and a node
 // that does not is an internal error.
 
-// small wave path, one wave per node; block 0 also resets the queue's apply counters (no
-// kernel that runs beside this one uses them) and every wave clears join marks of the
-// previous queue
-__global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, int cstart, int wcap, int ls, int ln, int prev_start,
-                                                   int prev_len)
+// small wave path, one wave per node; block 0 also resets the queue's apply counters
+__global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, int cstart, int wcap, int ls, int ln)
 {
     __shared__ NodeLds<VSMALL> s_l[EW];
     const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
@@ -375,8 +424,6 @@ __global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, int cstart, int wcap
         c->parts_total = 0;
         c->mslots = 0;
     }
-    if (lane == 0)
-        for (int k = p; k < prev_len; k += gridDim.x * EW) cx.joined_to[cx.order[prev_start + k]] = -1;
     if (p >= ln) return;                    // no block barriers in this kernel
     const int j = cx.plist[LF_PATH_SMALL][ls + p] - cstart;
     if (!eval_node<WAVE, VSMALL>(cx, cstart, j, lane, s_l[wv], wcap, LF_PATH_SMALL) && lane == 0)
@@ -739,6 +786,13 @@ __device__ __forceinline__ void touch(const Ctx &cx, int C, bool want)
     if (first) cx.tlist[pos] = C;
 }
 
+// community x joined in the current queue, -1 if none (entries of earlier queues are stale)
+__device__ __forceinline__ int joined_in_queue(const Ctx &cx, int x)
+{
+    unsigned long long v = cx.joined_to[x];
+    return (unsigned)(v >> 32) == cx.qtag ? (int)(unsigned)v : -1;
+}
+
 __global__ void k_apply_edit(Ctx cx, int cstart, int clen)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -763,8 +817,11 @@ __global__ void k_apply_edit(Ctx cx, int cstart, int clen)
     }
     unsigned long long ml = __ballot(L >= 0);
     if (lane == 0 && ml) atomicAdd(&cx.ctr->leaves, (unsigned long long)__popcll(ml));
+    if (!inq) return;
+    const int x = cx.order[cstart + j];
+    const unsigned long long tag = (unsigned long long)cx.qtag << 32;
+    cx.joined_to[x] = tag | 0xffffffffull;  // no join (yet) in this queue
     if (J < 0 && L < 0) return;
-    int x = cx.order[cstart + j];
     NodeHdr hx = cx.nh[x];
     int cnt = hx.cnt;
     if (L >= 0) {
@@ -784,7 +841,7 @@ __global__ void k_apply_edit(Ctx cx, int cstart, int clen)
             cx.slot[hx.off + cnt] = sn;
             cnt++;
             atomicAdd(&cx.cr[J].s, 1);
-            cx.joined_to[x] = J;
+            cx.joined_to[x] = tag | (unsigned)J;
             joined = true;
             int p = atomicAdd(&cx.cm_len[J], 1);
             long long cap = cx.cm_off[J + 1] - cx.cm_off[J];
@@ -840,7 +897,7 @@ __global__ void __launch_bounds__(256) k_apply_in(Ctx cx, int cstart, int clen, 
         if (k < 0) continue;
         int J = cx.dj[j], L = cx.dl[j];
         int x = cx.order[cstart + j];
-        if (J >= 0 && cx.joined_to[x] != J) J = -1;     // join did not fit (error flagged)
+        if (J >= 0 && joined_in_queue(cx, x) != J) J = -1;   // join did not fit (error flagged)
         long long rb = cx.rowptr[x];
         int d = cx.deg[x];
         int lo = k * INB, hi = lo + INB < d ? lo + INB : d;
@@ -848,7 +905,7 @@ __global__ void __launch_bounds__(256) k_apply_in(Ctx cx, int cstart, int clen, 
         for (int e = lo + lane; e < hi; e += WAVE) {
             int y = cx.col[rb + e];
             NodeHdr hy = cx.nh[y];
-            int jy = cx.joined_to[y];
+            int jy = joined_in_queue(cx, y);
             for (int t = 0; t < hy.cnt; t++) {
                 int c = cx.slot[hy.off + t].comm;
                 if (c == J && J >= 0) {
@@ -1307,9 +1364,8 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
         const long long *hit = h->hqoff + LF_PATH_COUNT * (nq + 1);   // first table item per queue
         LF_HIP(h, hipMemsetAsync(&h->ctr->joins, 0, sizeof(unsigned long long) * 2, st));
         Ctx cx = lf_ctx(h);
-        hipLaunchKernelGGL(k_chunk_begin, dim3(1), dim3(BS), 0, st, cx, 0, 0);
+        hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, st, cx);
         int gb = h->hub_blocks, rbk = h->refresh_blocks;
-        int prev_start = 0, prev_len = 0;
         for (long long k = 0; k < nq; k++) {
             const long long start = k * qq;
             int clen = (int)((n - start) < qq ? (n - start) : qq);
@@ -1320,9 +1376,9 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
                 ln[c] = (int)(qo[c * (nq + 1) + k + 1] - ls[c]);
             }
             LF_TRY(lf_prof_begin(h, LF_K_EVAL));
+            cx.qtag = h->qtag++;
             hipLaunchKernelGGL(k_eval, dim3(ln[0] > 0 ? grid_for(ln[0], EW) : 1), dim3(EW * WAVE), 0, st, cx,
-                               cstart, h->eval_wave_cap < 2 * VSMALL ? h->eval_wave_cap : 2 * VSMALL, ls[0], ln[0],
-                               prev_start, prev_len);
+                               cstart, h->eval_wave_cap < 2 * VSMALL ? h->eval_wave_cap : 2 * VSMALL, ls[0], ln[0]);
             LF_TRY(lf_prof_end(h, LF_K_EVAL, 1));
             BigRoles br;
             const long long titems = hit[k + 1] - hit[k];
@@ -1362,15 +1418,12 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
             LF_TRY(lf_prof_end(h, LF_K_REFRESH, 1));
             h->prof.chunks++;
             h->prof.node_evals += clen;
-            prev_start = cstart;
-            prev_len = clen;
         }
-        hipLaunchKernelGGL(k_chunk_begin, dim3(grid_for(prev_len > 0 ? prev_len : 1, BS)), dim3(BS), 0, st, cx,
-                           prev_start, prev_len);
+        hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, st, cx);
         LF_HIP(h, hipGetLastError());
         LF_TRY(lf_prof_begin(h, LF_K_ITEREND));
         long long joins = 0, leaves = 0, live = 0;
-        LF_TRY(lf_iteration_end(h, prev_start, prev_len, &joins, &leaves, &live));
+        LF_TRY(lf_iteration_end(h, &joins, &leaves, &live));
         LF_TRY(lf_prof_end(h, LF_K_ITEREND, 8));
         LF_TRY(lf_check_dev_error(h));
         out->iterations = it + 1;

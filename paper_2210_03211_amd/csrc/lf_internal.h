@@ -95,7 +95,9 @@ struct Ctx {
     int *cm_node;            // member lists
     int *tflag;              // touched flag per community
     int *tlist;              // touched list
-    int *joined_to;          // community joined in the current queue (-1 otherwise)
+    unsigned long long *joined_to;  // per node (queue tag << 32 | community joined, -1 if
+                                    // none); only entries with the current tag are valid
+    unsigned qtag;           // tag of the current queue (unique within a run)
     int *ovf_node;           // overflow joiners (node, community)
     int *ovf_comm;
     int *ovf_flag;
@@ -163,7 +165,9 @@ struct lf_handle {
     int *cm_len;
     int *cm_node;
     long long cm_cap;        // capacity of cm_node
-    int *tflag, *tlist, *joined_to;
+    int *tflag, *tlist;
+    unsigned long long *joined_to;
+    unsigned qtag;           // next queue tag
     int *ovf_node, *ovf_comm, *ovf_flag;
     int *dj, *dl;
     double *djd, *dld;
@@ -267,7 +271,7 @@ int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out);
 // ---- community stages (communities.hip) ----------------------------------------------------
 int lf_initial_clustering(lf_handle *h);
 int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out);
-int lf_iteration_end(lf_handle *h, int last_start, int last_len, long long *joins, long long *leaves,
+int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
                      long long *live);
 int lf_check_dev_error(lf_handle *h);
 void lf_free_iteration_buffers(lf_handle *h);
