@@ -36,6 +36,7 @@ extern "C" {
 #define LF_EDEVICE (-4)     /* HIP runtime error (text in lf_last_error) */
 #define LF_ERANGE (-5)      /* caller buffer too small */
 #define LF_EOVERFLOW (-6)   /* size beyond the supported integer ranges */
+#define LF_EAGAIN (-7)      /* not ready yet (a batch member or server job still runs) */
 #define LF_EINTERNAL (-8)   /* an internal consistency check failed */
 
 /* lf_load_graph flags */
@@ -195,7 +196,8 @@ int lf_reset_profile(lf_handle *h);
 #define LF_OPT_TRI_LDS_CAP 1       /* max out-list length staged in LDS by the workgroup
                                       triangle kernel (0 = as much as LDS holds); longer
                                       out-lists use global scratch */
-#define LF_OPT_HUB_BLOCKS 3        /* workgroups of the table-path evaluation kernels */
+#define LF_OPT_HUB_BLOCKS 3        /* most workgroups of the table path and of the workgroup
+                                      path per launch */
 #define LF_OPT_REFRESH_BLOCKS 4    /* workgroups of the in-count and re-sum kernels */
 #define LF_OPT_WAVE_TABLE 5        /* candidate-table entries per wave in the wave path
                                       (power of two, 16 .. 128); nodes needing more go to
@@ -215,6 +217,64 @@ int lf_get_option(lf_handle *h, int option, int64_t *value);
  * Values must be finite with magnitude in [2^-113, 2^30] or zero; LF_EOVERFLOW otherwise.
  */
 int lf_debug_exact_sum(lf_handle *h, const double *values_dev, int64_t n, double *out);
+
+/* Device memory the handle holds now and at most so far (bytes). */
+int lf_get_memory(lf_handle *h, uint64_t *bytes, uint64_t *peak);
+
+/*
+ * Many graphs advanced together (Algorithm 2 run for each of them).  A batch holds handles
+ * whose communities are initialised; each lf_batch_step runs one queue of every member
+ * still iterating, with one launch per kernel covering all members, and performs a
+ * member's iteration start and end (path lists, degenerate removal, exact score, stopping
+ * rule of "Stopping Criteria") between steps.  Each member computes exactly what
+ * lf_run_iterations(queue_size, threshold, max_iters) computes on it alone.
+ *
+ * lf_batch_create: `hip_stream` as for lf_create (NULL = a batch-owned stream); members'
+ *   work runs on it.  lf_batch_add: the handle (same device, state after
+ *   lf_init_communities) joins; while a member, it runs on the batch's stream and must not
+ *   be used otherwise.  *member_id identifies it.  LF_ESTATE before lf_init_communities.
+ * lf_batch_step: *running = members still iterating afterwards.
+ * lf_batch_member_info: LF_OK and `out` filled as by lf_run_iterations when the member is
+ *   done; LF_EAGAIN while it iterates; its error status if it failed.
+ * lf_batch_remove: the member leaves (done or not); its handle returns to its own stream.
+ * lf_batch_destroy: removes every member (handles are not destroyed) and frees the batch.
+ */
+typedef struct lf_batch lf_batch;
+int lf_batch_create(lf_batch **out, int device, void *hip_stream);
+int lf_batch_add(lf_batch *b, lf_handle *h, int32_t queue_size, double threshold, int32_t max_iters,
+                 int32_t *member_id);
+int lf_batch_step(lf_batch *b, int32_t *running);
+int lf_batch_member_info(lf_batch *b, int32_t member_id, lf_run_info *out);
+int lf_batch_remove(lf_batch *b, int32_t member_id);
+int lf_batch_destroy(lf_batch *b);
+const char *lf_batch_last_error(lf_batch *b);
+
+/*
+ * Serving: community-detection jobs on graphs of uneven size.  lf_server_submit copies a
+ * job's edge list (host memory, as for lf_load_graph without flags) and queues it;
+ * LF_ENOMEM if its estimated device footprint exceeds the whole budget.  Each
+ * lf_server_tick admits queued jobs in arrival order while their estimated footprints fit
+ * the budget and fewer than max_batch jobs run (load, initial clustering, join the
+ * batch), runs one batch step, and retires finished jobs: memberships and run info are
+ * copied to host memory and the job's device memory is released, so jobs that arrived
+ * meanwhile are admitted as memory frees up.  *pending = jobs queued or running.
+ * lf_server_poll: *state = 0 queued, 1 running, 2 done, < 0 failed with that status.
+ * lf_server_fetch: results of a done job, two-call pattern as lf_get_memberships
+ *   (LF_EAGAIN if not done); after a copy of the memberships the job is forgotten.
+ * lf_server_stats: device bytes reserved by admitted jobs, the budget, running and queued
+ *   jobs.  A job's results equal those of lf_run_iterations on its graph alone.
+ */
+typedef struct lf_server lf_server;
+int lf_server_create(lf_server **out, int device, void *hip_stream, uint64_t hbm_budget, int32_t max_batch);
+int lf_server_submit(lf_server *s, int64_t n, int64_t n_pairs, const int64_t *src, const int64_t *dst,
+                     int32_t queue_size, double threshold, int32_t max_iters, int64_t *job_id);
+int lf_server_tick(lf_server *s, int32_t *pending);
+int lf_server_poll(lf_server *s, int64_t job_id, int32_t *state);
+int lf_server_fetch(lf_server *s, int64_t job_id, int64_t *offsets, int32_t *comm_ids, int64_t capacity,
+                    int64_t *total, lf_run_info *info);
+int lf_server_stats(lf_server *s, uint64_t *used, uint64_t *budget, int32_t *running, int32_t *queued);
+int lf_server_destroy(lf_server *s);
+const char *lf_server_last_error(lf_server *s);
 
 #ifdef __cplusplus
 }

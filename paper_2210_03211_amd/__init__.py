@@ -12,9 +12,9 @@ library has not been built, importing the binding raises -- there is no CPU fall
     offsets, comm_ids = h.get_memberships()
 """
 from ._native import (  # noqa: F401
-    Handle, LazyFoxError, RunInfo, Profile, library_path, load_library,
-    LF_OK, LF_EINVAL, LF_ESTATE, LF_ENOMEM, LF_EDEVICE, LF_ERANGE, LF_EOVERFLOW, LF_EINTERNAL,
+    Handle, Batch, Server, LazyFoxError, RunInfo, Profile, library_path, load_library,
+    LF_OK, LF_EINVAL, LF_ESTATE, LF_ENOMEM, LF_EDEVICE, LF_ERANGE, LF_EOVERFLOW, LF_EAGAIN, LF_EINTERNAL,
     LF_RELABEL, LF_DEVICE_PTR, KERNEL_CLASSES, OPTIONS, PROF_COUNTERS_BIT, PATHS,
 )
 
-__all__ = ["Handle", "LazyFoxError", "RunInfo", "Profile", "library_path", "load_library"]
+__all__ = ["Handle", "Batch", "Server", "LazyFoxError", "RunInfo", "Profile", "library_path", "load_library"]

@@ -10,7 +10,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liblazyfox.so")
 
 LF_OK, LF_EINVAL, LF_ESTATE, LF_ENOMEM, LF_EDEVICE, LF_ERANGE, LF_EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
-LF_EINTERNAL = -8
+LF_EAGAIN, LF_EINTERNAL = -7, -8
 LF_RELABEL = 1
 LF_DEVICE_PTR = 2
 OPTIONS = {"tri_lds_cap": 1, "hub_blocks": 3, "refresh_blocks": 4, "wave_table": 5, "med_table": 6,
@@ -77,13 +77,29 @@ def load_library():
         "lf_debug_exact_sum": [vp, vp, i64, C.POINTER(dbl)],
         "lf_set_option": [vp, C.c_int, i64],
         "lf_get_option": [vp, C.c_int, C.POINTER(i64)],
+        "lf_get_memory": [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
+        "lf_batch_create": [C.POINTER(vp), C.c_int, vp],
+        "lf_batch_add": [vp, vp, i32, dbl, i32, C.POINTER(i32)],
+        "lf_batch_step": [vp, C.POINTER(i32)],
+        "lf_batch_member_info": [vp, i32, C.POINTER(RunInfo)],
+        "lf_batch_remove": [vp, i32],
+        "lf_batch_destroy": [vp],
+        "lf_server_create": [C.POINTER(vp), C.c_int, vp, C.c_uint64, i32],
+        "lf_server_submit": [vp, i64, i64, vp, vp, i32, dbl, i32, C.POINTER(i64)],
+        "lf_server_tick": [vp, C.POINTER(i32)],
+        "lf_server_poll": [vp, i64, C.POINTER(i32)],
+        "lf_server_fetch": [vp, i64, vp, vp, i64, C.POINTER(i64), C.POINTER(RunInfo)],
+        "lf_server_stats": [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(i32), C.POINTER(i32)],
+        "lf_server_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = C.c_int
-    L.lf_last_error.argtypes = [vp]
-    L.lf_last_error.restype = C.c_char_p
+    for name in ("lf_last_error", "lf_batch_last_error", "lf_server_last_error"):
+        f = getattr(L, name)
+        f.argtypes = [vp]
+        f.restype = C.c_char_p
     _lib = L
     return L
 
@@ -301,6 +317,11 @@ class Handle:
         self._check(self.L.lf_get_option(self.h, OPTIONS[name], C.byref(v)), "lf_get_option")
         return v.value
 
+    def lf_get_memory(self):
+        b, p = C.c_uint64(), C.c_uint64()
+        self._check(self.L.lf_get_memory(self.h, C.byref(b), C.byref(p)), "lf_get_memory")
+        return b.value, p.value
+
     def lf_debug_exact_sum(self, values_dev):
         p, is_dev = _ptr(values_dev)
         if not is_dev:
@@ -309,3 +330,184 @@ class Handle:
         self._check(self.L.lf_debug_exact_sum(self.h, C.c_void_p(p), int(values_dev.numel()), C.byref(out)),
                     "lf_debug_exact_sum")
         return out.value
+
+
+def _run_info_arrays(max_iters):
+    hist = np.zeros(max_iters + 1, np.float64)
+    joins = np.zeros(max(1, max_iters), np.int64)
+    leaves = np.zeros(max(1, max_iters), np.int64)
+    comms = np.zeros(max(1, max_iters), np.int64)
+    info = RunInfo()
+    info.wtilde_hist = hist.ctypes.data_as(C.POINTER(C.c_double))
+    info.joins = joins.ctypes.data_as(C.POINTER(C.c_int64))
+    info.leaves = leaves.ctypes.data_as(C.POINTER(C.c_int64))
+    info.communities = comms.ctypes.data_as(C.POINTER(C.c_int64))
+    return info, hist, joins, leaves, comms
+
+
+def _run_info_dict(info, hist, joins, leaves, comms):
+    it = info.iterations
+    return dict(iterations=it, converged=bool(info.converged), hit_max=bool(info.hit_max),
+                wcc_hat=info.wcc_hat, wtilde=info.wtilde, wtilde_hist=hist[: it + 1].copy(),
+                joins=joins[:it].copy(), leaves=leaves[:it].copy(), communities=comms[:it].copy())
+
+
+class Batch:
+    """Many graphs advanced together, one queue of each per step (``lf_batch``)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.L = load_library()
+        self.b = C.c_void_p()
+        if stream is None:
+            stream = _current_stream(device)
+        elif hasattr(stream, "cuda_stream"):
+            stream = C.c_void_p(stream.cuda_stream)
+        rc = self.L.lf_batch_create(C.byref(self.b), int(device), stream)
+        if rc != 0:
+            raise LazyFoxError(rc, "lf_batch_create", "device %d unavailable" % device)
+        self._max_iters = {}
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise LazyFoxError(rc, what, self.L.lf_batch_last_error(self.b).decode(errors="replace"))
+
+    def lf_batch_add(self, handle, queue_size, threshold=0.01, max_iters=50):
+        mid = C.c_int32()
+        self._check(self.L.lf_batch_add(self.b, handle.h, int(queue_size), float(threshold), int(max_iters),
+                                        C.byref(mid)), "lf_batch_add")
+        self._max_iters[mid.value] = int(max_iters)
+        return mid.value
+
+    add = lf_batch_add
+
+    def lf_batch_step(self):
+        running = C.c_int32()
+        self._check(self.L.lf_batch_step(self.b, C.byref(running)), "lf_batch_step")
+        return running.value
+
+    step = lf_batch_step
+
+    def lf_batch_member_info(self, member):
+        """Run info of a finished member (as Handle.run_iterations returns), None while it runs."""
+        arrays = _run_info_arrays(self._max_iters.get(member, 1))
+        rc = self.L.lf_batch_member_info(self.b, int(member), C.byref(arrays[0]))
+        if rc == LF_EAGAIN:
+            return None
+        self._check(rc, "lf_batch_member_info")
+        return _run_info_dict(*arrays)
+
+    member_info = lf_batch_member_info
+
+    def lf_batch_remove(self, member):
+        self._check(self.L.lf_batch_remove(self.b, int(member)), "lf_batch_remove")
+
+    remove = lf_batch_remove
+
+    def lf_batch_destroy(self):
+        if self.b:
+            self.L.lf_batch_destroy(self.b)
+            self.b = C.c_void_p()
+
+    close = lf_batch_destroy
+
+    def lf_batch_last_error(self):
+        return self.L.lf_batch_last_error(self.b).decode(errors="replace")
+
+    def __del__(self):
+        try:
+            self.lf_batch_destroy()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving runtime (``lf_server``): jobs admitted by device-memory footprint into a
+    shared batch as they arrive, results copied back as they finish."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 32 << 30, max_batch: int = 256, stream=None):
+        self.L = load_library()
+        self.s = C.c_void_p()
+        if stream is None:
+            stream = _current_stream(device)
+        elif hasattr(stream, "cuda_stream"):
+            stream = C.c_void_p(stream.cuda_stream)
+        rc = self.L.lf_server_create(C.byref(self.s), int(device), stream, int(hbm_budget), int(max_batch))
+        if rc != 0:
+            raise LazyFoxError(rc, "lf_server_create", "device %d unavailable" % device)
+        self._max_iters = {}
+        self._n = {}
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise LazyFoxError(rc, what, self.L.lf_server_last_error(self.s).decode(errors="replace"))
+
+    def lf_server_submit(self, n, src, dst, queue_size, threshold=0.01, max_iters=50):
+        src = np.ascontiguousarray(src, dtype=np.int64)
+        dst = np.ascontiguousarray(dst, dtype=np.int64)
+        if src.shape != dst.shape:
+            raise ValueError("src and dst differ in length")
+        jid = C.c_int64()
+        self._check(self.L.lf_server_submit(self.s, int(n), int(src.size), C.c_void_p(src.ctypes.data),
+                                            C.c_void_p(dst.ctypes.data), int(queue_size), float(threshold),
+                                            int(max_iters), C.byref(jid)), "lf_server_submit")
+        self._max_iters[jid.value] = int(max_iters)
+        self._n[jid.value] = int(n)
+        return jid.value
+
+    submit = lf_server_submit
+
+    def lf_server_tick(self):
+        pending = C.c_int32()
+        self._check(self.L.lf_server_tick(self.s, C.byref(pending)), "lf_server_tick")
+        return pending.value
+
+    tick = lf_server_tick
+
+    def lf_server_poll(self, job):
+        st = C.c_int32()
+        self._check(self.L.lf_server_poll(self.s, int(job), C.byref(st)), "lf_server_poll")
+        return st.value
+
+    poll = lf_server_poll
+
+    def lf_server_fetch(self, job):
+        """(offsets, community ids, run info) of a done job; None while it is not done."""
+        arrays = _run_info_arrays(self._max_iters.get(job, 1))
+        total = C.c_int64()
+        rc = self.L.lf_server_fetch(self.s, int(job), None, None, 0, C.byref(total), C.byref(arrays[0]))
+        if rc == LF_EAGAIN:
+            return None
+        self._check(rc, "lf_server_fetch")
+        off = np.zeros(self._n[job] + 1, np.int64)
+        ids = np.zeros(max(1, total.value), np.int32)
+        self._check(self.L.lf_server_fetch(self.s, int(job), C.c_void_p(off.ctypes.data), C.c_void_p(ids.ctypes.data),
+                                           ids.size, C.byref(total), None), "lf_server_fetch")
+        del self._max_iters[job], self._n[job]
+        return off, ids[: total.value], _run_info_dict(*arrays)
+
+    fetch = lf_server_fetch
+
+    def lf_server_stats(self):
+        used, budget = C.c_uint64(), C.c_uint64()
+        running, queued = C.c_int32(), C.c_int32()
+        self._check(self.L.lf_server_stats(self.s, C.byref(used), C.byref(budget), C.byref(running),
+                                           C.byref(queued)), "lf_server_stats")
+        return dict(used=used.value, budget=budget.value, running=running.value, queued=queued.value)
+
+    stats = lf_server_stats
+
+    def lf_server_destroy(self):
+        if self.s:
+            self.L.lf_server_destroy(self.s)
+            self.s = C.c_void_p()
+
+    close = lf_server_destroy
+
+    def lf_server_last_error(self):
+        return self.L.lf_server_last_error(self.s).decode(errors="replace")
+
+    def __del__(self):
+        try:
+            self.lf_server_destroy()
+        except Exception:
+            pass

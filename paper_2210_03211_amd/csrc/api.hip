@@ -14,6 +14,7 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     lf_handle *h = (lf_handle *)calloc(1, sizeof(lf_handle));
     if (!h) return LF_ENOMEM;
     h->allocs = new std::vector<void *>();
+    h->alloc_sizes = new std::vector<size_t>();
     h->evpool = new std::vector<hipEvent_t>();
     h->evkind = new std::vector<int>();
     h->evlaunch = new std::vector<int>();
@@ -21,11 +22,13 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         delete h->allocs;
+        delete h->alloc_sizes;
         free(h);
         return LF_EDEVICE;
     }
     if (hipSetDevice(device) != hipSuccess) {
         delete h->allocs;
+        delete h->alloc_sizes;
         free(h);
         return LF_EDEVICE;
     }
@@ -43,6 +46,7 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
         if (h->own_stream) (void)hipStreamDestroy(h->stream);
         delete h->allocs;
+        delete h->alloc_sizes;
         free(h);
         return LF_EDEVICE;
     }
@@ -65,6 +69,7 @@ int lf_destroy(lf_handle *h)
     (void)hipStreamSynchronize(h->stream);
     for (void *p : *h->allocs) (void)hipFree(p);
     delete h->allocs;
+    delete h->alloc_sizes;
     for (hipEvent_t e : *h->evpool) (void)hipEventDestroy(e);
     delete h->evpool;
     delete h->evkind;

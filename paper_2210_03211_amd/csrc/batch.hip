@@ -1,0 +1,578 @@
+// batch.hip -- many graphs advanced together, and the serving runtime built on it.
+//
+// A batch holds handles whose communities are initialised.  lf_batch_step runs one
+// queue of every member that is still iterating: the per-queue parameters of all members
+// go to the device in one copy, then each of the six per-queue launches covers every
+// member (blocks find their graph from per-member block offsets), so a launch carries
+// the work of many small graphs instead of leaving most of the device idle.  A member's
+// iteration start and end (path lists, degenerate removal, exact score, stop test) run
+// between steps.  Every member computes exactly what lf_run_iterations computes for it
+// alone: its kernels read and write only its own buffers, and the launch shapes do not
+// change a result.
+//
+// The server admits submitted jobs (edge lists copied to host memory) into the batch in
+// arrival order while their estimated device footprint fits the budget, steps the batch,
+// and retires finished jobs (memberships copied back, device memory released), so jobs
+// that arrive while others run join as memory frees up.
+#include <deque>
+#include <map>
+#include <stdlib.h>
+#include <vector>
+
+#include "lf_internal.h"
+
+struct BatchMember {
+    lf_handle *h;
+    hipStream_t saved_stream;
+    long long qq, nq, k;     // queue size, queues of the current iteration, next queue
+    int max_iters;
+    double theta;
+    int it;                  // iterations completed
+    bool in_iter;
+    int state;               // 0 iterating, 1 done, < 0 failed (status)
+    double prev;
+    int converged, hit_max;
+    Ctx cx;
+    std::vector<double> hist;
+    std::vector<long long> joins, leaves, comms;
+};
+
+struct lf_batch {
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    std::vector<BatchMember *> members;      // by member id; nullptr once removed
+    Member *hmem[2];
+    int *hboff[2];
+    hipEvent_t hev[2];
+    Member *dmem;
+    int *dboff;
+    int cap;                                 // members the buffers hold
+    int slot;
+    char err[512];
+};
+
+static int batch_error(lf_batch *b, int code, const char *msg)
+{
+    snprintf(b->err, sizeof b->err, "%s", msg);
+    return code;
+}
+
+static int batch_reserve(lf_batch *b, int nm)
+{
+    if (nm <= b->cap) return LF_OK;
+    int cap = b->cap ? b->cap : 64;
+    while (cap < nm) cap *= 2;
+    for (int s = 0; s < 2; s++) {
+        if (b->hmem[s]) {
+            (void)hipEventSynchronize(b->hev[s]);
+            (void)hipHostFree(b->hmem[s]);
+            (void)hipHostFree(b->hboff[s]);
+        }
+        if (hipHostMalloc((void **)&b->hmem[s], sizeof(Member) * cap, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&b->hboff[s], sizeof(int) * 6 * (cap + 1), hipHostMallocDefault) != hipSuccess)
+            return batch_error(b, LF_ENOMEM, "pinned host buffers of the batch");
+    }
+    (void)hipStreamSynchronize(b->stream);
+    if (b->dmem) (void)hipFree(b->dmem);
+    if (b->dboff) (void)hipFree(b->dboff);
+    if (hipMalloc((void **)&b->dmem, sizeof(Member) * cap) != hipSuccess ||
+        hipMalloc((void **)&b->dboff, sizeof(int) * 6 * (cap + 1)) != hipSuccess)
+        return batch_error(b, LF_ENOMEM, "device buffers of the batch");
+    b->cap = cap;
+    return LF_OK;
+}
+
+// record the result of a finished iteration and decide whether the member goes on
+static int member_iteration_done(BatchMember *m)
+{
+    lf_handle *h = m->h;
+    long long joins = 0, leaves = 0, live = 0;
+    int rc = lf_iter_finish(h, &joins, &leaves, &live);
+    if (rc != LF_OK) return rc;
+    m->it++;
+    m->hist.push_back(h->Wt);
+    m->joins.push_back(joins);
+    m->leaves.push_back(leaves);
+    m->comms.push_back(live);
+    bool stop = (m->prev == 0.0) || ((h->Wt - m->prev) / m->prev < m->theta);
+    m->prev = h->Wt;
+    m->in_iter = false;
+    if (stop) {
+        m->converged = 1;
+        m->state = 1;
+    } else if (m->it >= m->max_iters) {
+        m->hit_max = 1;
+        m->state = 1;
+    }
+    return LF_OK;
+}
+
+extern "C" {
+
+int lf_batch_create(lf_batch **out, int device, void *hip_stream)
+{
+    if (!out) return LF_EINVAL;
+    *out = nullptr;
+    if (hipSetDevice(device) != hipSuccess) return LF_EDEVICE;
+    lf_batch *b = new lf_batch();
+    b->device = device;
+    b->cap = 0;
+    b->slot = 0;
+    b->dmem = nullptr;
+    b->dboff = nullptr;
+    b->err[0] = 0;
+    for (int s = 0; s < 2; s++) {
+        b->hmem[s] = nullptr;
+        b->hboff[s] = nullptr;
+        if (hipEventCreateWithFlags(&b->hev[s], hipEventDisableTiming) != hipSuccess) {
+            delete b;
+            return LF_EDEVICE;
+        }
+    }
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+        b->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return LF_EDEVICE;
+        }
+        b->own_stream = true;
+    }
+    *out = b;
+    return LF_OK;
+}
+
+const char *lf_batch_last_error(lf_batch *b) { return b ? b->err : "null batch"; }
+
+int lf_batch_add(lf_batch *b, lf_handle *h, int32_t queue_size, double threshold, int32_t max_iters,
+                 int32_t *member_id)
+{
+    if (!b || !h || !member_id) return LF_EINVAL;
+    if (queue_size < 1 || !(threshold >= 0.0) || max_iters < 0)
+        return batch_error(b, LF_EINVAL, "queue_size >= 1, threshold >= 0 and max_iters >= 0 required");
+    if (h->state < 2) return batch_error(b, LF_ESTATE, "lf_batch_add: communities not initialised");
+    if (h->device != b->device) return batch_error(b, LF_EINVAL, "lf_batch_add: handle on another device");
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return batch_error(b, LF_EDEVICE, "stream sync failed");
+    BatchMember *m = new BatchMember();
+    m->h = h;
+    m->saved_stream = h->stream;
+    h->stream = b->stream;
+    long long n = h->n;
+    m->qq = queue_size < n ? queue_size : (n > 0 ? n : 1);
+    m->nq = 0;
+    m->k = 0;
+    m->max_iters = max_iters;
+    m->theta = threshold;
+    m->it = 0;
+    m->in_iter = false;
+    m->state = (h->cc == 0.0 || max_iters == 0) ? 1 : 0;
+    m->converged = h->cc == 0.0 ? 1 : 0;
+    m->hit_max = 0;
+    m->prev = h->Wt;
+    m->hist.push_back(h->Wt);
+    *member_id = (int32_t)b->members.size();
+    b->members.push_back(m);
+    return LF_OK;
+}
+
+int lf_batch_step(lf_batch *b, int32_t *running)
+{
+    if (!b) return LF_EINVAL;
+    std::vector<BatchMember *> act;
+    for (BatchMember *m : b->members) {
+        if (!m || m->state != 0) continue;
+        if (!m->in_iter) {
+            int rc = lf_iter_begin(m->h, m->qq, &m->nq);
+            if (rc != LF_OK) {
+                m->state = rc;
+                continue;
+            }
+            m->cx = lf_ctx(m->h);
+            m->k = 0;
+            m->in_iter = true;
+        }
+        act.push_back(m);
+    }
+    const int nm = (int)act.size();
+    if (nm > 0) {
+        LF_TRY(batch_reserve(b, nm));
+        const int s = b->slot;
+        b->slot ^= 1;
+        if (hipEventSynchronize(b->hev[s]) != hipSuccess) return batch_error(b, LF_EDEVICE, "event sync failed");
+        Member *hm = b->hmem[s];
+        int *hb = b->hboff[s];
+        int total[6] = {0, 0, 0, 0, 0, 0};
+        for (int i = 0; i < nm; i++) {
+            BatchMember *m = act[i];
+            QGrids g;
+            lf_queue_params(m->h, m->k, m->nq, m->qq, true, &hm[i].qs, &g);
+            m->cx.qtag = m->h->qtag++;
+            hm[i].cx = m->cx;
+            const int blocks[6] = {g.eval, g.big, g.fin, g.apply_edit, g.apply_in, g.refresh};
+            for (int t = 0; t < 6; t++) {
+                hb[t * (nm + 1) + i] = total[t];
+                total[t] += blocks[t];
+            }
+        }
+        for (int t = 0; t < 6; t++) hb[t * (nm + 1) + nm] = total[t];
+        if (hipMemcpyAsync(b->dmem, hm, sizeof(Member) * nm, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+            hipMemcpyAsync(b->dboff, hb, sizeof(int) * 6 * (nm + 1), hipMemcpyHostToDevice, b->stream) !=
+                hipSuccess ||
+            hipEventRecord(b->hev[s], b->stream) != hipSuccess)
+            return batch_error(b, LF_EDEVICE, "descriptor upload failed");
+        if (lf_launch_multi(b->stream, b->dmem, b->dboff, nm, total) != LF_OK)
+            return batch_error(b, LF_EDEVICE, "multi-graph launch failed");
+        for (BatchMember *m : act) {
+            m->k++;
+            if (m->k == m->nq) {
+                int rc = member_iteration_done(m);
+                if (rc != LF_OK) m->state = rc;
+            }
+        }
+    }
+    int live = 0;
+    for (BatchMember *m : b->members)
+        if (m && m->state == 0) live++;
+    if (running) *running = live;
+    return LF_OK;
+}
+
+// LF_OK and the results when the member is done; LF_EAGAIN while it still iterates; the
+// member's error status if it failed.  The arrays of `out` are sized as for
+// lf_run_iterations (any may be NULL).
+int lf_batch_member_info(lf_batch *b, int32_t member_id, lf_run_info *out)
+{
+    if (!b || member_id < 0 || member_id >= (int32_t)b->members.size() || !b->members[member_id])
+        return LF_EINVAL;
+    BatchMember *m = b->members[member_id];
+    if (m->state == 0) return LF_EAGAIN;
+    if (m->state < 0) return m->state;
+    if (out) {
+        lf_handle *h = m->h;
+        out->iterations = m->it;
+        out->converged = m->converged;
+        out->hit_max = m->hit_max;
+        out->wtilde = h->Wt;
+        out->wcc_hat = h->cc != 0.0 ? h->Wt / h->cc : 0.0;
+        for (int i = 0; i <= m->it; i++)
+            if (out->wtilde_hist) out->wtilde_hist[i] = m->hist[i];
+        for (int i = 0; i < m->it; i++) {
+            if (out->joins) out->joins[i] = m->joins[i];
+            if (out->leaves) out->leaves[i] = m->leaves[i];
+            if (out->communities) out->communities[i] = m->comms[i];
+        }
+    }
+    return LF_OK;
+}
+
+// Take a member out of the batch (done or not); its handle goes back to its own stream.
+int lf_batch_remove(lf_batch *b, int32_t member_id)
+{
+    if (!b || member_id < 0 || member_id >= (int32_t)b->members.size() || !b->members[member_id])
+        return LF_EINVAL;
+    BatchMember *m = b->members[member_id];
+    (void)hipStreamSynchronize(b->stream);
+    m->h->stream = m->saved_stream;
+    delete m;
+    b->members[member_id] = nullptr;
+    return LF_OK;
+}
+
+int lf_batch_destroy(lf_batch *b)
+{
+    if (!b) return LF_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    for (size_t i = 0; i < b->members.size(); i++)
+        if (b->members[i]) lf_batch_remove(b, (int32_t)i);
+    for (int s = 0; s < 2; s++) {
+        if (b->hmem[s]) (void)hipHostFree(b->hmem[s]);
+        if (b->hboff[s]) (void)hipHostFree(b->hboff[s]);
+        (void)hipEventDestroy(b->hev[s]);
+    }
+    if (b->dmem) (void)hipFree(b->dmem);
+    if (b->dboff) (void)hipFree(b->dboff);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return LF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------
+// serving runtime
+// ------------------------------------------------------------------------------------
+struct Job {
+    long long id;
+    int state;               // 0 queued, 1 running, 2 done, < 0 failed (status)
+    long long n;
+    std::vector<int64_t> src, dst;
+    int q;
+    double theta;
+    int max_iters;
+    size_t footprint;
+    lf_handle *h;
+    int member;
+    std::vector<int64_t> off;
+    std::vector<int32_t> ids;
+    lf_run_info info;
+    std::vector<double> hist;
+    std::vector<long long> joins, leaves, comms;
+};
+
+struct lf_server {
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    lf_batch *batch;
+    size_t budget, used;
+    int max_batch, running;
+    std::deque<Job *> queue;
+    std::map<long long, Job *> jobs;
+    long long next_id;
+    char err[512];
+};
+
+// Device bytes a job may hold at most: graph build scratch, CSR, node arrays, membership
+// slots, community records and member lists, and the per-queue work lists.
+static size_t job_footprint(long long n, long long npairs, int q)
+{
+    long long nn = n > 0 ? n : 1;
+    long long qq = q < nn ? q : nn;
+    return (size_t)(48ll << 20) + (size_t)nn * 420 + (size_t)npairs * 64 + (size_t)qq * 256;
+}
+
+static int server_error(lf_server *s, int code, const char *msg)
+{
+    snprintf(s->err, sizeof s->err, "%s", msg);
+    return code;
+}
+
+static void job_release_device(lf_server *s, Job *j)
+{
+    if (j->member >= 0) lf_batch_remove(s->batch, j->member);
+    j->member = -1;
+    if (j->h) lf_destroy(j->h);
+    j->h = nullptr;
+    s->used -= j->footprint;
+    s->running--;
+}
+
+// load the graph and the initial clustering of a job, then add it to the batch
+static int job_start(lf_server *s, Job *j)
+{
+    int rc = lf_create(&j->h, s->device, (void *)s->stream, 0);
+    if (rc != LF_OK) return rc;
+    rc = lf_load_graph(j->h, j->n, (int64_t)j->src.size(), j->src.data(), j->dst.data(), 0);
+    if (rc == LF_OK) rc = lf_init_communities(j->h);
+    if (rc == LF_OK) rc = lf_batch_add(s->batch, j->h, j->q, j->theta, j->max_iters, &j->member);
+    std::vector<int64_t>().swap(j->src);
+    std::vector<int64_t>().swap(j->dst);
+    return rc;
+}
+
+// copy a finished job's results to host memory and release its device state
+static void job_finish(lf_server *s, Job *j)
+{
+    j->hist.assign(j->max_iters + 1, 0.0);
+    j->joins.assign(j->max_iters > 0 ? j->max_iters : 1, 0);
+    j->leaves.assign(j->joins.size(), 0);
+    j->comms.assign(j->joins.size(), 0);
+    memset(&j->info, 0, sizeof j->info);
+    j->info.wtilde_hist = j->hist.data();
+    j->info.joins = (int64_t *)j->joins.data();
+    j->info.leaves = (int64_t *)j->leaves.data();
+    j->info.communities = (int64_t *)j->comms.data();
+    int rc = lf_batch_member_info(s->batch, j->member, &j->info);
+    int64_t total = 0;
+    if (rc == LF_OK) rc = lf_get_memberships(j->h, nullptr, nullptr, 0, &total);
+    if (rc == LF_OK) {
+        j->off.resize(j->n + 1);
+        j->ids.resize(total > 0 ? total : 1);
+        rc = lf_get_memberships(j->h, j->off.data(), j->ids.data(), (int64_t)j->ids.size(), &total);
+        j->ids.resize(total);
+    }
+    j->state = rc == LF_OK ? 2 : rc;
+    job_release_device(s, j);
+}
+
+extern "C" {
+
+int lf_server_create(lf_server **out, int device, void *hip_stream, uint64_t hbm_budget, int32_t max_batch)
+{
+    if (!out || max_batch < 1 || hbm_budget == 0) return LF_EINVAL;
+    *out = nullptr;
+    if (hipSetDevice(device) != hipSuccess) return LF_EDEVICE;
+    lf_server *s = new lf_server();
+    s->device = device;
+    s->budget = hbm_budget;
+    s->used = 0;
+    s->max_batch = max_batch;
+    s->running = 0;
+    s->next_id = 0;
+    s->err[0] = 0;
+    if (hip_stream) {
+        s->stream = (hipStream_t)hip_stream;
+        s->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete s;
+            return LF_EDEVICE;
+        }
+        s->own_stream = true;
+    }
+    int rc = lf_batch_create(&s->batch, device, (void *)s->stream);
+    if (rc != LF_OK) {
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return LF_OK;
+}
+
+const char *lf_server_last_error(lf_server *s) { return s ? s->err : "null server"; }
+
+int lf_server_submit(lf_server *s, int64_t n, int64_t n_pairs, const int64_t *src, const int64_t *dst,
+                     int32_t queue_size, double threshold, int32_t max_iters, int64_t *job_id)
+{
+    if (!s || !job_id || n < 0 || n_pairs < 0 || (n_pairs > 0 && (!src || !dst)) || queue_size < 1 ||
+        !(threshold >= 0.0) || max_iters < 0)
+        return LF_EINVAL;
+    size_t fp = job_footprint(n, n_pairs, queue_size);
+    if (fp > s->budget) return server_error(s, LF_ENOMEM, "job footprint exceeds the whole device budget");
+    Job *j = new Job();
+    j->id = s->next_id++;
+    j->state = 0;
+    j->n = n;
+    j->src.assign(src, src + n_pairs);
+    j->dst.assign(dst, dst + n_pairs);
+    j->q = queue_size;
+    j->theta = threshold;
+    j->max_iters = max_iters;
+    j->footprint = fp;
+    j->h = nullptr;
+    j->member = -1;
+    s->queue.push_back(j);
+    s->jobs[j->id] = j;
+    *job_id = j->id;
+    return LF_OK;
+}
+
+// Admit queued jobs that fit, run one step of the batch, retire finished jobs.
+// *pending = jobs queued or running afterwards.
+int lf_server_tick(lf_server *s, int32_t *pending)
+{
+    if (!s) return LF_EINVAL;
+    while (!s->queue.empty() && s->running < s->max_batch) {
+        Job *j = s->queue.front();
+        if (s->used + j->footprint > s->budget) break;   // arrival order: wait for memory
+        s->queue.pop_front();
+        s->used += j->footprint;
+        s->running++;
+        j->state = 1;
+        int rc = job_start(s, j);
+        if (rc != LF_OK) {
+            j->state = rc;
+            job_release_device(s, j);
+        }
+    }
+    int32_t live = 0;
+    LF_TRY(lf_batch_step(s->batch, &live));
+    for (auto &kv : s->jobs) {
+        Job *j = kv.second;
+        if (j->state != 1) continue;
+        int rc = lf_batch_member_info(s->batch, j->member, nullptr);
+        if (rc == LF_EAGAIN) continue;
+        if (rc == LF_OK) job_finish(s, j);
+        else {
+            j->state = rc;
+            job_release_device(s, j);
+        }
+    }
+    if (pending) *pending = (int32_t)s->queue.size() + s->running;
+    return LF_OK;
+}
+
+// 0 queued, 1 running, 2 done (results waiting), < 0 failed with that status
+int lf_server_poll(lf_server *s, int64_t job_id, int32_t *state)
+{
+    if (!s || !state) return LF_EINVAL;
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end()) return LF_EINVAL;
+    *state = it->second->state;
+    return LF_OK;
+}
+
+// Results of a done job, in the two-call pattern of lf_get_memberships; info as from
+// lf_run_iterations (its arrays sized max_iters + 1 / max_iters, any may be NULL).  The job
+// is forgotten once its memberships have been copied out.
+int lf_server_fetch(lf_server *s, int64_t job_id, int64_t *offsets, int32_t *comm_ids, int64_t capacity,
+                    int64_t *total, lf_run_info *info)
+{
+    if (!s || !total) return LF_EINVAL;
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end()) return LF_EINVAL;
+    Job *j = it->second;
+    if (j->state < 0) return j->state;
+    if (j->state != 2) return LF_EAGAIN;
+    *total = (int64_t)j->ids.size();
+    if (info) {
+        info->iterations = j->info.iterations;
+        info->converged = j->info.converged;
+        info->hit_max = j->info.hit_max;
+        info->wcc_hat = j->info.wcc_hat;
+        info->wtilde = j->info.wtilde;
+        for (int i = 0; i <= j->info.iterations; i++)
+            if (info->wtilde_hist) info->wtilde_hist[i] = j->hist[i];
+        for (int i = 0; i < j->info.iterations; i++) {
+            if (info->joins) info->joins[i] = j->joins[i];
+            if (info->leaves) info->leaves[i] = j->leaves[i];
+            if (info->communities) info->communities[i] = j->comms[i];
+        }
+    }
+    if (!offsets && !comm_ids) return LF_OK;
+    if (!offsets || !comm_ids || capacity < *total) return server_error(s, LF_ERANGE, "buffers too small");
+    memcpy(offsets, j->off.data(), sizeof(int64_t) * (j->n + 1));
+    if (*total > 0) memcpy(comm_ids, j->ids.data(), sizeof(int32_t) * *total);
+    delete j;
+    s->jobs.erase(it);
+    return LF_OK;
+}
+
+int lf_server_stats(lf_server *s, uint64_t *used, uint64_t *budget, int32_t *running, int32_t *queued)
+{
+    if (!s) return LF_EINVAL;
+    if (used) *used = s->used;
+    if (budget) *budget = s->budget;
+    if (running) *running = s->running;
+    if (queued) *queued = (int32_t)s->queue.size();
+    return LF_OK;
+}
+
+int lf_server_destroy(lf_server *s)
+{
+    if (!s) return LF_OK;
+    (void)hipSetDevice(s->device);
+    for (auto &kv : s->jobs) {
+        Job *j = kv.second;
+        if (j->state == 1) job_release_device(s, j);
+        delete j;
+    }
+    lf_batch_destroy(s->batch);
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return LF_OK;
+}
+
+int lf_get_memory(lf_handle *h, uint64_t *bytes, uint64_t *peak)
+{
+    if (!h) return LF_EINVAL;
+    if (bytes) *bytes = h->dev_bytes;
+    if (peak) *peak = h->dev_bytes_peak;
+    return LF_OK;
+}
+
+}  // extern "C"

@@ -99,6 +99,40 @@ struct NodeLds {
 #define VGRP 1024       // visits of the workgroup path
 #define GT 256          // threads of the workgroup path
 
+// member owning block b of a multi-graph launch (boff: first block of each member, nm + 1
+// entries); -1 past the last member's blocks
+__device__ __forceinline__ int find_member(const int *boff, int nm, int b)
+{
+    if (b >= boff[nm]) return -1;
+    int lo = 0, hi = nm - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (boff[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// single-graph kernel K(Ctx, QStep) and multi-graph kernel K_multi over Member descriptors,
+// both running BODY(cx, qs, block, blocks, lds)
+#define QUEUE_KERNELS(K, BOUNDS, LDS_T, BODY)                                                 \
+    __global__ void __launch_bounds__(BOUNDS) K(Ctx cx, QStep qs)                             \
+    {                                                                                         \
+        __shared__ LDS_T lds;                                                                 \
+        BODY(cx, qs, (int)blockIdx.x, (int)gridDim.x, lds);                                   \
+    }                                                                                         \
+    __global__ void __launch_bounds__(BOUNDS) K##_multi(const Member *mem, const int *boff, int nm) \
+    {                                                                                         \
+        __shared__ LDS_T lds;                                                                 \
+        const int m = find_member(boff, nm, (int)blockIdx.x);                                 \
+        if (m < 0) return;                                                                    \
+        BODY(mem[m].cx, mem[m].qs, (int)blockIdx.x - boff[m], boff[m + 1] - boff[m], lds);    \
+    }
+
+struct NoLds {
+    int unused;
+};
+
 // barrier over the NT threads that evaluate one node (one wave or the whole workgroup)
 template <int NT>
 __device__ __forceinline__ void node_sync()
@@ -412,23 +446,28 @@ __device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg)
 // that does not is an internal error.
 
 // small wave path, one wave per node; block 0 also resets the queue's apply counters
-__global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, int cstart, int wcap, int ls, int ln)
+struct EvalLds {
+    NodeLds<VSMALL> w[EW];
+};
+
+__device__ __forceinline__ void body_eval(const Ctx &cx, const QStep &qs, int blk, int nblk, EvalLds &L)
 {
-    __shared__ NodeLds<VSMALL> s_l[EW];
+    (void)nblk;
     const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    const int p = blockIdx.x * EW + wv;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int p = blk * EW + wv;
+    if (blk == 0 && threadIdx.x == 0) {
         DevCounters *c = cx.ctr;
         c->tcount = 0;
         c->in_items = 0;
         c->parts_total = 0;
         c->mslots = 0;
     }
-    if (p >= ln) return;                    // no block barriers in this kernel
-    const int j = cx.plist[LF_PATH_SMALL][ls + p] - cstart;
-    if (!eval_node<WAVE, VSMALL>(cx, cstart, j, lane, s_l[wv], wcap, LF_PATH_SMALL) && lane == 0)
+    if (p >= qs.ln) return;                 // no block barriers in this kernel
+    const int j = cx.plist[LF_PATH_SMALL][qs.ls + p] - qs.cstart;
+    if (!eval_node<WAVE, VSMALL>(cx, qs.cstart, j, lane, L.w[wv], qs.wcap, LF_PATH_SMALL) && lane == 0)
         atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
 }
+QUEUE_KERNELS(k_eval, EW * WAVE, EvalLds, body_eval)
 
 // ------------------------------------------------------------------------------------
 // evaluation, table path
@@ -636,16 +675,8 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
     if (capfail) atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
 }
 
-// The larger nodes of a queue in one launch, blocks by role: [0, bt) walk the table-path
-// work items, the next bg blocks evaluate workgroup-path nodes (one node per block at a
-// time), the last bm blocks medium-path nodes (one node per wave).  All read the state
+// The larger nodes of a queue in one launch, by block role (BigRoles).  All read the state
 // at the queue's start, so the roles are independent.
-struct BigRoles {
-    int bt, bg, bm;          // blocks per role
-    int lt, nt;              // table-path list positions of the queue
-    int lg, ng;              // workgroup-path list positions
-    int lm, nm;              // medium-path list positions
-};
 
 union BigLds {
     TabLds t;
@@ -653,10 +684,12 @@ union BigLds {
     NodeLds<VMED> m[GT / WAVE];
 };
 
-__global__ void __launch_bounds__(GT) k_eval_big(Ctx cx, int cstart, int mcap, int gcap, BigRoles r)
+__device__ __forceinline__ void body_eval_big(const Ctx &cx, const QStep &qs, int blk, int nblk, BigLds &L)
 {
-    __shared__ BigLds L;
-    int b = blockIdx.x;
+    (void)nblk;
+    const BigRoles &r = qs.br;
+    const int cstart = qs.cstart;
+    int b = blk;
     if (b < r.bt) {
         table_visits(cx, cstart, r.lt, r.nt, b, r.bt, L.t);
         return;
@@ -665,7 +698,7 @@ __global__ void __launch_bounds__(GT) k_eval_big(Ctx cx, int cstart, int mcap, i
     if (b < r.bg) {
         for (int p = b; p < r.ng; p += r.bg) {
             const int j = cx.plist[LF_PATH_GROUP][r.lg + p] - cstart;
-            if (!eval_node<GT, VGRP>(cx, cstart, j, threadIdx.x, L.g, gcap, LF_PATH_GROUP) && threadIdx.x == 0)
+            if (!eval_node<GT, VGRP>(cx, cstart, j, threadIdx.x, L.g, qs.gcap, LF_PATH_GROUP) && threadIdx.x == 0)
                 atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
             __syncthreads();                // the next node reuses the LDS
         }
@@ -675,20 +708,22 @@ __global__ void __launch_bounds__(GT) k_eval_big(Ctx cx, int cstart, int mcap, i
     const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     for (int p = b * (GT / WAVE) + wv; p < r.nm; p += r.bm * (GT / WAVE)) {   // no block barriers
         const int j = cx.plist[LF_PATH_MED][r.lm + p] - cstart;
-        if (!eval_node<WAVE, VMED>(cx, cstart, j, lane, L.m[wv], mcap, LF_PATH_MED) && lane == 0)
+        if (!eval_node<WAVE, VMED>(cx, cstart, j, lane, L.m[wv], qs.mcap, LF_PATH_MED) && lane == 0)
             atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
     }
 }
+QUEUE_KERNELS(k_eval_big, GT, BigLds, body_eval_big)
 
-__global__ void __launch_bounds__(256) k_big_final(Ctx cx, int cstart, int clen)
+__device__ __forceinline__ void body_big_final(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
 {
+    const int cstart = qs.cstart, clen = qs.clen;
     int count = __atomic_load_n(&cx.ctr->occ_cnt, __ATOMIC_RELAXED);
     int bad = 0;
     unsigned long long ncand = 0;
-    long long stride = (long long)gridDim.x * blockDim.x;
+    long long stride = (long long)nblk * blockDim.x;
     // every lane of a wave runs the same number of trips (invalid lanes idle), so the
     // per-wave reduction below sees all 64 lanes
-    for (long long base = blockIdx.x * (long long)blockDim.x; base < count; base += stride) {
+    for (long long base = blk * (long long)blockDim.x; base < count; base += stride) {
         long long e = base + threadIdx.x;
         bool valid = e < count;
         long long h = valid ? cx.occ[e] : 0;
@@ -760,11 +795,14 @@ __global__ void __launch_bounds__(256) k_big_final(Ctx cx, int cstart, int clen)
     if (bad) atomicOr(&cx.ctr->error, LF_DEVERR_INEXACT);
 }
 
-__global__ void __launch_bounds__(256) k_big_tie(Ctx cx)
+QUEUE_KERNELS(k_big_final, 256, NoLds, body_big_final)
+
+__device__ __forceinline__ void body_big_tie(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
 {
+    (void)qs;
     int count = __atomic_load_n(&cx.ctr->occ_cnt, __ATOMIC_RELAXED);
-    long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count; e += stride) {
+    long long stride = (long long)nblk * blockDim.x;
+    for (long long e = blk * (long long)blockDim.x + threadIdx.x; e < count; e += stride) {
         double dlt = cx.occ_d[e];
         if (!(dlt > 0.0)) continue;
         unsigned long long key = cx.occ_key[e];
@@ -774,6 +812,7 @@ __global__ void __launch_bounds__(256) k_big_tie(Ctx cx)
         if ((unsigned long long)__double_as_longlong(dlt) == best) atomicMin(leave ? &cx.big_cl[b] : &cx.big_cj[b], C);
     }
 }
+QUEUE_KERNELS(k_big_tie, 256, NoLds, body_big_tie)
 
 // ------------------------------------------------------------------------------------
 // bulk apply
@@ -793,9 +832,11 @@ __device__ __forceinline__ int joined_in_queue(const Ctx &cx, int x)
     return (unsigned)(v >> 32) == cx.qtag ? (int)(unsigned)v : -1;
 }
 
-__global__ void k_apply_edit(Ctx cx, int cstart, int clen)
+__device__ __forceinline__ void body_apply_edit(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    (void)nblk;
+    const int cstart = qs.cstart, clen = qs.clen;
+    int j = blk * blockDim.x + threadIdx.x;
     int lane = threadIdx.x & (WAVE - 1);
     if (j == 0) cx.ctr->occ_cnt = 0;        // the table path of this queue is done
 
@@ -871,6 +912,7 @@ __global__ void k_apply_edit(Ctx cx, int cstart, int clen)
         }
     }
 }
+QUEUE_KERNELS(k_apply_edit, 256, NoLds, body_apply_edit)
 
 // in-counts: a surviving member y of J (L) gains (loses) one per neighbour that joined
 // (left); a node that joined J in this queue gets its in-count counted afresh.  One wave
@@ -879,17 +921,18 @@ __device__ void refresh_plan(const Ctx &cx, int t);
 
 // Blocks [0, plan_blocks) split the touched communities into re-sum parts (one thread
 // each); the other blocks apply the in-count changes.  Both only need the edits.
-__global__ void __launch_bounds__(256) k_apply_in(Ctx cx, int cstart, int clen, int plan_blocks)
+__device__ __forceinline__ void body_apply_in(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
 {
-    if ((int)blockIdx.x < plan_blocks) {
-        refresh_plan(cx, blockIdx.x * blockDim.x + threadIdx.x);
+    const int cstart = qs.cstart, clen = qs.clen, plan_blocks = qs.plan_blocks;
+    if (blk < plan_blocks) {
+        refresh_plan(cx, blk * blockDim.x + threadIdx.x);
         return;
     }
     int count = __atomic_load_n(&cx.ctr->in_items, __ATOMIC_RELAXED);
     if (count > cx.in_cap) count = cx.in_cap;
     int lane = threadIdx.x & (WAVE - 1);
-    long long nw = (long long)(gridDim.x - plan_blocks) * (blockDim.x / WAVE);
-    for (long long p = ((blockIdx.x - plan_blocks) * (long long)blockDim.x + threadIdx.x) / WAVE; p < count;
+    long long nw = (long long)(nblk - plan_blocks) * (blockDim.x / WAVE);
+    for (long long p = ((blk - plan_blocks) * (long long)blockDim.x + threadIdx.x) / WAVE; p < count;
          p += nw) {
         int j = cx.in_item[p];
         if (j < 0 || j >= clen) continue;          // only after a flagged overflow
@@ -923,6 +966,7 @@ __global__ void __launch_bounds__(256) k_apply_in(Ctx cx, int cstart, int clen, 
         }
     }
 }
+QUEUE_KERNELS(k_apply_in, 256, NoLds, body_apply_in)
 
 // ------------------------------------------------------------------------------------
 // exact re-sum of the touched communities
@@ -991,14 +1035,15 @@ __device__ __forceinline__ X192 x192_from_digits6(const long long *D)
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_refresh(Ctx cx)
+__device__ __forceinline__ void body_refresh(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
 {
+    (void)qs;
     int count = __atomic_load_n(&cx.ctr->parts_total, __ATOMIC_RELAXED);
     if (count > cx.part_cap) count = cx.part_cap;
     int lane = threadIdx.x & (WAVE - 1);
-    long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
+    long long nw = (long long)nblk * (blockDim.x / WAVE);
     int bad = 0;
-    for (long long p = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE; p < count; p += nw) {
+    for (long long p = (blk * (long long)blockDim.x + threadIdx.x) / WAVE; p < count; p += nw) {
         int C = cx.part_comm[p];
         if (C < 0 || C >= cx.K) continue;          // only after a flagged overflow
         int k = (int)p - cx.part_base[C];
@@ -1049,6 +1094,7 @@ __global__ void __launch_bounds__(256) k_refresh(Ctx cx)
     }
     if (bad) atomicOr(&cx.ctr->error, LF_DEVERR_INEXACT);
 }
+QUEUE_KERNELS(k_refresh, 256, NoLds, body_refresh)
 
 // ------------------------------------------------------------------------------------
 // per-iteration sizing of the queue buffers
@@ -1337,10 +1383,135 @@ static int size_queue_buffers(lf_handle *h, long long q)
     return LF_OK;
 }
 
-int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out)
+// Start of an iteration: buffers and path lists for queues of qq nodes, counters reset.
+int lf_iter_begin(lf_handle *h, long long qq, long long *nq)
+{
+    LF_TRY(size_queue_buffers(h, qq));
+    *nq = (h->n + qq - 1) / qq;
+    LF_HIP(h, hipMemsetAsync(&h->ctr->joins, 0, sizeof(unsigned long long) * 2, h->stream));
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, h->stream, lf_ctx(h));
+    return LF_OK;
+}
+
+// Parameters and grids of queue k (of nq).  compact_grids sizes the grid-stride kernels by
+// the queue instead of by the whole device (for many graphs sharing one launch).
+void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool compact_grids, QStep *qs,
+                     QGrids *g)
+{
+    const long long *qo = h->hqoff;                                // [path][nq + 1]
+    const long long *hit = h->hqoff + LF_PATH_COUNT * (nq + 1);   // first table item per queue
+    const long long start = k * qq;
+    const int clen = (int)((h->n - start) < qq ? (h->n - start) : qq);
+    int ls[LF_PATH_COUNT], ln[LF_PATH_COUNT];
+    for (int c = 0; c < LF_PATH_COUNT; c++) {
+        ls[c] = (int)qo[c * (nq + 1) + k];
+        ln[c] = (int)(qo[c * (nq + 1) + k + 1] - ls[c]);
+    }
+    const int gb = h->hub_blocks;
+    int rbk = h->refresh_blocks;
+    if (compact_grids) {
+        int want = (int)grid_for(clen, 8);
+        if (want < rbk) rbk = want;
+    }
+    qs->cstart = (int)start;
+    qs->clen = clen;
+    qs->wcap = h->eval_wave_cap < 2 * VSMALL ? h->eval_wave_cap : 2 * VSMALL;
+    qs->mcap = h->eval_med_cap;
+    qs->gcap = h->eval_grp_cap;
+    qs->ls = ls[LF_PATH_SMALL];
+    qs->ln = ln[LF_PATH_SMALL];
+    BigRoles &br = qs->br;
+    const long long titems = hit[k + 1] - hit[k];
+    br.bt = ln[LF_PATH_TABLE] > 0 ? (int)grid_for(titems, 2 * EWB * WAVE) : 0;
+    if (br.bt > gb) br.bt = gb;
+    br.bg = ln[LF_PATH_GROUP] < gb ? ln[LF_PATH_GROUP] : gb;
+    br.bm = (int)grid_for(ln[LF_PATH_MED], GT / WAVE);
+    br.lt = ls[LF_PATH_TABLE];
+    br.nt = ln[LF_PATH_TABLE];
+    br.lg = ls[LF_PATH_GROUP];
+    br.ng = ln[LF_PATH_GROUP];
+    br.lm = ls[LF_PATH_MED];
+    br.nm = ln[LF_PATH_MED];
+    qs->plan_blocks = (int)grid_for(2ll * clen, 256);
+    g->eval = ln[LF_PATH_SMALL] > 0 ? (int)grid_for(ln[LF_PATH_SMALL], EW) : 1;
+    g->big = br.bt + br.bg + br.bm;
+    g->fin = ln[LF_PATH_TABLE] > 0 ? (compact_grids ? (br.bt > 0 ? br.bt : 1) : gb) : 0;
+    g->apply_edit = (int)grid_for(clen, 256);
+    g->apply_in = qs->plan_blocks + rbk;
+    g->refresh = rbk;
+}
+
+// the kernels of one queue of one graph, in order, on the handle's stream
+int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g)
 {
     hipStream_t st = h->stream;
-    const int BS = 256;
+    cx.qtag = h->qtag++;
+    LF_TRY(lf_prof_begin(h, LF_K_EVAL));
+    hipLaunchKernelGGL(k_eval, dim3(g.eval), dim3(EW * WAVE), 0, st, cx, qs);
+    LF_TRY(lf_prof_end(h, LF_K_EVAL, 1));
+    if (g.big > 0) {
+        LF_TRY(lf_prof_begin(h, LF_K_EVAL_BIG));
+        hipLaunchKernelGGL(k_eval_big, dim3(g.big), dim3(GT), 0, st, cx, qs);
+        LF_TRY(lf_prof_end(h, LF_K_EVAL_BIG, 1));
+    }
+    if (g.fin > 0) {
+        LF_TRY(lf_prof_begin(h, LF_K_TAB_FINAL));
+        hipLaunchKernelGGL(k_big_final, dim3(g.fin), dim3(256), 0, st, cx, qs);
+        LF_TRY(lf_prof_end(h, LF_K_TAB_FINAL, 1));
+        LF_TRY(lf_prof_begin(h, LF_K_TAB_TIE));
+        hipLaunchKernelGGL(k_big_tie, dim3(g.fin), dim3(256), 0, st, cx, qs);
+        LF_TRY(lf_prof_end(h, LF_K_TAB_TIE, 1));
+    }
+    LF_TRY(lf_prof_begin(h, LF_K_APPLY_EDIT));
+    hipLaunchKernelGGL(k_apply_edit, dim3(g.apply_edit), dim3(256), 0, st, cx, qs);
+    LF_TRY(lf_prof_end(h, LF_K_APPLY_EDIT, 1));
+    LF_TRY(lf_prof_begin(h, LF_K_APPLY_IN));
+    hipLaunchKernelGGL(k_apply_in, dim3(g.apply_in), dim3(256), 0, st, cx, qs);
+    LF_TRY(lf_prof_end(h, LF_K_APPLY_IN, 1));
+    LF_TRY(lf_prof_begin(h, LF_K_REFRESH));
+    hipLaunchKernelGGL(k_refresh, dim3(g.refresh), dim3(256), 0, st, cx, qs);
+    LF_TRY(lf_prof_end(h, LF_K_REFRESH, 1));
+    h->prof.chunks++;
+    h->prof.node_evals += qs.clen;
+    return LF_OK;
+}
+
+// One queue of each of nm graphs: six launches (the table-path finalisation counts as
+// one grid), each block finding its graph from dboff (6 arrays of nm + 1 first-block
+// offsets, one per kernel, in launch order); total[i] = blocks of launch i.
+int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int nm, const int *total)
+{
+    const int *o = dboff;
+    if (total[0] > 0) hipLaunchKernelGGL(k_eval_multi, dim3(total[0]), dim3(EW * WAVE), 0, st, dmem, o, nm);
+    o += nm + 1;
+    if (total[1] > 0) hipLaunchKernelGGL(k_eval_big_multi, dim3(total[1]), dim3(GT), 0, st, dmem, o, nm);
+    o += nm + 1;
+    if (total[2] > 0) {
+        hipLaunchKernelGGL(k_big_final_multi, dim3(total[2]), dim3(256), 0, st, dmem, o, nm);
+        hipLaunchKernelGGL(k_big_tie_multi, dim3(total[2]), dim3(256), 0, st, dmem, o, nm);
+    }
+    o += nm + 1;
+    if (total[3] > 0) hipLaunchKernelGGL(k_apply_edit_multi, dim3(total[3]), dim3(256), 0, st, dmem, o, nm);
+    o += nm + 1;
+    if (total[4] > 0) hipLaunchKernelGGL(k_apply_in_multi, dim3(total[4]), dim3(256), 0, st, dmem, o, nm);
+    o += nm + 1;
+    if (total[5] > 0) hipLaunchKernelGGL(k_refresh_multi, dim3(total[5]), dim3(256), 0, st, dmem, o, nm);
+    return hipGetLastError() == hipSuccess ? LF_OK : LF_EDEVICE;
+}
+
+// End of an iteration: counters reset, degenerate communities removed, exact score.
+int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long *live)
+{
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, h->stream, lf_ctx(h));
+    LF_HIP(h, hipGetLastError());
+    LF_TRY(lf_prof_begin(h, LF_K_ITEREND));
+    LF_TRY(lf_iteration_end(h, joins, leaves, live));
+    LF_TRY(lf_prof_end(h, LF_K_ITEREND, 8));
+    return lf_check_dev_error(h);
+}
+
+int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out)
+{
     long long n = h->n;
     lf_run_info dummy;
     memset(&dummy, 0, sizeof dummy);
@@ -1358,74 +1529,17 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
     long long qq = q < n ? q : (n > 0 ? n : 1);
     double prev = h->Wt;
     for (int it = 0; it < max_iters; it++) {
-        LF_TRY(size_queue_buffers(h, qq));
-        const long long nq = (n + qq - 1) / qq;
-        const long long *qo = h->hqoff;     // [path][nq + 1]
-        const long long *hit = h->hqoff + LF_PATH_COUNT * (nq + 1);   // first table item per queue
-        LF_HIP(h, hipMemsetAsync(&h->ctr->joins, 0, sizeof(unsigned long long) * 2, st));
+        long long nq = 0;
+        LF_TRY(lf_iter_begin(h, qq, &nq));
         Ctx cx = lf_ctx(h);
-        hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, st, cx);
-        int gb = h->hub_blocks, rbk = h->refresh_blocks;
         for (long long k = 0; k < nq; k++) {
-            const long long start = k * qq;
-            int clen = (int)((n - start) < qq ? (n - start) : qq);
-            int cstart = (int)start;
-            int ls[LF_PATH_COUNT], ln[LF_PATH_COUNT];
-            for (int c = 0; c < LF_PATH_COUNT; c++) {
-                ls[c] = (int)qo[c * (nq + 1) + k];
-                ln[c] = (int)(qo[c * (nq + 1) + k + 1] - ls[c]);
-            }
-            LF_TRY(lf_prof_begin(h, LF_K_EVAL));
-            cx.qtag = h->qtag++;
-            hipLaunchKernelGGL(k_eval, dim3(ln[0] > 0 ? grid_for(ln[0], EW) : 1), dim3(EW * WAVE), 0, st, cx,
-                               cstart, h->eval_wave_cap < 2 * VSMALL ? h->eval_wave_cap : 2 * VSMALL, ls[0], ln[0]);
-            LF_TRY(lf_prof_end(h, LF_K_EVAL, 1));
-            BigRoles br;
-            const long long titems = hit[k + 1] - hit[k];
-            br.bt = ln[LF_PATH_TABLE] > 0 ? (int)grid_for(titems, 2 * EWB * WAVE) : 0;
-            if (br.bt > gb) br.bt = gb;
-            br.bg = ln[LF_PATH_GROUP] < gb ? ln[LF_PATH_GROUP] : gb;
-            br.bm = (int)grid_for(ln[LF_PATH_MED], GT / WAVE);
-            br.lt = ls[LF_PATH_TABLE];
-            br.nt = ln[LF_PATH_TABLE];
-            br.lg = ls[LF_PATH_GROUP];
-            br.ng = ln[LF_PATH_GROUP];
-            br.lm = ls[LF_PATH_MED];
-            br.nm = ln[LF_PATH_MED];
-            if (br.bt + br.bg + br.bm > 0) {
-                LF_TRY(lf_prof_begin(h, LF_K_EVAL_BIG));
-                hipLaunchKernelGGL(k_eval_big, dim3(br.bt + br.bg + br.bm), dim3(GT), 0, st, cx, cstart,
-                                   h->eval_med_cap, h->eval_grp_cap, br);
-                LF_TRY(lf_prof_end(h, LF_K_EVAL_BIG, 1));
-            }
-            if (ln[LF_PATH_TABLE] > 0) {
-                LF_TRY(lf_prof_begin(h, LF_K_TAB_FINAL));
-                hipLaunchKernelGGL(k_big_final, dim3(gb), dim3(BS), 0, st, cx, cstart, clen);
-                LF_TRY(lf_prof_end(h, LF_K_TAB_FINAL, 1));
-                LF_TRY(lf_prof_begin(h, LF_K_TAB_TIE));
-                hipLaunchKernelGGL(k_big_tie, dim3(gb), dim3(BS), 0, st, cx);
-                LF_TRY(lf_prof_end(h, LF_K_TAB_TIE, 1));
-            }
-            LF_TRY(lf_prof_begin(h, LF_K_APPLY_EDIT));
-            hipLaunchKernelGGL(k_apply_edit, dim3(grid_for(clen, BS)), dim3(BS), 0, st, cx, cstart, clen);
-            LF_TRY(lf_prof_end(h, LF_K_APPLY_EDIT, 1));
-            int pb = (int)grid_for(2ll * clen, BS);
-            LF_TRY(lf_prof_begin(h, LF_K_APPLY_IN));
-            hipLaunchKernelGGL(k_apply_in, dim3(pb + rbk), dim3(BS), 0, st, cx, cstart, clen, pb);
-            LF_TRY(lf_prof_end(h, LF_K_APPLY_IN, 1));
-            LF_TRY(lf_prof_begin(h, LF_K_REFRESH));
-            hipLaunchKernelGGL(k_refresh, dim3(rbk), dim3(BS), 0, st, cx);
-            LF_TRY(lf_prof_end(h, LF_K_REFRESH, 1));
-            h->prof.chunks++;
-            h->prof.node_evals += clen;
+            QStep qs;
+            QGrids g;
+            lf_queue_params(h, k, nq, qq, false, &qs, &g);
+            LF_TRY(lf_launch_queue(h, cx, qs, g));
         }
-        hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, st, cx);
-        LF_HIP(h, hipGetLastError());
-        LF_TRY(lf_prof_begin(h, LF_K_ITEREND));
         long long joins = 0, leaves = 0, live = 0;
-        LF_TRY(lf_iteration_end(h, &joins, &leaves, &live));
-        LF_TRY(lf_prof_end(h, LF_K_ITEREND, 8));
-        LF_TRY(lf_check_dev_error(h));
+        LF_TRY(lf_iter_finish(h, &joins, &leaves, &live));
         out->iterations = it + 1;
         if (out->wtilde_hist) out->wtilde_hist[it + 1] = h->Wt;
         if (out->joins) out->joins[it] = joins;

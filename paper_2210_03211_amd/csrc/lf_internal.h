@@ -134,6 +134,36 @@ struct Ctx {
     int stats;               // collect the per-path work counters
 };
 
+// Block roles of k_eval_big: [0, bt) walk the table-path work items, the next bg blocks
+// evaluate workgroup-path nodes (one node per block at a time), the last bm blocks
+// medium-path nodes (one node per wave).
+struct BigRoles {
+    int bt, bg, bm;          // blocks per role
+    int lt, nt;              // table-path list positions of the queue
+    int lg, ng;              // workgroup-path list positions
+    int lm, nm;              // medium-path list positions
+};
+
+// Everything the kernels of one queue need besides the graph's Ctx.
+struct QStep {
+    int cstart, clen;        // the queue: order positions [cstart, cstart + clen)
+    int wcap, mcap, gcap;    // LDS table sizes of the small, medium and workgroup paths
+    int ls, ln;              // small-path list positions
+    BigRoles br;
+    int plan_blocks;         // re-sum planning blocks of k_apply_in
+};
+
+// One graph's queue in a multi-graph launch.
+struct Member {
+    Ctx cx;
+    QStep qs;
+};
+
+// launch grids of one queue's kernels (0 = not launched)
+struct QGrids {
+    int eval, big, fin, apply_edit, apply_in, refresh;
+};
+
 struct lf_handle {
     int device;
     hipStream_t stream;
@@ -219,6 +249,8 @@ struct lf_handle {
     int evused;                        // pairs recorded and not yet folded into prof
     // allocation registry
     std::vector<void *> *allocs;
+    std::vector<size_t> *alloc_sizes;
+    size_t dev_bytes, dev_bytes_peak;   // device memory the handle holds (now / at most)
 };
 
 // ---- host helpers --------------------------------------------------------------------
@@ -271,6 +303,14 @@ int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out);
 // ---- community stages (communities.hip) ----------------------------------------------------
 int lf_initial_clustering(lf_handle *h);
 int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out);
+// one LazyFox iteration split into its host steps (shared by lf_run_iterations and the
+// multi-graph batch): sizing and path lists, per-queue parameters, and the iteration end
+int lf_iter_begin(lf_handle *h, long long qq, long long *nq);
+void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool compact_grids, QStep *qs,
+                     QGrids *g);
+int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g);
+int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int nm, const int *total);
+int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long *live);
 int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
                      long long *live);
 int lf_check_dev_error(lf_handle *h);

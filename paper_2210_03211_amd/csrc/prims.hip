@@ -28,6 +28,9 @@ int lf_dev_alloc(lf_handle *h, void **p, size_t bytes)
         return lf_set_error(h, LF_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
     h->allocs->push_back(*p);
+    h->alloc_sizes->push_back(bytes);
+    h->dev_bytes += bytes;
+    if (h->dev_bytes > h->dev_bytes_peak) h->dev_bytes_peak = h->dev_bytes;
     return LF_OK;
 }
 
@@ -36,8 +39,11 @@ void lf_dev_free(lf_handle *h, void *p)
     if (!p) return;
     for (size_t k = 0; k < h->allocs->size(); k++)
         if ((*h->allocs)[k] == p) {
+            h->dev_bytes -= (*h->alloc_sizes)[k];
             (*h->allocs)[k] = h->allocs->back();
+            (*h->alloc_sizes)[k] = h->alloc_sizes->back();
             h->allocs->pop_back();
+            h->alloc_sizes->pop_back();
             break;
         }
     (void)hipFree(p);
