@@ -47,6 +47,11 @@ def parse():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (for HBM counter scaling)")
     ap.add_argument("--sweep", default="", help="comma-separated queue sizes: extra untimed-line runs")
+    ap.add_argument("--serving-jobs", type=int, default=300,
+                    help="jobs of the serving comparison (0 = skip it)")
+    ap.add_argument("--serving-rate", type=float, default=200.0, help="Poisson arrival rate (jobs/s)")
+    ap.add_argument("--serving-max-batch", type=int, default=256)
+    ap.add_argument("--serving-budget-gib", type=float, default=64.0)
     return ap.parse_args()
 
 
@@ -122,6 +127,86 @@ def cpu_baseline(args, wl):
             "sample": "same generator at %.0f%% scale (%d nodes, %d edges), queue %d, whole path "
                       "(build, triangles, order, init, %d iterations) in %.1f s"
                       % (100 * args.cpu_sample_scale, o.n, o.nedges, q, info["iterations"], dt)}
+
+
+def serving_bench(args, lf):
+    """The serving mix (Poisson arrivals, graphs of uneven size) served two ways on the
+    same GPU and trace: the server with continuous batching, and plain one-at-a-time runs
+    in arrival order.  Latency = completion - arrival.  Every job's memberships must be
+    the same both ways."""
+    import numpy as np
+    import graphgen
+    t0 = time.perf_counter()
+    jobs = graphgen.serving_mix(n_jobs=args.serving_jobs, rate=args.serving_rate, seed=args.seed)
+    graphs = [graphgen.serving_job_graph(j) for j in jobs]
+    print("[bench] serving mix: %d jobs, %d nodes in all, generated in %.1fs"
+          % (len(jobs), sum(g.n for g in graphs), time.perf_counter() - t0), file=sys.stderr, flush=True)
+
+    def digest(off, ids):
+        return hashlib.sha256(off.tobytes() + ids.tobytes()).hexdigest()
+
+    # continuous batching through the server
+    srv = lf.Server(0, hbm_budget=int(args.serving_budget_gib * (1 << 30)), max_batch=args.serving_max_batch)
+    lat_b, hashes_b, evals_b = {}, {}, 0
+    jid_of = {}
+    nxt = 0
+    start = time.perf_counter()
+    while len(lat_b) < len(jobs):
+        now = time.perf_counter() - start
+        while nxt < len(jobs) and jobs[nxt]["arrival"] <= now:
+            g = graphs[nxt]
+            jid_of[srv.submit(g.n, g.src, g.dst, jobs[nxt]["queue"], args.threshold, args.max_iters)] = nxt
+            nxt += 1
+        if not jid_of:
+            time.sleep(max(0.0, min(0.001, jobs[nxt]["arrival"] - now)))
+            continue
+        srv.tick()
+        for jid in list(jid_of):
+            r = srv.fetch(jid)
+            if r is not None:
+                k = jid_of.pop(jid)
+                lat_b[k] = time.perf_counter() - start - jobs[k]["arrival"]
+                hashes_b[k] = digest(r[0], r[1])
+                evals_b += graphs[k].n * r[2]["iterations"]
+    span_b = time.perf_counter() - start
+    server_ms = srv.timing()
+    srv.close()
+    # plain: one job at a time, in arrival order, each alone on the device
+    import torch
+    lat_p, evals_p, same = {}, 0, 0
+    start = time.perf_counter()
+    for k, (j, g) in enumerate(zip(jobs, graphs)):
+        now = time.perf_counter() - start
+        if now < j["arrival"]:
+            time.sleep(j["arrival"] - now)
+        h = lf.Handle(0)
+        h.load_graph(g.n, g.src, g.dst).init_communities()
+        info = h.run_iterations(j["queue"], args.threshold, args.max_iters)
+        off, ids = h.get_memberships()
+        h.close()
+        lat_p[k] = time.perf_counter() - start - j["arrival"]
+        evals_p += g.n * info["iterations"]
+        same += digest(off, ids) == hashes_b[k]
+    torch.cuda.synchronize()
+    span_p = time.perf_counter() - start
+    if same != len(jobs):
+        print("[bench] ERROR: %d of %d served results differ from the plain runs" % (len(jobs) - same, len(jobs)),
+              file=sys.stderr)
+        sys.exit(1)
+
+    def pct(d, p):
+        return 1000.0 * float(np.percentile(np.array(list(d.values())), p))
+    out = {"jobs": len(jobs), "rate_per_s": args.serving_rate,
+           "workload": "serving mix: Poisson arrivals, planted power-law graphs, nodes lognormal(median 2,000, "
+                       "sigma 1.2) in [50, 200,000], mean degree 8-40, mixing 0.2-0.4, per-job queue",
+           "batched": {"p50_ms": pct(lat_b, 50), "p99_ms": pct(lat_b, 99), "jobs_per_s": len(jobs) / span_b,
+                       "node_evals_per_s": evals_b / span_b, "makespan_s": span_b,
+                       "server_host_ms": {k: round(v, 1) for k, v in server_ms.items()}},
+           "plain": {"p50_ms": pct(lat_p, 50), "p99_ms": pct(lat_p, 99), "jobs_per_s": len(jobs) / span_p,
+                     "node_evals_per_s": evals_p / span_p, "makespan_s": span_p},
+           "results_equal": True}
+    print("[bench] serving: %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -245,6 +330,8 @@ def main():
                               "node_evals_per_s": n * si["iterations"] / s, "wcc_hat": si["wcc_hat"]}
             print("[bench] sweep q=%d: %.3fs %d iterations" % (qq, s, si["iterations"]), file=sys.stderr, flush=True)
         out["queue_sweep"] = sweep
+    if args.serving_jobs > 0:
+        out["serving"] = serving_bench(args, lf)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, wl)

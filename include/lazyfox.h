@@ -256,7 +256,8 @@ const char *lf_batch_last_error(lf_batch *b);
  * lf_server_tick admits queued jobs in arrival order while their estimated footprints fit
  * the budget and fewer than max_batch jobs run (load, initial clustering, join the
  * batch), runs one batch step, and retires finished jobs: memberships and run info are
- * copied to host memory and the job's device memory is released, so jobs that arrived
+ * copied to host memory and the job's device memory is released (retired jobs' memory is
+ * freed for many at once, at the latest when a queued job needs it), so jobs that arrived
  * meanwhile are admitted as memory frees up.  *pending = jobs queued or running.
  * lf_server_poll: *state = 0 queued, 1 running, 2 done, < 0 failed with that status.
  * lf_server_fetch: results of a done job, two-call pattern as lf_get_memberships
@@ -275,6 +276,10 @@ int lf_server_fetch(lf_server *s, int64_t job_id, int64_t *offsets, int32_t *com
 int lf_server_stats(lf_server *s, uint64_t *used, uint64_t *budget, int32_t *running, int32_t *queued);
 int lf_server_destroy(lf_server *s);
 const char *lf_server_last_error(lf_server *s);
+/* Host milliseconds spent so far in ms[0..4]: admission (graph load and initial
+   clustering, on a stream of its own), batch steps, retirement (results copied back),
+   freeing device memory of retired jobs (done for many at once), whole ticks. */
+int lf_server_timing(lf_server *s, double *ms);
 
 #ifdef __cplusplus
 }

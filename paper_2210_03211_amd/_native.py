@@ -91,6 +91,7 @@ def load_library():
         "lf_server_fetch": [vp, i64, vp, vp, i64, C.POINTER(i64), C.POINTER(RunInfo)],
         "lf_server_stats": [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(i32), C.POINTER(i32)],
         "lf_server_destroy": [vp],
+        "lf_server_timing": [vp, C.POINTER(C.c_double)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -495,6 +496,13 @@ class Server:
         return dict(used=used.value, budget=budget.value, running=running.value, queued=queued.value)
 
     stats = lf_server_stats
+
+    def lf_server_timing(self):
+        ms = (C.c_double * 5)()
+        self._check(self.L.lf_server_timing(self.s, ms), "lf_server_timing")
+        return dict(zip(("admit_ms", "step_ms", "retire_ms", "free_ms", "tick_ms"), list(ms)))
+
+    timing = lf_server_timing
 
     def lf_server_destroy(self):
         if self.s:

@@ -15,6 +15,7 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     if (!h) return LF_ENOMEM;
     h->allocs = new std::vector<void *>();
     h->alloc_sizes = new std::vector<size_t>();
+    h->tmp_chunks = new std::vector<TmpChunk>();
     h->evpool = new std::vector<hipEvent_t>();
     h->evkind = new std::vector<int>();
     h->evlaunch = new std::vector<int>();
@@ -23,12 +24,14 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         delete h->allocs;
         delete h->alloc_sizes;
+        delete h->tmp_chunks;
         free(h);
         return LF_EDEVICE;
     }
     if (hipSetDevice(device) != hipSuccess) {
         delete h->allocs;
         delete h->alloc_sizes;
+        delete h->tmp_chunks;
         free(h);
         return LF_EDEVICE;
     }
@@ -47,6 +50,7 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
         if (h->own_stream) (void)hipStreamDestroy(h->stream);
         delete h->allocs;
         delete h->alloc_sizes;
+        delete h->tmp_chunks;
         free(h);
         return LF_EDEVICE;
     }
@@ -70,6 +74,7 @@ int lf_destroy(lf_handle *h)
     for (void *p : *h->allocs) (void)hipFree(p);
     delete h->allocs;
     delete h->alloc_sizes;
+    delete h->tmp_chunks;
     for (hipEvent_t e : *h->evpool) (void)hipEventDestroy(e);
     delete h->evpool;
     delete h->evkind;

@@ -14,6 +14,7 @@
 // arrival order while their estimated device footprint fits the budget, steps the batch,
 // and retires finished jobs (memberships copied back, device memory released), so jobs
 // that arrive while others run join as memory frees up.
+#include <chrono>
 #include <deque>
 #include <map>
 #include <stdlib.h>
@@ -324,16 +325,40 @@ struct Job {
 
 struct lf_server {
     int device;
-    hipStream_t stream;
+    hipStream_t stream;      // the batch's work
+    hipStream_t admit;       // loading and initial clustering of admitted jobs
     bool own_stream;
     lf_batch *batch;
     size_t budget, used;
     int max_batch, running;
     std::deque<Job *> queue;
     std::map<long long, Job *> jobs;
+    std::vector<std::pair<lf_handle *, size_t>> retired;   // handles whose memory is not yet freed
     long long next_id;
+    double ms[5];            // host time: admission, batch steps, retirement, freeing, ticks
+    std::chrono::steady_clock::time_point last_free;
     char err[512];
 };
+
+static double ms_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// free the device memory of retired jobs (hipFree synchronises the device, so this is
+// done for many handles at once)
+static void server_free_retired(lf_server *s)
+{
+    if (s->retired.empty()) return;
+    auto t0 = std::chrono::steady_clock::now();
+    for (auto &r : s->retired) {
+        lf_destroy(r.first);
+        s->used -= r.second;
+    }
+    s->retired.clear();
+    s->last_free = std::chrono::steady_clock::now();
+    s->ms[3] += ms_since(t0);
+}
 
 // Device bytes a job may hold at most: graph build scratch, CSR, node arrays, membership
 // slots, community records and member lists, and the per-queue work lists.
@@ -350,20 +375,22 @@ static int server_error(lf_server *s, int code, const char *msg)
     return code;
 }
 
+// the job leaves the batch; its handle is destroyed later with others (its footprint
+// stays reserved until then)
 static void job_release_device(lf_server *s, Job *j)
 {
     if (j->member >= 0) lf_batch_remove(s->batch, j->member);
     j->member = -1;
-    if (j->h) lf_destroy(j->h);
+    if (j->h) s->retired.push_back({j->h, j->footprint});
+    else s->used -= j->footprint;
     j->h = nullptr;
-    s->used -= j->footprint;
     s->running--;
 }
 
 // load the graph and the initial clustering of a job, then add it to the batch
 static int job_start(lf_server *s, Job *j)
 {
-    int rc = lf_create(&j->h, s->device, (void *)s->stream, 0);
+    int rc = lf_create(&j->h, s->device, (void *)s->admit, 0);
     if (rc != LF_OK) return rc;
     rc = lf_load_graph(j->h, j->n, (int64_t)j->src.size(), j->src.data(), j->dst.data(), 0);
     if (rc == LF_OK) rc = lf_init_communities(j->h);
@@ -413,11 +440,18 @@ int lf_server_create(lf_server **out, int device, void *hip_stream, uint64_t hbm
     s->running = 0;
     s->next_id = 0;
     s->err[0] = 0;
+    for (int k = 0; k < 5; k++) s->ms[k] = 0.0;
+    s->last_free = std::chrono::steady_clock::now();
+    if (hipStreamCreateWithFlags(&s->admit, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return LF_EDEVICE;
+    }
     if (hip_stream) {
         s->stream = (hipStream_t)hip_stream;
         s->own_stream = false;
     } else {
         if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipStreamDestroy(s->admit);
             delete s;
             return LF_EDEVICE;
         }
@@ -426,6 +460,7 @@ int lf_server_create(lf_server **out, int device, void *hip_stream, uint64_t hbm
     int rc = lf_batch_create(&s->batch, device, (void *)s->stream);
     if (rc != LF_OK) {
         if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        (void)hipStreamDestroy(s->admit);
         delete s;
         return rc;
     }
@@ -466,9 +501,16 @@ int lf_server_submit(lf_server *s, int64_t n, int64_t n_pairs, const int64_t *sr
 int lf_server_tick(lf_server *s, int32_t *pending)
 {
     if (!s) return LF_EINVAL;
+    auto t_tick = std::chrono::steady_clock::now();
+    if (ms_since(s->last_free) > 50.0) server_free_retired(s);
+    auto t0 = std::chrono::steady_clock::now();
     while (!s->queue.empty() && s->running < s->max_batch) {
         Job *j = s->queue.front();
-        if (s->used + j->footprint > s->budget) break;   // arrival order: wait for memory
+        if (s->used + j->footprint > s->budget) {          // arrival order: wait for memory
+            if (s->retired.empty()) break;
+            server_free_retired(s);
+            continue;
+        }
         s->queue.pop_front();
         s->used += j->footprint;
         s->running++;
@@ -479,8 +521,12 @@ int lf_server_tick(lf_server *s, int32_t *pending)
             job_release_device(s, j);
         }
     }
+    s->ms[0] += ms_since(t0);
+    t0 = std::chrono::steady_clock::now();
     int32_t live = 0;
     LF_TRY(lf_batch_step(s->batch, &live));
+    s->ms[1] += ms_since(t0);
+    t0 = std::chrono::steady_clock::now();
     for (auto &kv : s->jobs) {
         Job *j = kv.second;
         if (j->state != 1) continue;
@@ -492,7 +538,18 @@ int lf_server_tick(lf_server *s, int32_t *pending)
             job_release_device(s, j);
         }
     }
+    s->ms[2] += ms_since(t0);
     if (pending) *pending = (int32_t)s->queue.size() + s->running;
+    s->ms[4] += ms_since(t_tick);
+    return LF_OK;
+}
+
+// host milliseconds spent so far in: admission (load + initial clustering), batch steps,
+// retirement (results copied back), freeing device memory, whole ticks
+int lf_server_timing(lf_server *s, double *ms)
+{
+    if (!s || !ms) return LF_EINVAL;
+    for (int k = 0; k < 5; k++) ms[k] = s->ms[k];
     return LF_OK;
 }
 
@@ -561,8 +618,10 @@ int lf_server_destroy(lf_server *s)
         if (j->state == 1) job_release_device(s, j);
         delete j;
     }
+    server_free_retired(s);
     lf_batch_destroy(s->batch);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    (void)hipStreamDestroy(s->admit);
     delete s;
     return LF_OK;
 }

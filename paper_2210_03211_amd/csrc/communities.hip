@@ -383,12 +383,13 @@ void lf_free_partition(lf_handle *h)
 // member lists with capacity for joiners; requires sizes and slots to be current
 static int rebuild_member_lists(lf_handle *h)
 {
+    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
     const int BS = 256;
     long long n = h->n;
     int K = h->K;
     long long *capx = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&capx, sizeof(long long) * (K + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&capx, sizeof(long long) * (K + 1)));
     LF_HIP(h, hipMemsetAsync(capx, 0, sizeof(long long) * (K + 1), st));
     Ctx cx = lf_ctx(h);
     if (n > 0) hipLaunchKernelGGL(k_member_extra, dim3(grid_for(n, BS)), dim3(BS), 0, st, h->nh, cx.slot, n, capx);
@@ -409,12 +410,12 @@ static int rebuild_member_lists(lf_handle *h)
     if (n > 0) hipLaunchKernelGGL(k_member_fill, dim3(grid_for(n, BS)), dim3(BS), 0, st, h->nh, cx.slot, n, h->cm_off, h->cm_len, h->cm_node);
     LF_HIP(h, hipGetLastError());
     LF_HIP(h, hipStreamSynchronize(st));
-    lf_dev_free(h, capx);
     return LF_OK;
 }
 
 static int partition_score(lf_handle *h, double *out)
 {
+    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
     int K = h->K;
     int nb = (int)((K + 255) / 256);
@@ -422,15 +423,13 @@ static int partition_score(lf_handle *h, double *out)
     if (nb < 1) nb = 1;
     X256 *part = nullptr;
     double *dw = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&part, sizeof(X256) * nb));
-    LF_TRY(lf_dev_alloc(h, (void **)&dw, sizeof(double)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&part, sizeof(X256) * nb));
+    LF_TRY(lf_tmp_alloc(h, (void **)&dw, sizeof(double)));
     hipLaunchKernelGGL(k_score_partials, dim3(nb), dim3(256), 0, st, h->cr, K, part, &h->ctr->error);
     hipLaunchKernelGGL(k_score_fold, dim3(1), dim3(WAVE), 0, st, part, nb, dw);
     LF_HIP(h, hipMemcpyAsync(out, dw, sizeof(double), hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
-    lf_dev_free(h, part);
-    lf_dev_free(h, dw);
     return LF_OK;
 }
 
@@ -449,6 +448,7 @@ int lf_check_dev_error(lf_handle *h)
 
 int lf_initial_clustering(lf_handle *h)
 {
+    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
     const int BS = 256;
     long long n = h->n;
@@ -459,13 +459,13 @@ int lf_initial_clustering(lf_handle *h)
     int *state = nullptr, *cursor = nullptr, *comm_of = nullptr, *flag = nullptr, *und = nullptr;
     long long *pos = nullptr;
     size_t nn = (size_t)(n > 0 ? n : 1);
-    LF_TRY(lf_dev_alloc(h, (void **)&state, sizeof(int) * nn));
-    LF_TRY(lf_dev_alloc(h, (void **)&cursor, sizeof(int) * nn));
-    LF_TRY(lf_dev_alloc(h, (void **)&comm_of, sizeof(int) * nn));
-    LF_TRY(lf_dev_alloc(h, (void **)&flag, sizeof(int) * nn));
-    LF_TRY(lf_dev_alloc(h, (void **)&pos, sizeof(long long) * (nn + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&state, sizeof(int) * nn));
+    LF_TRY(lf_tmp_alloc(h, (void **)&cursor, sizeof(int) * nn));
+    LF_TRY(lf_tmp_alloc(h, (void **)&comm_of, sizeof(int) * nn));
+    LF_TRY(lf_tmp_alloc(h, (void **)&flag, sizeof(int) * nn));
+    LF_TRY(lf_tmp_alloc(h, (void **)&pos, sizeof(long long) * (nn + 1)));
     const int RB = 8;   // rounds between host checks
-    LF_TRY(lf_dev_alloc(h, (void **)&und, sizeof(int) * RB));
+    LF_TRY(lf_tmp_alloc(h, (void **)&und, sizeof(int) * RB));
     LF_HIP(h, hipMemsetAsync(state, 0, sizeof(int) * nn, st));
     LF_HIP(h, hipMemsetAsync(cursor, 0, sizeof(int) * nn, st));
     int rounds = 0;
@@ -547,18 +547,13 @@ int lf_initial_clustering(lf_handle *h)
     LF_TRY(lf_prof_end(h, LF_K_INITCLUST, rounds + 8));
     LF_TRY(lf_prof_flush(h));
     LF_TRY(lf_check_dev_error(h));
-    lf_dev_free(h, state);
-    lf_dev_free(h, cursor);
-    lf_dev_free(h, comm_of);
-    lf_dev_free(h, flag);
-    lf_dev_free(h, pos);
-    lf_dev_free(h, und);
     return LF_OK;
 }
 
 int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
                      long long *live)
 {
+    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
     const int BS = 256;
     long long n = h->n;
@@ -568,8 +563,8 @@ int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
     LF_HIP(h, hipMemsetAsync(&h->ctr->ovf_cnt, 0, sizeof(int), st));
     if (K > 0) hipLaunchKernelGGL(k_mark_dead, dim3(grid_for(K, BS)), dim3(BS), 0, st, cx);
     long long *newcap = nullptr, *noff = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&newcap, sizeof(long long) * (n + 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&noff, sizeof(long long) * (n + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&newcap, sizeof(long long) * (n + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&noff, sizeof(long long) * (n + 1)));
     if (n > 0) hipLaunchKernelGGL(k_drop_dead, dim3(grid_for(n, BS)), dim3(BS), 0, st, cx, newcap);
     if (K > 0) hipLaunchKernelGGL(k_clear_dead, dim3(grid_for(K, BS)), dim3(BS), 0, st, cx);
     LF_HIP(h, hipMemsetAsync(newcap + n, 0, sizeof(long long), st));
@@ -595,8 +590,6 @@ int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
     LF_HIP(h, hipMemcpyAsync(lv, &h->ctr->live, sizeof(lv), hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
-    lf_dev_free(h, newcap);
-    lf_dev_free(h, noff);
     *joins = (long long)jl[0];
     *leaves = (long long)jl[1];
     *live = lv[0];
@@ -635,12 +628,13 @@ __global__ void k_member_out(const NodeHdr *nh, const Slot *slot, long long n, c
 int lf_fetch_memberships(lf_handle *h, long long *offsets, int *comm_ids, long long capacity,
                          long long *total, int *in_counts)
 {
+    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
     const int BS = 256;
     long long n = h->n;
     long long *cnt = nullptr, *doff = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&cnt, sizeof(long long) * (n + 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&doff, sizeof(long long) * (n + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&cnt, sizeof(long long) * (n + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&doff, sizeof(long long) * (n + 1)));
     hipLaunchKernelGGL(k_member_counts, dim3(grid_for(n + 1, BS)), dim3(BS), 0, st, h->nh, n, cnt);
     LF_TRY(lf_exclusive_scan_i64(h, cnt, doff, n + 1));
     long long tot = 0;
@@ -653,8 +647,8 @@ int lf_fetch_memberships(lf_handle *h, long long *offsets, int *comm_ids, long l
             rc = lf_set_error(h, LF_ERANGE, "capacity %lld < %lld memberships", capacity, tot);
         } else {
             int *dids = nullptr, *din = nullptr;
-            LF_TRY(lf_dev_alloc(h, (void **)&dids, sizeof(int) * (tot > 0 ? tot : 1)));
-            LF_TRY(lf_dev_alloc(h, (void **)&din, sizeof(int) * (tot > 0 ? tot : 1)));
+            LF_TRY(lf_tmp_alloc(h, (void **)&dids, sizeof(int) * (tot > 0 ? tot : 1)));
+            LF_TRY(lf_tmp_alloc(h, (void **)&din, sizeof(int) * (tot > 0 ? tot : 1)));
             if (n > 0)
                 hipLaunchKernelGGL(k_member_out, dim3(grid_for(n, BS)), dim3(BS), 0, st, h->nh, h->slot[h->cur], n,
                                    doff, dids, din);
@@ -665,11 +659,7 @@ int lf_fetch_memberships(lf_handle *h, long long *offsets, int *comm_ids, long l
                 LF_HIP(h, hipMemcpyAsync(in_counts, din, sizeof(int) * tot, hipMemcpyDeviceToHost, st));
             LF_HIP(h, hipStreamSynchronize(st));
             LF_HIP(h, hipGetLastError());
-            lf_dev_free(h, dids);
-            lf_dev_free(h, din);
         }
     }
-    lf_dev_free(h, cnt);
-    lf_dev_free(h, doff);
     return rc;
 }

@@ -138,22 +138,21 @@ static inline unsigned grid_for(long long n, int block) { return (unsigned)((n +
 int lf_build_graph(lf_handle *h, long long n, long long np, const long long *src,
                    const long long *dst, unsigned flags)
 {
+    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
     const int BS = 256;
     long long *dsrc = nullptr, *ddst = nullptr;
-    bool copied = false;
     if (flags & LF_DEVICE_PTR) {
         dsrc = (long long *)src;
         ddst = (long long *)dst;
     } else if (np > 0) {
-        LF_TRY(lf_dev_alloc(h, (void **)&dsrc, sizeof(long long) * np));
-        LF_TRY(lf_dev_alloc(h, (void **)&ddst, sizeof(long long) * np));
+        LF_TRY(lf_tmp_alloc(h, (void **)&dsrc, sizeof(long long) * np));
+        LF_TRY(lf_tmp_alloc(h, (void **)&ddst, sizeof(long long) * np));
         LF_HIP(h, hipMemcpyAsync(dsrc, src, sizeof(long long) * np, hipMemcpyHostToDevice, st));
         LF_HIP(h, hipMemcpyAsync(ddst, dst, sizeof(long long) * np, hipMemcpyHostToDevice, st));
-        copied = true;
     }
     int *derr = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&derr, sizeof(int) * 4));
+    LF_TRY(lf_tmp_alloc(h, (void **)&derr, sizeof(int) * 4));
     LF_HIP(h, hipMemsetAsync(derr, 0, sizeof(int) * 4, st));
 
     // scratch sized for the largest use: 2 * np 64-bit keys (ids) and 2 * ne directed keys
@@ -161,10 +160,10 @@ int lf_build_graph(lf_handle *h, long long n, long long np, const long long *src
     unsigned long long *ka = nullptr, *kb = nullptr;
     int *flag = nullptr;
     long long *pos = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&ka, sizeof(unsigned long long) * kcap));
-    LF_TRY(lf_dev_alloc(h, (void **)&kb, sizeof(unsigned long long) * kcap));
-    LF_TRY(lf_dev_alloc(h, (void **)&flag, sizeof(int) * kcap));
-    LF_TRY(lf_dev_alloc(h, (void **)&pos, sizeof(long long) * (kcap + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&ka, sizeof(unsigned long long) * kcap));
+    LF_TRY(lf_tmp_alloc(h, (void **)&kb, sizeof(unsigned long long) * kcap));
+    LF_TRY(lf_tmp_alloc(h, (void **)&flag, sizeof(int) * kcap));
+    LF_TRY(lf_tmp_alloc(h, (void **)&pos, sizeof(long long) * (kcap + 1)));
 
     unsigned long long *uniq_ids = nullptr;
     if (flags & LF_RELABEL) {
@@ -182,7 +181,7 @@ int lf_build_graph(lf_handle *h, long long n, long long np, const long long *src
         }
         LF_HIP(h, hipStreamSynchronize(st));
         n = (m > 0) ? last_pos + last_flag : 0;
-        LF_TRY(lf_dev_alloc(h, (void **)&uniq_ids, sizeof(unsigned long long) * (n > 0 ? n : 1)));
+        LF_TRY(lf_tmp_alloc(h, (void **)&uniq_ids, sizeof(unsigned long long) * (n > 0 ? n : 1)));
         if (m > 0) hipLaunchKernelGGL(k_compact_u64, dim3(grid_for(m, BS)), dim3(BS), 0, st, sorted, flag, pos, m, uniq_ids);
     }
     if (n >= (1ll << 31) - 1) {
@@ -229,7 +228,7 @@ int lf_build_graph(lf_handle *h, long long n, long long np, const long long *src
     long long *deg64 = pos;     // reuse: n <= kcap? not guaranteed, allocate if needed
     bool own_deg64 = false;
     if (n + 1 > kcap + 1) {
-        LF_TRY(lf_dev_alloc(h, (void **)&deg64, sizeof(long long) * (n + 1)));
+        LF_TRY(lf_tmp_alloc(h, (void **)&deg64, sizeof(long long) * (n + 1)));
         own_deg64 = true;
     }
     LF_HIP(h, hipMemsetAsync(derr, 0, sizeof(int) * 4, st));
@@ -241,17 +240,6 @@ int lf_build_graph(lf_handle *h, long long n, long long np, const long long *src
     LF_HIP(h, hipMemcpyAsync(&maxdeg, derr + 1, sizeof(int), hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
-    if (own_deg64) lf_dev_free(h, deg64);
-    lf_dev_free(h, ka);
-    lf_dev_free(h, kb);
-    lf_dev_free(h, flag);
-    lf_dev_free(h, pos);
-    lf_dev_free(h, derr);
-    if (uniq_ids) lf_dev_free(h, uniq_ids);
-    if (copied) {
-        lf_dev_free(h, dsrc);
-        lf_dev_free(h, ddst);
-    }
     h->n = n;
     h->ne = ne;
     h->max_deg = maxdeg;
@@ -583,6 +571,7 @@ __global__ void k_rank(const int *order, long long n, int *rank)
 
 int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out)
 {
+    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
     int nb = (int)((n + RED_BLOCK - 1) / RED_BLOCK);
     if (nb > 1024) nb = 1024;
@@ -590,9 +579,9 @@ int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out)
     X192 *part = nullptr;
     int *err = nullptr;
     double *dout = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&part, sizeof(X192) * nb));
-    LF_TRY(lf_dev_alloc(h, (void **)&err, sizeof(int)));
-    LF_TRY(lf_dev_alloc(h, (void **)&dout, sizeof(double)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&part, sizeof(X192) * nb));
+    LF_TRY(lf_tmp_alloc(h, (void **)&err, sizeof(int)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&dout, sizeof(double)));
     LF_HIP(h, hipMemsetAsync(err, 0, sizeof(int), st));
     hipLaunchKernelGGL(k_exact_partials, dim3(nb), dim3(RED_BLOCK), 0, st, v, n, part, err);
     hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(WAVE), 0, st, part, nb, 1.0, dout);
@@ -601,15 +590,13 @@ int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out)
     LF_HIP(h, hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
-    lf_dev_free(h, part);
-    lf_dev_free(h, err);
-    lf_dev_free(h, dout);
     if (herr) return lf_set_error(h, LF_EOVERFLOW, "value outside the exact accumulator's range");
     return LF_OK;
 }
 
 int lf_node_stats(lf_handle *h)
 {
+    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
     long long n = h->n;
     const int BS = 256;
@@ -622,17 +609,17 @@ int lf_node_stats(lf_handle *h)
     int *orc = nullptr;
     int *defer = nullptr;
     int *cnt = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&od, sizeof(int) * (n > 0 ? n : 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&oro, sizeof(long long) * (n + 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&orc, sizeof(int) * (h->ne > 0 ? h->ne : 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&defer, sizeof(int) * (n > 0 ? n : 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&cnt, sizeof(int) * 4));
+    LF_TRY(lf_tmp_alloc(h, (void **)&od, sizeof(int) * (n > 0 ? n : 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&oro, sizeof(long long) * (n + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&orc, sizeof(int) * (h->ne > 0 ? h->ne : 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&defer, sizeof(int) * (n > 0 ? n : 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&cnt, sizeof(int) * 4));
     LF_TRY(lf_dev_alloc(h, (void **)&h->tri, sizeof(unsigned long long) * (n > 0 ? n : 1)));
     LF_HIP(h, hipMemsetAsync(h->tri, 0, sizeof(unsigned long long) * (n > 0 ? n : 1), st));
     LF_HIP(h, hipMemsetAsync(cnt, 0, sizeof(int) * 4, st));
     unsigned gw = grid_for(n * WAVE, BS);
     long long *od64 = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&od64, sizeof(long long) * (n + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&od64, sizeof(long long) * (n + 1)));
     if (n > 0) {
         hipLaunchKernelGGL(k_out_degree, dim3(gw), dim3(BS), 0, st, h->rowptr, h->col, h->deg, n, od);
         hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n, BS)), dim3(BS), 0, st, od, n, od64, cnt + 2);
@@ -656,7 +643,7 @@ int lf_node_stats(lf_handle *h)
         int blocks = ndefer < 1024 ? ndefer : 1024;
         int *gs = nullptr;
         long long gslice = 3ll * maxod + 2;
-        if (maxod > lds_cap) LF_TRY(lf_dev_alloc(h, (void **)&gs, sizeof(int) * gslice * blocks));
+        if (maxod > lds_cap) LF_TRY(lf_tmp_alloc(h, (void **)&gs, sizeof(int) * gslice * blocks));
         size_t shmem = sizeof(int) * (3 * (size_t)lds_cap + 1);
         LF_HIP(h, hipFuncSetAttribute((const void *)k_tri_group,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
@@ -664,15 +651,9 @@ int lf_node_stats(lf_handle *h)
                            h->tri, lds_cap, gs, gslice);
         LF_HIP(h, hipGetLastError());
         LF_HIP(h, hipStreamSynchronize(st));
-        if (gs) lf_dev_free(h, gs);
     }
     LF_HIP(h, hipGetLastError());
     LF_TRY(lf_prof_end(h, LF_K_TRIANGLES, 5 + (ndefer > 0)));
-    lf_dev_free(h, od);
-    lf_dev_free(h, od64);
-    lf_dev_free(h, oro);
-    lf_dev_free(h, orc);
-    lf_dev_free(h, defer);
 
     // local CC, cc, T
     LF_TRY(lf_prof_begin(h, LF_K_ORDER));
@@ -683,9 +664,9 @@ int lf_node_stats(lf_handle *h)
     X192 *part = nullptr;
     unsigned long long *tsum = nullptr;
     double *dcc = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&part, sizeof(X192) * nb));
-    LF_TRY(lf_dev_alloc(h, (void **)&tsum, sizeof(unsigned long long)));
-    LF_TRY(lf_dev_alloc(h, (void **)&dcc, sizeof(double)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&part, sizeof(X192) * nb));
+    LF_TRY(lf_tmp_alloc(h, (void **)&tsum, sizeof(unsigned long long)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&dcc, sizeof(double)));
     LF_HIP(h, hipMemsetAsync(tsum, 0, sizeof(unsigned long long), st));
     LF_HIP(h, hipMemsetAsync(cnt, 0, sizeof(int) * 4, st));
     hipLaunchKernelGGL(k_local_cc, dim3(nb), dim3(RED_BLOCK), 0, st, h->tri, h->deg, n, h->ccl, part, tsum, cnt);
@@ -697,12 +678,12 @@ int lf_node_stats(lf_handle *h)
     unsigned *k1 = nullptr, *k1b = nullptr;
     int *v1 = nullptr, *v1b = nullptr;
     unsigned long long *k2 = nullptr, *k2b = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&k1, sizeof(unsigned) * (n > 0 ? n : 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&k1b, sizeof(unsigned) * (n > 0 ? n : 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&v1, sizeof(int) * (n > 0 ? n : 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&v1b, sizeof(int) * (n > 0 ? n : 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&k2, sizeof(unsigned long long) * (n > 0 ? n : 1)));
-    LF_TRY(lf_dev_alloc(h, (void **)&k2b, sizeof(unsigned long long) * (n > 0 ? n : 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&k1, sizeof(unsigned) * (n > 0 ? n : 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&k1b, sizeof(unsigned) * (n > 0 ? n : 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&v1, sizeof(int) * (n > 0 ? n : 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&v1b, sizeof(int) * (n > 0 ? n : 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&k2, sizeof(unsigned long long) * (n > 0 ? n : 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&k2b, sizeof(unsigned long long) * (n > 0 ? n : 1)));
     unsigned *rk1;
     int *rv1;
     if (n > 0) hipLaunchKernelGGL(k_order_keys_deg, dim3(grid_for(n, BS)), dim3(BS), 0, st, h->deg, n, h->max_deg, k1, v1);
@@ -724,9 +705,6 @@ int lf_node_stats(lf_handle *h)
     LF_TRY(lf_prof_flush(h));
     if (n == 0) h->cc = 0.0;
     h->T = (long long)(ht / 3);
-    lf_dev_free(h, k1); lf_dev_free(h, k1b); lf_dev_free(h, v1); lf_dev_free(h, v1b);
-    lf_dev_free(h, k2); lf_dev_free(h, k2b);
-    lf_dev_free(h, part); lf_dev_free(h, tsum); lf_dev_free(h, dcc); lf_dev_free(h, cnt);
     if (hc[0]) return lf_set_error(h, LF_EINTERNAL, "clustering coefficient not exactly summable");
     if (ht % 3) return lf_set_error(h, LF_EINTERNAL, "triangle credits not divisible by 3");
     return LF_OK;

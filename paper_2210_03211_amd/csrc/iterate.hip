@@ -1244,6 +1244,7 @@ void lf_free_iteration_buffers(lf_handle *h)
 
 static int size_queue_buffers(lf_handle *h, long long q)
 {
+    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
     const int BS = 256;
     long long n = h->n;
@@ -1283,7 +1284,7 @@ static int size_queue_buffers(lf_handle *h, long long q)
         h->hqoff_cap = nq + 1;
     }
     long long *dq = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&dq, sizeof(long long) * (LF_PATH_COUNT + 1) * (nq + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&dq, sizeof(long long) * (LF_PATH_COUNT + 1) * (nq + 1)));
     if (!h->titem_base) {
         LF_TRY(lf_dev_alloc(h, (void **)&h->titem_base, sizeof(long long) * (n + 1)));
         moved = true;
@@ -1300,7 +1301,7 @@ static int size_queue_buffers(lf_handle *h, long long q)
     LF_HIP(h, hipMemcpyAsync(h->hqoff, dq, sizeof(long long) * LF_PATH_COUNT * (nq + 1), hipMemcpyDeviceToHost,
                              st));
     unsigned long long *dout = nullptr;
-    LF_TRY(lf_dev_alloc(h, (void **)&dout, sizeof(unsigned long long) * 4));
+    LF_TRY(lf_tmp_alloc(h, (void **)&dout, sizeof(unsigned long long) * 4));
     LF_HIP(h, hipMemsetAsync(dout, 0, sizeof(unsigned long long) * 4, st));
     hipLaunchKernelGGL(k_chunk_bounds, dim3((unsigned)nq), dim3(BS), 0, st, cx, (const long long *)h->vbound,
                        (const int *)h->cls, (int)q, dout);
@@ -1308,7 +1309,6 @@ static int size_queue_buffers(lf_handle *h, long long q)
     LF_HIP(h, hipMemcpyAsync(hb, dout, sizeof(hb), hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
-    lf_dev_free(h, dout);
     long long keys = (long long)hb[1] + 64;
     long long initems = (long long)hb[2] + 64;
     if (keys >= (1ll << 30) || initems >= (1ll << 31))
@@ -1336,7 +1336,6 @@ static int size_queue_buffers(lf_handle *h, long long q)
     LF_HIP(h, hipMemcpyAsync(h->hqoff + LF_PATH_COUNT * (nq + 1), dq + LF_PATH_COUNT * (nq + 1),
                              sizeof(long long) * (nq + 1), hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
-    lf_dev_free(h, dq);
     long long T = 1024;
     while (T < 2 * keys) T <<= 1;
     if (T > h->gT) {

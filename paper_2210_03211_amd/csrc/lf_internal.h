@@ -164,6 +164,16 @@ struct QGrids {
     int eval, big, fin, apply_edit, apply_in, refresh;
 };
 
+struct TmpChunk {
+    void *ptr;
+    size_t size;
+};
+
+struct TmpMark {
+    int chunk;
+    size_t off;
+};
+
 struct lf_handle {
     int device;
     hipStream_t stream;
@@ -250,6 +260,9 @@ struct lf_handle {
     // allocation registry
     std::vector<void *> *allocs;
     std::vector<size_t> *alloc_sizes;
+    std::vector<TmpChunk> *tmp_chunks;      // scratch arena (lf_tmp_alloc)
+    int tmp_chunk;
+    size_t tmp_off;
     size_t dev_bytes, dev_bytes_peak;   // device memory the handle holds (now / at most)
 };
 
@@ -272,6 +285,16 @@ int lf_set_error(lf_handle *h, int code, const char *fmt, ...);
 
 int lf_dev_alloc(lf_handle *h, void **p, size_t bytes);
 void lf_dev_free(lf_handle *h, void *p);
+int lf_tmp_alloc(lf_handle *h, void **p, size_t bytes);
+TmpMark lf_tmp_mark(lf_handle *h);
+void lf_tmp_release(lf_handle *h, TmpMark m);
+// temporaries of the enclosing scope come from the arena and go back at its end
+struct TmpScope {
+    lf_handle *h;
+    TmpMark m;
+    explicit TmpScope(lf_handle *hh) : h(hh), m(lf_tmp_mark(hh)) {}
+    ~TmpScope() { lf_tmp_release(h, m); }
+};
 int lf_ensure_tmp(lf_handle *h, size_t bytes);
 Ctx lf_ctx(lf_handle *h);
 

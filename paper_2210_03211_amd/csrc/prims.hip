@@ -49,6 +49,55 @@ void lf_dev_free(lf_handle *h, void *p)
     (void)hipFree(p);
 }
 
+// Scratch arena of a handle: temporaries of one host routine are carved from chunks the
+// handle keeps, so iteration starts and ends allocate nothing once warm (hipFree would
+// synchronise the whole device).  Marks and releases nest like a stack; memory handed out
+// after a release is only used by work queued later on the same stream.
+int lf_tmp_alloc(lf_handle *h, void **p, size_t bytes)
+{
+    *p = nullptr;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    std::vector<TmpChunk> &ch = *h->tmp_chunks;
+    while (true) {
+        if (h->tmp_chunk < (int)ch.size()) {
+            TmpChunk &c = ch[h->tmp_chunk];
+            if (h->tmp_off + bytes <= c.size) {
+                *p = (char *)c.ptr + h->tmp_off;
+                h->tmp_off += bytes;
+                return LF_OK;
+            }
+            if (h->tmp_off == 0) {                  // an unused chunk that is too small
+                lf_dev_free(h, c.ptr);
+                c.ptr = nullptr;
+                size_t want = bytes > 2 * c.size ? bytes : 2 * c.size;
+                LF_TRY(lf_dev_alloc(h, &c.ptr, want));
+                c.size = want;
+                continue;
+            }
+            h->tmp_chunk++;
+            h->tmp_off = 0;
+            continue;
+        }
+        size_t last = ch.empty() ? 0 : ch.back().size;
+        size_t want = bytes;
+        if (want < 2 * last) want = 2 * last;
+        if (want < ((size_t)4 << 20)) want = (size_t)4 << 20;
+        TmpChunk c;
+        LF_TRY(lf_dev_alloc(h, &c.ptr, want));
+        c.size = want;
+        ch.push_back(c);
+    }
+}
+
+TmpMark lf_tmp_mark(lf_handle *h) { return TmpMark{h->tmp_chunk, h->tmp_off}; }
+
+void lf_tmp_release(lf_handle *h, TmpMark m)
+{
+    h->tmp_chunk = m.chunk;
+    h->tmp_off = m.off;
+}
+
 int lf_ensure_tmp(lf_handle *h, size_t bytes)
 {
     if (bytes <= h->tmp_bytes) return LF_OK;
