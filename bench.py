@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (for HBM counter scaling)")
     ap.add_argument("--sweep", default="", help="comma-separated queue sizes: extra untimed-line runs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip tuning the path thresholds and launch shapes on the workload (untimed)")
     ap.add_argument("--serving-jobs", type=int, default=300,
                     help="jobs of the serving comparison (0 = skip it)")
     ap.add_argument("--serving-rate", type=float, default=200.0, help="Poisson arrival rate (jobs/s)")
@@ -241,6 +243,12 @@ def main():
         off, ids = h.get_memberships()
         return info, off, ids
 
+    tuned = None
+    if not args.no_autotune:
+        h.load_graph(g.n, src, dst)
+        h.init_communities()
+        tuned = h.autotune(q, 3)
+        print("[bench] autotune: %s" % json.dumps(tuned), file=sys.stderr, flush=True)
     for w in range(args.warmup):
         info, off, ids = step()
         print("[bench] warmup %d: %d iterations" % (w, info["iterations"]), file=sys.stderr, flush=True)
@@ -314,6 +322,8 @@ def main():
         "kernel_ms_timing_pass": {k: round(v, 3) for k, v in timing["ms"].items()},
         "roofline": roof,
     }
+    if tuned is not None:
+        out["autotune"] = tuned
     if args.sweep:
         sweep = {}
         for qq in [int(x) for x in args.sweep.split(",") if x]:

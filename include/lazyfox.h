@@ -212,6 +212,28 @@ int lf_set_option(lf_handle *h, int option, int64_t value);
 int lf_get_option(lf_handle *h, int option, int64_t *value);
 
 /*
+ * Autotuner of the options above that shape the evaluation (where the medium, workgroup
+ * and table paths start: LF_OPT_WAVE_TABLE, LF_OPT_MED_TABLE, LF_OPT_GRP_TABLE) and the
+ * launches (LF_OPT_HUB_BLOCKS, LF_OPT_REFRESH_BLOCKS).  Needs initialised communities.
+ * Candidates are timed on `trial_iters` iterations of queue size `queue_size` from the
+ * initial clustering (coordinate descent, one option at a time); the fastest is set on
+ * the handle, which is left at its initial clustering again.  The choice is remembered
+ * for the graph's class (log2 degree histogram, log2 queue size, log2 node count) within
+ * the process; a handle of a known class takes it without trials (from_cache = 1).
+ * Results of lf_run_iterations do not depend on the choice.
+ */
+typedef struct {
+    int64_t value[5];       /* WAVE_TABLE, MED_TABLE, GRP_TABLE, HUB_BLOCKS, REFRESH_BLOCKS */
+    float default_ms;       /* trial time with the options the handle had */
+    float best_ms;          /* trial time with the chosen options */
+    int32_t trials;
+    int32_t from_cache;
+} lf_tune_result;
+int lf_autotune(lf_handle *h, int32_t queue_size, int32_t trial_iters, lf_tune_result *out);
+/* Forget every remembered class. */
+int lf_autotune_forget(void);
+
+/*
  * Diagnostic: the exact sum of n doubles (device pointer), rounded once to nearest-even,
  * computed by the library's device accumulator (the one behind every score sum).
  * Values must be finite with magnitude in [2^-113, 2^30] or zero; LF_EOVERFLOW otherwise.

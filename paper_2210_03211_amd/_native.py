@@ -34,6 +34,11 @@ class RunInfo(C.Structure):
                 ("leaves", C.POINTER(C.c_int64)), ("communities", C.POINTER(C.c_int64))]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("value", C.c_int64 * 5), ("default_ms", C.c_float), ("best_ms", C.c_float),
+                ("trials", C.c_int32), ("from_cache", C.c_int32)]
+
+
 class Profile(C.Structure):
     _fields_ = [("launches", C.c_int64 * 12), ("ms", C.c_double * 12), ("chunks", C.c_int64),
                 ("node_evals", C.c_int64), ("visits", C.c_int64), ("candidates", C.c_int64),
@@ -92,6 +97,8 @@ def load_library():
         "lf_server_stats": [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(i32), C.POINTER(i32)],
         "lf_server_destroy": [vp],
         "lf_server_timing": [vp, C.POINTER(C.c_double)],
+        "lf_autotune": [vp, i32, i32, C.POINTER(TuneResult)],
+        "lf_autotune_forget": [],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -317,6 +324,19 @@ class Handle:
         v = C.c_int64()
         self._check(self.L.lf_get_option(self.h, OPTIONS[name], C.byref(v)), "lf_get_option")
         return v.value
+
+    def lf_autotune(self, queue_size, trial_iters=2):
+        """Tune the path thresholds and launch shapes on this graph (see lazyfox.h)."""
+        r = TuneResult()
+        self._check(self.L.lf_autotune(self.h, int(queue_size), int(trial_iters), C.byref(r)), "lf_autotune")
+        names = ("wave_table", "med_table", "grp_table", "hub_blocks", "refresh_blocks")
+        return dict(options=dict(zip(names, list(r.value))), default_ms=r.default_ms, best_ms=r.best_ms,
+                    trials=r.trials, from_cache=bool(r.from_cache))
+
+    autotune = lf_autotune
+
+    def lf_autotune_forget(self):
+        self._check(self.L.lf_autotune_forget(), "lf_autotune_forget")
 
     def lf_get_memory(self):
         b, p = C.c_uint64(), C.c_uint64()

@@ -226,3 +226,38 @@ def test_server_reserves_at_least_the_device_peak(lf):
     with pytest.raises(lf.LazyFoxError):
         srv.submit(g.n, g.src, g.dst, 64)
     srv.close()
+
+
+def test_autotune_keeps_results_and_remembers_the_class(lf):
+    """The tuner picks options from its candidate lists, leaves the handle at its initial
+    clustering, changes no result, and reuses its choice for a graph of the same class."""
+    import torch
+    h0 = lf.Handle(0)
+    h0.lf_autotune_forget()
+    for name, q in (("copurchase_1pct", 32), ("social_0.2pct", 256)):
+        g = {"copurchase_1pct": G.named_config("copurchase", scale=0.01),
+             "social_0.2pct": G.named_config("social", scale=0.002)}[name]
+        say("autotune", name)
+        ref_h, ref_info, ref_off, ref_ids = alone(lf, g, q, 50)
+        ref_h.close()
+        h = lf.Handle(0)
+        h.load_graph(g.n, torch.from_numpy(g.src).cuda(), torch.from_numpy(g.dst).cuda()).init_communities()
+        r = h.autotune(q, 1)
+        assert not r["from_cache"] and r["trials"] >= 5 and r["best_ms"] <= r["default_ms"]
+        o = r["options"]
+        assert o["wave_table"] in (32, 64, 128) and o["med_table"] in (128, 256, 512)
+        assert o["grp_table"] in (512, 1024, 2048)
+        for k, v in o.items():
+            assert h.lf_get_option(k) == v
+        info = h.run_iterations(q, 0.01, 50)
+        same_info(info, ref_info)
+        off, ids = h.memberships()
+        assert np.array_equal(off, ref_off) and np.array_equal(ids, ref_ids)
+        h2 = lf.Handle(0)
+        h2.load_graph(g.n, torch.from_numpy(g.src).cuda(), torch.from_numpy(g.dst).cuda()).init_communities()
+        r2 = h2.autotune(q, 1)
+        assert r2["from_cache"] and r2["options"] == o
+        h.close()
+        h2.close()
+    h0.lf_autotune_forget()
+    h0.close()
