@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--serving-rate", type=float, default=200.0, help="Poisson arrival rate (jobs/s)")
     ap.add_argument("--serving-max-batch", type=int, default=256)
     ap.add_argument("--serving-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serving-no-graph", action="store_true", help="issue batch steps launch by launch")
     return ap.parse_args()
 
 
@@ -149,6 +150,7 @@ def serving_bench(args, lf):
 
     # continuous batching through the server
     srv = lf.Server(0, hbm_budget=int(args.serving_budget_gib * (1 << 30)), max_batch=args.serving_max_batch)
+    srv.set_graph(not args.serving_no_graph)
     lat_b, hashes_b, evals_b = {}, {}, 0
     jid_of = {}
     nxt = 0
@@ -198,7 +200,7 @@ def serving_bench(args, lf):
 
     def pct(d, p):
         return 1000.0 * float(np.percentile(np.array(list(d.values())), p))
-    out = {"jobs": len(jobs), "rate_per_s": args.serving_rate,
+    out = {"jobs": len(jobs), "rate_per_s": args.serving_rate, "graph_replay": not args.serving_no_graph,
            "workload": "serving mix: Poisson arrivals, planted power-law graphs, nodes lognormal(median 2,000, "
                        "sigma 1.2) in [50, 200,000], mean degree 8-40, mixing 0.2-0.4, per-job queue",
            "batched": {"p50_ms": pct(lat_b, 50), "p99_ms": pct(lat_b, 99), "jobs_per_s": len(jobs) / span_b,

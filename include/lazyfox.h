@@ -270,6 +270,10 @@ int lf_batch_member_info(lf_batch *b, int32_t member_id, lf_run_info *out);
 int lf_batch_remove(lf_batch *b, int32_t member_id);
 int lf_batch_destroy(lf_batch *b);
 const char *lf_batch_last_error(lf_batch *b);
+/* on != 0 (the default): each step replays a graph of the seven per-step launches,
+   captured once, with the step's grids and member count set on its kernel nodes;
+   on = 0: the launches are issued one by one.  Results are the same either way. */
+int lf_batch_set_graph(lf_batch *b, int32_t on);
 
 /*
  * Serving: community-detection jobs on graphs of uneven size.  lf_server_submit copies a
@@ -302,6 +306,8 @@ const char *lf_server_last_error(lf_server *s);
    clustering, on a stream of its own), batch steps, retirement (results copied back),
    freeing device memory of retired jobs (done for many at once), whole ticks. */
 int lf_server_timing(lf_server *s, double *ms);
+/* Graph replay of the server's batch steps (lf_batch_set_graph); on by default. */
+int lf_server_set_graph(lf_server *s, int32_t on);
 
 #ifdef __cplusplus
 }

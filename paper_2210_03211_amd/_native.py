@@ -89,6 +89,7 @@ def load_library():
         "lf_batch_member_info": [vp, i32, C.POINTER(RunInfo)],
         "lf_batch_remove": [vp, i32],
         "lf_batch_destroy": [vp],
+        "lf_batch_set_graph": [vp, i32],
         "lf_server_create": [C.POINTER(vp), C.c_int, vp, C.c_uint64, i32],
         "lf_server_submit": [vp, i64, i64, vp, vp, i32, dbl, i32, C.POINTER(i64)],
         "lf_server_tick": [vp, C.POINTER(i32)],
@@ -97,6 +98,7 @@ def load_library():
         "lf_server_stats": [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(i32), C.POINTER(i32)],
         "lf_server_destroy": [vp],
         "lf_server_timing": [vp, C.POINTER(C.c_double)],
+        "lf_server_set_graph": [vp, i32],
         "lf_autotune": [vp, i32, i32, C.POINTER(TuneResult)],
         "lf_autotune_forget": [],
     }
@@ -424,6 +426,11 @@ class Batch:
 
     remove = lf_batch_remove
 
+    def lf_batch_set_graph(self, on=True):
+        self._check(self.L.lf_batch_set_graph(self.b, 1 if on else 0), "lf_batch_set_graph")
+
+    set_graph = lf_batch_set_graph
+
     def lf_batch_destroy(self):
         if self.b:
             self.L.lf_batch_destroy(self.b)
@@ -523,6 +530,11 @@ class Server:
         return dict(zip(("admit_ms", "step_ms", "retire_ms", "free_ms", "tick_ms"), list(ms)))
 
     timing = lf_server_timing
+
+    def lf_server_set_graph(self, on=True):
+        self._check(self.L.lf_server_set_graph(self.s, 1 if on else 0), "lf_server_set_graph")
+
+    set_graph = lf_server_set_graph
 
     def lf_server_destroy(self):
         if self.s:

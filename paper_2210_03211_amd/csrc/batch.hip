@@ -50,6 +50,12 @@ struct lf_batch {
     int *dboff;
     int cap;                                 // members the buffers hold
     int slot;
+    bool use_graph;                          // replay the step from a captured graph
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    hipGraphNode_t node[7];
+    int graph_cap;                           // cap the graph was captured for
+    long long graph_steps;
     char err[512];
 };
 
@@ -57,6 +63,86 @@ static int batch_error(lf_batch *b, int code, const char *msg)
 {
     snprintf(b->err, sizeof b->err, "%s", msg);
     return code;
+}
+
+// Capture the seven multi-graph launches of a step once (grids and member counts are set
+// per step on the executable graph; descriptors live at fixed device addresses).
+static int batch_capture(lf_batch *b)
+{
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+    }
+    const void *fn[7];
+    int block[7];
+    lf_multi_kernels(fn, block);
+    const int zero = 0;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return batch_error(b, LF_EDEVICE, "stream capture failed to start");
+    for (int i = 0; i < 7; i++) {
+        const int t = i < 3 ? i : i - 1;     // final and tie share offsets
+        const int *o = b->dboff + t * (b->cap + 1);
+        void *args[3] = {(void *)&b->dmem, (void *)&o, (void *)&zero};
+        (void)hipLaunchKernel(fn[i], dim3(1), dim3(block[i]), args, 0, b->stream);
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(b->stream, &g) != hipSuccess || !g)
+        return batch_error(b, LF_EDEVICE, "stream capture failed");
+    size_t nn = 0;
+    (void)hipGraphGetNodes(g, nullptr, &nn);
+    std::vector<hipGraphNode_t> nodes(nn);
+    if (nn != 7 || hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return batch_error(b, LF_EDEVICE, "unexpected captured graph");
+    }
+    for (int i = 0; i < 7; i++) {               // match the nodes to the kernels
+        b->node[i] = nullptr;
+        for (size_t k = 0; k < nn; k++) {
+            hipKernelNodeParams p;
+            if (hipGraphKernelNodeGetParams(nodes[k], &p) == hipSuccess && p.func == fn[i]) b->node[i] = nodes[k];
+        }
+        if (!b->node[i]) {
+            (void)hipGraphDestroy(g);
+            return batch_error(b, LF_EDEVICE, "kernel node not found in the captured graph");
+        }
+    }
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        b->exec = nullptr;
+        return batch_error(b, LF_EDEVICE, "graph instantiation failed");
+    }
+    b->graph = g;
+    b->graph_cap = b->cap;
+    return LF_OK;
+}
+
+// one step from the executable graph: grids and member count of every node, then replay
+static int batch_replay(lf_batch *b, int nm, const int *total)
+{
+    if (!b->exec || b->graph_cap != b->cap) LF_TRY(batch_capture(b));
+    const void *fn[7];
+    int block[7];
+    lf_multi_kernels(fn, block);
+    for (int i = 0; i < 7; i++) {
+        const int t = i < 3 ? i : i - 1;
+        const int *o = b->dboff + t * (b->cap + 1);
+        void *args[3] = {(void *)&b->dmem, (void *)&o, (void *)&nm};
+        hipKernelNodeParams p;
+        memset(&p, 0, sizeof p);
+        p.func = (void *)fn[i];
+        p.gridDim = dim3(total[t] > 0 ? total[t] : 1);   // blocks past the last member return at once
+        p.blockDim = dim3(block[i]);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        if (hipGraphExecKernelNodeSetParams(b->exec, b->node[i], &p) != hipSuccess)
+            return batch_error(b, LF_EDEVICE, "graph node update failed");
+    }
+    if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return batch_error(b, LF_EDEVICE, "graph launch failed");
+    b->graph_steps++;
+    return LF_OK;
 }
 
 static int batch_reserve(lf_batch *b, int nm)
@@ -122,6 +208,11 @@ int lf_batch_create(lf_batch **out, int device, void *hip_stream)
     b->slot = 0;
     b->dmem = nullptr;
     b->dboff = nullptr;
+    b->use_graph = true;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->graph_cap = 0;
+    b->graph_steps = 0;
     b->err[0] = 0;
     for (int s = 0; s < 2; s++) {
         b->hmem[s] = nullptr;
@@ -146,6 +237,13 @@ int lf_batch_create(lf_batch **out, int device, void *hip_stream)
 }
 
 const char *lf_batch_last_error(lf_batch *b) { return b ? b->err : "null batch"; }
+
+int lf_batch_set_graph(lf_batch *b, int32_t on)
+{
+    if (!b) return LF_EINVAL;
+    b->use_graph = on != 0;
+    return LF_OK;
+}
 
 int lf_batch_add(lf_batch *b, lf_handle *h, int32_t queue_size, double threshold, int32_t max_iters,
                  int32_t *member_id)
@@ -213,18 +311,21 @@ int lf_batch_step(lf_batch *b, int32_t *running)
             hm[i].cx = m->cx;
             const int blocks[6] = {g.eval, g.big, g.fin, g.apply_edit, g.apply_in, g.refresh};
             for (int t = 0; t < 6; t++) {
-                hb[t * (nm + 1) + i] = total[t];
+                hb[t * (b->cap + 1) + i] = total[t];
                 total[t] += blocks[t];
             }
         }
-        for (int t = 0; t < 6; t++) hb[t * (nm + 1) + nm] = total[t];
+        for (int t = 0; t < 6; t++) hb[t * (b->cap + 1) + nm] = total[t];
         if (hipMemcpyAsync(b->dmem, hm, sizeof(Member) * nm, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-            hipMemcpyAsync(b->dboff, hb, sizeof(int) * 6 * (nm + 1), hipMemcpyHostToDevice, b->stream) !=
+            hipMemcpyAsync(b->dboff, hb, sizeof(int) * 6 * (b->cap + 1), hipMemcpyHostToDevice, b->stream) !=
                 hipSuccess ||
             hipEventRecord(b->hev[s], b->stream) != hipSuccess)
             return batch_error(b, LF_EDEVICE, "descriptor upload failed");
-        if (lf_launch_multi(b->stream, b->dmem, b->dboff, nm, total) != LF_OK)
+        if (b->use_graph) {
+            LF_TRY(batch_replay(b, nm, total));
+        } else if (lf_launch_multi(b->stream, b->dmem, b->dboff, b->cap, nm, total) != LF_OK) {
             return batch_error(b, LF_EDEVICE, "multi-graph launch failed");
+        }
         for (BatchMember *m : act) {
             m->k++;
             if (m->k == m->nq) {
@@ -293,6 +394,8 @@ int lf_batch_destroy(lf_batch *b)
         if (b->hboff[s]) (void)hipHostFree(b->hboff[s]);
         (void)hipEventDestroy(b->hev[s]);
     }
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->dmem) (void)hipFree(b->dmem);
     if (b->dboff) (void)hipFree(b->dboff);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
@@ -542,6 +645,12 @@ int lf_server_tick(lf_server *s, int32_t *pending)
     if (pending) *pending = (int32_t)s->queue.size() + s->running;
     s->ms[4] += ms_since(t_tick);
     return LF_OK;
+}
+
+int lf_server_set_graph(lf_server *s, int32_t on)
+{
+    if (!s) return LF_EINVAL;
+    return lf_batch_set_graph(s->batch, on);
 }
 
 // host milliseconds spent so far in: admission (load + initial clustering), batch steps,

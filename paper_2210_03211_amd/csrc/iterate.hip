@@ -1476,26 +1476,40 @@ int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g)
 }
 
 // One queue of each of nm graphs: six launches (the table-path finalisation counts as
-// one grid), each block finding its graph from dboff (6 arrays of nm + 1 first-block
-// offsets, one per kernel, in launch order); total[i] = blocks of launch i.
-int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int nm, const int *total)
+// one grid), each block finding its graph from dboff (6 arrays of first-block offsets, one
+// per launch, at stride cap + 1, each with nm + 1 entries); total[i] = blocks of launch i.
+int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int cap, int nm, const int *total)
 {
     const int *o = dboff;
     if (total[0] > 0) hipLaunchKernelGGL(k_eval_multi, dim3(total[0]), dim3(EW * WAVE), 0, st, dmem, o, nm);
-    o += nm + 1;
+    o += cap + 1;
     if (total[1] > 0) hipLaunchKernelGGL(k_eval_big_multi, dim3(total[1]), dim3(GT), 0, st, dmem, o, nm);
-    o += nm + 1;
+    o += cap + 1;
     if (total[2] > 0) {
         hipLaunchKernelGGL(k_big_final_multi, dim3(total[2]), dim3(256), 0, st, dmem, o, nm);
         hipLaunchKernelGGL(k_big_tie_multi, dim3(total[2]), dim3(256), 0, st, dmem, o, nm);
     }
-    o += nm + 1;
+    o += cap + 1;
     if (total[3] > 0) hipLaunchKernelGGL(k_apply_edit_multi, dim3(total[3]), dim3(256), 0, st, dmem, o, nm);
-    o += nm + 1;
+    o += cap + 1;
     if (total[4] > 0) hipLaunchKernelGGL(k_apply_in_multi, dim3(total[4]), dim3(256), 0, st, dmem, o, nm);
-    o += nm + 1;
+    o += cap + 1;
     if (total[5] > 0) hipLaunchKernelGGL(k_refresh_multi, dim3(total[5]), dim3(256), 0, st, dmem, o, nm);
     return hipGetLastError() == hipSuccess ? LF_OK : LF_EDEVICE;
+}
+
+// The seven multi-graph kernels in launch order (k_big_final and k_big_tie share grid 2)
+// with the block size of each, for building a graph of one batch step.
+void lf_multi_kernels(const void **fn, int *block)
+{
+    const void *f[7] = {(const void *)k_eval_multi, (const void *)k_eval_big_multi, (const void *)k_big_final_multi,
+                        (const void *)k_big_tie_multi, (const void *)k_apply_edit_multi,
+                        (const void *)k_apply_in_multi, (const void *)k_refresh_multi};
+    const int b[7] = {EW * WAVE, GT, 256, 256, 256, 256, 256};
+    for (int i = 0; i < 7; i++) {
+        fn[i] = f[i];
+        block[i] = b[i];
+    }
 }
 
 // End of an iteration: counters reset, degenerate communities removed, exact score.

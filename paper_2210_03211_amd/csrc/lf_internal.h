@@ -332,7 +332,8 @@ int lf_iter_begin(lf_handle *h, long long qq, long long *nq);
 void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool compact_grids, QStep *qs,
                      QGrids *g);
 int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g);
-int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int nm, const int *total);
+int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int cap, int nm, const int *total);
+void lf_multi_kernels(const void **fn, int *block);
 int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long *live);
 int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
                      long long *live);

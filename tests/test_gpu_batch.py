@@ -63,7 +63,10 @@ def same_info(a, b):
     assert a["wcc_hat"] == b["wcc_hat"]
 
 
-def test_batch_equals_alone_and_oracle(lf):
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_alone_and_oracle(lf, graph):
+    """Both ways of issuing a step: graph replay (several hundred replays, with the
+    members' eager iteration starts and ends in between) and launches one by one."""
     import torch
     import oracle
     oracle.build(force=False)
@@ -82,8 +85,9 @@ def test_batch_equals_alone_and_oracle(lf):
         assert oi["iterations"] == ref[name][0]["iterations"]
         ooff, oids = o.memberships()
         assert np.array_equal(ooff, ref[name][1]) and np.array_equal(oids, ref[name][2])
-    say("batch of", len(gs))
+    say("batch of", len(gs), "graph replay", graph)
     b = lf.Batch(0)
+    b.set_graph(graph)
     hs, mids = [], []
     for name, g, q, mi in gs:
         h = lf.Handle(0)
