@@ -66,7 +66,9 @@ B_NODE, B_NEIGHBOUR, B_VISIT, B_CAND = 60.0, 20.0, 12.0, 44.0
 
 
 def kernel_bytes(kernel, paths):
-    """Algorithmic bytes one pass moves through `kernel` (None if no model for it)."""
+    """Algorithmic bytes one pass moves through `kernel` (None if no model for it).  The
+    small path's work is counted under k_eval: on the benchmark workload its queues (>= 1024
+    small-path nodes) all launch it."""
     def full(p):
         w = paths[p]
         return (B_NODE * w["nodes"] + B_NEIGHBOUR * w["neighbours"] + B_VISIT * w["visits"]

@@ -68,9 +68,11 @@ typedef struct {
 #define LF_K_TRIANGLES 1    /* triangle counting (all launches) */
 #define LF_K_ORDER 2        /* CC, cc reduction, node order */
 #define LF_K_INITCLUST 3    /* initial clustering and state set-up */
-#define LF_K_EVAL 4         /* k_eval: small wave evaluation path (<= 64 visits per node) */
-#define LF_K_EVAL_BIG 5     /* k_eval_big: medium wave path (<= 256 visits), workgroup path
-                               (<= 1024 visits) and the table path's neighbour visits */
+#define LF_K_EVAL 4         /* k_eval: small wave path (<= 64 visits) of queues with many
+                               such nodes */
+#define LF_K_EVAL_BIG 5     /* k_eval_big: the other evaluation paths of a queue, by block
+                               role: table-path visits, workgroup path (<= 1024 visits),
+                               medium wave path (<= 256), small path of smaller queues */
 #define LF_K_TAB_FINAL 6    /* k_big_final: table path, candidate changes and maxima */
 #define LF_K_TAB_TIE 7      /* k_big_tie: table path, lowest id among equal maxima */
 #define LF_K_APPLY_EDIT 8   /* k_apply_edit: membership edits, sizes, member lists */

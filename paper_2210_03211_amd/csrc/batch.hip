@@ -2,7 +2,7 @@
 //
 // A batch holds handles whose communities are initialised.  lf_batch_step runs one
 // queue of every member that is still iterating: the per-queue parameters of all members
-// go to the device in one copy, then each of the six per-queue launches covers every
+// go to the device in one copy, then each of the per-queue launches covers every
 // member (blocks find their graph from per-member block offsets), so a launch carries
 // the work of many small graphs instead of leaving most of the device idle.  A member's
 // iteration start and end (path lists, degenerate removal, exact score, stop test) run
@@ -53,7 +53,7 @@ struct lf_batch {
     bool use_graph;                          // replay the step from a captured graph
     hipGraph_t graph;
     hipGraphExec_t exec;
-    hipGraphNode_t node[7];
+    hipGraphNode_t node[LF_MULTI_KERNELS];
     int graph_cap;                           // cap the graph was captured for
     long long graph_steps;
     char err[512];
@@ -65,7 +65,7 @@ static int batch_error(lf_batch *b, int code, const char *msg)
     return code;
 }
 
-// Capture the seven multi-graph launches of a step once (grids and member counts are set
+// Capture the multi-graph launches of a step once (grids and member counts are set
 // per step on the executable graph; descriptors live at fixed device addresses).
 static int batch_capture(lf_batch *b)
 {
@@ -75,15 +75,14 @@ static int batch_capture(lf_batch *b)
         b->exec = nullptr;
         b->graph = nullptr;
     }
-    const void *fn[7];
-    int block[7];
-    lf_multi_kernels(fn, block);
+    const void *fn[LF_MULTI_KERNELS];
+    int grid[LF_MULTI_KERNELS], block[LF_MULTI_KERNELS];
+    lf_multi_kernels(fn, grid, block);
     const int zero = 0;
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return batch_error(b, LF_EDEVICE, "stream capture failed to start");
-    for (int i = 0; i < 7; i++) {
-        const int t = i < 3 ? i : i - 1;     // final and tie share offsets
-        const int *o = b->dboff + t * (b->cap + 1);
+    for (int i = 0; i < LF_MULTI_KERNELS; i++) {
+        const int *o = b->dboff + grid[i] * (b->cap + 1);
         void *args[3] = {(void *)&b->dmem, (void *)&o, (void *)&zero};
         (void)hipLaunchKernel(fn[i], dim3(1), dim3(block[i]), args, 0, b->stream);
     }
@@ -93,11 +92,11 @@ static int batch_capture(lf_batch *b)
     size_t nn = 0;
     (void)hipGraphGetNodes(g, nullptr, &nn);
     std::vector<hipGraphNode_t> nodes(nn);
-    if (nn != 7 || hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) {
+    if (nn != LF_MULTI_KERNELS || hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) {
         (void)hipGraphDestroy(g);
         return batch_error(b, LF_EDEVICE, "unexpected captured graph");
     }
-    for (int i = 0; i < 7; i++) {               // match the nodes to the kernels
+    for (int i = 0; i < LF_MULTI_KERNELS; i++) {   // match the nodes to the kernels
         b->node[i] = nullptr;
         for (size_t k = 0; k < nn; k++) {
             hipKernelNodeParams p;
@@ -122,11 +121,11 @@ static int batch_capture(lf_batch *b)
 static int batch_replay(lf_batch *b, int nm, const int *total)
 {
     if (!b->exec || b->graph_cap != b->cap) LF_TRY(batch_capture(b));
-    const void *fn[7];
-    int block[7];
-    lf_multi_kernels(fn, block);
-    for (int i = 0; i < 7; i++) {
-        const int t = i < 3 ? i : i - 1;
+    const void *fn[LF_MULTI_KERNELS];
+    int grid[LF_MULTI_KERNELS], block[LF_MULTI_KERNELS];
+    lf_multi_kernels(fn, grid, block);
+    for (int i = 0; i < LF_MULTI_KERNELS; i++) {
+        const int t = grid[i];
         const int *o = b->dboff + t * (b->cap + 1);
         void *args[3] = {(void *)&b->dmem, (void *)&o, (void *)&nm};
         hipKernelNodeParams p;
@@ -157,14 +156,15 @@ static int batch_reserve(lf_batch *b, int nm)
             (void)hipHostFree(b->hboff[s]);
         }
         if (hipHostMalloc((void **)&b->hmem[s], sizeof(Member) * cap, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&b->hboff[s], sizeof(int) * 6 * (cap + 1), hipHostMallocDefault) != hipSuccess)
+            hipHostMalloc((void **)&b->hboff[s], sizeof(int) * LF_MULTI_GRIDS * (cap + 1), hipHostMallocDefault) !=
+                hipSuccess)
             return batch_error(b, LF_ENOMEM, "pinned host buffers of the batch");
     }
     (void)hipStreamSynchronize(b->stream);
     if (b->dmem) (void)hipFree(b->dmem);
     if (b->dboff) (void)hipFree(b->dboff);
     if (hipMalloc((void **)&b->dmem, sizeof(Member) * cap) != hipSuccess ||
-        hipMalloc((void **)&b->dboff, sizeof(int) * 6 * (cap + 1)) != hipSuccess)
+        hipMalloc((void **)&b->dboff, sizeof(int) * LF_MULTI_GRIDS * (cap + 1)) != hipSuccess)
         return batch_error(b, LF_ENOMEM, "device buffers of the batch");
     b->cap = cap;
     return LF_OK;
@@ -302,22 +302,22 @@ int lf_batch_step(lf_batch *b, int32_t *running)
         if (hipEventSynchronize(b->hev[s]) != hipSuccess) return batch_error(b, LF_EDEVICE, "event sync failed");
         Member *hm = b->hmem[s];
         int *hb = b->hboff[s];
-        int total[6] = {0, 0, 0, 0, 0, 0};
+        int total[LF_MULTI_GRIDS] = {0, 0, 0, 0, 0};
         for (int i = 0; i < nm; i++) {
             BatchMember *m = act[i];
             QGrids g;
             lf_queue_params(m->h, m->k, m->nq, m->qq, true, &hm[i].qs, &g);
             m->cx.qtag = m->h->qtag++;
             hm[i].cx = m->cx;
-            const int blocks[6] = {g.eval, g.big, g.fin, g.apply_edit, g.apply_in, g.refresh};
-            for (int t = 0; t < 6; t++) {
+            const int blocks[LF_MULTI_GRIDS] = {g.big, g.fin, g.apply_edit, g.apply_in, g.refresh};
+            for (int t = 0; t < LF_MULTI_GRIDS; t++) {
                 hb[t * (b->cap + 1) + i] = total[t];
                 total[t] += blocks[t];
             }
         }
-        for (int t = 0; t < 6; t++) hb[t * (b->cap + 1) + nm] = total[t];
+        for (int t = 0; t < LF_MULTI_GRIDS; t++) hb[t * (b->cap + 1) + nm] = total[t];
         if (hipMemcpyAsync(b->dmem, hm, sizeof(Member) * nm, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-            hipMemcpyAsync(b->dboff, hb, sizeof(int) * 6 * (b->cap + 1), hipMemcpyHostToDevice, b->stream) !=
+            hipMemcpyAsync(b->dboff, hb, sizeof(int) * LF_MULTI_GRIDS * (b->cap + 1), hipMemcpyHostToDevice, b->stream) !=
                 hipSuccess ||
             hipEventRecord(b->hev[s], b->stream) != hipSuccess)
             return batch_error(b, LF_EDEVICE, "descriptor upload failed");

@@ -6,14 +6,15 @@
 // its visits that holds for the whole iteration (k_node_bounds), and each path gets the
 // list of its nodes in order.  Per queue (all launches on the handle's stream, no host
 // synchronisation):
-//   k_eval           small path: one wave per node with <= 64 visits, decided entirely
-//                    in an LDS hash table; block 0 also resets the queue's counters
+//   k_eval           small path (queues with >= 1024 such nodes): one wave per node
+//                    with <= 64 visits, decided entirely in an LDS hash table
 //   k_eval_big       by block role: the table path's visits (largest nodes): every
 //                    neighbour membership (y in C) adds its exact correction to the entry
 //                    (node, C) of a global open-addressing table, own memberships add the
 //                    leave candidates; the workgroup path (one workgroup per node with
 //                    <= 1024 visits, LDS tables); the medium path (one wave per node with
-//                    <= 256 visits)
+//                    <= 256 visits); the small path of smaller queues; block 0 of either
+//                    launch resets the queue's counters
 //   k_big_final      every occupied table entry -> change of C's score; per node the
 //                    largest positive change (atomicMax on the bits of a positive double)
 //   k_big_tie        among the entries equal to that maximum the lowest community id
@@ -98,6 +99,7 @@ struct NodeLds {
 #define VMED 256        // visits of the medium wave path
 #define VGRP 1024       // visits of the workgroup path
 #define GT 256          // threads of the workgroup path
+#define SMALL_OWN_LAUNCH 1024   // small-path nodes from which a queue launches k_eval
 
 // member owning block b of a multi-graph launch (boff: first block of each member, nm + 1
 // entries); -1 past the last member's blocks
@@ -441,11 +443,12 @@ __device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg)
 }
 
 
-// The three in-LDS evaluation paths.  Each takes its queue's nodes from its path list
-// (list positions [ls, ls + ln)); the path was chosen so that the node fits, and a node
-// that does not is an internal error.
+// The in-LDS evaluation paths take their queue's nodes from their path lists; the path
+// was chosen so that the node fits, and a node that does not is an internal error.
 
-// small wave path, one wave per node; block 0 also resets the queue's apply counters
+// Small wave path on its own launch (one wave per node, 21 KB of LDS per block, so seven
+// blocks per CU): used for queues with many small-path nodes; otherwise the small path is
+// a block role of k_eval_big.  Block 0 also resets the queue's apply counters.
 struct EvalLds {
     NodeLds<VSMALL> w[EW];
 };
@@ -467,7 +470,12 @@ __device__ __forceinline__ void body_eval(const Ctx &cx, const QStep &qs, int bl
     if (!eval_node<WAVE, VSMALL>(cx, qs.cstart, j, lane, L.w[wv], qs.wcap, LF_PATH_SMALL) && lane == 0)
         atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
 }
-QUEUE_KERNELS(k_eval, EW * WAVE, EvalLds, body_eval)
+
+__global__ void __launch_bounds__(EW * WAVE) k_eval(Ctx cx, QStep qs)
+{
+    __shared__ EvalLds lds;
+    body_eval(cx, qs, (int)blockIdx.x, (int)gridDim.x, lds);
+}
 
 // ------------------------------------------------------------------------------------
 // evaluation, table path
@@ -682,6 +690,7 @@ union BigLds {
     TabLds t;
     NodeLds<VGRP> g;
     NodeLds<VMED> m[GT / WAVE];
+    NodeLds<VSMALL> s[GT / WAVE];
 };
 
 __device__ __forceinline__ void body_eval_big(const Ctx &cx, const QStep &qs, int blk, int nblk, BigLds &L)
@@ -689,6 +698,13 @@ __device__ __forceinline__ void body_eval_big(const Ctx &cx, const QStep &qs, in
     (void)nblk;
     const BigRoles &r = qs.br;
     const int cstart = qs.cstart;
+    if (blk == 0 && threadIdx.x == 0) {     // the queue's apply counters (no role uses them)
+        DevCounters *c = cx.ctr;
+        c->tcount = 0;
+        c->in_items = 0;
+        c->parts_total = 0;
+        c->mslots = 0;
+    }
     int b = blk;
     if (b < r.bt) {
         table_visits(cx, cstart, r.lt, r.nt, b, r.bt, L.t);
@@ -706,9 +722,18 @@ __device__ __forceinline__ void body_eval_big(const Ctx &cx, const QStep &qs, in
     }
     b -= r.bg;
     const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    for (int p = b * (GT / WAVE) + wv; p < r.nm; p += r.bm * (GT / WAVE)) {   // no block barriers
-        const int j = cx.plist[LF_PATH_MED][r.lm + p] - cstart;
-        if (!eval_node<WAVE, VMED>(cx, cstart, j, lane, L.m[wv], qs.mcap, LF_PATH_MED) && lane == 0)
+    if (b < r.bm) {
+        for (int p = b * (GT / WAVE) + wv; p < r.nm; p += r.bm * (GT / WAVE)) {   // no block barriers
+            const int j = cx.plist[LF_PATH_MED][r.lm + p] - cstart;
+            if (!eval_node<WAVE, VMED>(cx, cstart, j, lane, L.m[wv], qs.mcap, LF_PATH_MED) && lane == 0)
+                atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
+        }
+        return;
+    }
+    b -= r.bm;
+    for (int p = b * (GT / WAVE) + wv; p < r.ns; p += r.bs * (GT / WAVE)) {    // small path, one wave per node
+        const int j = cx.plist[LF_PATH_SMALL][qs.ls + p] - cstart;
+        if (!eval_node<WAVE, VSMALL>(cx, cstart, j, lane, L.s[wv], qs.wcap, LF_PATH_SMALL) && lane == 0)
             atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
     }
 }
@@ -1425,6 +1450,11 @@ void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool
     if (br.bt > gb) br.bt = gb;
     br.bg = ln[LF_PATH_GROUP] < gb ? ln[LF_PATH_GROUP] : gb;
     br.bm = (int)grid_for(ln[LF_PATH_MED], GT / WAVE);
+    // a queue with many small-path nodes gives them a launch of their own (more blocks per
+    // CU than the fused kernel's LDS allows); otherwise they are a role of k_eval_big
+    const bool own_small = !compact_grids && ln[LF_PATH_SMALL] >= SMALL_OWN_LAUNCH;
+    br.ns = own_small ? 0 : ln[LF_PATH_SMALL];
+    br.bs = (int)grid_for(br.ns, GT / WAVE);
     br.lt = ls[LF_PATH_TABLE];
     br.nt = ln[LF_PATH_TABLE];
     br.lg = ls[LF_PATH_GROUP];
@@ -1432,8 +1462,9 @@ void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool
     br.lm = ls[LF_PATH_MED];
     br.nm = ln[LF_PATH_MED];
     qs->plan_blocks = (int)grid_for(2ll * clen, 256);
-    g->eval = ln[LF_PATH_SMALL] > 0 ? (int)grid_for(ln[LF_PATH_SMALL], EW) : 1;
-    g->big = br.bt + br.bg + br.bm;
+    g->eval = own_small ? (int)grid_for(ln[LF_PATH_SMALL], EW) : 0;
+    g->big = br.bt + br.bg + br.bm + br.bs;
+    if (g->big < 1 && g->eval == 0) g->big = 1;   // block 0 resets the queue's counters
     g->fin = ln[LF_PATH_TABLE] > 0 ? (compact_grids ? (br.bt > 0 ? br.bt : 1) : gb) : 0;
     g->apply_edit = (int)grid_for(clen, 256);
     g->apply_in = qs->plan_blocks + rbk;
@@ -1445,9 +1476,11 @@ int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g)
 {
     hipStream_t st = h->stream;
     cx.qtag = h->qtag++;
-    LF_TRY(lf_prof_begin(h, LF_K_EVAL));
-    hipLaunchKernelGGL(k_eval, dim3(g.eval), dim3(EW * WAVE), 0, st, cx, qs);
-    LF_TRY(lf_prof_end(h, LF_K_EVAL, 1));
+    if (g.eval > 0) {
+        LF_TRY(lf_prof_begin(h, LF_K_EVAL));
+        hipLaunchKernelGGL(k_eval, dim3(g.eval), dim3(EW * WAVE), 0, st, cx, qs);
+        LF_TRY(lf_prof_end(h, LF_K_EVAL, 1));
+    }
     if (g.big > 0) {
         LF_TRY(lf_prof_begin(h, LF_K_EVAL_BIG));
         hipLaunchKernelGGL(k_eval_big, dim3(g.big), dim3(GT), 0, st, cx, qs);
@@ -1475,39 +1508,39 @@ int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g)
     return LF_OK;
 }
 
-// One queue of each of nm graphs: six launches (the table-path finalisation counts as
-// one grid), each block finding its graph from dboff (6 arrays of first-block offsets, one
-// per launch, at stride cap + 1, each with nm + 1 entries); total[i] = blocks of launch i.
+// One queue of each of nm graphs: five grids (k_big_final and k_big_tie share one), each
+// block finding its graph from dboff (LF_MULTI_GRIDS arrays of first-block offsets, at
+// stride cap + 1, each with nm + 1 entries); total[i] = blocks of grid i.
 int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int cap, int nm, const int *total)
 {
     const int *o = dboff;
-    if (total[0] > 0) hipLaunchKernelGGL(k_eval_multi, dim3(total[0]), dim3(EW * WAVE), 0, st, dmem, o, nm);
+    if (total[0] > 0) hipLaunchKernelGGL(k_eval_big_multi, dim3(total[0]), dim3(GT), 0, st, dmem, o, nm);
     o += cap + 1;
-    if (total[1] > 0) hipLaunchKernelGGL(k_eval_big_multi, dim3(total[1]), dim3(GT), 0, st, dmem, o, nm);
-    o += cap + 1;
-    if (total[2] > 0) {
-        hipLaunchKernelGGL(k_big_final_multi, dim3(total[2]), dim3(256), 0, st, dmem, o, nm);
-        hipLaunchKernelGGL(k_big_tie_multi, dim3(total[2]), dim3(256), 0, st, dmem, o, nm);
+    if (total[1] > 0) {
+        hipLaunchKernelGGL(k_big_final_multi, dim3(total[1]), dim3(256), 0, st, dmem, o, nm);
+        hipLaunchKernelGGL(k_big_tie_multi, dim3(total[1]), dim3(256), 0, st, dmem, o, nm);
     }
     o += cap + 1;
-    if (total[3] > 0) hipLaunchKernelGGL(k_apply_edit_multi, dim3(total[3]), dim3(256), 0, st, dmem, o, nm);
+    if (total[2] > 0) hipLaunchKernelGGL(k_apply_edit_multi, dim3(total[2]), dim3(256), 0, st, dmem, o, nm);
     o += cap + 1;
-    if (total[4] > 0) hipLaunchKernelGGL(k_apply_in_multi, dim3(total[4]), dim3(256), 0, st, dmem, o, nm);
+    if (total[3] > 0) hipLaunchKernelGGL(k_apply_in_multi, dim3(total[3]), dim3(256), 0, st, dmem, o, nm);
     o += cap + 1;
-    if (total[5] > 0) hipLaunchKernelGGL(k_refresh_multi, dim3(total[5]), dim3(256), 0, st, dmem, o, nm);
+    if (total[4] > 0) hipLaunchKernelGGL(k_refresh_multi, dim3(total[4]), dim3(256), 0, st, dmem, o, nm);
     return hipGetLastError() == hipSuccess ? LF_OK : LF_EDEVICE;
 }
 
-// The seven multi-graph kernels in launch order (k_big_final and k_big_tie share grid 2)
-// with the block size of each, for building a graph of one batch step.
-void lf_multi_kernels(const void **fn, int *block)
+// The multi-graph kernels in launch order, the grid each uses and its block size, for
+// building a graph of one batch step.
+void lf_multi_kernels(const void **fn, int *grid, int *block)
 {
-    const void *f[7] = {(const void *)k_eval_multi, (const void *)k_eval_big_multi, (const void *)k_big_final_multi,
-                        (const void *)k_big_tie_multi, (const void *)k_apply_edit_multi,
-                        (const void *)k_apply_in_multi, (const void *)k_refresh_multi};
-    const int b[7] = {EW * WAVE, GT, 256, 256, 256, 256, 256};
-    for (int i = 0; i < 7; i++) {
+    const void *f[LF_MULTI_KERNELS] = {(const void *)k_eval_big_multi, (const void *)k_big_final_multi,
+                                       (const void *)k_big_tie_multi, (const void *)k_apply_edit_multi,
+                                       (const void *)k_apply_in_multi, (const void *)k_refresh_multi};
+    const int gr[LF_MULTI_KERNELS] = {0, 1, 1, 2, 3, 4};
+    const int b[LF_MULTI_KERNELS] = {GT, 256, 256, 256, 256, 256};
+    for (int i = 0; i < LF_MULTI_KERNELS; i++) {
         fn[i] = f[i];
+        grid[i] = gr[i];
         block[i] = b[i];
     }
 }

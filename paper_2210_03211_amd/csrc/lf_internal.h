@@ -138,7 +138,8 @@ struct Ctx {
 // evaluate workgroup-path nodes (one node per block at a time), the last bm blocks
 // medium-path nodes (one node per wave).
 struct BigRoles {
-    int bt, bg, bm;          // blocks per role
+    int bt, bg, bm, bs;      // blocks per role (table, workgroup, medium, small)
+    int ns;                  // small-path nodes in this launch (the rest: k_eval)
     int lt, nt;              // table-path list positions of the queue
     int lg, ng;              // workgroup-path list positions
     int lm, nm;              // medium-path list positions
@@ -333,7 +334,9 @@ void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool
                      QGrids *g);
 int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g);
 int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int cap, int nm, const int *total);
-void lf_multi_kernels(const void **fn, int *block);
+#define LF_MULTI_GRIDS 5         // per-step launches of a batch with grids of their own
+#define LF_MULTI_KERNELS 6       // kernels of a batch step (k_big_final and k_big_tie share a grid)
+void lf_multi_kernels(const void **fn, int *grid, int *block);
 int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long *live);
 int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
                      long long *live);
