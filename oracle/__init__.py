@@ -58,6 +58,7 @@ def lib():
         L.lfo_last_error.argtypes = [vp]
         L.lfo_load_graph.argtypes = [vp, i64, i64, vp, vp, u32]
         L.lfo_init_communities.argtypes = [vp, C.c_int]
+        L.lfo_init_from_memberships.argtypes = [vp, vp, vp, i64, i32, C.c_int]
         L.lfo_run_iterations.argtypes = [vp, i32, dbl, i32, i32, i32, i32, C.POINTER(RunInfo)]
         L.lfo_check_state.argtypes = [vp]
         L.lfo_check_state.restype = i64
@@ -134,6 +135,18 @@ class Oracle:
     def init_communities(self, nthreads=None):
         nthreads = nthreads or min(8, os.cpu_count() or 1)
         self._check(self.L.lfo_init_communities(self.h, int(nthreads)), "init_communities")
+        return self
+
+    def init_from_memberships(self, offsets, ids, n_comms=-1, nthreads=None):
+        """Warm start: the given cover (offsets[n + 1], ids) replaces the greedy initial
+        clustering; ids in [0, n_comms) (n_comms < 0: largest id + 1)."""
+        nthreads = nthreads or min(8, os.cpu_count() or 1)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        if offsets.size != self.n + 1:
+            raise OracleError("init_from_memberships: %d offsets for %d nodes" % (offsets.size, self.n))
+        self._check(self.L.lfo_init_from_memberships(self.h, _p(offsets), _p(ids), int(ids.size),
+                                                     int(n_comms), int(nthreads)), "init_from_memberships")
         return self
 
     def run_iterations(self, queue_size, threshold=0.01, max_iters=50, mode=MODE_FAST,

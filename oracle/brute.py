@@ -152,8 +152,9 @@ def _end_iteration(P):
             del P[c]
 
 
-def run(n, src, dst, queue_size, threshold=0.01, max_iters=50, sequential=False):
-    """LazyFox (or Fox with sequential=True) on a tiny graph, exactly.
+def run(n, src, dst, queue_size, threshold=0.01, max_iters=50, sequential=False, initial=None):
+    """LazyFox (or Fox with sequential=True) on a tiny graph, exactly.  ``initial`` (a dict
+    community id -> set of nodes) replaces the greedy initial clustering (warm start).
 
     Returns dict(memberships (per node sorted community ids), iterations, history of
     WCC-hat(P) (Fractions), cc, order, triangles, near_tie flag).
@@ -163,7 +164,7 @@ def run(n, src, dst, queue_size, threshold=0.01, max_iters=50, sequential=False)
     ccl = local_cc(adj, k)
     cc = sum(ccl, Fraction(0)) / n if n else Fraction(0)
     order = node_order(adj, ccl)
-    P = initial_clustering(adj, order)
+    P = initial_clustering(adj, order) if initial is None else {c: set(C) for c, C in initial.items()}
     hist = [wcc_hat_partition(P, adj, cc) if cc > 0 else Fraction(0)]
     near_tie = False
     its = 0

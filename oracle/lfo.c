@@ -10,6 +10,8 @@
  *   lfo_load_graph        Preprocessing: "Remove Multi-Edges", "Dense Node Labels"
  *   lfo_init_communities  Preprocessing: "Node Order" (clustering-coefficient equation),
  *                         "Initial Clustering"; global cc from the WCC-hat subsection
+ *   lfo_init_from_memberships  the same with an existing division in place of the greedy
+ *                         initial clustering ("Initial Clustering", last paragraph)
  *   eval_*                WCC-hat definition (mean-field triangle estimate, upper bounds on
  *                         vt, the per-node / per-community / per-partition sums) and
  *                         "Node Changes" (join and leave actions, Algorithm 1)
@@ -495,16 +497,10 @@ static double partition_score(const lfo *h)
     return xs_round(&a);
 }
 
-/*
- * Node statistics (triangles, local CC, node order, global cc) and the greedy initial
- * clustering: walk the nodes in order; a node without a community opens a new one, and
- * each of its neighbours that has no community yet joins it.
- */
-int lfo_init_communities(lfo *h, int nthreads)
+/* Node statistics: triangles, local CC, node order ("Node Order") and global cc */
+static void node_statistics(lfo *h, int nthreads)
 {
-    if (!h || !h->rowptr) return LFO_ESTATE;
     int64_t n = h->n;
-    free_partition(h);
     free(h->tri); free(h->ccl); free(h->order); free(h->rank);
     if (nthreads < 1) nthreads = 1;
     count_triangles(h, nthreads);
@@ -526,6 +522,33 @@ int lfo_init_communities(lfo *h, int nthreads)
     g_sort_h = h;
     qsort(h->order, (size_t)n, sizeof(int32_t), cmp_order);
     for (int64_t r = 0; r < n; r++) h->rank[h->order[r]] = (int32_t)r;
+}
+
+/* community arrays for K ids, all empty */
+static void alloc_partition(lfo *h, int32_t K)
+{
+    int64_t n = h->n;
+    h->K = K;
+    h->mem = (memb_t *)xcalloc((size_t)(n ? n : 1), sizeof(memb_t));
+    h->cm = (cmem_t *)xcalloc((size_t)(K ? K : 1), sizeof(cmem_t));
+    h->m = (int64_t *)xcalloc((size_t)(K ? K : 1), sizeof(int64_t));
+    h->W = (double *)xcalloc((size_t)(K ? K : 1), sizeof(double));
+    h->S0 = (xsum *)xcalloc((size_t)(K ? K : 1), sizeof(xsum));
+    h->Sp = (xsum *)xcalloc((size_t)(K ? K : 1), sizeof(xsum));
+    h->Sm = (xsum *)xcalloc((size_t)(K ? K : 1), sizeof(xsum));
+}
+
+/*
+ * Node statistics and the greedy initial clustering: walk the nodes in order; a node
+ * without a community opens a new one, and each of its neighbours that has no community
+ * yet joins it.
+ */
+int lfo_init_communities(lfo *h, int nthreads)
+{
+    if (!h || !h->rowptr) return LFO_ESTATE;
+    int64_t n = h->n;
+    free_partition(h);
+    node_statistics(h, nthreads);
 
     int32_t *comm_of = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
     for (int64_t x = 0; x < n; x++) comm_of[x] = -1;
@@ -538,14 +561,7 @@ int lfo_init_communities(lfo *h, int nthreads)
         for (int64_t e = h->rowptr[x]; e < h->rowptr[x + 1]; e++)
             if (comm_of[h->col[e]] < 0) comm_of[h->col[e]] = c;
     }
-    h->K = K;
-    h->mem = (memb_t *)xcalloc((size_t)(n ? n : 1), sizeof(memb_t));
-    h->cm = (cmem_t *)xcalloc((size_t)(K ? K : 1), sizeof(cmem_t));
-    h->m = (int64_t *)xcalloc((size_t)(K ? K : 1), sizeof(int64_t));
-    h->W = (double *)xcalloc((size_t)(K ? K : 1), sizeof(double));
-    h->S0 = (xsum *)xcalloc((size_t)(K ? K : 1), sizeof(xsum));
-    h->Sp = (xsum *)xcalloc((size_t)(K ? K : 1), sizeof(xsum));
-    h->Sm = (xsum *)xcalloc((size_t)(K ? K : 1), sizeof(xsum));
+    alloc_partition(h, K);
     for (int64_t x = 0; x < n; x++) {
         int32_t i = 0;
         for (int64_t e = h->rowptr[x]; e < h->rowptr[x + 1]; e++) i += comm_of[h->col[e]] == comm_of[x];
@@ -553,6 +569,68 @@ int lfo_init_communities(lfo *h, int nthreads)
         cmem_add(&h->cm[comm_of[x]], (int32_t)x);
     }
     free(comm_of);
+    for (int32_t c = 0; c < K; c++) refresh_comm(h, c);
+    h->Wt = partition_score(h);
+    h->inited = 1;
+    h->iter_done = 0;
+    return xs_err ? LFO_EOVERFLOW : LFO_OK;
+}
+
+/*
+ * Warm start ("Initial Clustering": an existing division of the network can take the
+ * place of the greedy one).  Node statistics and order are computed as for the greedy
+ * start; the given memberships become the partition.  offsets[n + 1] (offsets[0] = 0,
+ * non-decreasing, offsets[n] = total) and ids[total] list each node's communities in any
+ * order, each id in [0, n_comms) and at most once per node; n_comms < 0 takes the largest
+ * id + 1.  Empty and one-member communities are allowed, as after the greedy start.  Every
+ * maintained quantity (in-counts, sizes, internal edges, exact sums, scores) is counted
+ * from its definition.
+ */
+int lfo_init_from_memberships(lfo *h, const int64_t *offsets, const int32_t *ids, int64_t total,
+                              int32_t n_comms, int nthreads)
+{
+    if (!h || !h->rowptr) return LFO_ESTATE;
+    int64_t n = h->n;
+    if (!offsets || (total > 0 && !ids) || total < 0) return LFO_EINVAL;
+    if (offsets[0] != 0 || offsets[n] != total) {
+        snprintf(h->err, sizeof h->err, "offsets must start at 0 and end at total");
+        return LFO_EINVAL;
+    }
+    int64_t maxid = -1;
+    for (int64_t x = 0; x < n; x++) {
+        if (offsets[x + 1] < offsets[x]) {
+            snprintf(h->err, sizeof h->err, "offsets decrease at node %lld", (long long)x);
+            return LFO_EINVAL;
+        }
+        for (int64_t a = offsets[x]; a < offsets[x + 1]; a++) {
+            if (ids[a] < 0 || (n_comms >= 0 && ids[a] >= n_comms)) {
+                snprintf(h->err, sizeof h->err, "community id %d of node %lld out of range", ids[a], (long long)x);
+                return LFO_EINVAL;
+            }
+            if (ids[a] > maxid) maxid = ids[a];
+            for (int64_t b = offsets[x]; b < a; b++)
+                if (ids[b] == ids[a]) {
+                    snprintf(h->err, sizeof h->err, "node %lld lists community %d twice", (long long)x, ids[a]);
+                    return LFO_EINVAL;
+                }
+        }
+    }
+    int32_t K = n_comms >= 0 ? n_comms : (int32_t)(maxid + 1);
+    free_partition(h);
+    node_statistics(h, nthreads);
+    alloc_partition(h, K);
+    for (int64_t x = 0; x < n; x++)
+        for (int64_t a = offsets[x]; a < offsets[x + 1]; a++) {
+            memb_insert(&h->mem[x], ids[a], 0);
+            cmem_add(&h->cm[ids[a]], (int32_t)x);
+        }
+    /* i_x(C) = |N(x) ∩ C| for every membership, from the now complete member lists */
+    for (int64_t x = 0; x < n; x++)
+        for (int32_t j = 0; j < h->mem[x].cnt; j++) {
+            int32_t c = h->mem[x].comm[j], i = 0;
+            for (int64_t e = h->rowptr[x]; e < h->rowptr[x + 1]; e++) i += memb_find(&h->mem[h->col[e]], c) >= 0;
+            h->mem[x].in[j] = i;
+        }
     for (int32_t c = 0; c < K; c++) refresh_comm(h, c);
     h->Wt = partition_score(h);
     h->inited = 1;

@@ -412,3 +412,122 @@ def test_generator_is_deterministic():
     assert np.array_equal(a.src, b.src) and np.array_equal(a.dst, b.dst)
     c = G.named_config("copurchase", seed=4, scale=0.01)
     assert not (a.src.size == c.src.size and np.array_equal(a.src, c.src))
+
+
+# ------------------------------------------------------------------ warm start
+def random_cover(n, n_comms, seed, max_per_node=3):
+    """Random overlapping cover with gaps in the ids, unsorted per node: (offsets, ids, P)."""
+    rng = random.Random(seed)
+    P = {}
+    per = []
+    for x in range(n):
+        k = rng.randint(0, max_per_node)
+        cs = rng.sample(range(n_comms), k)
+        per.append(cs)
+        for c in cs:
+            P.setdefault(c, set()).add(x)
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(c) for c in per])
+    ids = np.array([c for cs in per for c in cs], np.int32)
+    return off, ids, P
+
+
+def test_warm_start_from_greedy_clustering_is_the_cold_start(oracle_lib):
+    """Initial Clustering: inserting the greedy clustering as an existing division gives the
+    same state and the same run as the greedy start itself."""
+    g = G.named_config("tiny_sbm")
+    cold = load(oracle_lib, g)
+    off, ids = cold.memberships()
+    K = cold.communities()[0].size
+    warm = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(off, ids, K, 2)
+    assert warm.check_state() == 0
+    assert np.array_equal(warm.in_counts(), cold.in_counts())
+    for a, b in zip(warm.communities(), cold.communities()):
+        assert np.array_equal(a, b)
+    assert warm.scores()["wtilde"] == cold.scores()["wtilde"]
+    ia = cold.run_iterations(64, 0.01, 50)
+    ib = warm.run_iterations(64, 0.01, 50)
+    assert ia["iterations"] == ib["iterations"]
+    assert np.array_equal(ia["wtilde_hist"], ib["wtilde_hist"])
+    assert memberships_list(cold) == memberships_list(warm)
+
+
+def test_warm_start_score_and_in_counts_match_exact_rationals(oracle_lib):
+    """WCC-hat subsection: for random overlapping covers (empty and one-member communities
+    included), the warm-started in-counts are |N(x) ∩ C| and the partition score is the
+    exact rational WCC-hat (times cc) rounded once."""
+    for seed in range(10):
+        g = G.random_gnp(18, 0.3, 3000 + seed)
+        off, ids, P = random_cover(g.n, 9, seed)
+        o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(off, ids, 12, 1)
+        assert o.check_state() == 0
+        adj = brute.simple_graph(g.n, g.src, g.dst)
+        ooff, oids = o.memberships()
+        inc = o.in_counts()
+        for x in range(g.n):
+            cs = oids[ooff[x]:ooff[x + 1]].tolist()
+            assert cs == sorted(ids[off[x]:off[x + 1]].tolist())
+            for c, i in zip(cs, inc[ooff[x]:ooff[x + 1]].tolist()):
+                assert i == len(adj[x] & P[c])
+        k = brute.triangles(adj)
+        cc = sum(brute.local_cc(adj, k), Fraction(0)) / g.n
+        w = brute.wcc_hat_partition(P, adj, cc)
+        sc = o.scores()
+        assert abs(sc["wtilde"] / sc["cc"] - float(w)) <= 1e-12 * float(w)
+
+
+def test_warm_start_runs_match_brute_force(oracle_lib):
+    """Algorithm 2 from random existing covers against the exact brute force."""
+    done = 0
+    for seed in range(15):
+        g = G.random_gnp(15, 0.3, 4000 + seed)
+        off, ids, P = random_cover(g.n, 8, 50 + seed, max_per_node=2)
+        for q in (3, 15):
+            b = brute.run(g.n, g.src, g.dst, q, 0.01, 15, initial=P)
+            o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(off, ids, -1, 1)
+            info = o.run_iterations(q, 0.01, 15, mode=3, nthreads=2, check_every_chunk=True)
+            if b["near_tie"]:
+                continue
+            assert memberships_list(o) == b["memberships"]
+            assert info["iterations"] == b["iterations"]
+            done += 1
+    assert done >= 20
+
+
+def test_resume_from_memberships_continues_the_run(oracle_lib):
+    """Checkpoint and resume: stopping after k iterations and warm-starting from the
+    memberships reached gives the uninterrupted run's remaining iterations (the state is a
+    function of the memberships; the first resumed iteration compares with the score of the
+    partition it starts from, which is the score the uninterrupted run reached)."""
+    g = G.named_config("copurchase", scale=0.01)
+    full = load(oracle_lib, g)
+    fi = full.run_iterations(32, 0.001, 50)
+    assert fi["iterations"] >= 4
+    for k in (1, 3):
+        part = load(oracle_lib, g)
+        part.run_iterations(32, 0.001, k)
+        off, ids = part.memberships()
+        K = part.communities()[0].size
+        res = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(off, ids, K, 2)
+        assert res.scores()["wtilde"] == fi["wtilde_hist"][k]
+        ri = res.run_iterations(32, 0.001, 50)
+        assert ri["iterations"] == fi["iterations"] - k
+        assert np.array_equal(ri["wtilde_hist"], fi["wtilde_hist"][k:])
+        assert memberships_list(res) == memberships_list(full)
+
+
+def test_warm_start_rejects_bad_covers(oracle_lib):
+    g = G.random_gnp(10, 0.4, 1)
+    o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst)
+    off = np.arange(g.n + 1, dtype=np.int64)
+    with pytest.raises(oracle_lib.OracleError):
+        o.init_from_memberships(off, np.full(g.n, 5, np.int32), 3)          # id out of range
+    dup = np.concatenate([[0], np.full(g.n, 2, np.int64)])
+    with pytest.raises(oracle_lib.OracleError):
+        o.init_from_memberships(dup, np.array([1, 1], np.int32), 3)        # node 0 lists 1 twice
+    bad_total = off.copy()
+    bad_total[-1] += 1
+    with pytest.raises(oracle_lib.OracleError):
+        o.init_from_memberships(bad_total, np.zeros(g.n, np.int32), 3)     # offsets[n] != total
+    with pytest.raises(oracle_lib.OracleError):
+        o.init_from_memberships(off[:-1].copy(), np.zeros(g.n - 1, np.int32), 3)   # n offsets
