@@ -134,6 +134,34 @@ def cpu_baseline(args, wl):
                       % (100 * args.cpu_sample_scale, o.n, o.nedges, q, info["iterations"], dt)}
 
 
+def warm_start_bench(h, reps):
+    """Rebuild of the whole state from the final cover of the timed steps (device arrays)
+    with lf_init_from_memberships; the rebuilt partition must score exactly the same."""
+    import torch
+    off, ids = h.get_memberships()
+    K = h.lf_get_graph_info()[2]
+    want = h.scores()["wtilde"]
+    doff = torch.from_numpy(off).cuda()
+    dids = torch.from_numpy(ids).cuda()
+    h.lf_set_profiling(0)
+    h.init_from_memberships(doff, dids, K)          # warm-up (allocations, node statistics kept)
+    times = []
+    for _ in range(max(1, reps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.init_from_memberships(doff, dids, K)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    if h.scores()["wtilde"] != want:
+        print("[bench] ERROR: warm start changed the partition score", file=sys.stderr)
+        sys.exit(1)
+    ms = 1000.0 * sum(times) / len(times)
+    print("[bench] warm start: %.2f ms for %d memberships" % (ms, ids.size), file=sys.stderr, flush=True)
+    return {"ms": ms, "memberships": int(ids.size), "communities": int(K),
+            "memberships_per_s": ids.size / (ms * 1e-3), "what": "lf_init_from_memberships of the final "
+            "cover (device arrays): checks, slots and in-counts, member lists, exact statistics, score"}
+
+
 def serving_bench(args, lf):
     """The serving mix (Poisson arrivals, graphs of uneven size) served two ways on the
     same GPU and trace: the server with continuous batching, and plain one-at-a-time runs
@@ -328,6 +356,7 @@ def main():
     }
     if tuned is not None:
         out["autotune"] = tuned
+    out["warm_start"] = warm_start_bench(h, args.steps)
     if args.sweep:
         sweep = {}
         for qq in [int(x) for x in args.sweep.split(",") if x]:

@@ -35,6 +35,18 @@ class Graph:
     dst: np.ndarray          # int64 [npairs]
     planted: list | None = None   # planted communities (list of int64 arrays), for reference only
     meta: dict = dataclasses.field(default_factory=dict)
+    planted_pairs: tuple | None = None   # planted memberships as (node, community) int64 arrays
+
+    def planted_cover(self):
+        """Planted memberships as (offsets int64[n + 1], community ids int32), per node in
+        ascending id order; None if the generator plants none."""
+        if self.planted_pairs is None:
+            return None
+        node, comm = self.planted_pairs
+        o = np.lexsort((comm, node))
+        off = np.zeros(self.n + 1, np.int64)
+        np.cumsum(np.bincount(node, minlength=self.n), out=off[1:])
+        return off, comm[o].astype(np.int32)
 
     @property
     def npairs(self) -> int:
@@ -224,7 +236,8 @@ def planted_powerlaw(n, target_edges, deg_exp, deg_max, deg_min_floor, mem_max, 
     meta = dict(kind="planted_powerlaw", n=n, deg_exp=deg_exp, deg_max=deg_max, cutoff=cut,
                 mem_max=mem_max, size_exp=size_exp, size_min=smin, size_max=smax, mu=mu,
                 seed=seed, communities=int(sizes.size), raw_pairs=int(src.size))
-    return Graph(n, src.astype(np.int64), dst.astype(np.int64), None, meta)
+    return Graph(n, src.astype(np.int64), dst.astype(np.int64), None, meta,
+                 (mnode.astype(np.int64), mcomm.astype(np.int64)))
 
 
 def planted_sbm(n=2000, ncomm=20, size_lo=50, size_hi=200, p_two=0.2, p_in=0.15, mix=0.2, seed=0):
@@ -281,7 +294,8 @@ def planted_sbm(n=2000, ncomm=20, size_lo=50, size_hi=200, p_two=0.2, p_in=0.15,
     src, dst = np.where(flip, dst, src), np.where(flip, src, dst)
     meta = dict(kind="planted_sbm", n=n, ncomm=ncomm, p_in=p_in, mix=mix, seed=seed,
                 intra=int(intra), inter=int(inter_keys.size))
-    return Graph(n, src.astype(np.int64), dst.astype(np.int64), planted, meta)
+    return Graph(n, src.astype(np.int64), dst.astype(np.int64), planted, meta,
+                 (mnode.astype(np.int64), mcomm.astype(np.int64)))
 
 
 # ---------------------------------------------------------------- named workloads

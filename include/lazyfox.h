@@ -139,6 +139,28 @@ int lf_load_graph(lf_handle *h, int64_t n, int64_t n_pairs, const int64_t *src,
 int lf_init_communities(lf_handle *h);
 
 /*
+ * Warm start (Methods, "Initial Clustering", last paragraph: an existing division of the
+ * network can take the place of the greedy initial clustering, for instance a partition to
+ * be turned into an overlapping cover, or the memberships saved from an earlier run to
+ * resume it).  Node statistics and order as for lf_init_communities; the given cover then
+ * becomes the partition and every maintained quantity (in-counts, sizes, internal edges,
+ * exact sums, scores) is counted from its definition, so resuming from the memberships
+ * after k iterations continues that run exactly.
+ *   offsets   int64[n + 1], offsets[0] = 0, non-decreasing, offsets[n] = total
+ *   comm_ids  int32[total]: node x's communities at [offsets[x], offsets[x + 1]), any
+ *             order, each in [0, n_comms) and at most once per node; ids are kept as given
+ *             (empty and one-member communities are allowed; the first iteration end
+ *             removes those with fewer than two members)
+ *   n_comms   number of community ids; < 0: the largest id + 1
+ *   flags     LF_DEVICE_PTR: both arrays are device pointers (else host); read only
+ * The library copies what it needs; the caller keeps ownership of both arrays.
+ * Errors: LF_ESTATE (no graph), LF_EINVAL (bad offsets, id out of range, an id twice for
+ * a node; the previous partition is then kept), LF_EOVERFLOW, LF_ENOMEM, LF_EDEVICE.
+ */
+int lf_init_from_memberships(lf_handle *h, const int64_t *offsets, const int32_t *comm_ids,
+                             int64_t total, int32_t n_comms, uint32_t flags);
+
+/*
  * LazyFox iterations (Methods, "Node Changes", Algorithm 2, "Stopping Criteria",
  * "Post-processing").  Each iteration walks the node order in consecutive queues of
  * `queue_size` nodes (the last one partial); every node of a queue gets its best join

@@ -68,6 +68,7 @@ def load_library():
         "lf_destroy": [vp],
         "lf_load_graph": [vp, i64, i64, vp, vp, u32],
         "lf_init_communities": [vp],
+        "lf_init_from_memberships": [vp, vp, vp, i64, i32, u32],
         "lf_run_iterations": [vp, i32, dbl, i32, C.POINTER(RunInfo)],
         "lf_get_memberships": [vp, vp, vp, i64, C.POINTER(i64)],
         "lf_get_graph_info": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
@@ -196,6 +197,27 @@ class Handle:
         return self
 
     init_communities = lf_init_communities
+
+    def lf_init_from_memberships(self, offsets, comm_ids, n_comms=-1):
+        """Warm start from an existing cover: offsets int64[n + 1], comm_ids int32 (both
+        numpy arrays or both device tensors); n_comms < 0 takes the largest id + 1."""
+        po, do = _ptr(offsets)
+        pc, dc = _ptr(comm_ids)
+        if do != dc:
+            raise ValueError("offsets and comm_ids must both be host or both be device arrays")
+        if str(getattr(offsets, "dtype", "")) not in ("int64", "torch.int64"):
+            raise TypeError("offsets must be int64")
+        if str(getattr(comm_ids, "dtype", "")) not in ("int32", "torch.int32"):
+            raise TypeError("comm_ids must be int32")
+        n = self.lf_get_graph_info()[0]
+        if int(offsets.shape[0]) != n + 1:
+            raise ValueError("offsets must have n + 1 = %d entries" % (n + 1))
+        total = int(comm_ids.shape[0])
+        self._check(self.L.lf_init_from_memberships(self.h, C.c_void_p(po), C.c_void_p(pc), total, int(n_comms),
+                                                    LF_DEVICE_PTR if do else 0), "lf_init_from_memberships")
+        return self
+
+    init_from_memberships = lf_init_from_memberships
 
     def lf_run_iterations(self, queue_size, threshold=0.01, max_iters=50):
         hist = np.zeros(max_iters + 1, np.float64)

@@ -153,6 +153,43 @@ int lf_init_communities(lf_handle *h)
     return LF_OK;
 }
 
+int lf_init_from_memberships(lf_handle *h, const int64_t *offsets, const int32_t *comm_ids, int64_t total,
+                             int32_t n_comms, uint32_t flags)
+{
+    if (!h) return LF_EINVAL;
+    if (h->state < 1) return lf_set_error(h, LF_ESTATE, "lf_load_graph has not been called");
+    if (!offsets || total < 0 || (total > 0 && !comm_ids))
+        return lf_set_error(h, LF_EINVAL, "null cover arrays or negative total");
+    if (total + h->n >= (1ll << 31) - 1) return lf_set_error(h, LF_EOVERFLOW, "cover too large");
+    LF_HIP(h, hipSetDevice(h->device));
+    if (h->state == 1 || !h->order) {
+        void **ptrs[] = {(void **)&h->tri, (void **)&h->ccl, (void **)&h->order, (void **)&h->rank};
+        for (void **p : ptrs) {
+            lf_dev_free(h, *p);
+            *p = nullptr;
+        }
+        h->state = 1;
+        LF_TRY(lf_node_stats(h));
+    }
+    TmpScope tmp_scope(h);
+    const long long *doff = (const long long *)offsets;
+    const int *dids = comm_ids;
+    if (!(flags & LF_DEVICE_PTR)) {          // host arrays: staged into device temporaries
+        long long *o = nullptr;
+        int *c = nullptr;
+        LF_TRY(lf_tmp_alloc(h, (void **)&o, sizeof(long long) * (h->n + 1)));
+        LF_TRY(lf_tmp_alloc(h, (void **)&c, sizeof(int) * (total > 0 ? total : 1)));
+        LF_HIP(h, hipMemcpyAsync(o, offsets, sizeof(long long) * (h->n + 1), hipMemcpyHostToDevice, h->stream));
+        if (total > 0)
+            LF_HIP(h, hipMemcpyAsync(c, comm_ids, sizeof(int) * total, hipMemcpyHostToDevice, h->stream));
+        doff = o;
+        dids = c;
+    }
+    LF_TRY(lf_partition_from_cover(h, doff, dids, total, n_comms));
+    h->state = 2;
+    return LF_OK;
+}
+
 int lf_run_iterations(lf_handle *h, int32_t queue_size, double threshold, int32_t max_iters, lf_run_info *out)
 {
     if (!h) return LF_EINVAL;

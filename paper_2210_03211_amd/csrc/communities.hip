@@ -132,6 +132,73 @@ __global__ void __launch_bounds__(256) k_init_slots(const long long *rowptr, con
     }
 }
 
+// warm start: checks of a given cover (one wave per node): offsets non-decreasing within
+// [0, total] (bit 0), ids in [0, K) (bit 1; K < 0: any id >= 0), no id twice per node
+// (bit 2); chk[1] = largest id
+__global__ void __launch_bounds__(256) k_cover_check(const long long *off, const int *ids, long long n,
+                                                     long long total, int K, int *chk)
+{
+    long long x = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
+    int lane = threadIdx.x & (WAVE - 1);
+    if (x >= n) return;
+    const long long a0 = off[x], a1 = off[x + 1];
+    if (a0 < 0 || a1 < a0 || a1 > total) {
+        if (lane == 0) atomicOr(&chk[0], 1);
+        return;
+    }
+    int err = 0, mx = -1;
+    for (long long a = a0 + lane; a < a1; a += WAVE) {
+        const int c = ids[a];
+        if (c < 0 || (K >= 0 && c >= K)) err |= 2;
+        if (c > mx) mx = c;
+        for (long long b = a0; b < a; b++) err |= ids[b] == c ? 4 : 0;
+    }
+    if (err) atomicOr(&chk[0], err);
+    if (mx >= 0) atomicMax(&chk[1], mx);
+}
+
+// warm start: node x's memberships in the given order plus one free slot (slot offset
+// off[x] + x); in-count of each = neighbours whose cover lists the community; sizes
+__global__ void __launch_bounds__(256) k_cover_slots(const long long *rowptr, const int *col, const int *deg,
+                                                     const long long *off, const int *ids, long long n, NodeHdr *nh,
+                                                     Slot *slot, CommRec *cr)
+{
+    long long x = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
+    int lane = threadIdx.x & (WAVE - 1);
+    if (x > n) return;
+    if (x == n) {
+        if (lane == 0) { nh[n].off = off[n] + n; nh[n].cnt = 0; nh[n].deg = 0; }
+        return;
+    }
+    const long long a0 = off[x];
+    const int cnt = (int)(off[x + 1] - a0);
+    const long long base = a0 + x;
+    for (int a = 0; a < cnt; a++) {
+        const int c = ids[a0 + a];
+        int in = 0;
+        for (long long e = rowptr[x] + lane; e < rowptr[x + 1]; e += WAVE) {
+            const int z = col[e];
+            for (long long b = off[z]; b < off[z + 1]; b++)
+                if (ids[b] == c) { in++; break; }
+        }
+        in = wave_sum_int(in);
+        if (lane == 0) {
+            Slot sl = {c, in};
+            slot[base + a] = sl;
+            atomicAdd(&cr[c].s, 1);
+        }
+    }
+    if (lane == 0) {
+        NodeHdr hd;
+        hd.off = base;
+        hd.cnt = cnt;
+        hd.deg = deg[x];
+        nh[x] = hd;
+        Slot free_slot = {-1, 0};
+        slot[base + cnt] = free_slot;
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // member lists (rebuilt at initialisation and at every iteration end)
 // ------------------------------------------------------------------------------------
@@ -446,6 +513,9 @@ int lf_check_dev_error(lf_handle *h)
     return LF_OK;
 }
 
+static int alloc_partition_state(lf_handle *h, long long K, long long slots);
+static int finish_partition(lf_handle *h);
+
 int lf_initial_clustering(lf_handle *h)
 {
     TmpScope tmp_scope(h);
@@ -500,11 +570,28 @@ int lf_initial_clustering(lf_handle *h)
     LF_HIP(h, hipGetLastError());
     long long K = lastp + lastf;
     if (K >= (1ll << 31) - 1) return lf_set_error(h, LF_EOVERFLOW, "too many communities");
+    LF_TRY(alloc_partition_state(h, K, 2 * n));
+    if (n >= 0)
+        hipLaunchKernelGGL(k_init_slots, dim3(grid_for((n + 1) * WAVE, BS)), dim3(BS), 0, st, h->rowptr, h->col,
+                           h->deg, comm_of, n, h->nh, h->slot[0], h->cr);
+    LF_TRY(finish_partition(h));
+    LF_TRY(lf_prof_end(h, LF_K_INITCLUST, rounds + 8));
+    LF_TRY(lf_prof_flush(h));
+    LF_TRY(lf_check_dev_error(h));
+    return LF_OK;
+}
+
+// Partition arrays for K community ids and slot storage for `slots` memberships (at least
+// one); community records zeroed, no member lists yet.
+static int alloc_partition_state(lf_handle *h, long long K, long long slots)
+{
+    hipStream_t st = h->stream;
+    long long n = h->n;
+    size_t nn = (size_t)(n > 0 ? n : 1);
     h->K = (int)K;
     size_t KK = (size_t)(K > 0 ? K : 1);
-    // partition state
     LF_TRY(lf_dev_alloc(h, (void **)&h->nh, sizeof(NodeHdr) * (nn + 1)));
-    h->slot_capb[0] = h->slot_capb[1] = 2 * (n > 0 ? n : 1);
+    h->slot_capb[0] = h->slot_capb[1] = slots > 0 ? slots : 1;
     LF_TRY(lf_dev_alloc(h, (void **)&h->slot[0], sizeof(Slot) * h->slot_capb[0]));
     LF_TRY(lf_dev_alloc(h, (void **)&h->slot[1], sizeof(Slot) * h->slot_capb[1]));
     h->cur = 0;
@@ -530,11 +617,17 @@ int lf_initial_clustering(lf_handle *h)
     LF_HIP(h, hipMemsetAsync(h->ovf_flag, 0, sizeof(int) * KK, st));
     LF_HIP(h, hipMemsetAsync(h->joined_to, 0xff, sizeof(unsigned long long) * nn, st));
     h->qtag = 0;
-    if (n >= 0)
-        hipLaunchKernelGGL(k_init_slots, dim3(grid_for((n + 1) * WAVE, BS)), dim3(BS), 0, st, h->rowptr, h->col,
-                           h->deg, comm_of, n, h->nh, h->slot[0], h->cr);
+    return LF_OK;
+}
+
+// With slots, headers and community sizes written: member lists, every community's
+// statistics (internal edges, exact sums, score) and the partition score.
+static int finish_partition(lf_handle *h)
+{
+    hipStream_t st = h->stream;
+    const int BS = 256;
+    const long long K = h->K;
     LF_TRY(rebuild_member_lists(h));
-    // every community's statistics
     if (K > 0) hipLaunchKernelGGL(k_iota, dim3(grid_for(K, BS)), dim3(BS), 0, st, h->tlist, K);
     LF_HIP(h, hipMemsetAsync(&h->ctr->refresh_next, 0, sizeof(int), st));
     Ctx cx = lf_ctx(h);
@@ -544,7 +637,50 @@ int lf_initial_clustering(lf_handle *h)
     hipLaunchKernelGGL(k_refresh_list, dim3(rb), dim3(256), 0, st, cx, (int)K);
     LF_HIP(h, hipGetLastError());
     LF_TRY(partition_score(h, &h->Wt));
-    LF_TRY(lf_prof_end(h, LF_K_INITCLUST, rounds + 8));
+    return LF_OK;
+}
+
+// Warm start from an existing cover (Initial Clustering, last paragraph: an existing
+// division can replace the greedy one).  off[n + 1] / ids[total] on the device, each
+// node's communities in any order.  Node statistics must exist.
+int lf_partition_from_cover(lf_handle *h, const long long *off, const int *ids, long long total, int n_comms)
+{
+    TmpScope tmp_scope(h);
+    hipStream_t st = h->stream;
+    const int BS = 256;
+    const long long n = h->n;
+    long long ends[2] = {0, 0};
+    LF_HIP(h, hipMemcpyAsync(&ends[0], off, sizeof(long long), hipMemcpyDeviceToHost, st));
+    LF_HIP(h, hipMemcpyAsync(&ends[1], off + n, sizeof(long long), hipMemcpyDeviceToHost, st));
+    LF_HIP(h, hipStreamSynchronize(st));
+    if (ends[0] != 0 || ends[1] != total)
+        return lf_set_error(h, LF_EINVAL, "cover offsets must start at 0 and end at total (%lld)", total);
+    int *chk = nullptr;                      // [0] error bits, [1] largest id
+    LF_TRY(lf_tmp_alloc(h, (void **)&chk, 2 * sizeof(int)));
+    const int init[2] = {0, -1};
+    LF_HIP(h, hipMemcpyAsync(chk, init, sizeof init, hipMemcpyHostToDevice, st));
+    if (n > 0)
+        hipLaunchKernelGGL(k_cover_check, dim3(grid_for(n * WAVE, BS)), dim3(BS), 0, st, off, ids, n, total,
+                           n_comms, chk);
+    int hc[2];
+    LF_HIP(h, hipMemcpyAsync(hc, chk, sizeof hc, hipMemcpyDeviceToHost, st));
+    LF_HIP(h, hipStreamSynchronize(st));
+    LF_HIP(h, hipGetLastError());
+    if (hc[0] & 1) return lf_set_error(h, LF_EINVAL, "cover offsets decrease or leave [0, total]");
+    if (hc[0] & 2) return lf_set_error(h, LF_EINVAL, "a community id is negative or not below n_comms");
+    if (hc[0] & 4) return lf_set_error(h, LF_EINVAL, "a node lists a community twice");
+    const long long K = n_comms >= 0 ? n_comms : (long long)hc[1] + 1;
+    if (K >= (1ll << 31) - 1) return lf_set_error(h, LF_EOVERFLOW, "too many communities");
+    h->state = 1;                            // the previous partition is gone from here on
+    lf_free_partition(h);
+    LF_TRY(lf_dev_alloc(h, (void **)&h->ctr, sizeof(DevCounters)));
+    LF_HIP(h, hipMemsetAsync(h->ctr, 0, sizeof(DevCounters), st));
+    LF_TRY(lf_prof_begin(h, LF_K_INITCLUST));
+    LF_TRY(alloc_partition_state(h, K, total + n));
+    hipLaunchKernelGGL(k_cover_slots, dim3(grid_for((n + 1) * WAVE, BS)), dim3(BS), 0, st, h->rowptr, h->col,
+                       h->deg, off, ids, n, h->nh, h->slot[0], h->cr);
+    LF_TRY(finish_partition(h));
+    LF_TRY(lf_prof_end(h, LF_K_INITCLUST, 8));
     LF_TRY(lf_prof_flush(h));
     LF_TRY(lf_check_dev_error(h));
     return LF_OK;

@@ -326,6 +326,7 @@ int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out);
 
 // ---- community stages (communities.hip) ----------------------------------------------------
 int lf_initial_clustering(lf_handle *h);
+int lf_partition_from_cover(lf_handle *h, const long long *off, const int *ids, long long total, int n_comms);
 int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out);
 // one LazyFox iteration split into its host steps (shared by lf_run_iterations and the
 // multi-graph batch): sizing and path lists, per-queue parameters, and the iteration end

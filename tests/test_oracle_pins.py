@@ -510,8 +510,9 @@ def test_resume_from_memberships_continues_the_run(oracle_lib):
         K = part.communities()[0].size
         res = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(off, ids, K, 2)
         assert res.scores()["wtilde"] == fi["wtilde_hist"][k]
-        ri = res.run_iterations(32, 0.001, 50)
+        ri = res.run_iterations(32, 0.001, 50 - k)
         assert ri["iterations"] == fi["iterations"] - k
+        assert ri["converged"] == fi["converged"] and ri["hit_max"] == fi["hit_max"]
         assert np.array_equal(ri["wtilde_hist"], fi["wtilde_hist"][k:])
         assert memberships_list(res) == memberships_list(full)
 
