@@ -59,6 +59,8 @@ def lib():
         L.lfo_load_graph.argtypes = [vp, i64, i64, vp, vp, u32]
         L.lfo_init_communities.argtypes = [vp, C.c_int]
         L.lfo_init_from_memberships.argtypes = [vp, vp, vp, i64, i32, C.c_int]
+        L.lfo_exact_wcc.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
+        L.lfo_wcc_sample.argtypes = [vp, vp, i64, vp, vp, vp, vp]
         L.lfo_run_iterations.argtypes = [vp, i32, dbl, i32, i32, i32, i32, C.POINTER(RunInfo)]
         L.lfo_check_state.argtypes = [vp]
         L.lfo_check_state.restype = i64
@@ -170,6 +172,38 @@ class Oracle:
                     wcc_hat=info.wcc_hat, wtilde=info.wtilde, wtilde_hist=hist[: it + 1].copy(),
                     joins=joins[:it].copy(), leaves=leaves[:it].copy(),
                     communities=comms[:it].copy())
+
+    def exact_wcc(self, nthreads=None):
+        """Exact WCC of the current partition: dict(wcc, per-community wcc_comm[K], and per
+        membership in the memberships() order: wcc_node, t (t(x,C)), vt_out (vt(x, V\\C));
+        vt[n] = vt(x, V))."""
+        nthreads = nthreads or min(8, os.cpu_count() or 1)
+        off, ids = self.memberships()
+        K = int(self.L.lfo_num_communities_created(self.h))
+        tot = ids.size
+        wcc = C.c_double()
+        wc = np.zeros(max(1, K), np.float64)
+        wn = np.zeros(max(1, tot), np.float64)
+        t = np.zeros(max(1, tot), np.int32)
+        vo = np.zeros(max(1, tot), np.int32)
+        vx = np.zeros(max(1, self.n), np.int32)
+        self._check(self.L.lfo_exact_wcc(self.h, int(nthreads), C.byref(wcc), _p(wc), _p(wn), _p(t), _p(vo), _p(vx)),
+                    "exact_wcc")
+        return dict(wcc=wcc.value, wcc_comm=wc[:K], wcc_node=wn[:tot], t=t[:tot], vt_out=vo[:tot], vt=vx[:self.n])
+
+    def wcc_sample(self, nodes):
+        """WCC terms of the listed nodes only: (wcc_node, t, vt_out) over their memberships
+        (ascending ids, node after node) and vt per node."""
+        nodes = np.ascontiguousarray(nodes, dtype=np.int32)
+        off, ids = self.memberships()
+        tot = int(sum(off[x + 1] - off[x] for x in nodes))
+        wn = np.zeros(max(1, tot), np.float64)
+        t = np.zeros(max(1, tot), np.int32)
+        vo = np.zeros(max(1, tot), np.int32)
+        vx = np.zeros(max(1, nodes.size), np.int32)
+        self._check(self.L.lfo_wcc_sample(self.h, _p(nodes), int(nodes.size), _p(wn), _p(t), _p(vo), _p(vx)),
+                    "wcc_sample")
+        return wn[:tot], t[:tot], vo[:tot], vx[:nodes.size]
 
     def check_state(self):
         return int(self.L.lfo_check_state(self.h))

@@ -204,3 +204,20 @@ def run(n, src, dst, queue_size, threshold=0.01, max_iters=50, sequential=False,
     mem = [sorted(c for c, C in P.items() if x in C) for x in range(n)]
     return dict(memberships=mem, iterations=its, history=hist, cc=cc, order=order,
                 triangles=k, near_tie=near_tie, partition=P, adj=adj)
+
+
+def wcc_exact(adj, P):
+    """WCC of cover P (dict id -> set of nodes) from its definition (WCC paragraph of the
+    WCC-hat subsection), exactly: per membership (x, C) the tuple (t(x,C), vt(x, V\\C),
+    WCC(x,C) as a Fraction), vt(x, V) per node, and WCC(P)."""
+    n = len(adj)
+    tri = triangles(adj)
+    closes = [{y for y in adj[x] if adj[x] & adj[y]} for x in range(n)]
+    terms = {}
+    for c, C in P.items():
+        for x in C:
+            t = sum(1 for y in adj[x] & C for z in adj[x] & C if y < z and z in adj[y])
+            out = len(closes[x] - C)
+            w = Fraction(t, tri[x]) * Fraction(len(closes[x]), len(C) - 1 + out) if tri[x] else Fraction(0)
+            terms[(x, c)] = (t, out, w)
+    return terms, [len(s) for s in closes], sum((v[2] for v in terms.values()), Fraction(0))

@@ -18,6 +18,8 @@
  *   run_chunk             Algorithm 2: a queue of q nodes is evaluated on one frozen state,
  *                         then all changes are applied together
  *   end_iteration         "Stopping Criteria" and "Post-processing" (degenerate communities)
+ *   lfo_exact_wcc         WCC of a partition from exact triangle counts (WCC paragraph of the
+ *                         WCC-hat subsection), to set beside the WCC-hat estimate
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *  - self-loops are dropped; node order ties: degree descending, then id ascending;
@@ -1036,6 +1038,130 @@ int lfo_get_memberships(lfo *h, int64_t *offsets, int32_t *comm_ids, int64_t cap
         for (int32_t a = 0; a < h->mem[x].cnt; a++) comm_ids[p++] = h->mem[x].comm[a];
     }
     offsets[h->n] = p;
+    return LFO_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Exact WCC of the current partition (WCC paragraph of the WCC-hat subsection)          */
+/* ------------------------------------------------------------------------------------ */
+static int row_has(const lfo *h, int32_t x, int32_t z)   /* z in N(x)? (rows are sorted) */
+{
+    int64_t lo = h->rowptr[x], hi = h->rowptr[x + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (h->col[mid] == z) return 1;
+        if (h->col[mid] < z) lo = mid + 1; else hi = mid - 1;
+    }
+    return 0;
+}
+
+/*
+ * The WCC terms of node x, one per community C of x (ascending ids):
+ *   t(x,C)     triangles of x whose two other nodes are both in C,
+ *   t(x,V)     all triangles of x (k_x),
+ *   vt(x,S)    nodes of S that close at least one triangle with x (the third node anywhere),
+ *   WCC(x,C) = t(x,C) / t(x,V) * vt(x,V) / (|C \ {x}| + vt(x,V \ C)), 0 if t(x,V) = 0,
+ * evaluated in FP64 as  (t / t_V) * (vt_V / (|C| - 1 + vt_{V\C}))  (three roundings).
+ * Outputs t, vtc, w per community of x, and *vtx = vt(x,V).
+ */
+static void wcc_node_terms(const lfo *h, int32_t x, int32_t *has, int32_t *t, int32_t *vtc, double *w,
+                           int32_t *vtx)
+{
+    const int64_t r0 = h->rowptr[x], d = h->rowptr[x + 1] - r0;
+    int32_t vt = 0;
+    for (int64_t a = 0; a < d; a++) {          /* does the edge x-y close a triangle? */
+        int32_t y = h->col[r0 + a];
+        has[a] = 0;
+        for (int64_t f = h->rowptr[y]; f < h->rowptr[y + 1] && !has[a]; f++) has[a] = row_has(h, x, h->col[f]);
+        vt += has[a];
+    }
+    *vtx = vt;
+    const memb_t *mx = &h->mem[x];
+    for (int32_t k = 0; k < mx->cnt; k++) {
+        const int32_t c = mx->comm[k];
+        int64_t twice = 0;
+        int32_t out = 0;
+        for (int64_t a = 0; a < d; a++) {
+            int32_t y = h->col[r0 + a];
+            const int y_in = memb_find(&h->mem[y], c) >= 0;
+            if (has[a] && !y_in) out++;
+            if (!y_in) continue;
+            for (int64_t f = h->rowptr[y]; f < h->rowptr[y + 1]; f++) {
+                int32_t z = h->col[f];
+                if (memb_find(&h->mem[z], c) >= 0 && row_has(h, x, z)) twice++;   /* each pair twice */
+            }
+        }
+        t[k] = (int32_t)(twice / 2);
+        vtc[k] = out;
+        const int64_t kx = h->tri[x], s = h->cm[c].cnt;
+        w[k] = kx > 0 ? ((double)t[k] / (double)kx) * ((double)vt / (double)(s - 1 + out)) : 0.0;
+    }
+}
+
+/*
+ * WCC(P) = sum over communities C of WCC(C), WCC(C) = sum over x in C of WCC(x,C), both
+ * summed exactly and rounded once.  Optional outputs (NULL to skip): wcc_comm[K] per
+ * community id; per membership in the lfo_get_memberships order: wcc_node, t_xc, vt_xc;
+ * vt_x[n] = vt(x,V).
+ */
+int lfo_exact_wcc(lfo *h, int nthreads, double *wcc, double *wcc_comm, double *wcc_node, int32_t *t_xc,
+                  int32_t *vt_xc, int32_t *vt_x)
+{
+    if (!h || !h->inited || !wcc) return LFO_ESTATE;
+    const int64_t n = h->n;
+    int64_t *mo = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)(n + 1));
+    mo[0] = 0;
+    for (int64_t x = 0; x < n; x++) mo[x + 1] = mo[x] + h->mem[x].cnt;
+    const int64_t tot = mo[n];
+    int32_t *t = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(tot ? tot : 1));
+    int32_t *vc = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(tot ? tot : 1));
+    double *w = (double *)xmalloc(sizeof(double) * (size_t)(tot ? tot : 1));
+    int32_t *vx = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int64_t maxd = 1;
+        for (int64_t x = 0; x < n; x++) if (h->rowptr[x + 1] - h->rowptr[x] > maxd) maxd = h->rowptr[x + 1] - h->rowptr[x];
+        int32_t *has = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)maxd);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t x = 0; x < n; x++) wcc_node_terms(h, (int32_t)x, has, t + mo[x], vc + mo[x], w + mo[x], vx + x);
+        free(has);
+    }
+    xsum all;
+    xs_clear(&all);
+    xsum *per = (xsum *)xcalloc((size_t)(h->K ? h->K : 1), sizeof(xsum));
+    for (int64_t x = 0; x < n; x++)
+        for (int32_t k = 0; k < h->mem[x].cnt; k++) {
+            xs_add(&all, w[mo[x] + k]);
+            xs_add(&per[h->mem[x].comm[k]], w[mo[x] + k]);
+        }
+    *wcc = xs_round(&all);
+    if (wcc_comm)
+        for (int32_t c = 0; c < h->K; c++) wcc_comm[c] = xs_round(&per[c]);
+    if (wcc_node) memcpy(wcc_node, w, sizeof(double) * (size_t)tot);
+    if (t_xc) memcpy(t_xc, t, sizeof(int32_t) * (size_t)tot);
+    if (vt_xc) memcpy(vt_xc, vc, sizeof(int32_t) * (size_t)tot);
+    if (vt_x) memcpy(vt_x, vx, sizeof(int32_t) * (size_t)n);
+    free(per); free(mo); free(t); free(vc); free(w); free(vx);
+    return xs_err ? LFO_EOVERFLOW : LFO_OK;
+}
+
+/* the WCC terms of the listed nodes only (their memberships in ascending id order, the
+   nodes one after another), for spot checks of large graphs */
+int lfo_wcc_sample(lfo *h, const int32_t *nodes, int64_t count, double *wcc_node, int32_t *t_xc,
+                   int32_t *vt_xc, int32_t *vt_x)
+{
+    if (!h || !h->inited) return LFO_ESTATE;
+    int64_t p = 0;
+    for (int64_t i = 0; i < count; i++) {
+        int32_t x = nodes[i];
+        if (x < 0 || x >= h->n) return LFO_EINVAL;
+        int64_t d = h->rowptr[x + 1] - h->rowptr[x];
+        int32_t *has = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(d ? d : 1));
+        wcc_node_terms(h, x, has, t_xc + p, vt_xc + p, wcc_node + p, vt_x + i);
+        free(has);
+        p += h->mem[x].cnt;
+    }
     return LFO_OK;
 }
 

@@ -532,3 +532,92 @@ def test_warm_start_rejects_bad_covers(oracle_lib):
         o.init_from_memberships(bad_total, np.zeros(g.n, np.int32), 3)     # offsets[n] != total
     with pytest.raises(oracle_lib.OracleError):
         o.init_from_memberships(off[:-1].copy(), np.zeros(g.n - 1, np.int32), 3)   # n offsets
+
+
+# ------------------------------------------------------------------ exact WCC
+def _wcc_check(o, g, P):
+    """Oracle WCC terms vs exact rationals for the cover P (dict id -> set) it holds."""
+    adj = brute.simple_graph(g.n, g.src, g.dst)
+    terms, vt, total = brute.wcc_exact(adj, P)
+    r = o.exact_wcc(2)
+    off, ids = o.memberships()
+    assert np.array_equal(r["vt"], np.array(vt, np.int32))
+    for x in range(g.n):
+        for p in range(off[x], off[x + 1]):
+            t, out, w = terms[(x, int(ids[p]))]
+            assert r["t"][p] == t and r["vt_out"][p] == out
+            assert abs(r["wcc_node"][p] - float(w)) <= 4e-16 * float(w)
+    assert abs(r["wcc"] - float(total)) <= 1e-15 * float(total)
+    for c, C in P.items():
+        wc = sum((terms[(x, c)][2] for x in C), Fraction(0))
+        assert abs(r["wcc_comm"][c] - float(wc)) <= 1e-15 * float(wc)
+    return r
+
+
+def test_exact_wcc_matches_rationals_on_random_covers(oracle_lib):
+    """WCC paragraph: t(x,C), vt(x,V), vt(x,V\\C) from their set definitions, WCC(x,C) and
+    WCC(P) as exact rationals, for random overlapping covers and for LazyFox results."""
+    for seed in range(8):
+        g = G.random_gnp(22, 0.35, 5000 + seed)
+        off, ids, P = random_cover(g.n, 10, 70 + seed)
+        o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(off, ids, 10, 1)
+        _wcc_check(o, g, P)
+        o2 = load(oracle_lib, g)
+        o2.run_iterations(4, 0.01, 20)
+        off2, ids2 = o2.memberships()
+        P2 = {}
+        for x in range(g.n):
+            for c in ids2[off2[x]:off2[x + 1]]:
+                P2.setdefault(int(c), set()).add(x)
+        _wcc_check(o2, g, P2)
+
+
+def test_exact_wcc_closed_forms(oracle_lib):
+    """Closed forms: a clique as one community rates every node 1 (WCC = n); disjoint
+    cliques as communities likewise; a clique split into parts of a and n-a nodes rates a
+    node of the first part C(a-1,2)/C(n-1,2); a triangle-free graph rates 0."""
+    for n in (3, 5, 9):
+        g = complete(n)
+        o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(
+            np.arange(n + 1, dtype=np.int64), np.zeros(n, np.int32), 1, 1)
+        r = o.exact_wcc(1)
+        assert r["wcc"] == float(n) and np.all(r["wcc_node"] == 1.0)
+    g = cliques([3, 4, 6])
+    comm = np.repeat(np.arange(3), [3, 4, 6]).astype(np.int32)
+    o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(
+        np.arange(g.n + 1, dtype=np.int64), comm, 3, 1)
+    r = o.exact_wcc(1)
+    assert r["wcc"] == 13.0 and list(r["wcc_comm"]) == [3.0, 4.0, 6.0]
+    n, a = 10, 4
+    g = complete(n)
+    comm = np.array([0] * a + [1] * (n - a), np.int32)
+    o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(
+        np.arange(n + 1, dtype=np.int64), comm, 2, 1)
+    r = o.exact_wcc(1)
+    b2 = lambda v: v * (v - 1) // 2
+    assert np.all(r["wcc_node"][:a] == b2(a - 1) / b2(n - 1))
+    assert np.all(r["wcc_node"][a:] == b2(n - a - 1) / b2(n - 1))
+    for g in (cycle(12), star(8), path(9)):
+        o = load(oracle_lib, g)
+        r = o.exact_wcc(1)
+        assert r["wcc"] == 0.0 and not r["t"].any() and not r["vt"].any()
+
+
+def test_exact_wcc_bounds_and_sample(oracle_lib):
+    """0 <= WCC(x,C) <= 1 (vt(x,V) <= |C\\{x}| + vt(x,V\\C)), t(x,C) <= t(x,V),
+    vt(x,V\\C) <= vt(x,V); the per-node spot check equals the full pass."""
+    g = G.named_config("copurchase", scale=0.01)
+    o = load(oracle_lib, g)
+    o.run_iterations(32, 0.01, 5)
+    r = o.exact_wcc(4)
+    off, ids = o.memberships()
+    tri, _, _ = o.node_stats()
+    node_of = np.repeat(np.arange(g.n), np.diff(off))
+    assert np.all(r["wcc_node"] >= 0) and np.all(r["wcc_node"] <= 1.0)
+    assert np.all(r["t"] <= tri[node_of]) and np.all(r["vt_out"] <= r["vt"][node_of])
+    rng = np.random.default_rng(0)
+    sample = rng.choice(g.n, 50, replace=False).astype(np.int32)
+    wn, t, vo, vx = o.wcc_sample(sample)
+    sel = np.concatenate([np.arange(off[x], off[x + 1]) for x in sample])
+    assert np.array_equal(wn, r["wcc_node"][sel]) and np.array_equal(t, r["t"][sel])
+    assert np.array_equal(vo, r["vt_out"][sel]) and np.array_equal(vx, r["vt"][sample])
