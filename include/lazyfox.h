@@ -161,6 +161,26 @@ int lf_init_from_memberships(lf_handle *h, const int64_t *offsets, const int32_t
                              int64_t total, int32_t n_comms, uint32_t flags);
 
 /*
+ * Exact WCC of the current partition (Methods, WCC-hat subsection, paragraph "WCC"), the
+ * triangle-based score that WCC-hat estimates.  For a member x of C, with t(x,S) the
+ * triangles of x whose two other nodes lie in S and vt(x,S) the nodes of S that close at
+ * least one triangle with x:
+ *   WCC(x,C) = t(x,C) / t(x,V) * vt(x,V) / (|C \ {x}| + vt(x, V \ C)), 0 if t(x,V) = 0,
+ * evaluated in FP64 as (t / t_V) * (vt_V / (|C| - 1 + vt_out)); WCC(C) = sum over x in C,
+ * WCC(P) = sum over C, both summed exactly and rounded once.  Outputs are caller-owned host
+ * buffers; all but wcc may be NULL:
+ *   wcc        WCC(P)
+ *   wcc_comm   double[K], K = communities created (lf_get_graph_info); 0 for removed ids
+ *   wcc_node, t_xc, vt_xc   one entry per membership in the lf_get_memberships order
+ *              (node by node, community ids ascending): WCC(x,C), t(x,C), vt(x, V \ C)
+ *   vt_x       int32[n]: vt(x, V)
+ * Errors: LF_ESTATE (no communities), LF_EOVERFLOW (a term outside the exact range),
+ * LF_ENOMEM, LF_EDEVICE.
+ */
+int lf_exact_wcc(lf_handle *h, double *wcc, double *wcc_comm, double *wcc_node, int32_t *t_xc,
+                 int32_t *vt_xc, int32_t *vt_x);
+
+/*
  * LazyFox iterations (Methods, "Node Changes", Algorithm 2, "Stopping Criteria",
  * "Post-processing").  Each iteration walks the node order in consecutive queues of
  * `queue_size` nodes (the last one partial); every node of a queue gets its best join

@@ -69,6 +69,7 @@ def load_library():
         "lf_load_graph": [vp, i64, i64, vp, vp, u32],
         "lf_init_communities": [vp],
         "lf_init_from_memberships": [vp, vp, vp, i64, i32, u32],
+        "lf_exact_wcc": [vp, C.POINTER(dbl), vp, vp, vp, vp, vp],
         "lf_run_iterations": [vp, i32, dbl, i32, C.POINTER(RunInfo)],
         "lf_get_memberships": [vp, vp, vp, i64, C.POINTER(i64)],
         "lf_get_graph_info": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
@@ -218,6 +219,25 @@ class Handle:
         return self
 
     init_from_memberships = lf_init_from_memberships
+
+    def lf_exact_wcc(self):
+        """Exact WCC of the current partition: dict(wcc, wcc_comm[K], per membership in the
+        memberships() order wcc_node, t, vt_out; vt[n])."""
+        n, _, K = self.lf_get_graph_info()
+        off, ids = self.lf_get_memberships()
+        tot = ids.size
+        wcc = C.c_double()
+        wc = np.zeros(max(1, K), np.float64)
+        wn = np.zeros(max(1, tot), np.float64)
+        t = np.zeros(max(1, tot), np.int32)
+        vo = np.zeros(max(1, tot), np.int32)
+        vx = np.zeros(max(1, n), np.int32)
+        self._check(self.L.lf_exact_wcc(self.h, C.byref(wcc), C.c_void_p(wc.ctypes.data), C.c_void_p(wn.ctypes.data),
+                                        C.c_void_p(t.ctypes.data), C.c_void_p(vo.ctypes.data),
+                                        C.c_void_p(vx.ctypes.data)), "lf_exact_wcc")
+        return dict(wcc=wcc.value, wcc_comm=wc[:K], wcc_node=wn[:tot], t=t[:tot], vt_out=vo[:tot], vt=vx[:n])
+
+    exact_wcc = lf_exact_wcc
 
     def lf_run_iterations(self, queue_size, threshold=0.01, max_iters=50):
         hist = np.zeros(max_iters + 1, np.float64)

@@ -322,10 +322,39 @@ __device__ __forceinline__ int seg_of(const int *P, int m, int f)
 #define TRI_WAVE_CAP 256
 #define TRI_WAVES 4
 
+// A triangle {u, v, w} found at u (v = N+(u)[j], w = N+(u)[p]) in the exact-WCC pass:
+// the three oriented edges are marked as closing a triangle, and every community that u,
+// v and w share gains one triangle at each of them (a walk of their sorted id lists).
+__device__ __forceinline__ void wcc_hit(const WccTri &wt, int u, int v, int w, long long e_uv, long long e_uw,
+                                        long long e_vw)
+{
+    wt.eflag[e_uv] = 1;
+    wt.eflag[e_uw] = 1;
+    wt.eflag[e_vw] = 1;
+    long long a = wt.moff[u], b = wt.moff[v], c = wt.moff[w];
+    const long long ae = wt.moff[u + 1], be = wt.moff[v + 1], ce = wt.moff[w + 1];
+    while (a < ae && b < be && c < ce) {
+        const int x = wt.mid[a], y = wt.mid[b], z = wt.mid[c];
+        if (x == y && y == z) {
+            atomicAdd(&wt.tcm[a], 1);
+            atomicAdd(&wt.tcm[b], 1);
+            atomicAdd(&wt.tcm[c], 1);
+            a++; b++; c++;
+        } else {
+            const int m = x > y ? (x > z ? x : z) : (y > z ? y : z);
+            a += x < m;
+            b += y < m;
+            c += z < m;
+        }
+    }
+}
+
 // one wave per node with |N+(u)| <= TRI_WAVE_CAP; longer out-lists are deferred.  Every
 // wave of the block reaches both barriers (no early exit), inactive waves just idle.
+// WCC = false: triangle counts per node into tri; true: wcc_hit per triangle instead.
+template <bool WCC>
 __global__ void __launch_bounds__(256) k_tri_wave(const long long *oro, const int *orc, long long n,
-                                                  unsigned long long *tri, int *defer, int *ndefer)
+                                                  unsigned long long *tri, int *defer, int *ndefer, WccTri wt)
 {
     __shared__ int s_nbr[TRI_WAVES][TRI_WAVE_CAP];
     __shared__ int s_pre[TRI_WAVES][TRI_WAVE_CAP + 1];
@@ -370,27 +399,35 @@ __global__ void __launch_bounds__(256) k_tri_wave(const long long *oro, const in
     for (int f = lane; f < W; f += WAVE) {
         int j = seg_of(pre, m, f);
         int v = nbr[j];
-        int w = orc[oro[v] + (f - pre[j])];
+        long long evw = oro[v] + (f - pre[j]);
+        int w = orc[evw];
         int p = lds_find(nbr, m, w);
         if (p >= 0) {
-            atomicAdd(&cnt[p], 1);
-            atomicAdd(&cnt[j], 1);
-            total++;
+            if constexpr (WCC) {
+                wcc_hit(wt, (int)u, v, w, b + j, b + p, evw);
+            } else {
+                atomicAdd(&cnt[p], 1);
+                atomicAdd(&cnt[j], 1);
+                total++;
+            }
         }
     }
     __syncthreads();
-    for (int j = lane; j < m; j += WAVE)
-        if (cnt[j]) atomicAdd(&tri[nbr[j]], (unsigned long long)cnt[j]);
-    total = wave_sum_int(total);
-    if (lane == 0 && total) atomicAdd(&tri[u], (unsigned long long)total);
+    if constexpr (!WCC) {
+        for (int j = lane; j < m; j += WAVE)
+            if (cnt[j]) atomicAdd(&tri[nbr[j]], (unsigned long long)cnt[j]);
+        total = wave_sum_int(total);
+        if (lane == 0 && total) atomicAdd(&tri[u], (unsigned long long)total);
+    }
 }
 
 // one workgroup per deferred node; out-list, prefix and counters in LDS when they fit,
 // otherwise in this workgroup's slice of global scratch
+template <bool WCC>
 __global__ void __launch_bounds__(1024) k_tri_group(const long long *oro, const int *orc,
                                                     const int *list, int nlist,
                                                     unsigned long long *tri, int lds_cap,
-                                                    int *gscratch, long long gslice)
+                                                    int *gscratch, long long gslice, WccTri wt)
 {
     extern __shared__ int s_dyn[];
     __shared__ int s_total;
@@ -450,20 +487,29 @@ __global__ void __launch_bounds__(1024) k_tri_group(const long long *oro, const 
         for (int f = threadIdx.x; f < W; f += blockDim.x) {
             int j = seg_of(pre, m, f);
             int v = nbr[j];
-            int w = orc[oro[v] + (f - pre[j])];
+            long long evw = oro[v] + (f - pre[j]);
+            int w = orc[evw];
             int p = lds_find(nbr, m, w);
             if (p >= 0) {
-                atomicAdd(&cnt[p], 1);
-                atomicAdd(&cnt[j], 1);
-                total++;
+                if constexpr (WCC) {
+                    wcc_hit(wt, u, v, w, b + j, b + p, evw);
+                } else {
+                    atomicAdd(&cnt[p], 1);
+                    atomicAdd(&cnt[j], 1);
+                    total++;
+                }
             }
         }
-        total = wave_sum_int(total);
-        if (lane == 0 && total) atomicAdd(&s_total, total);
+        if constexpr (!WCC) {
+            total = wave_sum_int(total);
+            if (lane == 0 && total) atomicAdd(&s_total, total);
+        }
         __syncthreads();
-        for (int j = threadIdx.x; j < m; j += blockDim.x)
-            if (cnt[j]) atomicAdd(&tri[nbr[j]], (unsigned long long)cnt[j]);
-        if (threadIdx.x == 0 && s_total) atomicAdd(&tri[u], (unsigned long long)s_total);
+        if constexpr (!WCC) {
+            for (int j = threadIdx.x; j < m; j += blockDim.x)
+                if (cnt[j]) atomicAdd(&tri[nbr[j]], (unsigned long long)cnt[j]);
+            if (threadIdx.x == 0 && s_total) atomicAdd(&tri[u], (unsigned long long)s_total);
+        }
         __syncthreads();
     }
 }
@@ -594,16 +640,17 @@ int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out)
     return LF_OK;
 }
 
-int lf_node_stats(lf_handle *h)
+// Every triangle once, at its lowest endpoint in (degree, id) order: with wt == nullptr
+// the per-node counts go to h->tri, otherwise wcc_hit is applied to each triangle.
+// Oriented lists (out-offsets oro[n + 1], out-neighbours orc, ascending ids) are built
+// into temporaries of the caller's scratch scope and returned if asked for.
+int lf_triangle_pass(lf_handle *h, const WccTri *wt, int *launches, long long **oro_out, int **orc_out)
 {
-    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
-    long long n = h->n;
+    const long long n = h->n;
     const int BS = 256;
     int maxdev = 0;
     LF_HIP(h, hipDeviceGetAttribute(&maxdev, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
-
-    LF_TRY(lf_prof_begin(h, LF_K_TRIANGLES));
     int *od = nullptr;
     long long *oro = nullptr;
     int *orc = nullptr;
@@ -614,9 +661,10 @@ int lf_node_stats(lf_handle *h)
     LF_TRY(lf_tmp_alloc(h, (void **)&orc, sizeof(int) * (h->ne > 0 ? h->ne : 1)));
     LF_TRY(lf_tmp_alloc(h, (void **)&defer, sizeof(int) * (n > 0 ? n : 1)));
     LF_TRY(lf_tmp_alloc(h, (void **)&cnt, sizeof(int) * 4));
-    LF_TRY(lf_dev_alloc(h, (void **)&h->tri, sizeof(unsigned long long) * (n > 0 ? n : 1)));
-    LF_HIP(h, hipMemsetAsync(h->tri, 0, sizeof(unsigned long long) * (n > 0 ? n : 1), st));
     LF_HIP(h, hipMemsetAsync(cnt, 0, sizeof(int) * 4, st));
+    WccTri none;
+    memset(&none, 0, sizeof none);
+    const WccTri w = wt ? *wt : none;
     unsigned gw = grid_for(n * WAVE, BS);
     long long *od64 = nullptr;
     LF_TRY(lf_tmp_alloc(h, (void **)&od64, sizeof(long long) * (n + 1)));
@@ -628,13 +676,18 @@ int lf_node_stats(lf_handle *h)
     hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, st, oro, n, h->ne);
     if (n > 0) {
         hipLaunchKernelGGL(k_out_fill, dim3(gw), dim3(BS), 0, st, h->rowptr, h->col, h->deg, n, oro, orc);
-        hipLaunchKernelGGL(k_tri_wave, dim3(grid_for(n, TRI_WAVES)), dim3(TRI_WAVES * WAVE), 0, st,
-                           oro, orc, n, h->tri, defer, cnt);
+        if (wt)
+            hipLaunchKernelGGL(k_tri_wave<true>, dim3(grid_for(n, TRI_WAVES)), dim3(TRI_WAVES * WAVE), 0, st,
+                               oro, orc, n, h->tri, defer, cnt, w);
+        else
+            hipLaunchKernelGGL(k_tri_wave<false>, dim3(grid_for(n, TRI_WAVES)), dim3(TRI_WAVES * WAVE), 0, st,
+                               oro, orc, n, h->tri, defer, cnt, w);
     }
     int hc[4] = {0, 0, 0, 0};
     LF_HIP(h, hipMemcpyAsync(hc, cnt, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
     int ndefer = hc[0], maxod = hc[2];
+    *launches = 5;
     if (ndefer > 0) {
         // LDS: nbr, pre (+1), cnt
         int lds_cap = (maxdev - 1024) / (3 * (int)sizeof(int)) - 1;
@@ -645,15 +698,40 @@ int lf_node_stats(lf_handle *h)
         long long gslice = 3ll * maxod + 2;
         if (maxod > lds_cap) LF_TRY(lf_tmp_alloc(h, (void **)&gs, sizeof(int) * gslice * blocks));
         size_t shmem = sizeof(int) * (3 * (size_t)lds_cap + 1);
-        LF_HIP(h, hipFuncSetAttribute((const void *)k_tri_group,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-        hipLaunchKernelGGL(k_tri_group, dim3(blocks), dim3(1024), shmem, st, oro, orc, defer, ndefer,
-                           h->tri, lds_cap, gs, gslice);
+        const void *fn = wt ? (const void *)k_tri_group<true> : (const void *)k_tri_group<false>;
+        LF_HIP(h, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+        if (wt)
+            hipLaunchKernelGGL(k_tri_group<true>, dim3(blocks), dim3(1024), shmem, st, oro, orc, defer, ndefer,
+                               h->tri, lds_cap, gs, gslice, w);
+        else
+            hipLaunchKernelGGL(k_tri_group<false>, dim3(blocks), dim3(1024), shmem, st, oro, orc, defer, ndefer,
+                               h->tri, lds_cap, gs, gslice, w);
         LF_HIP(h, hipGetLastError());
         LF_HIP(h, hipStreamSynchronize(st));
+        *launches = 6;
     }
     LF_HIP(h, hipGetLastError());
-    LF_TRY(lf_prof_end(h, LF_K_TRIANGLES, 5 + (ndefer > 0)));
+    if (oro_out) *oro_out = oro;
+    if (orc_out) *orc_out = orc;
+    return LF_OK;
+}
+
+int lf_node_stats(lf_handle *h)
+{
+    TmpScope tmp_scope(h);
+    hipStream_t st = h->stream;
+    long long n = h->n;
+    const int BS = 256;
+
+    LF_TRY(lf_prof_begin(h, LF_K_TRIANGLES));
+    int *cnt = nullptr;
+    LF_TRY(lf_tmp_alloc(h, (void **)&cnt, sizeof(int) * 4));
+    LF_TRY(lf_dev_alloc(h, (void **)&h->tri, sizeof(unsigned long long) * (n > 0 ? n : 1)));
+    LF_HIP(h, hipMemsetAsync(h->tri, 0, sizeof(unsigned long long) * (n > 0 ? n : 1), st));
+    int launches = 0;
+    LF_TRY(lf_triangle_pass(h, nullptr, &launches, nullptr, nullptr));
+    int hc[4] = {0, 0, 0, 0};
+    LF_TRY(lf_prof_end(h, LF_K_TRIANGLES, launches));
 
     // local CC, cc, T
     LF_TRY(lf_prof_begin(h, LF_K_ORDER));

@@ -325,6 +325,17 @@ int lf_node_stats(lf_handle *h);
 int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out);
 
 // ---- community stages (communities.hip) ----------------------------------------------------
+// Exact-WCC pass over the triangles (wcc_hit in graph.hip): compact sorted memberships
+// (node x's community ids at [moff[x], moff[x + 1])), per-membership triangle counters and
+// per-oriented-edge "closes a triangle" flags.
+struct WccTri {
+    const long long *moff;
+    const int *mid;
+    int *tcm;
+    unsigned char *eflag;
+};
+int lf_triangle_pass(lf_handle *h, const WccTri *wt, int *launches, long long **oro_out, int **orc_out);
+
 int lf_initial_clustering(lf_handle *h);
 int lf_partition_from_cover(lf_handle *h, const long long *off, const int *ids, long long total, int n_comms);
 int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out);
