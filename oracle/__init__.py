@@ -61,6 +61,7 @@ def lib():
         L.lfo_init_from_memberships.argtypes = [vp, vp, vp, i64, i32, C.c_int]
         L.lfo_exact_wcc.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
         L.lfo_wcc_sample.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+        L.lfo_postprocess.argtypes = [vp, u32, vp, vp, C.c_int]
         L.lfo_run_iterations.argtypes = [vp, i32, dbl, i32, i32, i32, i32, C.POINTER(RunInfo)]
         L.lfo_check_state.argtypes = [vp]
         L.lfo_check_state.restype = i64
@@ -204,6 +205,17 @@ class Oracle:
         self._check(self.L.lfo_wcc_sample(self.h, _p(nodes), int(nodes.size), _p(wn), _p(t), _p(vo), _p(vx)),
                     "wcc_sample")
         return wn[:tot], t[:tot], vo[:tot], vx[:nodes.size]
+
+    def postprocess(self, duplicates=True, contained=True, apply=False, nthreads=None):
+        """Duplicated / contained community removal: (keep[K] uint8, (removed as duplicates,
+        removed as contained)); apply=True also rebuilds the state without them."""
+        nthreads = nthreads or min(8, os.cpu_count() or 1)
+        K = int(self.L.lfo_num_communities_created(self.h))
+        keep = np.zeros(max(1, K), np.uint8)
+        rem = np.zeros(2, np.int64)
+        flags = (1 if duplicates else 0) | (2 if contained else 0) | (4 if apply else 0)
+        self._check(self.L.lfo_postprocess(self.h, flags, _p(keep), _p(rem), int(nthreads)), "postprocess")
+        return keep[:K], (int(rem[0]), int(rem[1]))
 
     def check_state(self):
         return int(self.L.lfo_check_state(self.h))

@@ -20,6 +20,7 @@
  *   end_iteration         "Stopping Criteria" and "Post-processing" (degenerate communities)
  *   lfo_exact_wcc         WCC of a partition from exact triangle counts (WCC paragraph of the
  *                         WCC-hat subsection), to set beside the WCC-hat estimate
+ *   lfo_postprocess       removal of duplicated and contained communities ("Post-processing")
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *  - self-loops are dropped; node order ties: degree descending, then id ascending;
@@ -1163,6 +1164,79 @@ int lfo_wcc_sample(lfo *h, const int32_t *nodes, int64_t count, double *wcc_node
         p += h->mem[x].cnt;
     }
     return LFO_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Post-processing of the final cover ("Post-processing": duplicated and contained       */
+/* communities may be unwanted)                                                           */
+/* ------------------------------------------------------------------------------------ */
+/* is every member of community a also a member of community b? */
+static int comm_subset(const lfo *h, int32_t a, int32_t b)
+{
+    for (int32_t j = 0; j < h->cm[a].cnt; j++)
+        if (memb_find(&h->mem[h->cm[a].node[j]], b) < 0) return 0;
+    return 1;
+}
+
+/*
+ * Communities with at least one member are compared pairwise.  With LFO_PP_DUPLICATES a
+ * community is removed if another one has exactly its members and a lower id; with
+ * LFO_PP_CONTAINED if its members are a strict subset of another one's.  keep[K] (may be
+ * NULL) receives 1 for every community kept (0 for removed and for empty ids);
+ * removed[0] / removed[1] (may be NULL) count removals as duplicates / as contained (a
+ * community that is both counts as a duplicate).  With LFO_PP_APPLY the removed
+ * communities lose all their members and the state is rebuilt from the remaining cover
+ * as by lfo_init_from_memberships.
+ */
+#define LFO_PP_DUPLICATES 1u
+#define LFO_PP_CONTAINED 2u
+#define LFO_PP_APPLY 4u
+int lfo_postprocess(lfo *h, uint32_t flags, uint8_t *keep, int64_t *removed, int nthreads)
+{
+    if (!h || !h->inited) return LFO_ESTATE;
+    const int32_t K = h->K;
+    uint8_t *kp = (uint8_t *)xmalloc((size_t)(K ? K : 1));
+    int64_t ndup = 0, ncont = 0;
+    for (int32_t a = 0; a < K; a++) {
+        const int32_t sa = h->cm[a].cnt;
+        kp[a] = sa > 0;
+        if (sa == 0) continue;
+        int dup = 0, cont = 0;
+        for (int32_t b = 0; b < K; b++) {
+            if (b == a) continue;
+            const int32_t sb = h->cm[b].cnt;
+            if (sb < sa) continue;
+            if (sb == sa && !((flags & LFO_PP_DUPLICATES) && b < a)) continue;
+            if (sb > sa && !(flags & LFO_PP_CONTAINED)) continue;
+            if (!comm_subset(h, a, b)) continue;
+            if (sb == sa) dup = 1; else cont = 1;
+        }
+        if (dup) ndup++;
+        else if (cont) ncont++;
+        if (dup || cont) kp[a] = 0;
+    }
+    if (keep) memcpy(keep, kp, (size_t)K);
+    if (removed) { removed[0] = ndup; removed[1] = ncont; }
+    int rc = LFO_OK;
+    if (flags & LFO_PP_APPLY) {
+        const int64_t n = h->n;
+        int64_t *off = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)(n + 1));
+        int64_t tot = 0;
+        for (int64_t x = 0; x < n; x++) tot += h->mem[x].cnt;
+        int32_t *ids = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(tot ? tot : 1));
+        int64_t p = 0;
+        for (int64_t x = 0; x < n; x++) {
+            off[x] = p;
+            for (int32_t j = 0; j < h->mem[x].cnt; j++)
+                if (kp[h->mem[x].comm[j]]) ids[p++] = h->mem[x].comm[j];
+        }
+        off[n] = p;
+        rc = lfo_init_from_memberships(h, off, ids, p, K, nthreads);
+        free(off);
+        free(ids);
+    }
+    free(kp);
+    return rc;
 }
 
 /* per-community size, internal edges and cc-free score (all created ids) */

@@ -621,3 +621,80 @@ def test_exact_wcc_bounds_and_sample(oracle_lib):
     sel = np.concatenate([np.arange(off[x], off[x + 1]) for x in sample])
     assert np.array_equal(wn, r["wcc_node"][sel]) and np.array_equal(t, r["t"][sel])
     assert np.array_equal(vo, r["vt_out"][sel]) and np.array_equal(vx, r["vt"][sample])
+
+
+# ------------------------------------------------------------------ post-processing
+def cover_arrays(n, P):
+    """(offsets, ids) of a cover given as dict id -> set of nodes."""
+    per = [[] for _ in range(n)]
+    for c in sorted(P):
+        for x in P[c]:
+            per[x].append(c)
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(p) for p in per])
+    return off, np.array([c for p in per for c in p], np.int32)
+
+
+def nested_cover(n, seed):
+    """Random communities plus planted duplicates (equal member sets, higher and lower ids),
+    strict subsets and supersets, a chain A < B < C and a singleton."""
+    rng = random.Random(seed)
+    P = {}
+    for c in range(12):
+        P[c] = set(rng.sample(range(n), rng.randint(2, 8)))
+    P[12] = set(P[3])                       # duplicate of 3 (higher id)
+    P[13] = set(rng.sample(sorted(P[4]), max(1, len(P[4]) - 2)))   # strict subset of 4
+    P[14] = P[5] | {rng.randrange(n)}       # superset (or duplicate) of 5
+    a = set(rng.sample(range(n), 3))
+    P[15], P[16], P[17] = a, a | {0, 1}, a | {0, 1, 2, 3}   # chain
+    P[18] = set(P[16])                      # duplicate inside the chain
+    P[19] = {rng.randrange(n)}              # one member
+    return P
+
+
+def expected_pp(P, dup, cont):
+    keep, nd, nc = {}, 0, 0
+    for a, A in P.items():
+        d = dup and any(b < a and B == A for b, B in P.items() if b != a)
+        s = cont and any(A < B for b, B in P.items() if b != a)
+        keep[a] = not (d or s)
+        nd += d
+        nc += (s and not d)
+    return keep, nd, nc
+
+
+def test_postprocess_matches_set_definitions(oracle_lib):
+    """Post-processing: duplicates (equal member sets, the lowest id stays) and strictly
+    contained communities removed, each rule alone and both, against Python sets."""
+    for seed in range(12):
+        g = G.random_gnp(30, 0.2, 6000 + seed)
+        P = nested_cover(g.n, seed)
+        off, ids = cover_arrays(g.n, P)
+        for dup, cont in ((True, True), (True, False), (False, True)):
+            o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(off, ids, 25, 1)
+            keep, (nd, nc) = o.postprocess(dup, cont)
+            ek, end, enc = expected_pp(P, dup, cont)
+            assert (nd, nc) == (end, enc)
+            for c in range(25):
+                assert keep[c] == (1 if c in P and ek[c] else 0)
+
+
+def test_postprocess_apply_rebuilds_the_cover(oracle_lib):
+    """Applying the removal leaves exactly the kept communities, a consistent state, and
+    the exact-rational WCC-hat of the remaining cover."""
+    g = G.random_gnp(30, 0.25, 77)
+    P = nested_cover(g.n, 3)
+    off, ids = cover_arrays(g.n, P)
+    o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(off, ids, 25, 1)
+    keep, _ = o.postprocess(True, True, apply=True)
+    assert o.check_state() == 0
+    Q = {c: C for c, C in P.items() if keep[c]}
+    assert memberships_list(o) == [sorted(c for c, C in Q.items() if x in C) for x in range(g.n)]
+    adj = brute.simple_graph(g.n, g.src, g.dst)
+    k = brute.triangles(adj)
+    cc = sum(brute.local_cc(adj, k), Fraction(0)) / g.n
+    w = brute.wcc_hat_partition(Q, adj, cc)
+    sc = o.scores()
+    assert abs(sc["wtilde"] / sc["cc"] - float(w)) <= 1e-12 * float(w)
+    keep2, rem2 = o.postprocess(True, True)
+    assert rem2 == (0, 0) and np.array_equal(keep2, keep)
