@@ -160,6 +160,29 @@ def exact_wcc_bench(h, reps):
                     "membership intersections, closing-edge flags, per-membership terms, exact sums"}
 
 
+def postprocess_bench(h, reps):
+    """Duplicated / contained community detection on the final cover (not applied)."""
+    import torch
+    h.lf_set_profiling(0)
+    keep, rem = h.postprocess(True, True)             # warm-up
+    times = []
+    for _ in range(max(1, reps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        keep2, rem2 = h.postprocess(True, True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    if rem2 != rem:
+        print("[bench] ERROR: post-processing differs between calls", file=sys.stderr)
+        sys.exit(1)
+    ms = 1000.0 * sum(times) / len(times)
+    print("[bench] post-processing: %d duplicates, %d contained in %.2f ms" % (rem[0], rem[1], ms),
+          file=sys.stderr, flush=True)
+    return {"ms": ms, "removed_duplicates": rem[0], "removed_contained": rem[1], "kept": int(keep.sum()),
+            "what": "lf_postprocess (duplicates and strictly contained communities) of the final cover, "
+                    "keep flags copied to the host, not applied"}
+
+
 def warm_start_bench(h, reps):
     """Rebuild of the whole state from the final cover of the timed steps (device arrays)
     with lf_init_from_memberships; the rebuilt partition must score exactly the same."""
@@ -383,6 +406,7 @@ def main():
     if tuned is not None:
         out["autotune"] = tuned
     out["exact_wcc"] = exact_wcc_bench(h, args.steps)
+    out["postprocess"] = postprocess_bench(h, args.steps)
     out["warm_start"] = warm_start_bench(h, args.steps)
     if args.sweep:
         sweep = {}

@@ -180,6 +180,29 @@ int lf_init_from_memberships(lf_handle *h, const int64_t *offsets, const int32_t
 int lf_exact_wcc(lf_handle *h, double *wcc, double *wcc_comm, double *wcc_node, int32_t *t_xc,
                  int32_t *vt_xc, int32_t *vt_x);
 
+/* lf_postprocess flags */
+#define LF_PP_DUPLICATES 1u   /* remove a community whose members equal a lower id's */
+#define LF_PP_CONTAINED 2u    /* remove a community whose members are a strict subset of
+                                 another community's */
+#define LF_PP_APPLY 4u        /* also take the removed communities out of the partition */
+
+/*
+ * Optional post-processing of the final cover (Methods, "Post-processing": the result may
+ * hold duplicated communities and communities contained in others, which some uses do not
+ * want).  Communities with at least one member are compared: with LF_PP_DUPLICATES a
+ * community is removed if another one has exactly its members and a lower id, with
+ * LF_PP_CONTAINED if its members are a strict subset of another one's (so what remains is
+ * the distinct maximal communities, each under its lowest id).  Outputs, caller-owned host
+ * buffers, may be NULL: keep uint8[K] (K = communities created, lf_get_graph_info) with 1
+ * for each community kept and 0 for removed or empty ids; removed int64[2] = communities
+ * removed as duplicates, as contained (a community that is both counts as a duplicate).
+ * With LF_PP_APPLY the removed communities lose all their members and the state (in-counts,
+ * sizes, exact sums, score) is rebuilt from the remaining cover as by
+ * lf_init_from_memberships; ids are kept.
+ * Errors: LF_EINVAL (unknown flags), LF_ESTATE, LF_ENOMEM, LF_EDEVICE.
+ */
+int lf_postprocess(lf_handle *h, uint32_t flags, uint8_t *keep, int64_t *removed);
+
 /*
  * LazyFox iterations (Methods, "Node Changes", Algorithm 2, "Stopping Criteria",
  * "Post-processing").  Each iteration walks the node order in consecutive queues of

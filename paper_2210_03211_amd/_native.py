@@ -70,6 +70,7 @@ def load_library():
         "lf_init_communities": [vp],
         "lf_init_from_memberships": [vp, vp, vp, i64, i32, u32],
         "lf_exact_wcc": [vp, C.POINTER(dbl), vp, vp, vp, vp, vp],
+        "lf_postprocess": [vp, u32, vp, vp],
         "lf_run_iterations": [vp, i32, dbl, i32, C.POINTER(RunInfo)],
         "lf_get_memberships": [vp, vp, vp, i64, C.POINTER(i64)],
         "lf_get_graph_info": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
@@ -238,6 +239,19 @@ class Handle:
         return dict(wcc=wcc.value, wcc_comm=wc[:K], wcc_node=wn[:tot], t=t[:tot], vt_out=vo[:tot], vt=vx[:n])
 
     exact_wcc = lf_exact_wcc
+
+    def lf_postprocess(self, duplicates=True, contained=True, apply=False):
+        """Duplicated / contained community removal: (keep[K] uint8, (removed as duplicates,
+        removed as contained)); apply=True also takes them out of the partition."""
+        K = self.lf_get_graph_info()[2]
+        keep = np.zeros(max(1, K), np.uint8)
+        rem = np.zeros(2, np.int64)
+        flags = (1 if duplicates else 0) | (2 if contained else 0) | (4 if apply else 0)
+        self._check(self.L.lf_postprocess(self.h, flags, C.c_void_p(keep.ctypes.data), C.c_void_p(rem.ctypes.data)),
+                    "lf_postprocess")
+        return keep[:K], (int(rem[0]), int(rem[1]))
+
+    postprocess = lf_postprocess
 
     def lf_run_iterations(self, queue_size, threshold=0.01, max_iters=50):
         hist = np.zeros(max_iters + 1, np.float64)

@@ -683,6 +683,7 @@ int lf_partition_from_cover(lf_handle *h, const long long *off, const int *ids, 
     LF_TRY(lf_prof_end(h, LF_K_INITCLUST, 8));
     LF_TRY(lf_prof_flush(h));
     LF_TRY(lf_check_dev_error(h));
+    h->state = 2;
     return LF_OK;
 }
 
