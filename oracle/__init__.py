@@ -62,6 +62,7 @@ def lib():
         L.lfo_exact_wcc.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
         L.lfo_wcc_sample.argtypes = [vp, vp, i64, vp, vp, vp, vp]
         L.lfo_postprocess.argtypes = [vp, u32, vp, vp, C.c_int]
+        L.lfo_cover_f1.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.lfo_run_iterations.argtypes = [vp, i32, dbl, i32, i32, i32, i32, C.POINTER(RunInfo)]
         L.lfo_check_state.argtypes = [vp]
         L.lfo_check_state.restype = i64
@@ -216,6 +217,21 @@ class Oracle:
         flags = (1 if duplicates else 0) | (2 if contained else 0) | (4 if apply else 0)
         self._check(self.L.lfo_postprocess(self.h, flags, _p(keep), _p(rem), int(nthreads)), "postprocess")
         return keep[:K], (int(rem[0]), int(rem[1]))
+
+    def cover_f1(self, offsets, ids):
+        """F1-Score of the current partition against a reference cover: (f1, best[K],
+        match[K])."""
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        if offsets.size != self.n + 1:
+            raise OracleError("cover_f1: %d offsets for %d nodes" % (offsets.size, self.n))
+        K = int(self.L.lfo_num_communities_created(self.h))
+        f1 = C.c_double()
+        best = np.zeros(max(1, K), np.float64)
+        match = np.zeros(max(1, K), np.int32)
+        self._check(self.L.lfo_cover_f1(self.h, _p(offsets), _p(ids), int(ids.size), C.byref(f1), _p(best),
+                                        _p(match)), "cover_f1")
+        return f1.value, best[:K], match[:K]
 
     def check_state(self):
         return int(self.L.lfo_check_state(self.h))

@@ -698,3 +698,78 @@ def test_postprocess_apply_rebuilds_the_cover(oracle_lib):
     assert abs(sc["wtilde"] / sc["cc"] - float(w)) <= 1e-12 * float(w)
     keep2, rem2 = o.postprocess(True, True)
     assert rem2 == (0, 0) and np.array_equal(keep2, keep)
+
+
+# ------------------------------------------------------------------ cover F1
+def f1_exact(Pd, Pr):
+    """F1-Score(P', P) from the paper's precision / recall form, as Fractions: (score,
+    {c': (max F1, lowest reference id reaching it or -1)})."""
+    per = {}
+    for c, A in Pd.items():
+        if not A:
+            continue
+        bestv, arg = Fraction(0), -1
+        for r in sorted(Pr):
+            B = Pr[r]
+            i = len(A & B)
+            if not B or i == 0:
+                continue
+            p, q = Fraction(i, len(A)), Fraction(i, len(B))
+            f = 2 * p * q / (p + q)
+            if arg < 0 or f > bestv:
+                bestv, arg = f, r
+        per[c] = (bestv, arg)
+    score = sum((v[0] for v in per.values()), Fraction(0)) / len(per) if per else Fraction(0)
+    return score, per
+
+
+def test_cover_f1_matches_rationals(oracle_lib):
+    """F1-Score for Overlapping Communities: every community's best match and the average
+    against exact rationals, for random and LazyFox covers against random and planted
+    reference covers."""
+    for seed in range(8):
+        g = G.random_gnp(40, 0.2, 7000 + seed)
+        off, ids, Pd = random_cover(g.n, 15, 80 + seed)
+        roff, rids, Pr = random_cover(g.n, 12, 90 + seed, max_per_node=2)
+        for lazy in (False, True):
+            if lazy:
+                o = load(oracle_lib, g)
+                o.run_iterations(8, 0.01, 20)
+                mo, mi = o.memberships()
+                Pd = {}
+                for x in range(g.n):
+                    for c in mi[mo[x]:mo[x + 1]]:
+                        Pd.setdefault(int(c), set()).add(x)
+            else:
+                o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(off, ids, 15, 1)
+            f1, best, match = o.cover_f1(roff, rids)
+            score, per = f1_exact(Pd, Pr)
+            assert f1 == math.fsum(float(v[0]) for v in per.values()) / max(1, len(per))
+            assert abs(f1 - float(score)) <= 1e-15 * max(1.0, float(score))
+            for c in range(best.size):
+                if c in per:
+                    assert best[c] == float(per[c][0]) and match[c] == per[c][1]
+                else:
+                    assert best[c] == 0.0 and match[c] == -1
+
+
+def test_cover_f1_closed_forms(oracle_lib):
+    """Identical covers score 1; communities that are parts of one reference community of
+    all n nodes score 2s/(s+n) each; a reference meeting nothing scores 0; bad covers are
+    refused."""
+    g = G.named_config("tiny_sbm")
+    o = load(oracle_lib, g)
+    off, ids = o.memberships()
+    assert o.cover_f1(off, ids)[0] == 1.0
+    g = cliques([3, 4, 6])
+    comm = np.repeat(np.arange(3), [3, 4, 6]).astype(np.int32)
+    o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(
+        np.arange(g.n + 1, dtype=np.int64), comm, 3, 1)
+    f1, best, match = o.cover_f1(np.arange(g.n + 1, dtype=np.int64), np.zeros(g.n, np.int32))
+    assert list(best) == [6 / 16, 8 / 17, 12 / 19] and list(match) == [0, 0, 0]
+    assert f1 == math.fsum([6 / 16, 8 / 17, 12 / 19]) / 3
+    f1, best, match = o.cover_f1(np.zeros(g.n + 1, np.int64), np.zeros(0, np.int32))
+    assert f1 == 0.0 and not best.any() and np.all(match == -1)
+    dup = np.concatenate([[0], np.full(g.n, 2, np.int64)])
+    with pytest.raises(oracle_lib.OracleError):
+        o.cover_f1(dup, np.array([1, 1], np.int32))
