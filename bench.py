@@ -160,6 +160,33 @@ def exact_wcc_bench(h, reps):
                     "membership intersections, closing-edge flags, per-membership terms, exact sums"}
 
 
+def cover_f1_bench(h, g, reps):
+    """F1-Score of the final cover against the generator's planted cover."""
+    import torch
+    ref = g.planted_cover()
+    if ref is None:
+        return None
+    roff = torch.from_numpy(ref[0]).cuda()
+    rids = torch.from_numpy(ref[1]).cuda()
+    h.lf_set_profiling(0)
+    f1 = h.cover_f1(roff, rids)[0]                    # warm-up
+    times = []
+    for _ in range(max(1, reps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f1b = h.cover_f1(roff, rids)[0]
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    if f1b != f1:
+        print("[bench] ERROR: cover F1 differs between calls", file=sys.stderr)
+        sys.exit(1)
+    ms = 1000.0 * sum(times) / len(times)
+    print("[bench] F1 against the planted cover %.4f in %.2f ms" % (f1, ms), file=sys.stderr, flush=True)
+    return {"ms": ms, "f1_vs_planted": f1, "reference_memberships": int(ref[1].size),
+            "what": "lf_cover_f1 of the final cover against the planted cover (device arrays; per-community "
+                    "best F1 and match copied to the host)"}
+
+
 def postprocess_bench(h, reps):
     """Duplicated / contained community detection on the final cover (not applied)."""
     import torch
@@ -407,6 +434,7 @@ def main():
         out["autotune"] = tuned
     out["exact_wcc"] = exact_wcc_bench(h, args.steps)
     out["postprocess"] = postprocess_bench(h, args.steps)
+    out["cover_f1"] = cover_f1_bench(h, g, args.steps)
     out["warm_start"] = warm_start_bench(h, args.steps)
     if args.sweep:
         sweep = {}
@@ -422,6 +450,9 @@ def main():
             s = time.perf_counter() - t1
             sweep[str(qq)] = {"end_to_end_s": s, "iterations": si["iterations"],
                               "node_evals_per_s": n * si["iterations"] / s, "wcc_hat": si["wcc_hat"]}
+            ref = g.planted_cover()
+            if ref is not None:
+                sweep[str(qq)]["f1_vs_planted"] = h.cover_f1(*ref)[0]
             print("[bench] sweep q=%d: %.3fs %d iterations" % (qq, s, si["iterations"]), file=sys.stderr, flush=True)
         out["queue_sweep"] = sweep
     if args.serving_jobs > 0:

@@ -180,6 +180,25 @@ int lf_init_from_memberships(lf_handle *h, const int64_t *offsets, const int32_t
 int lf_exact_wcc(lf_handle *h, double *wcc, double *wcc_comm, double *wcc_node, int32_t *t_xc,
                  int32_t *vt_xc, int32_t *vt_x);
 
+/*
+ * F1-Score of the current partition against a reference cover (Methods, "F1-Score for
+ * Overlapping Communities"): each detected community C' with at least one member is
+ * matched to the reference community C with the largest F1(C', C), the harmonic mean of
+ * precision |C n C'| / |C'| and recall |C n C'| / |C|, evaluated as the single correctly
+ * rounded division 2 |C n C'| / (|C| + |C'|); the score is the mean of the maxima (exact
+ * sum rounded once, divided by the number of detected communities; 0 if there are none).
+ *   offsets, ids  the reference cover as for lf_init_from_memberships (ids >= 0, at most
+ *                 once per node, any order); host pointers, or device with LF_DEVICE_PTR;
+ *                 read only
+ *   f1            the score (required)
+ *   best, match   optional caller-owned host buffers of K entries (K = communities created,
+ *                 lf_get_graph_info): the maximum F1 of each detected id (0 for empty ids or
+ *                 no overlap) and the lowest reference id reaching it (-1 if none)
+ * Errors: LF_ESTATE, LF_EINVAL (bad cover), LF_ENOMEM, LF_EDEVICE.
+ */
+int lf_cover_f1(lf_handle *h, const int64_t *offsets, const int32_t *ids, int64_t total,
+                uint32_t flags, double *f1, double *best, int32_t *match);
+
 /* lf_postprocess flags */
 #define LF_PP_DUPLICATES 1u   /* remove a community whose members equal a lower id's */
 #define LF_PP_CONTAINED 2u    /* remove a community whose members are a strict subset of

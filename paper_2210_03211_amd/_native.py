@@ -71,6 +71,7 @@ def load_library():
         "lf_init_from_memberships": [vp, vp, vp, i64, i32, u32],
         "lf_exact_wcc": [vp, C.POINTER(dbl), vp, vp, vp, vp, vp],
         "lf_postprocess": [vp, u32, vp, vp],
+        "lf_cover_f1": [vp, vp, vp, i64, u32, C.POINTER(dbl), vp, vp],
         "lf_run_iterations": [vp, i32, dbl, i32, C.POINTER(RunInfo)],
         "lf_get_memberships": [vp, vp, vp, i64, C.POINTER(i64)],
         "lf_get_graph_info": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
@@ -252,6 +253,30 @@ class Handle:
         return keep[:K], (int(rem[0]), int(rem[1]))
 
     postprocess = lf_postprocess
+
+    def lf_cover_f1(self, offsets, ids):
+        """F1-Score of the current partition against a reference cover (offsets int64[n + 1],
+        ids int32; numpy or device tensors): (f1, best[K], match[K])."""
+        po, do = _ptr(offsets)
+        pc, dc = _ptr(ids)
+        if do != dc:
+            raise ValueError("offsets and ids must both be host or both be device arrays")
+        if str(getattr(offsets, "dtype", "")) not in ("int64", "torch.int64"):
+            raise TypeError("offsets must be int64")
+        if str(getattr(ids, "dtype", "")) not in ("int32", "torch.int32"):
+            raise TypeError("ids must be int32")
+        n, _, K = self.lf_get_graph_info()
+        if int(offsets.shape[0]) != n + 1:
+            raise ValueError("offsets must have n + 1 = %d entries" % (n + 1))
+        f1 = C.c_double()
+        best = np.zeros(max(1, K), np.float64)
+        match = np.zeros(max(1, K), np.int32)
+        self._check(self.L.lf_cover_f1(self.h, C.c_void_p(po), C.c_void_p(pc), int(ids.shape[0]),
+                                       LF_DEVICE_PTR if do else 0, C.byref(f1), C.c_void_p(best.ctypes.data),
+                                       C.c_void_p(match.ctypes.data)), "lf_cover_f1")
+        return f1.value, best[:K], match[:K]
+
+    cover_f1 = lf_cover_f1
 
     def lf_run_iterations(self, queue_size, threshold=0.01, max_iters=50):
         hist = np.zeros(max_iters + 1, np.float64)

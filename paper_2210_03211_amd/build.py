@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblazyfox.so")
-SOURCES = ["prims.hip", "graph.hip", "communities.hip", "iterate.hip", "batch.hip", "tune.hip", "wcc.hip", "post.hip", "api.hip"]
+SOURCES = ["prims.hip", "graph.hip", "communities.hip", "iterate.hip", "batch.hip", "tune.hip", "wcc.hip", "post.hip", "f1.hip", "api.hip"]
 ARCH = os.environ.get("LF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

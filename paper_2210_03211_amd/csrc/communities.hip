@@ -643,7 +643,9 @@ static int finish_partition(lf_handle *h)
 // Warm start from an existing cover (Initial Clustering, last paragraph: an existing
 // division can replace the greedy one).  off[n + 1] / ids[total] on the device, each
 // node's communities in any order.  Node statistics must exist.
-int lf_partition_from_cover(lf_handle *h, const long long *off, const int *ids, long long total, int n_comms)
+// Checks of a cover on the device (offsets, ids in [0, n_comms) or >= 0 if n_comms < 0, no
+// id twice per node); *maxid = the largest id (-1 if none).
+int lf_check_cover(lf_handle *h, const long long *off, const int *ids, long long total, int n_comms, int *maxid)
 {
     TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
@@ -669,7 +671,19 @@ int lf_partition_from_cover(lf_handle *h, const long long *off, const int *ids, 
     if (hc[0] & 1) return lf_set_error(h, LF_EINVAL, "cover offsets decrease or leave [0, total]");
     if (hc[0] & 2) return lf_set_error(h, LF_EINVAL, "a community id is negative or not below n_comms");
     if (hc[0] & 4) return lf_set_error(h, LF_EINVAL, "a node lists a community twice");
-    const long long K = n_comms >= 0 ? n_comms : (long long)hc[1] + 1;
+    *maxid = hc[1];
+    return LF_OK;
+}
+
+int lf_partition_from_cover(lf_handle *h, const long long *off, const int *ids, long long total, int n_comms)
+{
+    TmpScope tmp_scope(h);
+    hipStream_t st = h->stream;
+    const int BS = 256;
+    const long long n = h->n;
+    int maxid = -1;
+    LF_TRY(lf_check_cover(h, off, ids, total, n_comms, &maxid));
+    const long long K = n_comms >= 0 ? n_comms : (long long)maxid + 1;
     if (K >= (1ll << 31) - 1) return lf_set_error(h, LF_EOVERFLOW, "too many communities");
     h->state = 1;                            // the previous partition is gone from here on
     lf_free_partition(h);

@@ -338,6 +338,7 @@ int lf_triangle_pass(lf_handle *h, const WccTri *wt, int *launches, long long **
 
 int lf_initial_clustering(lf_handle *h);
 int lf_partition_from_cover(lf_handle *h, const long long *off, const int *ids, long long total, int n_comms);
+int lf_check_cover(lf_handle *h, const long long *off, const int *ids, long long total, int n_comms, int *maxid);
 int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out);
 // one LazyFox iteration split into its host steps (shared by lf_run_iterations and the
 // multi-graph batch): sizing and path lists, per-queue parameters, and the iteration end
