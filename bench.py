@@ -46,7 +46,9 @@ def parse():
     ap.add_argument("--cpu-sample-scale", type=float, default=0.2)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (for HBM counter scaling)")
-    ap.add_argument("--sweep", default="", help="comma-separated queue sizes: extra untimed-line runs")
+    ap.add_argument("--sweep", default="1024,16384,65536",
+                    help="comma-separated queue sizes run after the timed steps (end-to-end time, F1, "
+                         "per-kernel bandwidth); empty to skip")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip tuning the path thresholds and launch shapes on the workload (untimed)")
     ap.add_argument("--serving-jobs", type=int, default=300,
@@ -80,6 +82,26 @@ def kernel_bytes(kernel, paths):
                                + B_NEIGHBOUR * t["neighbours"] + B_VISIT * t["visits"]),
         "k_big_final": lambda: B_CAND * t["candidates"],
     }.get(kernel, lambda: None)()
+
+
+def kernel_rooflines(timing, paths):
+    """Achieved algorithmic GB/s of each evaluation kernel with a byte model (HIP-event
+    times of a profiled pass), and of the evaluation kernels together."""
+    out = {}
+    tot_b, tot_ms = 0.0, 0.0
+    for k in ("k_eval", "k_eval_big", "k_big_final"):
+        b = kernel_bytes(k, paths)
+        ms = timing["ms"].get(k, 0.0)
+        if b is None or ms <= 0.0:
+            continue
+        gbs = b / (ms * 1e-3) / 1e9
+        out[k] = {"GB_s": gbs, "frac": gbs / HBM_PEAK_GBS, "launches": timing["launches"][k], "ms": ms}
+        tot_b += b
+        tot_ms += ms
+    ms = tot_ms + timing["ms"].get("k_big_tie", 0.0)
+    if ms > 0.0:
+        out["evaluation"] = {"GB_s": tot_b / (ms * 1e-3) / 1e9, "frac": tot_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
 
 
 def kernel_sources_sha():
@@ -436,6 +458,7 @@ def main():
     out["postprocess"] = postprocess_bench(h, args.steps)
     out["cover_f1"] = cover_f1_bench(h, g, args.steps)
     out["warm_start"] = warm_start_bench(h, args.steps)
+    out["kernel_rooflines"] = kernel_rooflines(timing, work["paths"])
     if args.sweep:
         sweep = {}
         for qq in [int(x) for x in args.sweep.split(",") if x]:
@@ -453,6 +476,19 @@ def main():
             ref = g.planted_cover()
             if ref is not None:
                 sweep[str(qq)]["f1_vs_planted"] = h.cover_f1(*ref)[0]
+            # per-kernel bandwidth at this queue size: a timed pass and a counter pass
+            for mask, key in ((True, "t"), (1 << lf.PROF_COUNTERS_BIT, "w")):
+                h.lf_reset_profile()
+                h.lf_set_profiling(mask)
+                h.load_graph(g.n, src, dst)
+                h.init_communities()
+                h.run_iterations(qq, args.threshold, args.max_iters)
+                if key == "t":
+                    tprof = h.lf_get_profile()
+                else:
+                    wprof = h.lf_get_profile()
+            h.lf_set_profiling(0)
+            sweep[str(qq)]["kernel_rooflines"] = kernel_rooflines(tprof, wprof["paths"])
             print("[bench] sweep q=%d: %.3fs %d iterations" % (qq, s, si["iterations"]), file=sys.stderr, flush=True)
         out["queue_sweep"] = sweep
     if args.serving_jobs > 0:
