@@ -399,7 +399,10 @@ Ctx lf_ctx(lf_handle *h)
     c.dld = h->dld;
     c.ctr = h->ctr;
     c.big_idx = h->big_idx;
-    for (int k = 0; k < LF_PATH_COUNT; k++) c.plist[k] = h->plist[k];
+    for (int k = 0; k < LF_PATH_COUNT; k++) {
+        c.plist[k] = h->plist[k];
+        c.prec[k] = h->prec[k];
+    }
     c.rank = h->rank;
     c.titem_base = h->titem_base;
     c.titem_node = h->titem_node;
@@ -435,7 +438,7 @@ void lf_free_partition(lf_handle *h)
                      (void **)&h->ovf_comm, (void **)&h->ovf_flag, (void **)&h->ctr, (void **)&h->part_base,
                      (void **)&h->part_cnt, (void **)&h->part_done, (void **)&h->mslot, (void **)&h->vbound,
                      (void **)&h->cls, (void **)&h->cscan, (void **)&h->plist[0], (void **)&h->plist[1],
-                     (void **)&h->plist[2], (void **)&h->plist[3]};
+                     (void **)&h->plist[2], (void **)&h->plist[3], (void **)&h->prec_all, (void **)&h->pbase};
     for (void **p : ptrs) {
         lf_dev_free(h, *p);
         *p = nullptr;
@@ -609,6 +612,9 @@ static int alloc_partition_state(lf_handle *h, long long K, long long slots)
     LF_TRY(lf_dev_alloc(h, (void **)&h->cls, sizeof(int) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->cscan, sizeof(long long) * (nn + 1)));
     for (int k = 0; k < LF_PATH_COUNT; k++) LF_TRY(lf_dev_alloc(h, (void **)&h->plist[k], sizeof(int) * nn));
+    LF_TRY(lf_dev_alloc(h, (void **)&h->prec_all, sizeof(NodeRec) * nn));
+    LF_TRY(lf_dev_alloc(h, (void **)&h->pbase, sizeof(long long) * (LF_PATH_COUNT + 1)));
+    for (int k = 0; k < LF_PATH_COUNT; k++) h->prec[k] = h->prec_all;
     LF_TRY(lf_dev_alloc(h, (void **)&h->joined_to, sizeof(unsigned long long) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->ovf_node, sizeof(int) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->ovf_comm, sizeof(int) * nn));

@@ -181,24 +181,26 @@ __device__ __forceinline__ int node_incl_scan(int v, int tid, NodeLds<VCAP> &L, 
 // a handful of memory round trips whatever its size: own slots + column indices,
 // neighbour headers, neighbour slots, and one record per candidate.
 template <int NT, int VCAP>
-__device__ __forceinline__ bool eval_node(const Ctx &cx, int cstart, int j, int tid, NodeLds<VCAP> &L, int wcap,
-                                          int path)
+__device__ __forceinline__ bool eval_node(const Ctx &cx, int j, const NodeRec nr, int tid, NodeLds<VCAP> &L,
+                                          int wcap, int path)
 {
     constexpr int NB = VCAP / NT;
     const int lane = tid & (WAVE - 1);
-    const int x = cx.order[cstart + j];
-    const NodeHdr hx = cx.nh[x];
-    const long long rb = cx.rowptr[x];
-    const int d = hx.deg, mcnt = hx.cnt;
-    if (d > VCAP || mcnt > MXCAP) return false;
-    Slot own = {-1, 0};
-    if (tid < mcnt) own = cx.slot[hx.off + tid];
+    const int x = nr.x, d = nr.d;
+    const long long rb = nr.rb;
+    if (d > VCAP) return false;
+    // the adjacency gathers need only the node record; the header is fetched beside them
     int yv[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         int e = b * NT + tid;
         yv[b] = e < d ? cx.col[rb + e] : -1;
     }
+    const NodeHdr hx = cx.nh[x];
+    const int mcnt = hx.cnt;
+    if (mcnt > MXCAP) return false;
+    Slot own = {-1, 0};
+    if (tid < mcnt) own = cx.slot[hx.off + tid];
     NodeHdr hy[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
@@ -467,7 +469,8 @@ __device__ __forceinline__ void body_eval(const Ctx &cx, const QStep &qs, int bl
     }
     if (p >= qs.ln) return;                 // no block barriers in this kernel
     const int j = cx.plist[LF_PATH_SMALL][qs.ls + p] - qs.cstart;
-    if (!eval_node<WAVE, VSMALL>(cx, qs.cstart, j, lane, L.w[wv], qs.wcap, LF_PATH_SMALL) && lane == 0)
+    const NodeRec nr = cx.prec[LF_PATH_SMALL][qs.ls + p];
+    if (!eval_node<WAVE, VSMALL>(cx, j, nr, lane, L.w[wv], qs.wcap, LF_PATH_SMALL) && lane == 0)
         atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
 }
 
@@ -562,7 +565,7 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
             int r = cx.plist[LF_PATH_TABLE][p];
             int j = r - cstart;
             {
-                int x = cx.order[r];
+                int x = cx.prec[LF_PATH_TABLE][p].x;
                 NodeHdr hx = cx.nh[x];
                 long long e = ib0 + f - cx.titem_base[p];
                 if (e == 0) mark_table(cx, j, hx.deg);   // k_big_final reads it after this launch
@@ -714,7 +717,8 @@ __device__ __forceinline__ void body_eval_big(const Ctx &cx, const QStep &qs, in
     if (b < r.bg) {
         for (int p = b; p < r.ng; p += r.bg) {
             const int j = cx.plist[LF_PATH_GROUP][r.lg + p] - cstart;
-            if (!eval_node<GT, VGRP>(cx, cstart, j, threadIdx.x, L.g, qs.gcap, LF_PATH_GROUP) && threadIdx.x == 0)
+            const NodeRec nr = cx.prec[LF_PATH_GROUP][r.lg + p];
+            if (!eval_node<GT, VGRP>(cx, j, nr, threadIdx.x, L.g, qs.gcap, LF_PATH_GROUP) && threadIdx.x == 0)
                 atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
             __syncthreads();                // the next node reuses the LDS
         }
@@ -725,7 +729,8 @@ __device__ __forceinline__ void body_eval_big(const Ctx &cx, const QStep &qs, in
     if (b < r.bm) {
         for (int p = b * (GT / WAVE) + wv; p < r.nm; p += r.bm * (GT / WAVE)) {   // no block barriers
             const int j = cx.plist[LF_PATH_MED][r.lm + p] - cstart;
-            if (!eval_node<WAVE, VMED>(cx, cstart, j, lane, L.m[wv], qs.mcap, LF_PATH_MED) && lane == 0)
+            const NodeRec nr = cx.prec[LF_PATH_MED][r.lm + p];
+            if (!eval_node<WAVE, VMED>(cx, j, nr, lane, L.m[wv], qs.mcap, LF_PATH_MED) && lane == 0)
                 atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
         }
         return;
@@ -733,7 +738,8 @@ __device__ __forceinline__ void body_eval_big(const Ctx &cx, const QStep &qs, in
     b -= r.bm;
     for (int p = b * (GT / WAVE) + wv; p < r.ns; p += r.bs * (GT / WAVE)) {    // small path, one wave per node
         const int j = cx.plist[LF_PATH_SMALL][qs.ls + p] - cstart;
-        if (!eval_node<WAVE, VSMALL>(cx, cstart, j, lane, L.s[wv], qs.wcap, LF_PATH_SMALL) && lane == 0)
+        const NodeRec nr = cx.prec[LF_PATH_SMALL][qs.ls + p];
+        if (!eval_node<WAVE, VSMALL>(cx, j, nr, lane, L.s[wv], qs.wcap, LF_PATH_SMALL) && lane == 0)
             atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
     }
 }
@@ -1201,16 +1207,33 @@ __global__ void k_class_flags(const int *cls, int c, long long *flags, long long
     else if (r == n) flags[r] = 0;
 }
 
-// path c's list (ascending order positions) and its first list position per queue
+// path c's list (ascending order positions) with its node records (at pbase[c] of the
+// shared record array), and its first list position per queue
 __global__ void k_class_scatter(const int *cls, int c, const long long *scan, int *list, long long n, int q,
-                                long long nq, long long *qoff)
+                                long long nq, long long *qoff, const int *order, const long long *rowptr,
+                                const int *deg, const long long *pbase, NodeRec *prec)
 {
     long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (r < n && cls[r] == c) list[scan[r]] = (int)r;
+    if (r < n && cls[r] == c) {
+        const long long i = scan[r];
+        const int x = order[r];
+        list[i] = (int)r;
+        NodeRec nr;
+        nr.rb = rowptr[x];
+        nr.x = x;
+        nr.d = deg[x];
+        prec[pbase[c] + i] = nr;
+    }
     if (r <= nq) {
         long long p = r * q < n ? r * q : n;
         qoff[r] = scan[p];
     }
+}
+
+// pbase[c + 1] = pbase[c] + the number of path-c nodes (scan[n])
+__global__ void k_path_base(const long long *scan, long long n, int c, long long *pbase)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) pbase[c + 1] = pbase[c] + scan[n];
 }
 
 // work items of every table-path node: its neighbours, its own memberships and one spare
@@ -1314,6 +1337,7 @@ static int size_queue_buffers(lf_handle *h, long long q)
         LF_TRY(lf_dev_alloc(h, (void **)&h->titem_base, sizeof(long long) * (n + 1)));
         moved = true;
     }
+    LF_HIP(h, hipMemsetAsync(h->pbase, 0, sizeof(long long), st));
     for (int c = 0; c < LF_PATH_COUNT; c++) {
         // titem_base serves as the flag array until the table-path items are laid out
         hipLaunchKernelGGL(k_class_flags, dim3(grid_for(n + 1, BS)), dim3(BS), 0, st, (const int *)h->cls, c,
@@ -1321,7 +1345,10 @@ static int size_queue_buffers(lf_handle *h, long long q)
         LF_TRY(lf_exclusive_scan_i64(h, h->titem_base, h->cscan, n + 1));
         long long m = (n > nq ? n : nq) + 1;
         hipLaunchKernelGGL(k_class_scatter, dim3(grid_for(m, BS)), dim3(BS), 0, st, (const int *)h->cls, c,
-                           (const long long *)h->cscan, h->plist[c], n, (int)q, nq, dq + c * (nq + 1));
+                           (const long long *)h->cscan, h->plist[c], n, (int)q, nq, dq + c * (nq + 1),
+                           (const int *)h->order, (const long long *)h->rowptr, (const int *)h->deg,
+                           (const long long *)h->pbase, h->prec_all);
+        hipLaunchKernelGGL(k_path_base, dim3(1), dim3(1), 0, st, (const long long *)h->cscan, n, c, h->pbase);
     }
     LF_HIP(h, hipMemcpyAsync(h->hqoff, dq, sizeof(long long) * LF_PATH_COUNT * (nq + 1), hipMemcpyDeviceToHost,
                              st));
@@ -1334,6 +1361,13 @@ static int size_queue_buffers(lf_handle *h, long long q)
     LF_HIP(h, hipMemcpyAsync(hb, dout, sizeof(hb), hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
+    {   // the records of path c start after those of the paths before it
+        long long base = 0;
+        for (int c = 0; c < LF_PATH_COUNT; c++) {
+            h->prec[c] = h->prec_all + base;
+            base += h->hqoff[c * (nq + 1) + nq];
+        }
+    }
     long long keys = (long long)hb[1] + 64;
     long long initems = (long long)hb[2] + 64;
     if (keys >= (1ll << 30) || initems >= (1ll << 31))

@@ -23,6 +23,14 @@ struct Slot {
     int in;
 };
 
+// A node of a path list with what its evaluation reads first (row offset, id, degree), so
+// that its adjacency gathers can start without first resolving the order position.
+struct NodeRec {
+    long long rb;    // first adjacency position
+    int x;           // node id
+    int d;           // degree
+};
+
 // One community, one 64-byte line: everything a candidate evaluation reads.  The exact
 // sums S+ / S- (sum of g over the members at size s+1 / s-1) are stored as 160-bit
 // non-negative fixed point (lowest bit 2^-120; every such sum is below 2^31).
@@ -109,6 +117,7 @@ struct Ctx {
     // evaluation path of every node for the current iteration: per path the order
     // positions of its nodes, ascending (a queue's nodes of a path are contiguous)
     int *plist[LF_PATH_COUNT];
+    const NodeRec *prec[LF_PATH_COUNT];   // parallel to plist: the node's record
     const int *rank;         // [n] order position of each node
     long long *titem_base;   // [table-path nodes + 1] first work item of each
     int *titem_node;         // [items] table-path list position owning each item
@@ -218,6 +227,9 @@ struct lf_handle {
     int *cls;                // [n] evaluation path per order position (this iteration)
     long long *cscan;        // [n + 1] scan scratch of the path lists
     int *plist[LF_PATH_COUNT];
+    NodeRec *prec_all;       // [n] node records of all path lists, path after path
+    long long *pbase;        // [LF_PATH_COUNT + 1] device: first record of each path
+    NodeRec *prec[LF_PATH_COUNT];   // host-set views into prec_all
     long long *titem_base;
     int *titem_node;
     long long titem_cap;
