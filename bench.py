@@ -104,14 +104,18 @@ def kernel_rooflines(timing, paths):
     return out
 
 
+# the translation unit of the evaluation and apply kernels and every header it includes
+KERNEL_SOURCES = ("iterate.hip", "method.h", "exact.h", "lf_internal.h")
+
+
 def kernel_sources_sha():
-    """Hash of the HIP sources and headers the kernels are built from."""
+    """Hash of the sources the queue kernels are built from (their translation unit and
+    its headers, the public header included)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2210_03211_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     with open(os.path.join(ROOT, "include", "lazyfox.h"), "rb") as fh:
         h.update(fh.read())
     return h.hexdigest()
