@@ -132,29 +132,38 @@ __global__ void __launch_bounds__(256) k_init_slots(const long long *rowptr, con
     }
 }
 
-// warm start: checks of a given cover (one wave per node): offsets non-decreasing within
-// [0, total] (bit 0), ids in [0, K) (bit 1; K < 0: any id >= 0), no id twice per node
-// (bit 2); chk[1] = largest id
+// warm start: checks of a given cover (waves stride over the nodes): offsets non-decreasing
+// within [0, total] (bit 0), ids in [0, K) (bit 1; K < 0: any id >= 0), no id twice per
+// node (bit 2); chk[1] = largest id.  One atomic per wave at the end: a single hot
+// counter updated per node would serialise millions of atomics.
 __global__ void __launch_bounds__(256) k_cover_check(const long long *off, const int *ids, long long n,
                                                      long long total, int K, int *chk)
 {
-    long long x = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
-    int lane = threadIdx.x & (WAVE - 1);
-    if (x >= n) return;
-    const long long a0 = off[x], a1 = off[x + 1];
-    if (a0 < 0 || a1 < a0 || a1 > total) {
-        if (lane == 0) atomicOr(&chk[0], 1);
-        return;
-    }
+    const int lane = threadIdx.x & (WAVE - 1);
+    const long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
     int err = 0, mx = -1;
-    for (long long a = a0 + lane; a < a1; a += WAVE) {
-        const int c = ids[a];
-        if (c < 0 || (K >= 0 && c >= K)) err |= 2;
-        if (c > mx) mx = c;
-        for (long long b = a0; b < a; b++) err |= ids[b] == c ? 4 : 0;
+    for (long long x = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE; x < n; x += nw) {
+        const long long a0 = off[x], a1 = off[x + 1];
+        if (a0 < 0 || a1 < a0 || a1 > total) {
+            err |= 1;
+            continue;
+        }
+        for (long long a = a0 + lane; a < a1; a += WAVE) {
+            const int c = ids[a];
+            if (c < 0 || (K >= 0 && c >= K)) err |= 2;
+            if (c > mx) mx = c;
+            for (long long b = a0; b < a; b++) err |= ids[b] == c ? 4 : 0;
+        }
     }
-    if (err) atomicOr(&chk[0], err);
-    if (mx >= 0) atomicMax(&chk[1], mx);
+    for (int o = 32; o >= 1; o >>= 1) {
+        err |= __shfl_xor(err, o, WAVE);
+        const int om = __shfl_xor(mx, o, WAVE);
+        mx = om > mx ? om : mx;
+    }
+    if (lane == 0) {
+        if (err) atomicOr(&chk[0], err);
+        if (mx >= 0) atomicMax(&chk[1], mx);
+    }
 }
 
 // warm start: node x's memberships in the given order plus one free slot (slot offset
@@ -667,9 +676,9 @@ int lf_check_cover(lf_handle *h, const long long *off, const int *ids, long long
     LF_TRY(lf_tmp_alloc(h, (void **)&chk, 2 * sizeof(int)));
     const int init[2] = {0, -1};
     LF_HIP(h, hipMemcpyAsync(chk, init, sizeof init, hipMemcpyHostToDevice, st));
-    if (n > 0)
-        hipLaunchKernelGGL(k_cover_check, dim3(grid_for(n * WAVE, BS)), dim3(BS), 0, st, off, ids, n, total,
-                           n_comms, chk);
+    unsigned gc = grid_for(n * WAVE, BS);
+    if (gc > 2048) gc = 2048;
+    if (n > 0) hipLaunchKernelGGL(k_cover_check, dim3(gc), dim3(BS), 0, st, off, ids, n, total, n_comms, chk);
     int hc[2];
     LF_HIP(h, hipMemcpyAsync(hc, chk, sizeof hc, hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
