@@ -54,6 +54,16 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
         free(h);
         return LF_EDEVICE;
     }
+    if (hipHostMalloc((void **)&h->hrep, sizeof(long long) * 16, hipHostMallocDefault) != hipSuccess) {
+        (void)hipEventDestroy(h->ev0);
+        (void)hipEventDestroy(h->ev1);
+        if (h->own_stream) (void)hipStreamDestroy(h->stream);
+        delete h->allocs;
+        delete h->alloc_sizes;
+        delete h->tmp_chunks;
+        free(h);
+        return LF_ENOMEM;
+    }
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     h->eval_wave_cap = 128;
@@ -82,7 +92,8 @@ int lf_destroy(lf_handle *h)
     (void)hipEventDestroy(h->ev0);
     (void)hipEventDestroy(h->ev1);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
-    free(h->hqoff);
+    if (h->hqoff) (void)hipHostFree(h->hqoff);
+    if (h->hrep) (void)hipHostFree(h->hrep);
     free(h);
     return LF_OK;
 }

@@ -469,7 +469,7 @@ static size_t job_footprint(long long n, long long npairs, int q)
 {
     long long nn = n > 0 ? n : 1;
     long long qq = q < nn ? q : nn;
-    return (size_t)(48ll << 20) + (size_t)nn * 436 + (size_t)npairs * 64 + (size_t)qq * 256;
+    return (size_t)(48ll << 20) + (size_t)nn * 480 + (size_t)npairs * 64 + (size_t)qq * 256;
 }
 
 static int server_error(lf_server *s, int code, const char *msg)

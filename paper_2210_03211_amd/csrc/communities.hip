@@ -229,11 +229,11 @@ __global__ void k_member_cap(long long *capx, const CommRec *cr, int K, long lon
     capx[c] = cr[c].s + ex;
 }
 
-__global__ void k_member_fill(const NodeHdr *nh, const Slot *slot, long long n, const long long *cm_off,
-                              int *cm_len, int *cm_node)
+__global__ void k_member_fill(const NodeHdr *nh, const Slot *slot, long long n, int K, const long long *cm_off,
+                              int *cm_len, int *cm_node, long long cap)
 {
     long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (x >= n) return;
+    if (x >= n || cm_off[K] > cap) return;          // over capacity: the host grows it and refills
     NodeHdr hd = nh[x];
     for (int t = 0; t < hd.cnt; t++) {
         int c = slot[hd.off + t].comm;
@@ -335,11 +335,11 @@ __global__ void k_clear_dead(Ctx cx)
     cx.tflag[c] = 0;
 }
 
-__global__ void k_copy_slots(Ctx cx, const long long *noff, Slot *dst, long long total)
+__global__ void k_copy_slots(Ctx cx, const long long *noff, Slot *dst)
 {
     long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (x > cx.n) return;
-    if (x == cx.n) { cx.nh[x].off = total; return; }
+    if (x == cx.n) { cx.nh[x].off = noff[x]; return; }
     NodeHdr hx = cx.nh[x];
     long long o = noff[x];
     for (int t = 0; t < hx.cnt; t++) dst[o + t] = cx.slot[hx.off + t];
@@ -368,6 +368,27 @@ __global__ void __launch_bounds__(256) k_score_partials(const CommRec *cr, int K
         for (int k = 1; k < 256 / WAVE; k++) x256_add(s, s_w[k]);
         part[blockIdx.x] = s;
     }
+}
+
+// everything an iteration end reports to the host, gathered into one record
+#define REP_SLOTS 0
+#define REP_MEMBERS 1
+#define REP_SCORE 2
+#define REP_JOINS 3
+#define REP_LEAVES 4
+#define REP_LIVE 5
+#define REP_ERROR 6
+__global__ void k_end_report(const DevCounters *c, const long long *slots, const long long *members,
+                             const double *score, long long *rep)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    rep[REP_SLOTS] = *slots;
+    rep[REP_MEMBERS] = *members;
+    rep[REP_SCORE] = __double_as_longlong(*score);
+    rep[REP_JOINS] = (long long)c->joins;
+    rep[REP_LEAVES] = (long long)c->leaves;
+    rep[REP_LIVE] = c->live;
+    rep[REP_ERROR] = c->error;
 }
 
 __global__ void k_score_fold(const X256 *part, int np, double *out)
@@ -459,8 +480,10 @@ void lf_free_partition(lf_handle *h)
     h->graph_version++;
 }
 
-// member lists with capacity for joiners; requires sizes and slots to be current
-static int rebuild_member_lists(lf_handle *h)
+// member lists with capacity for joiners; requires sizes and slots to be current.  Queued
+// on the stream without waiting: if the lists outgrow cm_node nothing is written, and the
+// total (cm_off[K]) tells the host to grow it and call this again.
+static int rebuild_member_lists_async(lf_handle *h)
 {
     TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
@@ -474,25 +497,44 @@ static int rebuild_member_lists(lf_handle *h)
     if (n > 0) hipLaunchKernelGGL(k_member_extra, dim3(grid_for(n, BS)), dim3(BS), 0, st, h->nh, cx.slot, n, capx);
     if (K > 0) hipLaunchKernelGGL(k_member_cap, dim3(grid_for(K, BS)), dim3(BS), 0, st, capx, h->cr, K, n);
     LF_TRY(lf_exclusive_scan_i64(h, capx, h->cm_off, K + 1));
-    long long total = 0;
-    LF_HIP(h, hipMemcpyAsync(&total, h->cm_off + K, sizeof(long long), hipMemcpyDeviceToHost, st));
-    LF_HIP(h, hipStreamSynchronize(st));
-    if (total > h->cm_cap) {
-        lf_dev_free(h, h->cm_node);
-        h->cm_node = nullptr;
-        long long want = total + total / 8 + 1024;
+    if (!h->cm_node) {
+        long long want = 2 * n + 1024;
         LF_TRY(lf_dev_alloc(h, (void **)&h->cm_node, sizeof(int) * want));
         h->cm_cap = want;
-        cx = lf_ctx(h);
     }
     LF_HIP(h, hipMemsetAsync(h->cm_len, 0, sizeof(int) * (K > 0 ? K : 1), st));
-    if (n > 0) hipLaunchKernelGGL(k_member_fill, dim3(grid_for(n, BS)), dim3(BS), 0, st, h->nh, cx.slot, n, h->cm_off, h->cm_len, h->cm_node);
+    if (n > 0)
+        hipLaunchKernelGGL(k_member_fill, dim3(grid_for(n, BS)), dim3(BS), 0, st, h->nh, cx.slot, n, K, h->cm_off,
+                           h->cm_len, h->cm_node, h->cm_cap);
     LF_HIP(h, hipGetLastError());
-    LF_HIP(h, hipStreamSynchronize(st));
     return LF_OK;
 }
 
-static int partition_score(lf_handle *h, double *out)
+// grow cm_node to hold `total` member entries and fill the lists again (waits)
+static int grow_member_lists(lf_handle *h, long long total)
+{
+    LF_HIP(h, hipStreamSynchronize(h->stream));
+    lf_dev_free(h, h->cm_node);
+    h->cm_node = nullptr;
+    long long want = total + total / 8 + 1024;
+    LF_TRY(lf_dev_alloc(h, (void **)&h->cm_node, sizeof(int) * want));
+    h->cm_cap = want;
+    return rebuild_member_lists_async(h);
+}
+
+static int rebuild_member_lists(lf_handle *h)
+{
+    LF_TRY(rebuild_member_lists_async(h));
+    long long total = 0;
+    LF_HIP(h, hipMemcpyAsync(&total, h->cm_off + h->K, sizeof(long long), hipMemcpyDeviceToHost, h->stream));
+    LF_HIP(h, hipStreamSynchronize(h->stream));
+    if (total > h->cm_cap) LF_TRY(grow_member_lists(h, total));
+    LF_HIP(h, hipStreamSynchronize(h->stream));
+    return LF_OK;
+}
+
+// exact partition score into the device double *dw (queued, no wait)
+static int partition_score_async(lf_handle *h, double *dw)
 {
     TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
@@ -501,13 +543,21 @@ static int partition_score(lf_handle *h, double *out)
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
     X256 *part = nullptr;
-    double *dw = nullptr;
     LF_TRY(lf_tmp_alloc(h, (void **)&part, sizeof(X256) * nb));
-    LF_TRY(lf_tmp_alloc(h, (void **)&dw, sizeof(double)));
     hipLaunchKernelGGL(k_score_partials, dim3(nb), dim3(256), 0, st, h->cr, K, part, &h->ctr->error);
     hipLaunchKernelGGL(k_score_fold, dim3(1), dim3(WAVE), 0, st, part, nb, dw);
-    LF_HIP(h, hipMemcpyAsync(out, dw, sizeof(double), hipMemcpyDeviceToHost, st));
-    LF_HIP(h, hipStreamSynchronize(st));
+    LF_HIP(h, hipGetLastError());
+    return LF_OK;
+}
+
+static int partition_score(lf_handle *h, double *out)
+{
+    TmpScope tmp_scope(h);
+    double *dw = nullptr;
+    LF_TRY(lf_tmp_alloc(h, (void **)&dw, sizeof(double)));
+    LF_TRY(partition_score_async(h, dw));
+    LF_HIP(h, hipMemcpyAsync(out, dw, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LF_HIP(h, hipStreamSynchronize(h->stream));
     LF_HIP(h, hipGetLastError());
     return LF_OK;
 }
@@ -517,6 +567,11 @@ int lf_check_dev_error(lf_handle *h)
     int e = 0;
     LF_HIP(h, hipMemcpyAsync(&e, &h->ctr->error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     LF_HIP(h, hipStreamSynchronize(h->stream));
+    return lf_dev_error_status(h, e);
+}
+
+int lf_dev_error_status(lf_handle *h, int e)
+{
     if (e & LF_DEVERR_INEXACT) return lf_set_error(h, LF_EOVERFLOW, "a score term left the exact accumulator's range");
     if (e & LF_DEVERR_SLOTS) return lf_set_error(h, LF_EINTERNAL, "membership slot capacity exceeded");
     if (e & LF_DEVERR_INCOUNT) return lf_set_error(h, LF_EINTERNAL, "in-count bookkeeping inconsistent");
@@ -604,6 +659,7 @@ static int alloc_partition_state(lf_handle *h, long long K, long long slots)
     size_t KK = (size_t)(K > 0 ? K : 1);
     LF_TRY(lf_dev_alloc(h, (void **)&h->nh, sizeof(NodeHdr) * (nn + 1)));
     h->slot_capb[0] = h->slot_capb[1] = slots > 0 ? slots : 1;
+    h->slot_used = slots;
     LF_TRY(lf_dev_alloc(h, (void **)&h->slot[0], sizeof(Slot) * h->slot_capb[0]));
     LF_TRY(lf_dev_alloc(h, (void **)&h->slot[1], sizeof(Slot) * h->slot_capb[1]));
     h->cur = 0;
@@ -735,27 +791,43 @@ int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
     if (K > 0) hipLaunchKernelGGL(k_clear_dead, dim3(grid_for(K, BS)), dim3(BS), 0, st, cx);
     LF_HIP(h, hipMemsetAsync(newcap + n, 0, sizeof(long long), st));
     LF_TRY(lf_exclusive_scan_i64(h, newcap, noff, n + 1));
-    long long total = 0;
-    LF_HIP(h, hipMemcpyAsync(&total, noff + n, sizeof(long long), hipMemcpyDeviceToHost, st));
-    LF_HIP(h, hipStreamSynchronize(st));
+    // the new layout holds at most the current one's entries plus one per node (a node's
+    // count grows only into its free slot), so the copy needs no wait for its size
     int other = 1 - h->cur;
-    if (total > h->slot_capb[other]) {
-        long long want = total + total / 4 + 1024;
+    const long long bound = h->slot_used + n + 1;
+    if (bound > h->slot_capb[other]) {
+        long long want = bound + bound / 4 + 1024;
         lf_dev_free(h, h->slot[other]);
         h->slot[other] = nullptr;
         LF_TRY(lf_dev_alloc(h, (void **)&h->slot[other], sizeof(Slot) * want));
         h->slot_capb[other] = want;
     }
-    hipLaunchKernelGGL(k_copy_slots, dim3(grid_for(n + 1, BS)), dim3(BS), 0, st, cx, noff, h->slot[other], total);
+    hipLaunchKernelGGL(k_copy_slots, dim3(grid_for(n + 1, BS)), dim3(BS), 0, st, cx, noff, h->slot[other]);
     h->cur = other;
-    LF_TRY(rebuild_member_lists(h));
-    LF_TRY(partition_score(h, &h->Wt));
-    unsigned long long jl[2] = {0, 0};
-    int lv[2] = {0, 0};
-    LF_HIP(h, hipMemcpyAsync(jl, &h->ctr->joins, sizeof(jl), hipMemcpyDeviceToHost, st));
-    LF_HIP(h, hipMemcpyAsync(lv, &h->ctr->live, sizeof(lv), hipMemcpyDeviceToHost, st));
+    LF_TRY(rebuild_member_lists_async(h));
+    double *dw = nullptr;
+    LF_TRY(lf_tmp_alloc(h, (void **)&dw, sizeof(double)));
+    LF_TRY(partition_score_async(h, dw));
+    // the host's one wait of the iteration end: every value it needs in one pinned record
+    long long *drep = nullptr;
+    LF_TRY(lf_tmp_alloc(h, (void **)&drep, sizeof(long long) * 16));
+    hipLaunchKernelGGL(k_end_report, dim3(1), dim3(1), 0, st, (const DevCounters *)h->ctr, noff + n,
+                       (const long long *)h->cm_off + K, (const double *)dw, drep);
+    LF_HIP(h, hipMemcpyAsync(h->hrep, drep, sizeof(long long) * 16, hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
+    const long long *r = h->hrep;
+    h->slot_used = r[REP_SLOTS];
+    if (r[REP_MEMBERS] > h->cm_cap) {        // rare: member lists outgrew their buffer
+        LF_TRY(grow_member_lists(h, r[REP_MEMBERS]));
+        LF_HIP(h, hipStreamSynchronize(st));
+    }
+    double wt;
+    memcpy(&wt, &r[REP_SCORE], sizeof wt);
+    h->Wt = wt;
+    unsigned long long jl[2] = {(unsigned long long)r[REP_JOINS], (unsigned long long)r[REP_LEAVES]};
+    int lv[2] = {(int)r[REP_LIVE], 0};
+    h->last_dev_error = (int)r[REP_ERROR];
     *joins = (long long)jl[0];
     *leaves = (long long)jl[1];
     *live = lv[0];

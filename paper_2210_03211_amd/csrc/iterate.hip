@@ -1236,12 +1236,14 @@ __global__ void k_path_base(const long long *scan, long long n, int c, long long
     if (threadIdx.x == 0 && blockIdx.x == 0) pbase[c + 1] = pbase[c] + scan[n];
 }
 
-// work items of every table-path node: its neighbours, its own memberships and one spare
-__global__ void k_titem_counts(Ctx cx, long long nt, long long *cnt)
+// work items of every table-path node: its neighbours, its own memberships and one spare;
+// the number of table-path nodes nt is read on the device (the path list's length), and
+// the counts are written for all n + 1 positions (0 from nt on)
+__global__ void k_titem_counts(Ctx cx, const long long *nt_dev, long long n, long long *cnt)
 {
     long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (p > nt) return;
-    if (p == nt) { cnt[p] = 0; return; }
+    if (p > n) return;
+    if (p >= *nt_dev) { cnt[p] = 0; return; }
     NodeHdr hx = cx.nh[cx.order[cx.plist[LF_PATH_TABLE][p]]];
     cnt[p] = (long long)hx.deg + hx.cnt + 1;
 }
@@ -1252,13 +1254,18 @@ __global__ void k_queue_items(const long long *titem_base, const long long *qoff
     if (k <= nq) out[k] = titem_base[qoff_t[k]];
 }
 
-__global__ void __launch_bounds__(256) k_titem_fill(Ctx cx, long long nt)
+// owner of every work item; waves stride over the nt table-path nodes.  Nothing is written
+// if the items exceed the buffer's capacity (the host then grows it and runs this again).
+__global__ void __launch_bounds__(256) k_titem_fill(Ctx cx, const long long *nt_dev, long long cap)
 {
-    long long p = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
-    int lane = threadIdx.x & (WAVE - 1);
-    if (p >= nt) return;
-    long long a = cx.titem_base[p], b = cx.titem_base[p + 1];
-    for (long long f = a + lane; f < b; f += WAVE) cx.titem_node[f] = (int)p;
+    const long long nt = *nt_dev;
+    if (cx.titem_base[nt] > cap) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
+    for (long long p = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE; p < nt; p += nw) {
+        long long a = cx.titem_base[p], b = cx.titem_base[p + 1];
+        for (long long f = a + lane; f < b; f += WAVE) cx.titem_node[f] = (int)p;
+    }
 }
 
 __global__ void k_empty_table(GEntry *t, long long n)
@@ -1325,14 +1332,18 @@ static int size_queue_buffers(lf_handle *h, long long q)
     hipLaunchKernelGGL(k_node_bounds, dim3(grid_for(n * WAVE, BS)), dim3(BS), 0, st, cx, h->vbound, h->cls,
                        h->eval_wave_cap < 2 * VSMALL ? h->eval_wave_cap : 2 * VSMALL, h->eval_med_cap,
                        h->eval_grp_cap);
-    if (h->hqoff_cap < nq + 1) {
-        free(h->hqoff);
-        h->hqoff = (long long *)malloc(sizeof(long long) * (LF_PATH_COUNT + 1) * (nq + 1));
-        if (!h->hqoff) return lf_set_error(h, LF_ENOMEM, "host queue offsets");
+    if (h->hqoff_cap < nq + 1) {            // pinned, so the one copy below is truly asynchronous
+        if (h->hqoff) (void)hipHostFree(h->hqoff);
+        h->hqoff = nullptr;
+        h->hqoff_cap = 0;
+        if (hipHostMalloc((void **)&h->hqoff, sizeof(long long) * ((LF_PATH_COUNT + 1) * (nq + 1) + 4),
+                          hipHostMallocDefault) != hipSuccess)
+            return lf_set_error(h, LF_ENOMEM, "host queue offsets");
         h->hqoff_cap = nq + 1;
     }
+    const long long nrep = (LF_PATH_COUNT + 1) * (nq + 1) + 4;   // list offsets, queue items, bounds
     long long *dq = nullptr;
-    LF_TRY(lf_tmp_alloc(h, (void **)&dq, sizeof(long long) * (LF_PATH_COUNT + 1) * (nq + 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&dq, sizeof(long long) * nrep));
     if (!h->titem_base) {
         LF_TRY(lf_dev_alloc(h, (void **)&h->titem_base, sizeof(long long) * (n + 1)));
         moved = true;
@@ -1350,17 +1361,34 @@ static int size_queue_buffers(lf_handle *h, long long q)
                            (const long long *)h->pbase, h->prec_all);
         hipLaunchKernelGGL(k_path_base, dim3(1), dim3(1), 0, st, (const long long *)h->cscan, n, c, h->pbase);
     }
-    LF_HIP(h, hipMemcpyAsync(h->hqoff, dq, sizeof(long long) * LF_PATH_COUNT * (nq + 1), hipMemcpyDeviceToHost,
-                             st));
-    unsigned long long *dout = nullptr;
-    LF_TRY(lf_tmp_alloc(h, (void **)&dout, sizeof(unsigned long long) * 4));
+    unsigned long long *dout = (unsigned long long *)(dq + (LF_PATH_COUNT + 1) * (nq + 1));
     LF_HIP(h, hipMemsetAsync(dout, 0, sizeof(unsigned long long) * 4, st));
     hipLaunchKernelGGL(k_chunk_bounds, dim3((unsigned)nq), dim3(BS), 0, st, cx, (const long long *)h->vbound,
                        (const int *)h->cls, (int)q, dout);
-    unsigned long long hb[4];
-    LF_HIP(h, hipMemcpyAsync(hb, dout, sizeof(hb), hipMemcpyDeviceToHost, st));
+    // static work-item layout of the table-path nodes (list position p owns deg + cnt + 1),
+    // all on the device: the table path's length is the last queue offset of its list
+    const long long *nt_dev = dq + LF_PATH_TABLE * (nq + 1) + nq;
+    hipLaunchKernelGGL(k_titem_counts, dim3(grid_for(n + 1, BS)), dim3(BS), 0, st, lf_ctx(h), nt_dev, n, h->cscan);
+    LF_TRY(lf_exclusive_scan_i64(h, h->cscan, h->titem_base, n + 1));
+    if (!h->titem_node) {
+        long long want = 4096 + n / 4;
+        LF_TRY(lf_dev_alloc(h, (void **)&h->titem_node, sizeof(int) * want));
+        h->titem_cap = want;
+        moved = true;
+    }
+    unsigned fill_grid = grid_for(n * WAVE, BS);
+    if (fill_grid > 2048) fill_grid = 2048;
+    if (fill_grid < 1) fill_grid = 1;
+    hipLaunchKernelGGL(k_titem_fill, dim3(fill_grid), dim3(BS), 0, st, lf_ctx(h), nt_dev, h->titem_cap);
+    // first table-path work item of every queue (sizes the table-visit role)
+    hipLaunchKernelGGL(k_queue_items, dim3(grid_for(nq + 1, BS)), dim3(BS), 0, st, (const long long *)h->titem_base,
+                       (const long long *)(dq + LF_PATH_TABLE * (nq + 1)), nq, dq + LF_PATH_COUNT * (nq + 1));
+    // the host's one wait of the iteration start: list offsets per queue and path, the
+    // queues' first table items, the bounds
+    LF_HIP(h, hipMemcpyAsync(h->hqoff, dq, sizeof(long long) * nrep, hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
+    const unsigned long long *hb = (const unsigned long long *)(h->hqoff + (LF_PATH_COUNT + 1) * (nq + 1));
     {   // the records of path c start after those of the paths before it
         long long base = 0;
         for (int c = 0; c < LF_PATH_COUNT; c++) {
@@ -1372,29 +1400,18 @@ static int size_queue_buffers(lf_handle *h, long long q)
     long long initems = (long long)hb[2] + 64;
     if (keys >= (1ll << 30) || initems >= (1ll << 31))
         return lf_set_error(h, LF_EOVERFLOW, "queue of %lld nodes too large for the table path", q);
-    // static work-item layout of the table-path nodes: list position p owns deg + cnt + 1
     const long long nt = h->hqoff[LF_PATH_TABLE * (nq + 1) + nq];
-    hipLaunchKernelGGL(k_titem_counts, dim3(grid_for(nt + 1, BS)), dim3(BS), 0, st, lf_ctx(h), nt, h->cscan);
-    LF_TRY(lf_exclusive_scan_i64(h, h->cscan, h->titem_base, nt + 1));
-    long long items = 0;
-    LF_HIP(h, hipMemcpyAsync(&items, h->titem_base + nt, sizeof(long long), hipMemcpyDeviceToHost, st));
-    LF_HIP(h, hipStreamSynchronize(st));
-    if (items > h->titem_cap || !h->titem_node) {
+    const long long items = h->hqoff[LF_PATH_COUNT * (nq + 1) + nq];
+    if (items > h->titem_cap) {             // rare: grow and lay the items out again
         lf_dev_free(h, h->titem_node);
         h->titem_node = nullptr;
         long long want = items + items / 8 + 1024;
         LF_TRY(lf_dev_alloc(h, (void **)&h->titem_node, sizeof(int) * want));
         h->titem_cap = want;
         moved = true;
+        if (nt > 0)
+            hipLaunchKernelGGL(k_titem_fill, dim3(fill_grid), dim3(BS), 0, st, lf_ctx(h), nt_dev, h->titem_cap);
     }
-    if (nt > 0)
-        hipLaunchKernelGGL(k_titem_fill, dim3(grid_for(nt * WAVE, BS)), dim3(BS), 0, st, lf_ctx(h), nt);
-    // first table-path work item of every queue (sizes the table-visit role)
-    hipLaunchKernelGGL(k_queue_items, dim3(grid_for(nq + 1, BS)), dim3(BS), 0, st, (const long long *)h->titem_base,
-                       (const long long *)(dq + LF_PATH_TABLE * (nq + 1)), nq, dq + LF_PATH_COUNT * (nq + 1));
-    LF_HIP(h, hipMemcpyAsync(h->hqoff + LF_PATH_COUNT * (nq + 1), dq + LF_PATH_COUNT * (nq + 1),
-                             sizeof(long long) * (nq + 1), hipMemcpyDeviceToHost, st));
-    LF_HIP(h, hipStreamSynchronize(st));
     long long T = 1024;
     while (T < 2 * keys) T <<= 1;
     if (T > h->gT) {
@@ -1437,7 +1454,6 @@ static int size_queue_buffers(lf_handle *h, long long q)
         moved = true;
     }
     if (moved) h->graph_version++;
-    LF_HIP(h, hipStreamSynchronize(st));
     return LF_OK;
 }
 
@@ -1587,7 +1603,7 @@ int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long 
     LF_TRY(lf_prof_begin(h, LF_K_ITEREND));
     LF_TRY(lf_iteration_end(h, joins, leaves, live));
     LF_TRY(lf_prof_end(h, LF_K_ITEREND, 8));
-    return lf_check_dev_error(h);
+    return lf_dev_error_status(h, h->last_dev_error);   // the flags came with the iteration-end report
 }
 
 int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out)

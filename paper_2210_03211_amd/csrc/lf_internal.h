@@ -233,9 +233,13 @@ struct lf_handle {
     long long *titem_base;
     int *titem_node;
     long long titem_cap;
-    long long *hqoff;        // host: [LF_PATH_COUNT][nq + 1] first list position per queue,
-                             // then [nq + 1] first table-path work item per queue
-    long long hqoff_cap;
+    long long *hqoff;        // pinned host: [LF_PATH_COUNT][nq + 1] first list position per
+                             // queue, then [nq + 1] first table-path work item per queue,
+                             // then the 4 bounds of k_chunk_bounds
+    long long hqoff_cap;     // queues (nq + 1) it has room for
+    long long *hrep;         // pinned host report of an iteration end (REP_* entries)
+    long long slot_used;     // slot entries of the current layout (nh[n].off)
+    int last_dev_error;      // device error flags read with the last iteration-end report
     unsigned long long *big_bj, *big_bl;
     int *big_cj, *big_cl;
     GEntry *gt;
@@ -366,6 +370,7 @@ int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long 
 int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
                      long long *live);
 int lf_check_dev_error(lf_handle *h);
+int lf_dev_error_status(lf_handle *h, int e);
 void lf_free_iteration_buffers(lf_handle *h);
 int lf_fetch_memberships(lf_handle *h, long long *offsets, int *comm_ids, long long capacity,
                          long long *total, int *in_counts);
