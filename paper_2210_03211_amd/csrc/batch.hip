@@ -29,7 +29,8 @@ struct BatchMember {
     int max_iters;
     double theta;
     int it;                  // iterations completed
-    bool in_iter;
+    int phase;               // PH_*: where the member is between and within iterations
+    hipEvent_t ev;           // recorded behind its queued iteration start or end
     int state;               // 0 iterating, 1 done, < 0 failed (status)
     double prev;
     int converged, hit_max;
@@ -170,12 +171,22 @@ static int batch_reserve(lf_batch *b, int nm)
     return LF_OK;
 }
 
-// record the result of a finished iteration and decide whether the member goes on
+// A member's iteration start and end are queued on the batch stream like its queue
+// kernels, with an event behind them; the host finishes them on a later step once the event
+// has completed, so it never waits for the stream and the device never drains.  The member
+// sits out the steps in between.
+#define PH_BEGIN 0           // an iteration start is to be queued
+#define PH_BEGIN_WAIT 1      // queued; waiting for its event
+#define PH_RUN 2             // launching queues
+#define PH_END_WAIT 3        // the iteration end is queued; waiting for its event
+
+// record the result of a finished iteration (its end has completed on the device) and
+// decide whether the member goes on
 static int member_iteration_done(BatchMember *m)
 {
     lf_handle *h = m->h;
     long long joins = 0, leaves = 0, live = 0;
-    int rc = lf_iter_finish(h, &joins, &leaves, &live);
+    int rc = lf_iter_finish_complete(h, &joins, &leaves, &live);
     if (rc != LF_OK) return rc;
     m->it++;
     m->hist.push_back(h->Wt);
@@ -184,7 +195,7 @@ static int member_iteration_done(BatchMember *m)
     m->comms.push_back(live);
     bool stop = (m->prev == 0.0) || ((h->Wt - m->prev) / m->prev < m->theta);
     m->prev = h->Wt;
-    m->in_iter = false;
+    m->phase = PH_BEGIN;
     if (stop) {
         m->converged = 1;
         m->state = 1;
@@ -255,6 +266,10 @@ int lf_batch_add(lf_batch *b, lf_handle *h, int32_t queue_size, double threshold
     if (h->device != b->device) return batch_error(b, LF_EINVAL, "lf_batch_add: handle on another device");
     if (hipStreamSynchronize(h->stream) != hipSuccess) return batch_error(b, LF_EDEVICE, "stream sync failed");
     BatchMember *m = new BatchMember();
+    if (hipEventCreateWithFlags(&m->ev, hipEventDisableTiming) != hipSuccess) {
+        delete m;
+        return batch_error(b, LF_EDEVICE, "event creation failed");
+    }
     m->h = h;
     m->saved_stream = h->stream;
     h->stream = b->stream;
@@ -265,7 +280,7 @@ int lf_batch_add(lf_batch *b, lf_handle *h, int32_t queue_size, double threshold
     m->max_iters = max_iters;
     m->theta = threshold;
     m->it = 0;
-    m->in_iter = false;
+    m->phase = PH_BEGIN;
     m->state = (h->cc == 0.0 || max_iters == 0) ? 1 : 0;
     m->converged = h->cc == 0.0 ? 1 : 0;
     m->hit_max = 0;
@@ -280,19 +295,52 @@ int lf_batch_step(lf_batch *b, int32_t *running)
 {
     if (!b) return LF_EINVAL;
     std::vector<BatchMember *> act;
+    BatchMember *waiting = nullptr;
     for (BatchMember *m : b->members) {
         if (!m || m->state != 0) continue;
-        if (!m->in_iter) {
-            int rc = lf_iter_begin(m->h, m->qq, &m->nq);
+        if (m->phase == PH_END_WAIT || m->phase == PH_BEGIN_WAIT) {
+            hipError_t q = hipEventQuery(m->ev);
+            if (q == hipErrorNotReady) {
+                if (!waiting) waiting = m;
+                continue;
+            }
+            if (q != hipSuccess) {
+                m->state = LF_EDEVICE;
+                continue;
+            }
+            int rc = LF_OK;
+            if (m->phase == PH_END_WAIT) {
+                rc = member_iteration_done(m);        // PH_BEGIN, or done
+            } else {
+                rc = lf_iter_begin_complete(m->h, m->qq, &m->nq);
+                if (rc == LF_OK) {
+                    m->cx = lf_ctx(m->h);
+                    m->k = 0;
+                    m->phase = PH_RUN;
+                }
+            }
             if (rc != LF_OK) {
                 m->state = rc;
                 continue;
             }
-            m->cx = lf_ctx(m->h);
-            m->k = 0;
-            m->in_iter = true;
+            if (m->state != 0) continue;
+        }
+        if (m->phase == PH_BEGIN) {
+            int rc = lf_iter_begin_enqueue(m->h, m->qq);
+            if (rc == LF_OK && hipEventRecord(m->ev, b->stream) != hipSuccess) rc = LF_EDEVICE;
+            if (rc != LF_OK) {
+                m->state = rc;
+                continue;
+            }
+            m->phase = PH_BEGIN_WAIT;
+            if (!waiting) waiting = m;
+            continue;
         }
         act.push_back(m);
+    }
+    if (act.empty() && waiting) {
+        // nothing to launch: wait for the oldest queued start or end instead of spinning
+        if (hipEventSynchronize(waiting->ev) != hipSuccess) return batch_error(b, LF_EDEVICE, "event sync failed");
     }
     const int nm = (int)act.size();
     if (nm > 0) {
@@ -329,8 +377,10 @@ int lf_batch_step(lf_batch *b, int32_t *running)
         for (BatchMember *m : act) {
             m->k++;
             if (m->k == m->nq) {
-                int rc = member_iteration_done(m);
+                int rc = lf_iter_finish_enqueue(m->h);
+                if (rc == LF_OK && hipEventRecord(m->ev, b->stream) != hipSuccess) rc = LF_EDEVICE;
                 if (rc != LF_OK) m->state = rc;
+                else m->phase = PH_END_WAIT;
             }
         }
     }
@@ -377,6 +427,7 @@ int lf_batch_remove(lf_batch *b, int32_t member_id)
     BatchMember *m = b->members[member_id];
     (void)hipStreamSynchronize(b->stream);
     m->h->stream = m->saved_stream;
+    (void)hipEventDestroy(m->ev);
     delete m;
     b->members[member_id] = nullptr;
     return LF_OK;

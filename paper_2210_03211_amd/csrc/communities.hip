@@ -772,8 +772,9 @@ int lf_partition_from_cover(lf_handle *h, const long long *off, const int *ids, 
     return LF_OK;
 }
 
-int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
-                     long long *live)
+// Iteration end, first half (queued): degenerate communities removed, slots compacted,
+// member lists rebuilt, score reduced, and one report copied to pinned host memory.
+int lf_iteration_end_enqueue(lf_handle *h)
 {
     TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
@@ -814,8 +815,15 @@ int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
     hipLaunchKernelGGL(k_end_report, dim3(1), dim3(1), 0, st, (const DevCounters *)h->ctr, noff + n,
                        (const long long *)h->cm_off + K, (const double *)dw, drep);
     LF_HIP(h, hipMemcpyAsync(h->hrep, drep, sizeof(long long) * 16, hipMemcpyDeviceToHost, st));
-    LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
+    return LF_OK;
+}
+
+// second half: read the report (the caller has waited for it), grow the member lists if
+// they did not fit
+int lf_iteration_end_complete(lf_handle *h, long long *joins, long long *leaves, long long *live)
+{
+    hipStream_t st = h->stream;
     const long long *r = h->hrep;
     h->slot_used = r[REP_SLOTS];
     if (r[REP_MEMBERS] > h->cm_cap) {        // rare: member lists outgrew their buffer

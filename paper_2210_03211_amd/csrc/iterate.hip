@@ -1297,7 +1297,10 @@ void lf_free_iteration_buffers(lf_handle *h)
     h->titem_cap = 0;
 }
 
-static int size_queue_buffers(lf_handle *h, long long q)
+// Start of an iteration, first half: everything the host does not need to see, queued on
+// the stream, ending with one copy of the queue offsets and bounds to pinned host memory.
+// The second half (size_queue_complete) runs once that copy has landed.
+static int size_queue_enqueue(lf_handle *h, long long q)
 {
     TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
@@ -1342,8 +1345,13 @@ static int size_queue_buffers(lf_handle *h, long long q)
         h->hqoff_cap = nq + 1;
     }
     const long long nrep = (LF_PATH_COUNT + 1) * (nq + 1) + 4;   // list offsets, queue items, bounds
-    long long *dq = nullptr;
-    LF_TRY(lf_tmp_alloc(h, (void **)&dq, sizeof(long long) * nrep));
+    if (nrep > h->dq_cap) {                 // kept across the two halves (and iterations)
+        lf_dev_free(h, h->dq);
+        h->dq = nullptr;
+        LF_TRY(lf_dev_alloc(h, (void **)&h->dq, sizeof(long long) * (nrep + nrep / 4 + 64)));
+        h->dq_cap = nrep + nrep / 4 + 64;
+    }
+    long long *dq = h->dq;
     if (!h->titem_base) {
         LF_TRY(lf_dev_alloc(h, (void **)&h->titem_base, sizeof(long long) * (n + 1)));
         moved = true;
@@ -1386,8 +1394,23 @@ static int size_queue_buffers(lf_handle *h, long long q)
     // the host's one wait of the iteration start: list offsets per queue and path, the
     // queues' first table items, the bounds
     LF_HIP(h, hipMemcpyAsync(h->hqoff, dq, sizeof(long long) * nrep, hipMemcpyDeviceToHost, st));
-    LF_HIP(h, hipStreamSynchronize(st));
     LF_HIP(h, hipGetLastError());
+    h->pending_moved = moved;
+    h->fill_grid = fill_grid;
+    return LF_OK;
+}
+
+// second half: the host reads what the first half copied (the caller has waited for it)
+// and grows whatever it found too small
+static int size_queue_complete(lf_handle *h, long long q)
+{
+    hipStream_t st = h->stream;
+    const int BS = 256;
+    const long long n = h->n;
+    const long long nq = (n + q - 1) / q;
+    bool moved = h->pending_moved;
+    const unsigned fill_grid = h->fill_grid;
+    const long long *nt_dev = h->dq + LF_PATH_TABLE * (nq + 1) + nq;
     const unsigned long long *hb = (const unsigned long long *)(h->hqoff + (LF_PATH_COUNT + 1) * (nq + 1));
     {   // the records of path c start after those of the paths before it
         long long base = 0;
@@ -1458,13 +1481,28 @@ static int size_queue_buffers(lf_handle *h, long long q)
 }
 
 // Start of an iteration: buffers and path lists for queues of qq nodes, counters reset.
-int lf_iter_begin(lf_handle *h, long long qq, long long *nq)
+// lf_iter_begin_enqueue queues the work; lf_iter_begin_complete must follow once it is done
+// (after a stream sync or a completed event recorded behind it).
+int lf_iter_begin_enqueue(lf_handle *h, long long qq)
 {
-    LF_TRY(size_queue_buffers(h, qq));
-    *nq = (h->n + qq - 1) / qq;
+    LF_TRY(size_queue_enqueue(h, qq));
     LF_HIP(h, hipMemsetAsync(&h->ctr->joins, 0, sizeof(unsigned long long) * 2, h->stream));
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, h->stream, lf_ctx(h));
     return LF_OK;
+}
+
+int lf_iter_begin_complete(lf_handle *h, long long qq, long long *nq)
+{
+    LF_TRY(size_queue_complete(h, qq));
+    *nq = (h->n + qq - 1) / qq;
+    return LF_OK;
+}
+
+int lf_iter_begin(lf_handle *h, long long qq, long long *nq)
+{
+    LF_TRY(lf_iter_begin_enqueue(h, qq));
+    LF_HIP(h, hipStreamSynchronize(h->stream));
+    return lf_iter_begin_complete(h, qq, nq);
 }
 
 // Parameters and grids of queue k (of nq).  compact_grids sizes the grid-stride kernels by
@@ -1596,14 +1634,28 @@ void lf_multi_kernels(const void **fn, int *grid, int *block)
 }
 
 // End of an iteration: counters reset, degenerate communities removed, exact score.
-int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long *live)
+// End of an iteration, in the same two halves as its start.
+int lf_iter_finish_enqueue(lf_handle *h)
 {
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, h->stream, lf_ctx(h));
     LF_HIP(h, hipGetLastError());
     LF_TRY(lf_prof_begin(h, LF_K_ITEREND));
-    LF_TRY(lf_iteration_end(h, joins, leaves, live));
+    LF_TRY(lf_iteration_end_enqueue(h));
     LF_TRY(lf_prof_end(h, LF_K_ITEREND, 8));
+    return LF_OK;
+}
+
+int lf_iter_finish_complete(lf_handle *h, long long *joins, long long *leaves, long long *live)
+{
+    LF_TRY(lf_iteration_end_complete(h, joins, leaves, live));
     return lf_dev_error_status(h, h->last_dev_error);   // the flags came with the iteration-end report
+}
+
+int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long *live)
+{
+    LF_TRY(lf_iter_finish_enqueue(h));
+    LF_HIP(h, hipStreamSynchronize(h->stream));
+    return lf_iter_finish_complete(h, joins, leaves, live);
 }
 
 int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *out)

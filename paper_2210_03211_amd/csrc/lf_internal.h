@@ -240,6 +240,10 @@ struct lf_handle {
     long long *hrep;         // pinned host report of an iteration end (REP_* entries)
     long long slot_used;     // slot entries of the current layout (nh[n].off)
     int last_dev_error;      // device error flags read with the last iteration-end report
+    long long *dq;           // [dq_cap] device: what the iteration start copies to hqoff
+    long long dq_cap;
+    bool pending_moved;      // buffers moved in the first half of an iteration start
+    unsigned fill_grid;      // grid of the table work-item fill of that start
     unsigned long long *big_bj, *big_bl;
     int *big_cj, *big_cl;
     GEntry *gt;
@@ -359,6 +363,10 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
 // one LazyFox iteration split into its host steps (shared by lf_run_iterations and the
 // multi-graph batch): sizing and path lists, per-queue parameters, and the iteration end
 int lf_iter_begin(lf_handle *h, long long qq, long long *nq);
+// the same in two halves: work queued on the handle's stream, then the host's part once
+// that work is done (a stream sync or a completed event behind it)
+int lf_iter_begin_enqueue(lf_handle *h, long long qq);
+int lf_iter_begin_complete(lf_handle *h, long long qq, long long *nq);
 void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool compact_grids, QStep *qs,
                      QGrids *g);
 int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g);
@@ -367,8 +375,10 @@ int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int ca
 #define LF_MULTI_KERNELS 6       // kernels of a batch step (k_big_final and k_big_tie share a grid)
 void lf_multi_kernels(const void **fn, int *grid, int *block);
 int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long *live);
-int lf_iteration_end(lf_handle *h, long long *joins, long long *leaves,
-                     long long *live);
+int lf_iter_finish_enqueue(lf_handle *h);
+int lf_iter_finish_complete(lf_handle *h, long long *joins, long long *leaves, long long *live);
+int lf_iteration_end_enqueue(lf_handle *h);
+int lf_iteration_end_complete(lf_handle *h, long long *joins, long long *leaves, long long *live);
 int lf_check_dev_error(lf_handle *h);
 int lf_dev_error_status(lf_handle *h, int e);
 void lf_free_iteration_buffers(lf_handle *h);
