@@ -28,6 +28,8 @@ WORKLOADS = {
                                "~35M edges (exp 2.3, max degree 15,000, 1-4 memberships, mixing 0.4)"),
     "copurchase": ("copurchase", 256, "co-purchase-shaped graph, 335,000 nodes, ~926k edges"),
     "tiny_sbm": ("tiny_sbm", 64, "2,000-node overlapping SBM"),
+    "dense": ("dense", 16384, "dense heavy-tail planted-overlap graph, 3,000,000 nodes, ~117M edges "
+                              "(exp 2.1, max degree 33,000, 1-5 memberships, mixing 0.5)"),
 }
 
 

@@ -75,6 +75,7 @@ SMALL = {
     "path": lambda: path(9),
     "social_0.2pct": lambda: G.named_config("social", scale=0.002),
     "dense300": lambda: G.random_gnp(300, 0.9, 4),
+    "dense_1pct": lambda: G.named_config("dense", scale=0.01),
 }
 
 
@@ -208,10 +209,49 @@ def test_run_parity_random_graphs(lf, orc, q):
 
 @pytest.mark.parametrize("name,q", [("sbm2000", 64), ("sbm2000", 1), ("sbm2000", 2000),
                                     ("copurchase_1pct", 32), ("social_0.2pct", 256),
-                                    ("cliques", 3), ("path", 2)])
+                                    ("cliques", 3), ("path", 2), ("dense_1pct", 512)])
 def test_run_parity_named(lf, orc, name, q):
     say("run", name, "q", q)
     compare_runs(lf, orc, SMALL[name](), q)
+
+
+def test_dense_tenth_scale_properties(lf):
+    """The dense heavy-tail workload at a tenth of its size (300,000 nodes, ~14M edge pairs,
+    hubs up to ~33,000 neighbours) in its launch configuration (queue 16384): two runs give
+    identical results, resuming from the memberships after two iterations reproduces the
+    rest of the run, and the cover is well formed (ids ascending per node, every community
+    with at least two members)."""
+    import torch
+    g = G.named_config("dense", scale=0.1)
+    say("dense 10% n", g.n, "pairs", g.npairs)
+    runs = []
+    for _ in range(2):
+        h = gpu_graph(lf, g).init_communities()
+        info = h.run_iterations(16384, 0.01, 50)
+        off, ids = h.memberships()
+        runs.append((info, off, ids))
+        h.close()
+    (ia, oa, da), (ib, ob, db) = runs
+    assert ia["iterations"] == ib["iterations"] and np.array_equal(ia["wtilde_hist"], ib["wtilde_hist"])
+    assert np.array_equal(oa, ob) and np.array_equal(da, db)
+    assert ia["iterations"] > 2
+    for x in range(0, g.n, 997):
+        seg = da[oa[x]:oa[x + 1]]
+        assert np.all(np.diff(seg) > 0)
+    assert np.all(np.bincount(da)[np.unique(da)] >= 2)
+    say("dense 10% resume")
+    h = gpu_graph(lf, g).init_communities()
+    h.run_iterations(16384, 0.01, 2)
+    off, ids = h.memberships()
+    K = h.lf_get_graph_info()[2]
+    h.close()
+    r = gpu_graph(lf, g).init_from_memberships(off, ids, K)
+    ri = r.run_iterations(16384, 0.01, 48)
+    assert ri["iterations"] == ia["iterations"] - 2
+    assert np.array_equal(ri["wtilde_hist"], ia["wtilde_hist"][2:])
+    ro, rd = r.memberships()
+    assert np.array_equal(ro, oa) and np.array_equal(rd, da)
+    r.close()
 
 
 def test_run_parity_copurchase_full(lf, orc):
