@@ -32,8 +32,8 @@
 #define EW 4            // waves per block in the wave evaluation path
 #define ECAP 128        // table entries per wave (power of two)
 #define MXCAP 32        // own memberships kept in LDS (wave path)
-#define INB 512         // neighbours per in-count work item
-#define PART 512        // members per re-sum part
+#define INB 64          // neighbours per in-count work item (one per lane)
+#define PART 128        // members per re-sum part
 #define MACC 19         // carry-save counters per multi-part community (3 x 6 digits + in-sum)
 #define GEMPTY (~0ull)
 
