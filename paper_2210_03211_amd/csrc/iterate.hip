@@ -505,19 +505,10 @@ __device__ __forceinline__ long long gfind(const Ctx &cx, int b, int C, bool &cl
     return -1;
 }
 
-// append the entries claimed by the lanes executing this call to the occupied list with
-// one atomic per wave
-__device__ __forceinline__ void occ_append(const Ctx &cx, bool claimed, long long h)
-{
-    unsigned long long m = __ballot(claimed);
-    if (!m) return;
-    int lane = threadIdx.x & (WAVE - 1);
-    int leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&cx.ctr->occ_cnt, __popcll(m));
-    base = __shfl(base, leader, WAVE);
-    if (claimed) cx.occ[base + __popcll(m & ((1ull << lane) - 1))] = (int)h;
-}
+// The occupied list: a wave reserves one slot per visit of its 64 work items with a single
+// atomic (a returning atomic on one shared counter costs ~10-20 ns, serialised, so one per
+// 64-visit step would be the table path's bottleneck); each visit then writes the entry it
+// claimed, or -1, into its own slot.
 
 #define EWB 4           // waves per block in the table-path kernels
 
@@ -591,6 +582,9 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
             if (lane >= o) incl += t;
         }
         const int Vw = __shfl(incl, WAVE - 1, WAVE);
+        long long obase = 0;                   // this chunk's occupied-list slots [obase, obase + Vw)
+        if (lane == 0 && Vw > 0) obase = atomicAdd(&cx.ctr->occ_cnt, Vw);
+        obase = __shfl(obase, 0, WAVE);
         s_start[wv][lane] = incl - vc;
         s_sbase[wv][lane] = sb;
         s_dy[wv][lane] = dy;
@@ -622,7 +616,7 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
                 hh = gfind(cx, j, C, claimed);
                 if (hh < 0) capfail = 1;
             }
-            occ_append(cx, claimed, hh);
+            if (act) cx.occ[obase + v] = claimed ? (int)hh : -1;
             const bool vis = act && hh >= 0 && !ownv;
             if (vis && claimed) {
                 cx.gt[hh].ii = iv;
@@ -756,8 +750,9 @@ __device__ __forceinline__ void body_big_final(const Ctx &cx, const QStep &qs, i
     // per-wave reduction below sees all 64 lanes
     for (long long base = blk * (long long)blockDim.x; base < count; base += stride) {
         long long e = base + threadIdx.x;
-        bool valid = e < count;
-        long long h = valid ? cx.occ[e] : 0;
+        const bool inrange = e < count;
+        long long h = inrange ? cx.occ[e] : -1;   // -1: a visit that claimed no entry
+        bool valid = h >= 0;
         GEntry ge;
         ge.key = GEMPTY;
         if (valid) ge = cx.gt[h];
@@ -807,6 +802,7 @@ __device__ __forceinline__ void body_big_final(const Ctx &cx, const QStep &qs, i
                 if (lb) atomicMax(&cx.big_bl[b], lb);
             }
         }
+        if (inrange && !valid) cx.occ_d[e] = 0.0;   // k_big_tie skips it
         if (valid) {
             cx.occ_key[e] = key | (leave ? (1ull << 63) : 0ull);
             cx.occ_d[e] = dlt;
