@@ -519,6 +519,8 @@ __device__ __forceinline__ long long gfind(const Ctx &cx, int b, int C, bool &cl
 // other visit adds its exact correction, with lanes of one wave that hit the same entry
 // summed first so that a hot entry gets one set of atomics per wave.
 struct TabLds {
+    int vw[EWB];             // visits of each wave's chunk (block-wide slot reservation)
+    long long obase;         // first occupied-list slot of the block's chunk
     long long sbase[EWB][WAVE];
     long long xoff[EWB][WAVE];
     int start[EWB][WAVE];
@@ -543,11 +545,13 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
     const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     const long long ib0 = cx.titem_base[ls];
     const long long count = cx.titem_base[ls + ln] - ib0;
-    const long long gw = (blk * (long long)(EWB * WAVE) + threadIdx.x) / WAVE;
-    const long long nw = (long long)nblk * EWB;
+    const long long bstride = (long long)nblk * EWB * WAVE;
     int bad = 0, capfail = 0;
     unsigned long long nvis = 0;
-    for (long long base = gw * WAVE; base < count; base += nw * WAVE) {
+    // the block walks its chunks of EWB * 64 items in lockstep (same trip count for every
+    // wave), so its waves can reserve their occupied-list slots with one atomic
+    for (long long bbase = (long long)blk * EWB * WAVE; bbase < count; bbase += bstride) {
+        const long long base = bbase + (long long)wv * WAVE;
         long long f = base + lane;
         int vc = 0, dy = 0, jj = -1, own = 0, xcnt = 0;
         long long sb = 0, xoff = 0;
@@ -556,12 +560,14 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
             int r = cx.plist[LF_PATH_TABLE][p];
             int j = r - cstart;
             {
-                int x = cx.prec[LF_PATH_TABLE][p].x;
-                NodeHdr hx = cx.nh[x];
+                const NodeRec nr = cx.prec[LF_PATH_TABLE][p];
+                const int x = nr.x;
                 long long e = ib0 + f - cx.titem_base[p];
+                int y = -1;
+                if (e < nr.d) y = cx.col[nr.rb + e];  // issued beside the node's header
+                NodeHdr hx = cx.nh[x];
                 if (e == 0) mark_table(cx, j, hx.deg);   // k_big_final reads it after this launch
                 if (e < hx.deg) {
-                    int y = cx.col[cx.rowptr[x] + e];
                     NodeHdr hy = cx.nh[y];
                     vc = hy.cnt;
                     sb = hy.off;
@@ -582,9 +588,17 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
             if (lane >= o) incl += t;
         }
         const int Vw = __shfl(incl, WAVE - 1, WAVE);
-        long long obase = 0;                   // this chunk's occupied-list slots [obase, obase + Vw)
-        if (lane == 0 && Vw > 0) obase = atomicAdd(&cx.ctr->occ_cnt, Vw);
-        obase = __shfl(obase, 0, WAVE);
+        // this wave's occupied-list slots [obase, obase + Vw): one atomic for the block
+        if (lane == 0) S.vw[wv] = Vw;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w = 0; w < EWB; w++) tot += S.vw[w];
+            S.obase = tot > 0 ? (long long)atomicAdd(&cx.ctr->occ_cnt, tot) : 0;
+        }
+        __syncthreads();
+        long long obase = S.obase;
+        for (int w = 0; w < wv; w++) obase += S.vw[w];
         s_start[wv][lane] = incl - vc;
         s_sbase[wv][lane] = sb;
         s_dy[wv][lane] = dy;
@@ -670,7 +684,7 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
             }
             nvis += vis ? 1 : 0;
         }
-        WAVE_SYNC();
+        __syncthreads();                      // the chunk's LDS (and the reservation) is reused
     }
     if (cx.stats) {
         nvis = (unsigned long long)wave_sum_i64((long long)nvis);
