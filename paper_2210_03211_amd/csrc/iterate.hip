@@ -858,19 +858,39 @@ QUEUE_KERNELS(k_big_tie, 256, NoLds, body_big_tie)
 // ------------------------------------------------------------------------------------
 // bulk apply
 // ------------------------------------------------------------------------------------
-// first touch of C in this queue appends it to the touched list
-__device__ __forceinline__ void touch(const Ctx &cx, int C, bool want)
-{
-    bool first = want && atomicExch(&cx.tflag[C], 1) == 0;
-    int pos = wave_reserve(&cx.ctr->tcount, first);
-    if (first) cx.tlist[pos] = C;
-}
 
 // community x joined in the current queue, -1 if none (entries of earlier queues are stale)
 __device__ __forceinline__ int joined_in_queue(const Ctx &cx, int x)
 {
     unsigned long long v = cx.joined_to[x];
     return (unsigned)(v >> 32) == cx.qtag ? (int)(unsigned)v : -1;
+}
+
+// Block-wide reservation of a and b slots of two shared counters for each thread (one
+// returning atomic per counter and block: such atomics on one address serialise).  Every
+// thread of the block must call it; *pa / *pb get the thread's first slot.
+__device__ __forceinline__ void block_reserve2(int a, int b, int *ctr_a, int *ctr_b, int *pa, int *pb)
+{
+    __shared__ int s_a[256 / WAVE], s_b[256 / WAVE], s_base[2];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    int ia = a, ib = b;                       // inclusive scans within the wave
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int ta = __shfl_up(ia, o, WAVE), tb = __shfl_up(ib, o, WAVE);
+        if (lane >= o) { ia += ta; ib += tb; }
+    }
+    if (lane == WAVE - 1) { s_a[wv] = ia; s_b[wv] = ib; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ta = 0, tb = 0;
+        for (int w = 0; w < nw; w++) { ta += s_a[w]; tb += s_b[w]; }
+        s_base[0] = ta > 0 ? atomicAdd(ctr_a, ta) : 0;
+        s_base[1] = tb > 0 ? atomicAdd(ctr_b, tb) : 0;
+    }
+    __syncthreads();
+    int oa = s_base[0] + ia - a, ob = s_base[1] + ib - b;
+    for (int w = 0; w < wv; w++) { oa += s_a[w]; ob += s_b[w]; }
+    *pa = oa;
+    *pb = ob;
 }
 
 __device__ __forceinline__ void body_apply_edit(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
@@ -899,51 +919,59 @@ __device__ __forceinline__ void body_apply_edit(const Ctx &cx, const QStep &qs, 
     }
     unsigned long long ml = __ballot(L >= 0);
     if (lane == 0 && ml) atomicAdd(&cx.ctr->leaves, (unsigned long long)__popcll(ml));
-    if (!inq) return;
-    const int x = cx.order[cstart + j];
-    const unsigned long long tag = (unsigned long long)cx.qtag << 32;
-    cx.joined_to[x] = tag | 0xffffffffull;  // no join (yet) in this queue
-    if (J < 0 && L < 0) return;
-    NodeHdr hx = cx.nh[x];
-    int cnt = hx.cnt;
-    if (L >= 0) {
-        int t = find_slot(cx.slot, hx.off, cnt, L);
-        cx.slot[hx.off + t] = cx.slot[hx.off + cnt - 1];
-        cnt--;
-        atomicSub(&cx.cr[L].s, 1);
+    const bool act = inq && (J >= 0 || L >= 0);
+    int x = -1;
+    if (inq) {
+        x = cx.order[cstart + j];
+        const unsigned long long tag = (unsigned long long)cx.qtag << 32;
+        cx.joined_to[x] = tag | 0xffffffffull;  // no join (yet) in this queue
     }
-    touch(cx, L, L >= 0);
-    bool joined = false;
-    if (J >= 0) {
-        long long capx = cx.nh[x + 1].off - hx.off;
-        if (cnt >= capx) {
-            atomicOr(&cx.ctr->error, LF_DEVERR_SLOTS);
-        } else {
-            Slot sn = {J, 0};
-            cx.slot[hx.off + cnt] = sn;
-            cnt++;
-            atomicAdd(&cx.cr[J].s, 1);
-            cx.joined_to[x] = tag | (unsigned)J;
-            joined = true;
-            int p = atomicAdd(&cx.cm_len[J], 1);
-            long long cap = cx.cm_off[J + 1] - cx.cm_off[J];
-            if (p < cap) {
-                cx.cm_node[cx.cm_off[J] + p] = x;
+    bool firstL = false, firstJ = false, joined = false;
+    int blocks = 0;
+    if (act) {
+        NodeHdr hx = cx.nh[x];
+        int cnt = hx.cnt;
+        if (L >= 0) {
+            int t = find_slot(cx.slot, hx.off, cnt, L);
+            cx.slot[hx.off + t] = cx.slot[hx.off + cnt - 1];
+            cnt--;
+            atomicSub(&cx.cr[L].s, 1);
+            firstL = atomicExch(&cx.tflag[L], 1) == 0;   // first touch of L in this queue
+        }
+        if (J >= 0) {
+            long long capx = cx.nh[x + 1].off - hx.off;
+            if (cnt >= capx) {
+                atomicOr(&cx.ctr->error, LF_DEVERR_SLOTS);
             } else {
-                int e = atomicAdd(&cx.ctr->ovf_cnt, 1);
-                cx.ovf_node[e] = x;
-                cx.ovf_comm[e] = J;
-                cx.ovf_flag[J] = 1;
+                Slot sn = {J, 0};
+                cx.slot[hx.off + cnt] = sn;
+                cnt++;
+                atomicAdd(&cx.cr[J].s, 1);
+                cx.joined_to[x] = ((unsigned long long)cx.qtag << 32) | (unsigned)J;
+                joined = true;
+                int p = atomicAdd(&cx.cm_len[J], 1);
+                long long cap = cx.cm_off[J + 1] - cx.cm_off[J];
+                if (p < cap) {
+                    cx.cm_node[cx.cm_off[J] + p] = x;
+                } else {
+                    int e = atomicAdd(&cx.ctr->ovf_cnt, 1);
+                    cx.ovf_node[e] = x;
+                    cx.ovf_comm[e] = J;
+                    cx.ovf_flag[J] = 1;
+                }
+                firstJ = atomicExch(&cx.tflag[J], 1) == 0;
             }
         }
+        cx.nh[x].cnt = cnt;
+        blocks = (hx.deg + INB - 1) / INB;
     }
-    touch(cx, J, joined);
     unsigned long long mj = __ballot(joined);
     if (mj && lane == __ffsll((long long)mj) - 1) atomicAdd(&cx.ctr->joins, (unsigned long long)__popcll(mj));
-    cx.nh[x].cnt = cnt;
-    int blocks = (hx.deg + INB - 1) / INB;
-    int p0 = wave_reserve(&cx.ctr->in_items, blocks == 1);
-    if (blocks > 1) p0 = atomicAdd(&cx.ctr->in_items, blocks);
+    // touched communities and in-count work items: one reservation per block
+    int tpos = 0, p0 = 0;
+    block_reserve2((int)firstL + (int)firstJ, blocks, &cx.ctr->tcount, &cx.ctr->in_items, &tpos, &p0);
+    if (firstL) cx.tlist[tpos++] = L;
+    if (firstJ) cx.tlist[tpos] = J;
     if (blocks > 0) {
         if (p0 + blocks > cx.in_cap) {
             atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
