@@ -781,13 +781,14 @@ __device__ __forceinline__ void body_big_final(const Ctx &cx, const QStep &qs, i
                 NodeHdr hx = cx.nh[x];
                 int k = ge.cnt + (ge.idy > 0 ? 1 : 0);
                 X192 corr = x192_from_digits(ge.d[0], ge.d[1], ge.d[2], ge.d[3]);
-                int a = find_slot(cx.slot, hx.off, hx.cnt, C);
+                int own_in = 0;
+                int a = find_slot_in(cx.slot, hx.off, hx.cnt, C, &own_in);
                 leave = a >= 0;
                 if (ge.idy > 0) {
                     X192 t = visit_term(leave, ge.ii, ge.idy, cx.cr[C].s, bad);
                     x192_add(corr, t);
                 }
-                if (leave && cx.slot[hx.off + a].in != k) atomicOr(&cx.ctr->error, LF_DEVERR_INCOUNT);
+                if (leave && own_in != k) atomicOr(&cx.ctr->error, LF_DEVERR_INCOUNT);
                 dlt = candidate_delta(cx, C, leave, k, hx.deg, corr, bad);
                 ncand++;
             }

@@ -68,10 +68,36 @@ __device__ __forceinline__ void store_comm(const Ctx &cx, int C, long long s, X1
     cx.tflag[C] = 0;
 }
 
+// position of community c among a node's cnt slots (-1 if absent); *in gets its in-count
+__device__ __forceinline__ int find_slot_in(const Slot *slot, long long off, int cnt, int c, int *in)
+{
+    for (int t = 0; t < cnt; t += 4) {         // four independent loads per round trip
+        const Slot s0 = slot[off + t];
+        Slot s1 = {-2, 0}, s2 = {-2, 0}, s3 = {-2, 0};
+        if (t + 1 < cnt) s1 = slot[off + t + 1];
+        if (t + 2 < cnt) s2 = slot[off + t + 2];
+        if (t + 3 < cnt) s3 = slot[off + t + 3];
+        if (s0.comm == c) { *in = s0.in; return t; }
+        if (s1.comm == c) { *in = s1.in; return t + 1; }
+        if (s2.comm == c) { *in = s2.in; return t + 2; }
+        if (s3.comm == c) { *in = s3.in; return t + 3; }
+    }
+    return -1;
+}
+
 __device__ __forceinline__ int find_slot(const Slot *slot, long long off, int cnt, int c)
 {
-    for (int t = 0; t < cnt; t++)
-        if (slot[off + t].comm == c) return t;
+    // four independent loads per round trip (a node holds a handful of memberships)
+    for (int t = 0; t < cnt; t += 4) {
+        const int c0 = slot[off + t].comm;
+        const int c1 = t + 1 < cnt ? slot[off + t + 1].comm : -2;
+        const int c2 = t + 2 < cnt ? slot[off + t + 2].comm : -2;
+        const int c3 = t + 3 < cnt ? slot[off + t + 3].comm : -2;
+        if (c0 == c) return t;
+        if (c1 == c) return t + 1;
+        if (c2 == c) return t + 2;
+        if (c3 == c) return t + 3;
+    }
     return -1;
 }
 
@@ -159,9 +185,10 @@ __device__ __forceinline__ void member_terms(const Ctx &cx, int y, int C, long l
                                              X192 &am, long long &sumi, int &bad)
 {
     NodeHdr hy = cx.nh[y];
-    int t = find_slot(cx.slot, hy.off, hy.cnt, C);
+    int in = 0;
+    int t = find_slot_in(cx.slot, hy.off, hy.cnt, C, &in);
     if (t < 0) return;                       // left C earlier in this iteration
-    long long i = cx.slot[hy.off + t].in;
+    long long i = in;
     long long d = hy.deg;
     sumi += i;
     X192 v = x192_from_double(g_term(i, d, s), bad);
