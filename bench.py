@@ -53,6 +53,9 @@ def parse():
                          "per-kernel bandwidth); empty to skip")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip tuning the path thresholds and launch shapes on the workload (untimed)")
+    ap.add_argument("--options", default="",
+                    help="fixed options instead of tuning, e.g. wave_table=128,med_table=512,grp_table=2048,"
+                         "hub_blocks=1024,refresh_blocks=1024")
     ap.add_argument("--serving-jobs", type=int, default=300,
                     help="jobs of the serving comparison (0 = skip it)")
     ap.add_argument("--serving-rate", type=float, default=200.0, help="Poisson arrival rate (jobs/s)")
@@ -123,10 +126,18 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def stored_traffic(kernel, workload):
+def active_options(h):
+    return ",".join("%s=%d" % (k, h.lf_get_option(k)) for k in TRAFFIC_OPTIONS)
+
+
+TRAFFIC_OPTIONS = ("wave_table", "med_table", "grp_table", "hub_blocks", "refresh_blocks")
+
+
+def stored_traffic(kernel, workload, options=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by the same counters on a copy of known
-    size), or None if there is none or the kernel sources changed since it was taken."""
+    size), or None if there is none, the kernel sources changed since it was taken, or it
+    was taken with other launch options (they decide which paths share a launch)."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
     if not os.path.exists(path):
         return None
@@ -137,6 +148,8 @@ def stored_traffic(kernel, workload):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    if options is not None and kv.get("options") != options:
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
@@ -380,7 +393,11 @@ def main():
         return info, off, ids
 
     tuned = None
-    if not args.no_autotune:
+    if args.options:
+        for kv in args.options.split(","):
+            k, v = kv.split("=")
+            h.lf_set_option(k.strip(), int(v))
+    elif not args.no_autotune:
         h.load_graph(g.n, src, dst)
         h.init_communities()
         tuned = h.autotune(q, 3)
@@ -439,7 +456,7 @@ def main():
     pass_bytes = kernel_bytes(dom, work["paths"])
     per_launch = pass_bytes / max(1, timing["launches"][dom]) if pass_bytes is not None else None
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if per_launch is not None else None
-    traffic = stored_traffic(dom, args.workload)
+    traffic = stored_traffic(dom, args.workload, active_options(h))
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
             "kernel": dom, "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches": launches}
@@ -460,6 +477,7 @@ def main():
     }
     if tuned is not None:
         out["autotune"] = tuned
+    out["options"] = active_options(h)
     out["exact_wcc"] = exact_wcc_bench(h, args.steps)
     out["postprocess"] = postprocess_bench(h, args.steps)
     out["cover_f1"] = cover_f1_bench(h, g, args.steps)
