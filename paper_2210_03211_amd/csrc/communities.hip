@@ -446,7 +446,6 @@ Ctx lf_ctx(lf_handle *h)
     c.occ_d = h->occ_d;
     c.gmask = h->gT > 0 ? h->gT - 1 : 0;
     c.in_item = h->in_item;
-    c.in_base = h->in_base;
     c.in_cap = (int)h->in_cap;
     c.part_comm = h->part_comm;
     c.part_base = h->part_base;

@@ -928,8 +928,10 @@ __device__ __forceinline__ void body_apply_edit(const Ctx &cx, const QStep &qs, 
         cx.joined_to[x] = tag | 0xffffffffull;  // no join (yet) in this queue
     }
     bool firstL = false, firstJ = false, joined = false;
-    int blocks = 0;
+    int blocks = 0, deg = 0;
+    long long rb = 0, jslot = 0;
     if (act) {
+        rb = cx.rowptr[x];
         NodeHdr hx = cx.nh[x];
         int cnt = hx.cnt;
         if (L >= 0) {
@@ -945,7 +947,8 @@ __device__ __forceinline__ void body_apply_edit(const Ctx &cx, const QStep &qs, 
                 atomicOr(&cx.ctr->error, LF_DEVERR_SLOTS);
             } else {
                 Slot sn = {J, 0};
-                cx.slot[hx.off + cnt] = sn;
+                jslot = hx.off + cnt;
+                cx.slot[jslot] = sn;
                 cnt++;
                 atomicAdd(&cx.cr[J].s, 1);
                 cx.joined_to[x] = ((unsigned long long)cx.qtag << 32) | (unsigned)J;
@@ -964,7 +967,8 @@ __device__ __forceinline__ void body_apply_edit(const Ctx &cx, const QStep &qs, 
             }
         }
         cx.nh[x].cnt = cnt;
-        blocks = (hx.deg + INB - 1) / INB;
+        deg = hx.deg;
+        blocks = (deg + INB - 1) / INB;
     }
     unsigned long long mj = __ballot(joined);
     if (mj && lane == __ffsll((long long)mj) - 1) atomicAdd(&cx.ctr->joins, (unsigned long long)__popcll(mj));
@@ -974,11 +978,19 @@ __device__ __forceinline__ void body_apply_edit(const Ctx &cx, const QStep &qs, 
     if (firstL) cx.tlist[tpos++] = L;
     if (firstJ) cx.tlist[tpos] = J;
     if (blocks > 0) {
-        if (p0 + blocks > cx.in_cap) {
-            atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
-        } else {
-            cx.in_base[j] = p0;
-            for (int k = 0; k < blocks; k++) cx.in_item[p0 + k] = j;
+        const bool fits = p0 + blocks <= cx.in_cap;
+        if (!fits) atomicOr(&cx.ctr->error, LF_DEVERR_CAP);   // the run fails with this error
+        InItem it;
+        it.rb = rb;
+        it.jslot = jslot;
+        it.x = fits ? x : -1;                 // over capacity: the slots that exist stay empty
+        it.J = fits && joined ? J : -1;
+        it.L = fits ? L : -1;
+        it.d = fits ? deg : 0;
+        it.pad = 0;
+        for (int k = 0; k < blocks && p0 + k < cx.in_cap; k++) {
+            it.k = k;
+            cx.in_item[p0 + k] = it;
         }
     }
 }
@@ -993,7 +1005,7 @@ __device__ void refresh_plan(const Ctx &cx, int t);
 // each); the other blocks apply the in-count changes.  Both only need the edits.
 __device__ __forceinline__ void body_apply_in(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
 {
-    const int cstart = qs.cstart, clen = qs.clen, plan_blocks = qs.plan_blocks;
+    const int plan_blocks = qs.plan_blocks;
     if (blk < plan_blocks) {
         refresh_plan(cx, blk * blockDim.x + threadIdx.x);
         return;
@@ -1004,36 +1016,33 @@ __device__ __forceinline__ void body_apply_in(const Ctx &cx, const QStep &qs, in
     long long nw = (long long)(nblk - plan_blocks) * (blockDim.x / WAVE);
     for (long long p = ((blk - plan_blocks) * (long long)blockDim.x + threadIdx.x) / WAVE; p < count;
          p += nw) {
-        int j = cx.in_item[p];
-        if (j < 0 || j >= clen) continue;          // only after a flagged overflow
-        int k = (int)p - cx.in_base[j];
-        if (k < 0) continue;
-        int J = cx.dj[j], L = cx.dl[j];
-        int x = cx.order[cstart + j];
-        if (J >= 0 && joined_in_queue(cx, x) != J) J = -1;   // join did not fit (error flagged)
-        long long rb = cx.rowptr[x];
-        int d = cx.deg[x];
-        int lo = k * INB, hi = lo + INB < d ? lo + INB : d;
+        const InItem it = cx.in_item[p];
+        if (it.x < 0) continue;                    // only after a flagged overflow
+        const int J = it.J, L = it.L;
+        const int lo = it.k * INB, hi = lo + INB < it.d ? lo + INB : it.d;
         int fresh = 0;
         for (int e = lo + lane; e < hi; e += WAVE) {
-            int y = cx.col[rb + e];
+            int y = cx.col[it.rb + e];
             NodeHdr hy = cx.nh[y];
             int jy = joined_in_queue(cx, y);
-            for (int t = 0; t < hy.cnt; t++) {
-                int c = cx.slot[hy.off + t].comm;
-                if (c == J && J >= 0) {
-                    fresh++;
-                    if (jy != J) atomicAdd(&cx.slot[hy.off + t].in, 1);
-                } else if (c == L && L >= 0) {
-                    if (jy != L) atomicSub(&cx.slot[hy.off + t].in, 1);
+            for (int t0 = 0; t0 < hy.cnt; t0 += 4) {   // four slot loads per round trip
+                int cc[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) cc[u] = t0 + u < hy.cnt ? cx.slot[hy.off + t0 + u].comm : -2;
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int c = cc[u];
+                    if (c == J && J >= 0) {
+                        fresh++;
+                        if (jy != J) atomicAdd(&cx.slot[hy.off + t0 + u].in, 1);
+                    } else if (c == L && L >= 0) {
+                        if (jy != L) atomicSub(&cx.slot[hy.off + t0 + u].in, 1);
+                    }
                 }
             }
         }
         fresh = wave_sum_int(fresh);
-        if (lane == 0 && J >= 0 && fresh) {
-            NodeHdr hx = cx.nh[x];
-            atomicAdd(&cx.slot[hx.off + hx.cnt - 1].in, fresh);
-        }
+        if (lane == 0 && J >= 0 && fresh) atomicAdd(&cx.slot[it.jslot].in, fresh);
     }
 }
 QUEUE_KERNELS(k_apply_in, 256, NoLds, body_apply_in)
@@ -1321,7 +1330,7 @@ void lf_free_iteration_buffers(lf_handle *h)
     void **ptrs[] = {(void **)&h->dj, (void **)&h->dl, (void **)&h->djd, (void **)&h->dld,
                      (void **)&h->big_idx,
                      (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl,
-                     (void **)&h->in_base, (void **)&h->gt, (void **)&h->occ, (void **)&h->occ_key, (void **)&h->occ_d,
+                     (void **)&h->gt, (void **)&h->occ, (void **)&h->occ_key, (void **)&h->occ_d,
                      (void **)&h->in_item, (void **)&h->part_comm, (void **)&h->macc,
                      (void **)&h->titem_base, (void **)&h->titem_node};
     for (void **p : ptrs) {
@@ -1349,8 +1358,7 @@ static int size_queue_enqueue(lf_handle *h, long long q)
     if (q > h->q_cap) {
         void **ptrs[] = {(void **)&h->dj, (void **)&h->dl, (void **)&h->djd, (void **)&h->dld,
                          (void **)&h->big_idx,
-                         (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl,
-                         (void **)&h->in_base};
+                         (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl};
         for (void **p : ptrs) {
             lf_dev_free(h, *p);
             *p = nullptr;
@@ -1364,7 +1372,6 @@ static int size_queue_enqueue(lf_handle *h, long long q)
         LF_TRY(lf_dev_alloc(h, (void **)&h->big_bl, sizeof(unsigned long long) * q));
         LF_TRY(lf_dev_alloc(h, (void **)&h->big_cj, sizeof(int) * q));
         LF_TRY(lf_dev_alloc(h, (void **)&h->big_cl, sizeof(int) * q));
-        LF_TRY(lf_dev_alloc(h, (void **)&h->in_base, sizeof(int) * q));
         h->q_cap = q;
         moved = true;
     }
@@ -1495,7 +1502,7 @@ static int size_queue_complete(lf_handle *h, long long q)
         lf_dev_free(h, h->in_item);
         h->in_item = nullptr;
         long long want = initems + initems / 4;
-        LF_TRY(lf_dev_alloc(h, (void **)&h->in_item, sizeof(int) * want));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->in_item, sizeof(InItem) * want));
         h->in_cap = want;
         moved = true;
     }

@@ -23,6 +23,18 @@ struct Slot {
     int in;
 };
 
+// One in-count work item: a block of INB neighbours of a node that moved in this queue,
+// with everything the item needs (written by the membership edits).
+struct InItem {
+    long long rb;            // first adjacency position of the moved node
+    long long jslot;         // absolute slot of its join (valid if J >= 0)
+    int x;                   // the moved node
+    int J, L;                // community joined (-1: none or it did not fit) and left (-1: none)
+    int d;                   // its degree
+    int k;                   // which block of neighbours
+    int pad;
+};
+
 // A node of a path list with what its evaluation reads first (row offset, id, degree), so
 // that its adjacency gathers can start without first resolving the order position.
 struct NodeRec {
@@ -129,8 +141,7 @@ struct Ctx {
     double *occ_d;             // [gT] change of each occupied entry
     long long gmask;           // gT - 1
     // in-count work items
-    int *in_item;            // [in_cap] queue index of each item
-    int *in_base;            // [q] first item of queue index j
+    InItem *in_item;         // [in_cap] the in-count work items of the queue
     int in_cap;
     // re-sum parts
     int *part_comm;          // [part_cap]
@@ -251,7 +262,7 @@ struct lf_handle {
     unsigned long long *occ_key;
     double *occ_d;
     long long gT;
-    int *in_item, *in_base;
+    InItem *in_item;         // [in_cap]
     long long in_cap;
     int *part_comm, *part_base, *part_cnt, *part_done, *mslot;
     long long *macc;
