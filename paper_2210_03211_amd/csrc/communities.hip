@@ -447,11 +447,8 @@ Ctx lf_ctx(lf_handle *h)
     c.gmask = h->gT > 0 ? h->gT - 1 : 0;
     c.in_item = h->in_item;
     c.in_cap = (int)h->in_cap;
-    c.part_comm = h->part_comm;
-    c.part_base = h->part_base;
-    c.part_cnt = h->part_cnt;
+    c.part_rec = h->part_rec;
     c.part_done = h->part_done;
-    c.mslot = h->mslot;
     c.macc = h->macc;
     c.part_cap = (int)h->part_cap;
     c.mslot_cap = (int)h->mslot_cap;
@@ -464,8 +461,8 @@ void lf_free_partition(lf_handle *h)
     void **ptrs[] = {(void **)&h->nh, (void **)&h->slot[0], (void **)&h->slot[1], (void **)&h->cr,
                      (void **)&h->cm_off, (void **)&h->cm_len, (void **)&h->cm_node, (void **)&h->tflag,
                      (void **)&h->tlist, (void **)&h->joined_to, (void **)&h->ovf_node,
-                     (void **)&h->ovf_comm, (void **)&h->ovf_flag, (void **)&h->ctr, (void **)&h->part_base,
-                     (void **)&h->part_cnt, (void **)&h->part_done, (void **)&h->mslot, (void **)&h->vbound,
+                     (void **)&h->ovf_comm, (void **)&h->ovf_flag, (void **)&h->ctr,
+                     (void **)&h->part_done, (void **)&h->vbound,
                      (void **)&h->cls, (void **)&h->cscan, (void **)&h->plist[0], (void **)&h->plist[1],
                      (void **)&h->plist[2], (void **)&h->plist[3], (void **)&h->prec_all, (void **)&h->pbase};
     for (void **p : ptrs) {
@@ -668,10 +665,7 @@ static int alloc_partition_state(lf_handle *h, long long K, long long slots)
     LF_TRY(lf_dev_alloc(h, (void **)&h->tflag, sizeof(int) * KK));
     LF_TRY(lf_dev_alloc(h, (void **)&h->tlist, sizeof(int) * KK));
     LF_TRY(lf_dev_alloc(h, (void **)&h->ovf_flag, sizeof(int) * KK));
-    LF_TRY(lf_dev_alloc(h, (void **)&h->part_base, sizeof(int) * KK));
-    LF_TRY(lf_dev_alloc(h, (void **)&h->part_cnt, sizeof(int) * KK));
     LF_TRY(lf_dev_alloc(h, (void **)&h->part_done, sizeof(int) * KK));
-    LF_TRY(lf_dev_alloc(h, (void **)&h->mslot, sizeof(int) * KK));
     LF_TRY(lf_dev_alloc(h, (void **)&h->vbound, sizeof(long long) * (nn + 1)));
     LF_TRY(lf_dev_alloc(h, (void **)&h->cls, sizeof(int) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->cscan, sizeof(long long) * (nn + 1)));

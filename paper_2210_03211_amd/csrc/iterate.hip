@@ -1055,29 +1055,38 @@ __device__ void refresh_plan(const Ctx &cx, int t)
     int count = __atomic_load_n(&cx.ctr->tcount, __ATOMIC_RELAXED);
     if (t >= count) return;
     int C = cx.tlist[t];
-    long long cap = cx.cm_off[C + 1] - cx.cm_off[C];
+    PartRec pr;
+    pr.base = cx.cm_off[C];
+    long long cap = cx.cm_off[C + 1] - pr.base;
     long long len = cx.cm_len[C];
     if (len > cap) len = cap;
     int parts = (int)((len + PART - 1) / PART);
     if (parts < 1) parts = 1;
+    pr.C = C;
+    pr.parts = parts;
+    pr.s = cx.cr[C].s;
+    pr.len = (int)len;
+    pr.ovf = cx.ovf_flag[C];
+    pr.ms = -1;
+    pr.pad = 0;
     int p0 = wave_reserve(&cx.ctr->parts_total, parts == 1);
     if (parts > 1) p0 = atomicAdd(&cx.ctr->parts_total, parts);
     if (p0 + parts > cx.part_cap) {
-        atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
-        return;
-    }
-    cx.part_base[C] = p0;
-    cx.part_cnt[C] = parts;
-    cx.part_done[C] = 0;
-    for (int k = 0; k < parts; k++) cx.part_comm[p0 + k] = C;
-    if (parts > 1) {
+        atomicOr(&cx.ctr->error, LF_DEVERR_CAP);    // the run fails with this error
+        pr.C = -1;                                    // the records that exist stay empty
+    } else if (parts > 1) {
+        cx.part_done[C] = 0;
         int ms = atomicAdd(&cx.ctr->mslots, 1);
         if (ms >= cx.mslot_cap) {
             atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
             ms = 0;
         }
-        cx.mslot[C] = ms;
+        pr.ms = ms;
         for (int k = 0; k < MACC; k++) cx.macc[(long long)ms * MACC + k] = 0;
+    }
+    for (int k = 0; k < parts && p0 + k < cx.part_cap; k++) {
+        pr.k = k;
+        cx.part_rec[p0 + k] = pr;
     }
 }
 
@@ -1123,22 +1132,17 @@ __device__ __forceinline__ void body_refresh(const Ctx &cx, const QStep &qs, int
     long long nw = (long long)nblk * (blockDim.x / WAVE);
     int bad = 0;
     for (long long p = (blk * (long long)blockDim.x + threadIdx.x) / WAVE; p < count; p += nw) {
-        int C = cx.part_comm[p];
+        const PartRec pr = cx.part_rec[p];
+        const int C = pr.C;
         if (C < 0 || C >= cx.K) continue;          // only after a flagged overflow
-        int k = (int)p - cx.part_base[C];
-        int parts = cx.part_cnt[C];
-        if (k < 0 || k >= parts) continue;
-        long long s = cx.cr[C].s;
-        long long base = cx.cm_off[C];
-        long long cap = cx.cm_off[C + 1] - base;
-        long long len = cx.cm_len[C];
-        if (len > cap) len = cap;
+        const int k = pr.k, parts = pr.parts;
+        const long long s = pr.s, base = pr.base, len = pr.len;
         long long lo = (long long)k * PART, hi = lo + PART < len ? lo + PART : len;
         X192 a0 = x192_zero(), ap = x192_zero(), am = x192_zero();
         long long sumi = 0;
         for (long long q = lo + lane; q < hi; q += WAVE)
             member_terms(cx, cx.cm_node[base + q], C, s, a0, ap, am, sumi, bad);
-        if (k == 0 && cx.ovf_flag[C]) {
+        if (k == 0 && pr.ovf) {
             int no = __atomic_load_n(&cx.ctr->ovf_cnt, __ATOMIC_RELAXED);
             for (int e = lane; e < no; e += WAVE)
                 if (cx.ovf_comm[e] == C) member_terms(cx, cx.ovf_node[e], C, s, a0, ap, am, sumi, bad);
@@ -1152,7 +1156,7 @@ __device__ __forceinline__ void body_refresh(const Ctx &cx, const QStep &qs, int
             store_comm(cx, C, s, a0, ap, am, sumi, bad);
             continue;
         }
-        unsigned long long *acc = (unsigned long long *)&cx.macc[(long long)cx.mslot[C] * MACC];
+        unsigned long long *acc = (unsigned long long *)&cx.macc[(long long)pr.ms * MACC];
         long long dg[6];
         x192_to_digits6(a0, dg);
         for (int q = 0; q < 6; q++) atomicAdd(acc + q, (unsigned long long)dg[q]);
@@ -1331,7 +1335,7 @@ void lf_free_iteration_buffers(lf_handle *h)
                      (void **)&h->big_idx,
                      (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl,
                      (void **)&h->gt, (void **)&h->occ, (void **)&h->occ_key, (void **)&h->occ_d,
-                     (void **)&h->in_item, (void **)&h->part_comm, (void **)&h->macc,
+                     (void **)&h->in_item, (void **)&h->part_rec, (void **)&h->macc,
                      (void **)&h->titem_base, (void **)&h->titem_node};
     for (void **p : ptrs) {
         lf_dev_free(h, *p);
@@ -1508,9 +1512,9 @@ static int size_queue_complete(lf_handle *h, long long q)
     }
     long long pcap = 2 * q + (h->cm_cap + n) / PART + 64;
     if (pcap > h->part_cap) {
-        lf_dev_free(h, h->part_comm);
-        h->part_comm = nullptr;
-        LF_TRY(lf_dev_alloc(h, (void **)&h->part_comm, sizeof(int) * pcap));
+        lf_dev_free(h, h->part_rec);
+        h->part_rec = nullptr;
+        LF_TRY(lf_dev_alloc(h, (void **)&h->part_rec, sizeof(PartRec) * pcap));
         h->part_cap = pcap;
         moved = true;
     }

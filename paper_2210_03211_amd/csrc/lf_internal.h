@@ -35,6 +35,19 @@ struct InItem {
     int pad;
 };
 
+// One re-sum part: up to PART members of a touched community, with everything the re-sum
+// needs (written by the planning blocks of the in-count kernel).
+struct PartRec {
+    long long base;          // the community's member-list offset
+    int C;                   // the community (-1: an empty record after a flagged overflow)
+    int k, parts;            // this part and the community's number of parts
+    int s;                   // its size
+    int len;                 // members in its list
+    int ms;                  // carry-save counter slot of a multi-part community (-1: one part)
+    int ovf;                 // members also sit in the overflow list
+    int pad;
+};
+
 // A node of a path list with what its evaluation reads first (row offset, id, degree), so
 // that its adjacency gathers can start without first resolving the order position.
 struct NodeRec {
@@ -144,11 +157,8 @@ struct Ctx {
     InItem *in_item;         // [in_cap] the in-count work items of the queue
     int in_cap;
     // re-sum parts
-    int *part_comm;          // [part_cap]
-    int *part_base;          // [K]
-    int *part_cnt;           // [K]
-    int *part_done;          // [K]
-    int *mslot;              // [K]
+    PartRec *part_rec;       // [part_cap] the re-sum parts of the queue
+    int *part_done;          // [K] parts of a multi-part community finished
     long long *macc;         // [mslot_cap * 19] carry-save accumulators
     int part_cap, mslot_cap;
     int stats;               // collect the per-path work counters
@@ -264,7 +274,8 @@ struct lf_handle {
     long long gT;
     InItem *in_item;         // [in_cap]
     long long in_cap;
-    int *part_comm, *part_base, *part_cnt, *part_done, *mslot;
+    PartRec *part_rec;
+    int *part_done;
     long long *macc;
     long long part_cap, mslot_cap;
     long long *vbound;       // [n] per-node bounds used to size the per-queue buffers
