@@ -1,0 +1,111 @@
+"""Host logic of bench.py (CPU): the one-GPU refusal, the rule that stored rocprofv3 traffic
+is reported only for the kernel sources and launch options it was measured with, and the
+algorithmic byte model behind the roofline."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def write_traffic(dirpath, sha, options, value=1234567):
+    os.makedirs(os.path.join(dirpath, "profiles"), exist_ok=True)
+    with open(os.path.join(dirpath, "profiles", "traffic_k_x_w.txt"), "w") as f:
+        f.write("# comment: with a colon\n")
+        f.write("traffic_bytes_per_launch: %d\n" % value)
+        f.write("kernel_sources_sha256: %s\n" % sha)
+        f.write("options: %s\n" % options)
+
+
+def test_stored_traffic_needs_matching_sources_and_options(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_sources_sha", lambda: "abc")
+    opts = "wave_table=128,med_table=512"
+    assert bench.stored_traffic("k_x", "w", opts) is None          # no file
+    write_traffic(str(tmp_path), "abc", opts)
+    assert bench.stored_traffic("k_x", "w", opts) == 1234567.0
+    assert bench.stored_traffic("k_x", "w") == 1234567.0          # options not checked
+    assert bench.stored_traffic("k_x", "w", "wave_table=64,med_table=512") is None
+    assert bench.stored_traffic("k_x", "other", opts) is None
+    monkeypatch.setattr(bench, "kernel_sources_sha", lambda: "def")
+    assert bench.stored_traffic("k_x", "w", opts) is None          # sources changed
+
+
+def test_kernel_sources_sha_tracks_every_kernel_source(tmp_path, monkeypatch):
+    csrc = tmp_path / "paper_2210_03211_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (tmp_path / "include").mkdir()
+    for f in bench.KERNEL_SOURCES:
+        (csrc / f).write_text("// " + f + "\n")
+    (tmp_path / "include" / "lazyfox.h").write_text("// header\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    base = bench.kernel_sources_sha()
+    assert bench.kernel_sources_sha() == base
+    for f in bench.KERNEL_SOURCES:
+        p = csrc / f
+        old = p.read_text()
+        p.write_text(old + " ")
+        assert bench.kernel_sources_sha() != base, f
+        p.write_text(old)
+    (tmp_path / "include" / "lazyfox.h").write_text("// header changed\n")
+    assert bench.kernel_sources_sha() != base
+
+
+def test_committed_traffic_file_is_well_formed():
+    path = os.path.join(ROOT, "profiles", "traffic_k_eval_big_social.txt")
+    if not os.path.exists(path):
+        pytest.skip("no stored traffic")
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+    write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+    # the scale factors are printed to six decimals
+    assert abs((fetch + write) * 1024 / float(kv["traffic_bytes_per_launch"]) - 1.0) < 1e-6
+    ratio = float(kv["traffic_bytes_per_launch"]) / float(kv["algorithmic_bytes_per_launch"])
+    assert abs(ratio - float(kv["traffic_over_algorithmic"])) < 0.01
+    assert kv["kernel"] == "k_eval_big" and kv["workload"] == "social"
+    assert sorted(o.split("=")[0] for o in kv["options"].split(",")) == sorted(bench.TRAFFIC_OPTIONS)
+
+
+def paths(**w):
+    z = {"nodes": 0, "neighbours": 0, "visits": 0, "candidates": 0}
+    return {p: dict(z, **w.get(p, {})) for p in ("small", "medium", "group", "table")}
+
+
+def test_kernel_byte_model():
+    p = paths(small={"nodes": 1, "neighbours": 2, "visits": 3, "candidates": 4},
+              medium={"nodes": 10}, group={"candidates": 1},
+              table={"nodes": 1, "neighbours": 1, "visits": 1, "candidates": 100})
+    assert bench.kernel_bytes("k_eval", p) == 60 + 2 * 20 + 3 * 12 + 4 * 44
+    # the table path's candidates are scored in k_big_final, not in k_eval_big
+    assert bench.kernel_bytes("k_eval_big", p) == 10 * 60 + 44 + 60 + 20 + 12
+    assert bench.kernel_bytes("k_big_final", p) == 100 * 44
+    assert bench.kernel_bytes("k_refresh", p) is None
+
+
+def test_kernel_rooflines_divide_bytes_by_event_time():
+    p = paths(small={"nodes": 1_000_000}, medium={"neighbours": 1_000_000}, table={"candidates": 1_000_000})
+    timing = {"ms": {"k_eval": 0.06, "k_eval_big": 0.02, "k_big_final": 0.044, "k_big_tie": 0.0},
+              "launches": {"k_eval": 1, "k_eval_big": 1, "k_big_final": 1}}
+    r = bench.kernel_rooflines(timing, p)
+    for k in ("k_eval", "k_eval_big", "k_big_final"):
+        assert abs(r[k]["GB_s"] - 1000.0) < 1e-9
+        assert abs(r[k]["frac"] - 1000.0 / bench.HBM_PEAK_GBS) < 1e-12
+    assert abs(r["evaluation"]["GB_s"] - 1000.0) < 1e-9
+    timing["ms"]["k_big_tie"] = 0.124
+    assert abs(bench.kernel_rooflines(timing, p)["evaluation"]["GB_s"] - 500.0) < 1e-9
