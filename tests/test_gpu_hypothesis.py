@@ -3,12 +3,13 @@ self-loops, isolated nodes, n from 1).  For each drawn graph and queue size the 
 and the oracle must agree bit for bit on the CSR, the node statistics, the initial
 clustering, the whole run (score history, move counts, memberships, in-counts, community
 table), the exact WCC of the final cover, its post-processing flags and its F1 against the
-initial clustering."""
+initial clustering.  Drawn sets of such graphs run through a batch and through the
+serving runtime must each give the oracle's result for the graph alone."""
 import sys
 
 import numpy as np
 import pytest
-from hypothesis import given
+from hypothesis import given, settings
 from hypothesis import strategies as st
 
 from raw_graphs import SETTINGS, edge_lists
@@ -85,3 +86,84 @@ def test_raw_tiny_graphs_match_oracle(lf, orc, g, qfrac, device_ptr):
             assert bits(x) == bits(y)
     finally:
         h.close()
+
+
+def oracle_run(orc, g, q, max_iters):
+    o = orc.Oracle().load_graph(g.n, g.src, g.dst).init_communities(1)
+    info = o.run_iterations(q, 0.01, max_iters, mode=orc.MODE_FAST)
+    return info, o.memberships()
+
+
+def same_run(info, ref):
+    assert info["iterations"] == ref["iterations"]
+    assert info["converged"] == ref["converged"] and info["hit_max"] == ref["hit_max"]
+    for k in ("wtilde_hist", "joins", "leaves", "communities"):
+        assert bits(info[k]) == bits(ref[k]), k
+
+
+jobs = st.lists(st.tuples(edge_lists(), st.floats(0.0, 1.0), st.sampled_from([1, 2, 12])), min_size=1, max_size=5)
+
+
+@SETTINGS
+@given(js=jobs, replay=st.booleans())
+def test_raw_tiny_graphs_batched_match_oracle(lf, orc, js, replay):
+    """Several drawn graphs advanced together by one batch (graph replay or launches one by
+    one): each member's run equals the oracle's run of its graph alone."""
+    import torch
+    print("[case] batch of", len(js), "n", [g.n for g, _, _ in js], "replay", replay, flush=True)
+    b = lf.Batch(0)
+    b.set_graph(replay)
+    hs, mids, refs = [], [], []
+    try:
+        for g, qf, mi in js:
+            q = max(1, int(round(qf * g.n)))
+            h = lf.Handle(0)
+            hs.append(h)
+            h.load_graph(g.n, torch.from_numpy(g.src).cuda(), torch.from_numpy(g.dst).cuda()).init_communities()
+            mids.append(b.add(h, q, 0.01, mi))
+            refs.append(oracle_run(orc, g, q, mi))
+        steps = 0
+        while b.step() > 0:
+            steps += 1
+            assert steps < 100000
+        for h, m, (ref, (ooff, oids)) in zip(hs, mids, refs):
+            same_run(b.member_info(m), ref)
+            b.remove(m)
+            off, ids = h.memberships()
+            assert np.array_equal(off, ooff) and np.array_equal(ids, oids)
+    finally:
+        for h in hs:
+            h.close()
+        b.close()
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, database=None)
+@given(js=jobs, max_batch=st.integers(1, 3))
+def test_raw_tiny_graphs_served_match_oracle(lf, orc, js, max_batch):
+    """The same graphs submitted to the serving runtime with few jobs admitted at a time:
+    each fetched result equals the oracle's run of its graph alone."""
+    print("[case] serve", len(js), "n", [g.n for g, _, _ in js], "max_batch", max_batch, flush=True)
+    srv = lf.Server(0, hbm_budget=1 << 30, max_batch=max_batch)
+    try:
+        want = {}
+        for g, qf, mi in js:
+            q = max(1, int(round(qf * g.n)))
+            want[srv.submit(g.n, g.src, g.dst, q, 0.01, mi)] = oracle_run(orc, g, q, mi)
+        done = {}
+        ticks = 0
+        while True:
+            pending = srv.tick()
+            for jid in [j for j in want if j not in done]:
+                r = srv.fetch(jid)
+                if r is not None:
+                    done[jid] = r
+            ticks += 1
+            assert ticks < 100000
+            if pending == 0 and len(done) == len(want):
+                break
+        for jid, (ref, (ooff, oids)) in want.items():
+            off, ids, info = done[jid]
+            same_run(info, ref)
+            assert np.array_equal(off, ooff) and np.array_equal(ids, oids)
+    finally:
+        srv.close()
