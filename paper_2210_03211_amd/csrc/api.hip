@@ -6,6 +6,24 @@
 
 extern "C" {
 
+// Releases what a handle under construction already holds (lf_create's failure paths;
+// the handle is zero-initialised, so members not created yet are null).
+static int create_failed(lf_handle *h, int rc)
+{
+    if (h->hrep) (void)hipHostFree(h->hrep);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h->allocs;
+    delete h->alloc_sizes;
+    delete h->tmp_chunks;
+    delete h->evpool;
+    delete h->evkind;
+    delete h->evlaunch;
+    free(h);
+    return rc;
+}
+
 int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
 {
     (void)flags;
@@ -21,48 +39,23 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     h->evlaunch = new std::vector<int>();
     h->device = device;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
-        delete h->allocs;
-        delete h->alloc_sizes;
-        delete h->tmp_chunks;
-        free(h);
-        return LF_EDEVICE;
-    }
-    if (hipSetDevice(device) != hipSuccess) {
-        delete h->allocs;
-        delete h->alloc_sizes;
-        delete h->tmp_chunks;
-        free(h);
-        return LF_EDEVICE;
-    }
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return create_failed(h, LF_EDEVICE);
+    if (hipSetDevice(device) != hipSuccess) return create_failed(h, LF_EDEVICE);
     if (hip_stream) {
         h->stream = (hipStream_t)hip_stream;
         h->own_stream = false;
     } else {
         if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete h->allocs;
-            free(h);
-            return LF_EDEVICE;
+            h->stream = nullptr;
+            return create_failed(h, LF_EDEVICE);
         }
         h->own_stream = true;
     }
-    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
-        if (h->own_stream) (void)hipStreamDestroy(h->stream);
-        delete h->allocs;
-        delete h->alloc_sizes;
-        delete h->tmp_chunks;
-        free(h);
-        return LF_EDEVICE;
-    }
+    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+        return create_failed(h, LF_EDEVICE);
     if (hipHostMalloc((void **)&h->hrep, sizeof(long long) * 16, hipHostMallocDefault) != hipSuccess) {
-        (void)hipEventDestroy(h->ev0);
-        (void)hipEventDestroy(h->ev1);
-        if (h->own_stream) (void)hipStreamDestroy(h->stream);
-        delete h->allocs;
-        delete h->alloc_sizes;
-        delete h->tmp_chunks;
-        free(h);
-        return LF_ENOMEM;
+        h->hrep = nullptr;
+        return create_failed(h, LF_ENOMEM);
     }
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
@@ -248,6 +241,8 @@ int lf_get_csr(lf_handle *h, int64_t *rowptr, int32_t *col, int64_t *orig_ids)
     if (!h) return LF_EINVAL;
     if (h->state < 1) return lf_set_error(h, LF_ESTATE, "no graph loaded");
     LF_HIP(h, hipSetDevice(h->device));
+    // blocking copies go through the null stream, which does not wait for a non-blocking one
+    LF_HIP(h, hipStreamSynchronize(h->stream));
     if (rowptr) LF_HIP(h, hipMemcpy(rowptr, h->rowptr, sizeof(long long) * (h->n + 1), hipMemcpyDeviceToHost));
     if (col && h->ne > 0) LF_HIP(h, hipMemcpy(col, h->col, sizeof(int) * 2 * h->ne, hipMemcpyDeviceToHost));
     if (orig_ids && h->n > 0) LF_HIP(h, hipMemcpy(orig_ids, h->orig_id, sizeof(long long) * h->n, hipMemcpyDeviceToHost));
@@ -259,6 +254,7 @@ int lf_get_node_stats(lf_handle *h, int64_t *tri, double *cc_local, int32_t *ord
     if (!h) return LF_EINVAL;
     if (h->state < 2) return lf_set_error(h, LF_ESTATE, "lf_init_communities has not been called");
     LF_HIP(h, hipSetDevice(h->device));
+    LF_HIP(h, hipStreamSynchronize(h->stream));
     size_t n = (size_t)h->n;
     if (n == 0) return LF_OK;
     if (tri) LF_HIP(h, hipMemcpy(tri, h->tri, sizeof(long long) * n, hipMemcpyDeviceToHost));
@@ -283,6 +279,7 @@ int lf_get_communities(lf_handle *h, int32_t *size, int64_t *internal_edges, dou
     if (!h) return LF_EINVAL;
     if (h->state < 2) return lf_set_error(h, LF_ESTATE, "lf_init_communities has not been called");
     LF_HIP(h, hipSetDevice(h->device));
+    LF_HIP(h, hipStreamSynchronize(h->stream));
     size_t K = (size_t)h->K;
     if (K == 0) return LF_OK;
     std::vector<CommRec> rec(K);

@@ -228,20 +228,22 @@ int lf_batch_create(lf_batch **out, int device, void *hip_stream)
     for (int s = 0; s < 2; s++) {
         b->hmem[s] = nullptr;
         b->hboff[s] = nullptr;
-        if (hipEventCreateWithFlags(&b->hev[s], hipEventDisableTiming) != hipSuccess) {
-            delete b;
-            return LF_EDEVICE;
-        }
+        b->hev[s] = nullptr;
     }
-    if (hip_stream) {
+    bool ok = hipEventCreateWithFlags(&b->hev[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b->hev[1], hipEventDisableTiming) == hipSuccess;
+    b->own_stream = false;
+    if (ok && hip_stream) {
         b->stream = (hipStream_t)hip_stream;
-        b->own_stream = false;
-    } else {
-        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete b;
-            return LF_EDEVICE;
-        }
-        b->own_stream = true;
+    } else if (ok) {
+        ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
+        b->own_stream = ok;
+    }
+    if (!ok) {
+        for (int s = 0; s < 2; s++)
+            if (b->hev[s]) (void)hipEventDestroy(b->hev[s]);
+        delete b;
+        return LF_EDEVICE;
     }
     *out = b;
     return LF_OK;
