@@ -66,9 +66,10 @@ def parse():
 
 
 # Algorithmic bytes per unit of evaluation work, from the data layout: per decided node
-# 60 B (order 4, node header 16, row offsets 16, decision 24); per neighbour 20 B (column
-# index 4, node header 16); per neighbour membership visited 12 B (slot 8, community size
-# 4); per candidate scored 44 B (size 4, internal edges 8, score 8, one exact sum 24).
+# 60 B (node record 16, node header 16, row offsets 4, decision 24); per neighbour 20 B
+# (column index 4, node header 16); per neighbour membership visited 12 B (slot 8,
+# community size 4); per candidate scored 44 B (size 4, internal edges 8, score 8, one
+# exact sum 24).
 B_NODE, B_NEIGHBOUR, B_VISIT, B_CAND = 60.0, 20.0, 12.0, 44.0
 
 
