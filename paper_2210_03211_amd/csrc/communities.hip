@@ -167,7 +167,11 @@ __global__ void __launch_bounds__(256) k_cover_check(const long long *off, const
 }
 
 // warm start: node x's memberships in the given order plus one free slot (slot offset
-// off[x] + x); in-count of each = neighbours whose cover lists the community; sizes
+// off[x] + x); in-count of each = neighbours whose cover lists the community; sizes.
+// One wave per node; a pass over the neighbours' lists counts up to COVER_CHUNK of x's
+// communities at once (a node's ids are distinct, so each neighbour adds at most one to
+// each count), so a node with few memberships gathers its neighbourhood once.
+#define COVER_CHUNK 8
 __global__ void __launch_bounds__(256) k_cover_slots(const long long *rowptr, const int *col, const int *deg,
                                                      const long long *off, const int *ids, long long n, NodeHdr *nh,
                                                      Slot *slot, CommRec *cr)
@@ -182,19 +186,34 @@ __global__ void __launch_bounds__(256) k_cover_slots(const long long *rowptr, co
     const long long a0 = off[x];
     const int cnt = (int)(off[x + 1] - a0);
     const long long base = a0 + x;
-    for (int a = 0; a < cnt; a++) {
-        const int c = ids[a0 + a];
-        int in = 0;
-        for (long long e = rowptr[x] + lane; e < rowptr[x + 1]; e += WAVE) {
-            const int z = col[e];
-            for (long long b = off[z]; b < off[z + 1]; b++)
-                if (ids[b] == c) { in++; break; }
+    const long long e0 = rowptr[x], e1 = rowptr[x + 1];
+    for (int a = 0; a < cnt; a += COVER_CHUNK) {
+        const int m = cnt - a < COVER_CHUNK ? cnt - a : COVER_CHUNK;   // uniform over the wave
+        int c[COVER_CHUNK], in[COVER_CHUNK];
+#pragma unroll
+        for (int k = 0; k < COVER_CHUNK; k++) {
+            c[k] = k < m ? ids[a0 + a + k] : -1;   // ids are >= 0: -1 matches nothing
+            in[k] = 0;
         }
-        in = wave_sum_int(in);
-        if (lane == 0) {
-            Slot sl = {c, in};
-            slot[base + a] = sl;
-            atomicAdd(&cr[c].s, 1);
+        for (long long e = e0 + lane; e < e1; e += WAVE) {
+            const int z = col[e];
+            const long long b1 = off[z + 1];
+            for (long long b = off[z]; b < b1; b++) {
+                const int d = ids[b];
+#pragma unroll
+                for (int k = 0; k < COVER_CHUNK; k++) in[k] += d == c[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < COVER_CHUNK; k++) {
+            if (k < m) {
+                const int t = wave_sum_int(in[k]);
+                if (lane == 0) {
+                    Slot sl = {c[k], t};
+                    slot[base + a + k] = sl;
+                    atomicAdd(&cr[c[k]].s, 1);
+                }
+            }
         }
     }
     if (lane == 0) {
