@@ -67,3 +67,34 @@ def test_product_code_never_reaches_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liblfo" not in text and "lfo_" not in text, f
+
+
+def _imports(path):
+    """(module name, enclosing top-level function or None) of every import in a file."""
+    import ast
+    tree = ast.parse(open(path).read())
+    out = []
+
+    def walk(node, fn):
+        for ch in ast.iter_child_nodes(node):
+            f = ch.name if isinstance(ch, ast.FunctionDef) and fn is None else fn
+            if isinstance(ch, ast.Import):
+                out.extend((a.name.split(".")[0], f) for a in ch.names)
+            elif isinstance(ch, ast.ImportFrom) and ch.module:
+                out.append((ch.module.split(".")[0], f))
+            walk(ch, f)
+    walk(tree, None)
+    return out
+
+
+def test_oracle_users_are_the_allowed_ones():
+    """Only the test-side users touch the oracle: the stored expected values are written from
+    the oracle and the generator alone (never from the HIP library), the benchmark imports the
+    oracle only in its CPU-baseline leg, and the entry file only to build it and in smoke()."""
+    golden = _imports(os.path.join(ROOT, "tests", "golden", "make_golden.py"))
+    mods = {m for m, _ in golden}
+    assert "oracle" in mods and "paper_2210_03211_amd" not in mods and "torch" not in mods
+    bench = [(m, f) for m, f in _imports(os.path.join(ROOT, "bench.py")) if m == "oracle"]
+    assert bench and all(f == "cpu_baseline" for _, f in bench), bench
+    entry = [(m, f) for m, f in _imports(os.path.join(ROOT, "__graft_entry__.py")) if m == "oracle"]
+    assert entry and all(f in ("build", "smoke") for _, f in entry), entry
