@@ -35,3 +35,19 @@ def edge_lists(draw, max_n=12, max_pairs=40):
 
 SETTINGS = settings(max_examples=150, deadline=None, derandomize=True, database=None,
                     suppress_health_check=[HealthCheck.too_slow])
+
+
+@st.composite
+def covers(draw, n, max_comms=8, max_per_node=3):
+    """A cover of n nodes as a dict community id -> set of nodes: each node lists up to
+    max_per_node distinct ids drawn from [0, max_comms), in drawn order."""
+    k = draw(st.integers(1, max_comms))
+    per = [draw(st.lists(st.integers(0, k - 1), max_size=max_per_node, unique=True)) for _ in range(n)]
+    P = {}
+    for x, cs in enumerate(per):
+        for c in cs:
+            P.setdefault(c, set()).add(x)
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(cs) for cs in per])
+    ids = np.array([c for cs in per for c in cs], np.int32)
+    return k, off, ids, P

@@ -8,13 +8,20 @@ the exact brute force, which shares no code with the oracle:
   bit-identical) and the node order of Node Order;
 * the greedy Initial Clustering;
 * a full LazyFox run (Algorithm 2) for a drawn queue size, skipped when an FP64 near-tie
-  could legitimately separate the two.
+  could legitimately separate the two;
+* for a drawn cover: the warm-started state (in-counts from their definition, WCC-hat as
+  an exact rational), the exact WCC terms, the post-processing flags from set definitions
+  and the F1-Score against a second drawn cover as exact rationals.
 """
+from fractions import Fraction
+
+import numpy as np
 from hypothesis import given
 from hypothesis import strategies as st
 
 from oracle import brute
-from raw_graphs import SETTINGS, edge_lists
+from raw_graphs import SETTINGS, covers, edge_lists
+from test_oracle_pins import _wcc_check, expected_pp, f1_exact
 
 
 def memberships_list(o):
@@ -53,3 +60,40 @@ def test_full_run_against_brute_force(oracle_lib, g, qfrac, mode):
         cc = o.scores()["cc"]
         for w_o, w_b in zip(info["wtilde_hist"], b["history"]):
             assert abs(w_o / cc - float(w_b)) <= 1e-12 * float(w_b)
+
+
+@SETTINGS
+@given(data=st.data())
+def test_covers_against_exact_definitions(oracle_lib, data):
+    g = data.draw(edge_lists(max_n=10, max_pairs=30))
+    k, off, ids, P = data.draw(covers(g.n))
+    kr, roff, rids, Pr = data.draw(covers(g.n, max_comms=5, max_per_node=2))
+    o = oracle_lib.Oracle().load_graph(g.n, g.src, g.dst).init_from_memberships(off, ids, k, 1)
+    assert o.check_state() == 0
+    adj = brute.simple_graph(g.n, g.src, g.dst)
+    mo, mi = o.memberships()
+    inc = o.in_counts()
+    for x in range(g.n):
+        assert sorted(mi[mo[x]:mo[x + 1]].tolist()) == sorted(c for c, C in P.items() if x in C)
+        for p in range(mo[x], mo[x + 1]):
+            assert inc[p] == len(adj[x] & P[int(mi[p])])
+    tri = brute.triangles(adj)
+    cc = sum(brute.local_cc(adj, tri), Fraction(0)) / g.n
+    if cc > 0:
+        w = brute.wcc_hat_partition(P, adj, cc)
+        sc = o.scores()
+        assert abs(sc["wtilde"] / sc["cc"] - float(w)) <= 1e-12 * max(float(w), 1e-300)
+    _wcc_check(o, g, P)
+    keep, (nd, nc) = o.postprocess(True, True)
+    ek, end, enc = expected_pp(P, True, True)
+    assert (nd, nc) == (end, enc)
+    for c in range(k):
+        assert keep[c] == (1 if c in P and ek[c] else 0)
+    f1, best, match = o.cover_f1(roff, rids)
+    score, per = f1_exact(P, Pr)
+    assert abs(f1 - float(score)) <= 1e-15 * max(1.0, float(score))
+    for c in range(k):
+        if c in per:
+            assert best[c] == float(per[c][0]) and match[c] == per[c][1]
+        else:
+            assert best[c] == 0.0 and match[c] == -1
