@@ -64,3 +64,26 @@ def test_recipe_at_reduced_scale(name, scale, mem_max, mu):
     assert cnt.min() >= 1 and cnt.max() <= mem_max
     m = realised_mixing(g, u, v)
     assert mu <= m <= mu + 0.15, m
+
+
+def test_serving_mix_recipe():
+    """Poisson arrivals at the stated rate, node counts lognormal (median 2,000) clipped to
+    [50, 200,000], per-job queue size clamp(2^round(log2(n/32)), 16, 4096), mean degree and
+    mixing in their ranges, and each job's graph a pure function of the job."""
+    import math
+    jobs = G.serving_mix(n_jobs=4000, rate=200.0, seed=0)
+    arr = np.array([j["arrival"] for j in jobs])
+    gaps = np.diff(np.concatenate([[0.0], arr]))
+    assert np.all(gaps >= 0) and abs(gaps.mean() * 200.0 - 1.0) < 0.05
+    ns = np.array([j["n"] for j in jobs])
+    assert ns.min() >= 50 and ns.max() <= 200_000
+    assert abs(math.log(np.median(ns) / 2000.0)) < 0.1
+    for j in jobs:
+        assert j["queue"] == min(4096, max(16, 2 ** round(math.log2(j["n"] / 32.0))))
+        assert 8 <= j["mean_deg"] <= 40 and 0.2 <= j["mu"] <= 0.4
+    j = next(j for j in jobs if 200 <= j["n"] <= 2000)
+    a, b = G.serving_job_graph(j), G.serving_job_graph(dict(j))
+    assert a.n == j["n"] and np.array_equal(a.src, b.src) and np.array_equal(a.dst, b.dst)
+    u, v = simple_pairs(a)
+    deg = np.bincount(np.concatenate([u, v]), minlength=a.n)
+    assert deg.max() <= min(a.n - 1, 1000)
