@@ -108,6 +108,29 @@ def test_g_and_density_are_single_roundings(oracle_lib):
         assert got_p == (0.0 if s < 2 else float(Fraction(2 * m, s * (s - 1))))
 
 
+def test_exact_accumulator_ranges_hold_at_the_extremes(oracle_lib):
+    """The fixed-point widths rest on three facts, checked at the limits of the integer
+    ranges (d, s < 2^31, a member's in-count i <= min(d, s - 1)): a non-zero g lies in
+    (2^-62, 1] with its lowest set bit at or above 2^-114; a community score
+    p * R(sum g) lies in (2^-124, 2^31) with its lowest set bit at or above 2^-176."""
+    top = (1 << 31) - 1
+    cases = [(2, top, top), (2, 2, top), (2, top, 3), (top - 1, top, top), (3, 3, 4), (2, 2, 3),
+             (1000, 5000, 100000), (2, 5000, 100000)]
+    gmin = 1.0
+    for i, d, s in cases:
+        g = oracle_lib.g_term(i, d, s)
+        assert g == float(Fraction(i * (i - 1), (d - 1) * (s - 1 + d - i)))
+        assert 2.0 ** -62 < g <= 1.0, (i, d, s, g)
+        assert (Fraction(g) * 2 ** 114).denominator == 1
+        gmin = min(gmin, g)
+    # the smallest density times the smallest sum, and the largest score
+    pmin = oracle_lib.density(top, 1)
+    assert pmin == float(Fraction(2, top * (top - 1)))
+    w = pmin * gmin
+    assert 2.0 ** -124 < w and (Fraction(w) * 2 ** 176).denominator == 1
+    assert oracle_lib.density(top, top * (top - 1) // 2) == 1.0 and float(top - 1) < 2.0 ** 31
+
+
 # ------------------------------------------------------------------ preprocessing
 def test_load_graph_dedup_selfloops_relabel(oracle_lib):
     """Multi-edges become one edge, self-loops are dropped, rows are sorted; with relabel
