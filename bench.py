@@ -158,6 +158,33 @@ def stored_traffic(kernel, workload, options=None):
         return None
 
 
+def copy_peak_gbs(torch, nbytes=1 << 30, reps=5, device="cuda"):
+    """Achievable memory rate of a plain device copy: bytes read plus bytes written per
+    second, best of `reps` copies of `nbytes` (events on torch's current stream, where the
+    copy runs; the host clock on a CPU device)."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)                       # first touch
+    best = None
+    for _ in range(reps):
+        if device == "cuda":
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3
+        else:
+            t = time.perf_counter()
+            b.copy_(a)
+            sec = time.perf_counter() - t
+        if sec > 0 and (best is None or sec < best):
+            best = sec
+    return 2.0 * nbytes / best / 1e9 if best else None
+
+
 def cpu_baseline(args, wl):
     import oracle
     import graphgen
@@ -461,6 +488,15 @@ def main():
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
             "kernel": dom, "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches": launches}
+    try:                                # informative only: never fails the bench line
+        cp = copy_peak_gbs(torch)
+        roof["achievable_GB_s"] = cp
+        roof["frac_of_achievable"] = achieved / cp if (achieved and cp) else None
+        print("[bench] device copy: %.0f GB/s" % cp, file=sys.stderr, flush=True)
+    except Exception as e:              # noqa: BLE001
+        print("[bench] device copy rate not measured: %s" % e, file=sys.stderr, flush=True)
+        roof["achievable_GB_s"] = None
+        roof["frac_of_achievable"] = None
     eval_kernels = ("k_eval", "k_eval_big", "k_big_final", "k_big_tie")
     out = {
         "metric": "dWCC-hat node-evals/s (whole hot path, end-to-end)",

@@ -109,3 +109,11 @@ def test_kernel_rooflines_divide_bytes_by_event_time():
     assert abs(r["evaluation"]["GB_s"] - 1000.0) < 1e-9
     timing["ms"]["k_big_tie"] = 0.124
     assert abs(bench.kernel_rooflines(timing, p)["evaluation"]["GB_s"] - 500.0) < 1e-9
+
+
+def test_copy_rate_counts_read_and_written_bytes():
+    """The achievable-rate probe: 2 x bytes / best copy time (CPU device here; on the GPU the
+    same arithmetic with event times)."""
+    torch = pytest.importorskip("torch")
+    r = bench.copy_peak_gbs(torch, nbytes=1 << 20, reps=3, device="cpu")
+    assert r is not None and r > 0.0
