@@ -90,6 +90,21 @@ def kernel_bytes(kernel, paths):
     }.get(kernel, lambda: None)()
 
 
+EVAL_KERNELS = ("k_eval", "k_eval_big", "k_big_final", "k_big_tie")
+
+
+def eval_rates(timing, work):
+    """Node evaluations, candidate scores and neighbour-membership visits per second of
+    evaluation-kernel time (HIP-event times of the timing pass, counts of the counter pass)."""
+    sec = sum(timing["ms"].get(k, 0.0) for k in EVAL_KERNELS) * 1e-3
+    if sec <= 0.0:
+        return None
+    paths = work["paths"].values()
+    return {"node_evals_per_s": timing["node_evals"] / sec,
+            "candidate_evals_per_s": sum(p["candidates"] for p in paths) / sec,
+            "membership_visits_per_s": sum(p["visits"] for p in paths) / sec}
+
+
 def kernel_rooflines(timing, paths):
     """Achieved algorithmic GB/s of each evaluation kernel with a byte model (HIP-event
     times of a profiled pass), and of the evaluation kernels together."""
@@ -508,6 +523,7 @@ def main():
                    "communities_created": K, "memberships_sha256": next(iter(hashes))[:16]},
         "end_to_end_s": ms_per_step / 1000.0,
         "kernel_node_evals_per_s": timing["node_evals"] / max(1e-9, sum(timing["ms"][k] for k in eval_kernels) * 1e-3),
+        "kernel_eval_rates": eval_rates(timing, work),
         "work_per_step": {"node_evals": work["node_evals"], "chunks": work["chunks"], "paths": work["paths"]},
         "kernel_ms_timing_pass": {k: round(v, 3) for k, v in timing["ms"].items()},
         "roofline": roof,

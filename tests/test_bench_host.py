@@ -117,3 +117,14 @@ def test_copy_rate_counts_read_and_written_bytes():
     torch = pytest.importorskip("torch")
     r = bench.copy_peak_gbs(torch, nbytes=1 << 20, reps=3, device="cpu")
     assert r is not None and r > 0.0
+
+
+def test_eval_rates():
+    timing = {"ms": {"k_eval": 500.0, "k_eval_big": 300.0, "k_big_final": 150.0, "k_big_tie": 50.0,
+                     "k_refresh": 999.0}, "node_evals": 4_000_000}
+    work = {"paths": {"small": {"nodes": 1, "neighbours": 2, "visits": 10_000_000, "candidates": 6_000_000},
+                      "table": {"nodes": 1, "neighbours": 2, "visits": 2_000_000, "candidates": 0}}}
+    r = bench.eval_rates(timing, work)
+    assert r == {"node_evals_per_s": 4_000_000.0, "candidate_evals_per_s": 6_000_000.0,
+                 "membership_visits_per_s": 12_000_000.0}
+    assert bench.eval_rates({"ms": {}, "node_evals": 1}, work) is None
