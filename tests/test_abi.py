@@ -98,3 +98,20 @@ def test_oracle_users_are_the_allowed_ones():
     assert bench and all(f == "cpu_baseline" for _, f in bench), bench
     entry = [(m, f) for m, f in _imports(os.path.join(ROOT, "__graft_entry__.py")) if m == "oracle"]
     assert entry and all(f in ("build", "smoke") for _, f in entry), entry
+
+
+def test_design_notes_cite_existing_tests():
+    """Every test the design notes name (as `test_x`, `test_x_*` or file::test_x) and every
+    tests/ file they name exists."""
+    import glob
+    text = open(os.path.join(ROOT, "DESIGN.md")).read()
+    src = "".join(open(f).read() for f in glob.glob(os.path.join(ROOT, "tests", "*.py")))
+    names = set(re.findall(r"`(test_[a-z0-9_]+)\*?`", text)) | set(re.findall(r"::(test_[a-z0-9_]+)", text))
+    files = set(re.findall(r"`tests/([a-z0-9_]+\.py)", text))
+    for f in files:
+        assert os.path.exists(os.path.join(ROOT, "tests", f)), f
+    for n in names:
+        if n in {os.path.splitext(f)[0] for f in files}:
+            continue
+        pat = r"def %s" % re.escape(n) if n.endswith("_") else r"def %s\b" % re.escape(n)
+        assert re.search(pat, src), n
