@@ -326,6 +326,21 @@ int lf_autotune_forget(void);
  */
 int lf_debug_exact_sum(lf_handle *h, const double *values_dev, int64_t n, double *out);
 
+/*
+ * Diagnostics of the library's own device primitives (the sorts behind "Remove
+ * Multi-Edges" and "Node Order" in Methods, and the prefix sums behind every compaction).
+ * lf_debug_sort_pairs: stable LSD radix sort in place of n keys (device, uint64) by their
+ *   bits [0, end_bit), 0 <= end_bit <= 64, with the int32 values (device, may be NULL)
+ *   moved alongside.  lf_debug_sort_pairs_u32: the same for uint32 keys (all 32 bits),
+ *   values required.  Both: n < 2^31 (LF_EOVERFLOW otherwise).
+ * lf_debug_exclusive_scan: out[i] = sum of in[0..i) as int64, for in of n int32
+ *   (in_bytes = 4) or int64 (in_bytes = 8) entries (device); in and out may alias.
+ * Temporaries come from the handle's scratch arena; the calls wait for the stream.
+ */
+int lf_debug_sort_pairs(lf_handle *h, uint64_t *keys_dev, int32_t *vals_dev, int64_t n, int32_t end_bit);
+int lf_debug_sort_pairs_u32(lf_handle *h, uint32_t *keys_dev, int32_t *vals_dev, int64_t n);
+int lf_debug_exclusive_scan(lf_handle *h, const void *in_dev, int32_t in_bytes, int64_t *out_dev, int64_t n);
+
 /* Device memory the handle holds now and at most so far (bytes). */
 int lf_get_memory(lf_handle *h, uint64_t *bytes, uint64_t *peak);
 

@@ -84,6 +84,9 @@ def load_library():
         "lf_get_profile": [vp, C.POINTER(Profile)],
         "lf_reset_profile": [vp],
         "lf_debug_exact_sum": [vp, vp, i64, C.POINTER(dbl)],
+        "lf_debug_sort_pairs": [vp, vp, vp, i64, i32],
+        "lf_debug_sort_pairs_u32": [vp, vp, vp, i64],
+        "lf_debug_exclusive_scan": [vp, vp, i32, vp, i64],
         "lf_set_option": [vp, C.c_int, i64],
         "lf_get_option": [vp, C.c_int, C.POINTER(i64)],
         "lf_get_memory": [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
@@ -434,6 +437,35 @@ class Handle:
         self._check(self.L.lf_debug_exact_sum(self.h, C.c_void_p(p), int(values_dev.numel()), C.byref(out)),
                     "lf_debug_exact_sum")
         return out.value
+
+    def lf_debug_sort_pairs(self, keys_dev, vals_dev=None, end_bit=64):
+        """Stable radix sort in place of uint64 keys (as int64 tensor bits) and int32 values."""
+        kp, kd = _ptr(keys_dev)
+        vp_, vd = _ptr(vals_dev) if vals_dev is not None else (0, True)
+        if not (kd and vd):
+            raise ValueError("lf_debug_sort_pairs takes device arrays")
+        self._check(self.L.lf_debug_sort_pairs(self.h, C.c_void_p(kp), C.c_void_p(vp_) if vals_dev is not None
+                                               else None, int(keys_dev.numel()), int(end_bit)),
+                    "lf_debug_sort_pairs")
+
+    def lf_debug_sort_pairs_u32(self, keys_dev, vals_dev):
+        """Stable radix sort in place of uint32 keys (as int32 tensor bits) and int32 values."""
+        kp, kd = _ptr(keys_dev)
+        vp_, vd = _ptr(vals_dev)
+        if not (kd and vd):
+            raise ValueError("lf_debug_sort_pairs_u32 takes device arrays")
+        self._check(self.L.lf_debug_sort_pairs_u32(self.h, C.c_void_p(kp), C.c_void_p(vp_), int(keys_dev.numel())),
+                    "lf_debug_sort_pairs_u32")
+
+    def lf_debug_exclusive_scan(self, in_dev, out_dev):
+        """out[i] = sum of in[0..i) (int64) for an int32 or int64 device array."""
+        ip, idv = _ptr(in_dev)
+        op, odv = _ptr(out_dev)
+        if not (idv and odv):
+            raise ValueError("lf_debug_exclusive_scan takes device arrays")
+        self._check(self.L.lf_debug_exclusive_scan(self.h, C.c_void_p(ip), int(in_dev.element_size()),
+                                                   C.c_void_p(op), int(in_dev.numel())),
+                    "lf_debug_exclusive_scan")
 
 
 def _run_info_arrays(max_iters):

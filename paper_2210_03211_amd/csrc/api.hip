@@ -368,4 +368,27 @@ int lf_debug_exact_sum(lf_handle *h, const double *values_dev, int64_t n, double
     return lf_exact_sum_dev(h, values_dev, n, out);
 }
 
+int lf_debug_sort_pairs(lf_handle *h, uint64_t *keys_dev, int32_t *vals_dev, int64_t n, int32_t end_bit)
+{
+    if (!h || n < 0 || (n > 0 && !keys_dev) || end_bit < 0 || end_bit > 64) return LF_EINVAL;
+    if (n >= (1ll << 31)) return lf_set_error(h, LF_EOVERFLOW, "n >= 2^31");
+    LF_HIP(h, hipSetDevice(h->device));
+    return lf_sort_dev_u64(h, (unsigned long long *)keys_dev, (int *)vals_dev, n, end_bit);
+}
+
+int lf_debug_sort_pairs_u32(lf_handle *h, uint32_t *keys_dev, int32_t *vals_dev, int64_t n)
+{
+    if (!h || n < 0 || (n > 0 && (!keys_dev || !vals_dev))) return LF_EINVAL;
+    if (n >= (1ll << 31)) return lf_set_error(h, LF_EOVERFLOW, "n >= 2^31");
+    LF_HIP(h, hipSetDevice(h->device));
+    return lf_sort_dev_u32(h, (unsigned *)keys_dev, (int *)vals_dev, n);
+}
+
+int lf_debug_exclusive_scan(lf_handle *h, const void *in_dev, int32_t in_bytes, int64_t *out_dev, int64_t n)
+{
+    if (!h || n < 0 || (in_bytes != 4 && in_bytes != 8) || (n > 0 && (!in_dev || !out_dev))) return LF_EINVAL;
+    LF_HIP(h, hipSetDevice(h->device));
+    return lf_scan_dev(h, in_dev, in_bytes, (long long *)out_dev, n);
+}
+
 }  // extern "C"

@@ -282,9 +282,6 @@ struct lf_handle {
     int graph_version;       // bumped whenever a buffer used by captured launches moves
     DevCounters *ctr;
     double Wt;               // cc-free partition score
-    // generic device scratch
-    void *tmp;
-    size_t tmp_bytes;
     // tuning
     int eval_wave_cap;       // table entries per wave in the small wave path
     int eval_med_cap;        // table entries per wave in the medium wave path
@@ -338,7 +335,6 @@ struct TmpScope {
     explicit TmpScope(lf_handle *hh) : h(hh), m(lf_tmp_mark(hh)) {}
     ~TmpScope() { lf_tmp_release(h, m); }
 };
-int lf_ensure_tmp(lf_handle *h, size_t bytes);
 Ctx lf_ctx(lf_handle *h);
 
 // profiling brackets around a launch sequence on the handle's stream; events are only
@@ -359,6 +355,9 @@ int lf_sort_pairs_u32_i32(lf_handle *h, unsigned *keys, unsigned *keys_alt, int 
                           int *vals_alt, long long n, unsigned **rkeys, int **rvals);
 int lf_exclusive_scan_i64(lf_handle *h, const long long *in, long long *out, long long n);
 int lf_exclusive_scan_i32_to_i64(lf_handle *h, const int *in, long long *out, long long n);
+int lf_sort_dev_u64(lf_handle *h, unsigned long long *keys, int *vals, long long n, int end_bit);
+int lf_sort_dev_u32(lf_handle *h, unsigned *keys, int *vals, long long n);
+int lf_scan_dev(lf_handle *h, const void *in, int in_bytes, long long *out, long long n);
 
 // ---- graph stages (graph.hip) ------------------------------------------------------------
 int lf_build_graph(lf_handle *h, long long n, long long npairs, const long long *src,

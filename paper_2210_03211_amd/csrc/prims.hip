@@ -1,8 +1,7 @@
-// prims.hip -- library primitives: device radix sorts and prefix sums (hipCUB), plus
-// the handle's allocation registry and error/profiling helpers.
+// prims.hip -- library primitives: device-wide LSD radix sorts and exclusive prefix sums
+// written for gfx950 (wave64 ballots, LDS tiles), plus the handle's allocation registry
+// and error/profiling helpers.
 #include <stdarg.h>
-
-#include <hipcub/hipcub.hpp>
 
 #include "lf_internal.h"
 
@@ -98,20 +97,6 @@ void lf_tmp_release(lf_handle *h, TmpMark m)
     h->tmp_off = m.off;
 }
 
-int lf_ensure_tmp(lf_handle *h, size_t bytes)
-{
-    if (bytes <= h->tmp_bytes) return LF_OK;
-    if (h->tmp) {
-        LF_HIP(h, hipStreamSynchronize(h->stream));
-        lf_dev_free(h, h->tmp);
-        h->tmp = nullptr;
-    }
-    size_t want = bytes + bytes / 4 + 4096;
-    LF_TRY(lf_dev_alloc(h, &h->tmp, want));
-    h->tmp_bytes = want;
-    return LF_OK;
-}
-
 static bool prof_on(lf_handle *h, int kind) { return kind < LF_K_COUNT && ((h->profiling >> kind) & 1); }
 
 int lf_prof_begin(lf_handle *h, int kind) { return lf_prof_begin_on(h, kind, h->stream); }
@@ -161,81 +146,395 @@ int lf_prof_flush(lf_handle *h)
     return LF_OK;
 }
 
+// ------------------------------------------------------------------------------------
+// device-wide exclusive prefix sum (64-bit results)
+// ------------------------------------------------------------------------------------
+// Reduce-then-scan over tiles of SCAN_TILE elements: one pass sums every tile, the tile
+// sums are scanned the same way (recursively, a single tile at the top), and a last
+// pass scans every tile from its offset.  Each tile is staged through LDS so that the
+// global loads and stores are coalesced while every thread scans SCAN_ITEMS
+// consecutive elements.  in and out may be the same array.
+#define PW 64                     // wavefront width
+#define SCAN_BLOCK 256
+#define SCAN_ITEMS 16
+#define SCAN_TILE (SCAN_BLOCK * SCAN_ITEMS)
+#define SCAN_PAD(p) ((p) + ((p) >> 4))   // one spare word per 16: fewer LDS bank conflicts
+
+static inline unsigned grid_of(long long n, long long per) { return (unsigned)((n + per - 1) / per); }
+
+// exclusive prefix of v over the block's threads; *total gets the block's sum
+__device__ __forceinline__ long long block_excl_scan(long long v, long long *s_w, long long *total)
+{
+    const int lane = threadIdx.x & (PW - 1), wv = threadIdx.x / PW;
+    long long incl = v;
+    for (int o = 1; o < PW; o <<= 1) {
+        long long t = __shfl_up(incl, o, PW);
+        if (lane >= o) incl += t;
+    }
+    if (lane == PW - 1) s_w[wv] = incl;
+    __syncthreads();
+    long long off = 0, tot = 0;
+    for (int w = 0; w < SCAN_BLOCK / PW; w++) {
+        long long t = s_w[w];
+        if (w < wv) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(const T *in, long long n, long long *sums)
+{
+    __shared__ long long s_w[SCAN_BLOCK / PW];
+    const long long base = (long long)blockIdx.x * SCAN_TILE;
+    long long acc = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        long long p = base + i * SCAN_BLOCK + threadIdx.x;
+        if (p < n) acc += (long long)in[p];
+    }
+    long long tot;
+    (void)block_excl_scan(acc, s_w, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// offs: first value of every tile (nullptr: a single tile starting at 0)
+template <typename T>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_down(const T *in, long long *out, long long n,
+                                                          const long long *offs)
+{
+    __shared__ long long tile[SCAN_PAD(SCAN_TILE)];
+    __shared__ long long s_w[SCAN_BLOCK / PW];
+    const long long base = (long long)blockIdx.x * SCAN_TILE;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const int q = i * SCAN_BLOCK + threadIdx.x;
+        const long long p = base + q;
+        tile[SCAN_PAD(q)] = p < n ? (long long)in[p] : 0;
+    }
+    __syncthreads();
+    const int q0 = threadIdx.x * SCAN_ITEMS;
+    long long v = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) v += tile[SCAN_PAD(q0 + i)];
+    long long tot;
+    long long run = block_excl_scan(v, s_w, &tot) + (offs ? offs[blockIdx.x] : 0);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const long long x = tile[SCAN_PAD(q0 + i)];
+        tile[SCAN_PAD(q0 + i)] = run;
+        run += x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const int q = i * SCAN_BLOCK + threadIdx.x;
+        const long long p = base + q;
+        if (p < n) out[p] = tile[SCAN_PAD(q)];
+    }
+}
+
+template <typename T>
+static int scan_impl(lf_handle *h, const T *in, long long *out, long long n)
+{
+    if (n <= 0) return LF_OK;
+    hipStream_t st = h->stream;
+    const long long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_down<T>, dim3(1), dim3(SCAN_BLOCK), 0, st, in, out, n, (const long long *)nullptr);
+        LF_HIP(h, hipGetLastError());
+        return LF_OK;
+    }
+    TmpScope tmp_scope(h);
+    long long *sums = nullptr, *soff = nullptr;
+    LF_TRY(lf_tmp_alloc(h, (void **)&sums, sizeof(long long) * nb));
+    LF_TRY(lf_tmp_alloc(h, (void **)&soff, sizeof(long long) * nb));
+    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, st, in, n, sums);
+    LF_TRY(scan_impl<long long>(h, sums, soff, nb));
+    hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, st, in, out, n,
+                       (const long long *)soff);
+    LF_HIP(h, hipGetLastError());
+    return LF_OK;
+}
+
+int lf_exclusive_scan_i64(lf_handle *h, const long long *in, long long *out, long long n)
+{
+    return scan_impl<long long>(h, in, out, n);
+}
+
+int lf_exclusive_scan_i32_to_i64(lf_handle *h, const int *in, long long *out, long long n)
+{
+    return scan_impl<int>(h, in, out, n);
+}
+
+// ------------------------------------------------------------------------------------
+// device-wide LSD radix sort (stable), 8-bit digits
+// ------------------------------------------------------------------------------------
+// Per pass over digit [shift, shift + nbits):
+//   k_radix_hist     every tile of RS_TILE keys counts its digits -> cnt[digit][tile]
+//   scan             exclusive scan of cnt, digit-major: the first output position of
+//                    (digit, tile) = keys of smaller digits + keys of this digit in
+//                    earlier tiles
+//   k_radix_scatter  every tile ranks its keys stably and writes them to those positions
+// A tile is split into one contiguous range per wave.  A wave ranks 64 keys at a time:
+// the lanes holding the same digit are found with nbits ballots, a key's rank is the
+// number of those lanes below it plus the wave's running count of the digit (LDS), so
+// ranks follow the input order.  The keys are then placed in digit order in LDS and
+// written out in runs of equal digit (coalesced).
+#define RS_BLOCK 256
+#define RS_WAVES (RS_BLOCK / PW)
+#define RS_ITEMS 16
+#define RS_WTILE (PW * RS_ITEMS)          // keys per wave
+#define RS_TILE (RS_BLOCK * RS_ITEMS)     // keys per tile
+#define RS_BINS 256
+
+template <typename K>
+__device__ __forceinline__ unsigned rs_digit(K k, int shift, unsigned mask)
+{
+    return (unsigned)(k >> shift) & mask;
+}
+
+// lanes of the wave (among those in `valid`) whose digit equals this lane's
+__device__ __forceinline__ unsigned long long rs_match(unsigned d, int nbits, unsigned long long valid)
+{
+    unsigned long long m = valid;
+    for (int b = 0; b < nbits; b++) {
+        const bool bit = (d >> b) & 1u;
+        const unsigned long long bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+template <typename K>
+__global__ void __launch_bounds__(RS_BLOCK) k_radix_hist(const K *keys, long long n, int shift, int nbits,
+                                                         int *cnt, long long ntiles)
+{
+    __shared__ int hist[RS_WAVES][RS_BINS];
+    const int lane = threadIdx.x & (PW - 1), wv = threadIdx.x / PW;
+    for (int t = threadIdx.x; t < RS_WAVES * RS_BINS; t += RS_BLOCK) (&hist[0][0])[t] = 0;
+    __syncthreads();
+    const unsigned mask = (1u << nbits) - 1u;
+    const long long base = (long long)blockIdx.x * RS_TILE + (long long)wv * RS_WTILE;
+    K k[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; i++) {
+        const long long p = base + i * PW + lane;
+        k[i] = p < n ? keys[p] : (K)0;
+    }
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; i++) {
+        const long long p = base + i * PW + lane;
+        const unsigned long long valid = __ballot(p < n);
+        if (!valid) break;                    // uniform over the wave
+        const unsigned d = rs_digit(k[i], shift, mask);
+        const unsigned long long m = rs_match(d, nbits, valid);
+        if (p < n && __popcll(m & ((1ull << lane) - 1)) == 0) hist[wv][d] += __popcll(m);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < RS_BINS; d += RS_BLOCK) {
+        int c = 0;
+        for (int w = 0; w < RS_WAVES; w++) c += hist[w][d];
+        if (d <= (int)mask) cnt[(long long)d * ntiles + blockIdx.x] = c;
+    }
+}
+
+template <typename K, bool PAIRS>
+__global__ void __launch_bounds__(RS_BLOCK) k_radix_scatter(const K *kin, K *kout, const int *vin, int *vout,
+                                                            long long n, int shift, int nbits,
+                                                            const long long *goff, long long ntiles)
+{
+    __shared__ K skey[RS_TILE];
+    __shared__ int sval[PAIRS ? RS_TILE : 1];
+    __shared__ int wrun[RS_WAVES][RS_BINS];   // per wave: running count, then its offset
+    __shared__ int toff[RS_BINS];             // first tile position of each digit
+    __shared__ long long gbase[RS_BINS];      // first output position of each digit
+    __shared__ long long s_w[RS_BLOCK / PW];
+    const int lane = threadIdx.x & (PW - 1), wv = threadIdx.x / PW;
+    const unsigned mask = (1u << nbits) - 1u;
+    const int nbins = (int)mask + 1;
+    for (int t = threadIdx.x; t < RS_WAVES * RS_BINS; t += RS_BLOCK) (&wrun[0][0])[t] = 0;
+    for (int d = threadIdx.x; d < RS_BINS; d += RS_BLOCK)
+        gbase[d] = d < nbins ? goff[(long long)d * ntiles + blockIdx.x] : 0;
+    const long long tbase = (long long)blockIdx.x * RS_TILE;
+    const long long base = tbase + (long long)wv * RS_WTILE;
+    K k[RS_ITEMS];
+    int v[RS_ITEMS];
+    int r[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; i++) {
+        const long long p = base + i * PW + lane;
+        k[i] = p < n ? kin[p] : (K)0;
+        v[i] = (PAIRS && p < n) ? vin[p] : 0;
+    }
+    __syncthreads();
+    // ranks within the wave's range, in input order
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; i++) {
+        const long long p = base + i * PW + lane;
+        const unsigned long long valid = __ballot(p < n);
+        r[i] = 0;
+        if (!valid) continue;                 // uniform over the wave
+        const unsigned d = rs_digit(k[i], shift, mask);
+        const unsigned long long m = rs_match(d, nbits, valid);
+        const int below = __popcll(m & ((1ull << lane) - 1));
+        if (p < n) {
+            const int prev = wrun[wv][d];     // read by every lane before the leader writes
+            r[i] = prev + below;
+            if (below == 0) wrun[wv][d] = prev + __popcll(m);
+        }
+    }
+    __syncthreads();
+    // per digit: the waves' offsets and the tile's count, then the tile's digit offsets
+    int dcount = 0;
+    const int d0 = threadIdx.x;               // RS_BLOCK == RS_BINS: one digit per thread
+    {
+        int run = 0;
+        for (int w = 0; w < RS_WAVES; w++) {
+            const int c = wrun[w][d0];
+            wrun[w][d0] = run;
+            run += c;
+        }
+        dcount = run;
+    }
+    long long ttot;
+    const long long tpos = block_excl_scan((long long)dcount, s_w, &ttot);
+    toff[d0] = (int)tpos;
+    __syncthreads();
+    // keys in digit order in LDS
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; i++) {
+        const long long p = base + i * PW + lane;
+        if (p < n) {
+            const unsigned d = rs_digit(k[i], shift, mask);
+            const int pos = toff[d] + wrun[wv][d] + r[i];
+            skey[pos] = k[i];
+            if (PAIRS) sval[pos] = v[i];
+        }
+    }
+    __syncthreads();
+    // runs of equal digit go to consecutive output positions
+    const long long left = n - tbase;
+    const int cnt_tile = left < RS_TILE ? (int)left : RS_TILE;
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; i++) {
+        const int pos = i * RS_BLOCK + threadIdx.x;
+        if (pos < cnt_tile) {
+            const K key = skey[pos];
+            const unsigned d = rs_digit(key, shift, mask);
+            const long long o = gbase[d] + (pos - toff[d]);
+            kout[o] = key;
+            if (PAIRS) vout[o] = sval[pos];
+        }
+    }
+}
+
+// Sorts keys[0, n) by bits [0, end_bit) (stable; values move with their keys).  The
+// passes alternate between the two buffers; *rk / *rv receive the one holding the result.
+template <typename K, bool PAIRS>
+static int radix_sort(lf_handle *h, K *keys, K *keys_alt, int *vals, int *vals_alt, long long n, int end_bit,
+                      K **rk, int **rv)
+{
+    *rk = keys;
+    if (rv) *rv = vals;
+    if (n <= 1 || end_bit <= 0) return LF_OK;
+    if (n >= (1ll << 31)) return lf_set_error(h, LF_EOVERFLOW, "radix sort of %lld keys exceeds 2^31 - 1", n);
+    if (end_bit > (int)(8 * sizeof(K))) end_bit = (int)(8 * sizeof(K));
+    TmpScope tmp_scope(h);
+    hipStream_t st = h->stream;
+    const long long ntiles = (n + RS_TILE - 1) / RS_TILE;
+    int *cnt = nullptr;
+    long long *goff = nullptr;
+    LF_TRY(lf_tmp_alloc(h, (void **)&cnt, sizeof(int) * RS_BINS * ntiles));
+    LF_TRY(lf_tmp_alloc(h, (void **)&goff, sizeof(long long) * RS_BINS * ntiles));
+    K *ki = keys, *ko = keys_alt;
+    int *vi = vals, *vo = vals_alt;
+    for (int shift = 0; shift < end_bit; shift += 8) {
+        const int nbits = end_bit - shift < 8 ? end_bit - shift : 8;
+        hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)ntiles), dim3(RS_BLOCK), 0, st, (const K *)ki, n, shift,
+                           nbits, cnt, ntiles);
+        LF_TRY(scan_impl<int>(h, cnt, goff, (long long)(1 << nbits) * ntiles));
+        hipLaunchKernelGGL((k_radix_scatter<K, PAIRS>), dim3((unsigned)ntiles), dim3(RS_BLOCK), 0, st,
+                           (const K *)ki, ko, (const int *)vi, vo, n, shift, nbits, (const long long *)goff, ntiles);
+        LF_HIP(h, hipGetLastError());
+        K *kt = ki;
+        ki = ko;
+        ko = kt;
+        if (PAIRS) {
+            int *vt = vi;
+            vi = vo;
+            vo = vt;
+        }
+    }
+    *rk = ki;
+    if (rv) *rv = vi;
+    return LF_OK;
+}
+
 int lf_sort_u64(lf_handle *h, unsigned long long *keys, unsigned long long *keys_alt, long long n,
                 int end_bit, unsigned long long **result)
 {
-    *result = keys;
-    if (n <= 1) return LF_OK;
-    hipcub::DoubleBuffer<unsigned long long> db(keys, keys_alt);
-    size_t bytes = 0;
-    LF_HIP(h, hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, db, (int)n, 0, end_bit, h->stream));
-    LF_TRY(lf_ensure_tmp(h, bytes));
-    bytes = h->tmp_bytes;
-    LF_HIP(h, hipcub::DeviceRadixSort::SortKeys(h->tmp, bytes, db, (int)n, 0, end_bit, h->stream));
-    *result = db.Current();
-    return LF_OK;
+    return radix_sort<unsigned long long, false>(h, keys, keys_alt, nullptr, nullptr, n, end_bit, result, nullptr);
 }
 
 int lf_sort_pairs_u64_i32(lf_handle *h, unsigned long long *keys, unsigned long long *keys_alt,
                           int *vals, int *vals_alt, long long n, int end_bit,
                           unsigned long long **rkeys, int **rvals)
 {
-    *rkeys = keys;
-    *rvals = vals;
-    if (n <= 1) return LF_OK;
-    hipcub::DoubleBuffer<unsigned long long> dk(keys, keys_alt);
-    hipcub::DoubleBuffer<int> dv(vals, vals_alt);
-    size_t bytes = 0;
-    LF_HIP(h, hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, dk, dv, (int)n, 0, end_bit, h->stream));
-    LF_TRY(lf_ensure_tmp(h, bytes));
-    bytes = h->tmp_bytes;
-    LF_HIP(h, hipcub::DeviceRadixSort::SortPairs(h->tmp, bytes, dk, dv, (int)n, 0, end_bit, h->stream));
-    *rkeys = dk.Current();
-    *rvals = dv.Current();
-    return LF_OK;
+    return radix_sort<unsigned long long, true>(h, keys, keys_alt, vals, vals_alt, n, end_bit, rkeys, rvals);
 }
 
 int lf_sort_pairs_u32_i32(lf_handle *h, unsigned *keys, unsigned *keys_alt, int *vals,
                           int *vals_alt, long long n, unsigned **rkeys, int **rvals)
 {
-    *rkeys = keys;
-    *rvals = vals;
-    if (n <= 1) return LF_OK;
-    hipcub::DoubleBuffer<unsigned> dk(keys, keys_alt);
-    hipcub::DoubleBuffer<int> dv(vals, vals_alt);
-    size_t bytes = 0;
-    LF_HIP(h, hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, dk, dv, (int)n, 0, 32, h->stream));
-    LF_TRY(lf_ensure_tmp(h, bytes));
-    bytes = h->tmp_bytes;
-    LF_HIP(h, hipcub::DeviceRadixSort::SortPairs(h->tmp, bytes, dk, dv, (int)n, 0, 32, h->stream));
-    *rkeys = dk.Current();
-    *rvals = dv.Current();
+    return radix_sort<unsigned, true>(h, keys, keys_alt, vals, vals_alt, n, 32, rkeys, rvals);
+}
+
+// In-place forms of the sorts and scans above for the diagnostic entry points: the result
+// is copied back into the caller's arrays when it ends in the alternate buffers.
+int lf_sort_dev_u64(lf_handle *h, unsigned long long *keys, int *vals, long long n, int end_bit)
+{
+    TmpScope tmp_scope(h);
+    hipStream_t st = h->stream;
+    unsigned long long *kalt = nullptr, *rk = keys;
+    int *valt = nullptr, *rv = vals;
+    LF_TRY(lf_tmp_alloc(h, (void **)&kalt, sizeof(unsigned long long) * (n > 0 ? n : 1)));
+    if (vals) {
+        LF_TRY(lf_tmp_alloc(h, (void **)&valt, sizeof(int) * (n > 0 ? n : 1)));
+        LF_TRY(lf_sort_pairs_u64_i32(h, keys, kalt, vals, valt, n, end_bit, &rk, &rv));
+    } else {
+        LF_TRY(lf_sort_u64(h, keys, kalt, n, end_bit, &rk));
+    }
+    if (rk != keys) LF_HIP(h, hipMemcpyAsync(keys, rk, sizeof(unsigned long long) * n, hipMemcpyDeviceToDevice, st));
+    if (vals && rv != vals) LF_HIP(h, hipMemcpyAsync(vals, rv, sizeof(int) * n, hipMemcpyDeviceToDevice, st));
+    LF_HIP(h, hipStreamSynchronize(st));
+    LF_HIP(h, hipGetLastError());
     return LF_OK;
 }
 
-int lf_exclusive_scan_i64(lf_handle *h, const long long *in, long long *out, long long n)
+int lf_sort_dev_u32(lf_handle *h, unsigned *keys, int *vals, long long n)
 {
-    if (n <= 0) return LF_OK;
-    size_t bytes = 0;
-    LF_HIP(h, hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, h->stream));
-    LF_TRY(lf_ensure_tmp(h, bytes));
-    bytes = h->tmp_bytes;
-    LF_HIP(h, hipcub::DeviceScan::ExclusiveSum(h->tmp, bytes, in, out, (int)n, h->stream));
+    TmpScope tmp_scope(h);
+    hipStream_t st = h->stream;
+    unsigned *kalt = nullptr, *rk = keys;
+    int *valt = nullptr, *rv = vals;
+    LF_TRY(lf_tmp_alloc(h, (void **)&kalt, sizeof(unsigned) * (n > 0 ? n : 1)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&valt, sizeof(int) * (n > 0 ? n : 1)));
+    LF_TRY(lf_sort_pairs_u32_i32(h, keys, kalt, vals, valt, n, &rk, &rv));
+    if (rk != keys) LF_HIP(h, hipMemcpyAsync(keys, rk, sizeof(unsigned) * n, hipMemcpyDeviceToDevice, st));
+    if (rv != vals) LF_HIP(h, hipMemcpyAsync(vals, rv, sizeof(int) * n, hipMemcpyDeviceToDevice, st));
+    LF_HIP(h, hipStreamSynchronize(st));
+    LF_HIP(h, hipGetLastError());
     return LF_OK;
 }
 
-struct I32ToI64 {
-    __host__ __device__ long long operator()(const int &v) const { return (long long)v; }
-};
-
-int lf_exclusive_scan_i32_to_i64(lf_handle *h, const int *in, long long *out, long long n)
+int lf_scan_dev(lf_handle *h, const void *in, int in_bytes, long long *out, long long n)
 {
-    if (n <= 0) return LF_OK;
-    hipcub::TransformInputIterator<long long, I32ToI64, const int *> it(in, I32ToI64());
-    size_t bytes = 0;
-    LF_HIP(h, hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, it, out, (int)n, h->stream));
-    LF_TRY(lf_ensure_tmp(h, bytes));
-    bytes = h->tmp_bytes;
-    LF_HIP(h, hipcub::DeviceScan::ExclusiveSum(h->tmp, bytes, it, out, (int)n, h->stream));
+    if (in_bytes == 8) LF_TRY(lf_exclusive_scan_i64(h, (const long long *)in, out, n));
+    else LF_TRY(lf_exclusive_scan_i32_to_i64(h, (const int *)in, out, n));
+    LF_HIP(h, hipStreamSynchronize(h->stream));
+    LF_HIP(h, hipGetLastError());
     return LF_OK;
 }
