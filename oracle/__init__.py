@@ -66,6 +66,10 @@ def lib():
         L.lfo_run_iterations.argtypes = [vp, i32, dbl, i32, i32, i32, i32, C.POINTER(RunInfo)]
         L.lfo_check_state.argtypes = [vp]
         L.lfo_check_state.restype = i64
+        L.lfo_set_chunk_limit.argtypes = [vp, i64]
+        L.lfo_set_chunk_limit.restype = None
+        L.lfo_chunks_done.argtypes = [vp]
+        L.lfo_chunks_done.restype = i64
         L.lfo_num_nodes.argtypes = [vp]
         L.lfo_num_nodes.restype = i64
         L.lfo_num_edges.argtypes = [vp]
@@ -174,6 +178,17 @@ class Oracle:
                     wcc_hat=info.wcc_hat, wtilde=info.wtilde, wtilde_hist=hist[: it + 1].copy(),
                     joins=joins[:it].copy(), leaves=leaves[:it].copy(),
                     communities=comms[:it].copy())
+
+    def run_queue_prefix(self, queue_size, chunks, mode=MODE_FAST, nthreads=None):
+        """Timing sample: evaluate and apply the first `chunks` queues of the first
+        iteration and stop there (the state is left mid-iteration).  Returns the number of
+        queues done."""
+        self.L.lfo_set_chunk_limit(self.h, int(chunks))
+        try:
+            self.run_iterations(queue_size, 0.0, 1, mode=mode, nthreads=nthreads)
+        finally:
+            self.L.lfo_set_chunk_limit(self.h, 0)
+        return int(self.L.lfo_chunks_done(self.h))
 
     def exact_wcc(self, nthreads=None):
         """Exact WCC of the current partition: dict(wcc, per-community wcc_comm[K], and per

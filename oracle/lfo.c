@@ -232,6 +232,8 @@ typedef struct {
     xsum *S0, *Sp, *Sm;   /* exact sums of g at size s, s+1, s-1 */
     double Wt;            /* cc-free partition score R(sum W) */
     int64_t iter_done;
+    int64_t chunk_limit;  /* > 0: run_iterations stops after this many queues (timing samples) */
+    int64_t chunks_done;  /* queues evaluated and applied by the last run_iterations */
     char err[256];
 } lfo;
 
@@ -938,9 +940,12 @@ int lfo_run_iterations(lfo *h, int32_t q, double theta, int32_t max_iters, int32
     for (int t = 0; t < nthreads; t++) scratch_init(&ws[t], h);
     double prev = h->Wt;
     int rc = LFO_OK;
+    h->chunks_done = 0;
     for (int32_t it = 0; it < max_iters; it++) {
         int64_t joins = 0, leaves = 0;
         for (int64_t start = 0; start < n; start += q) {
+            /* a timing sample ends after a fixed number of queues, mid-iteration */
+            if (h->chunk_limit > 0 && h->chunks_done >= h->chunk_limit) goto done;
             int32_t cnt = (int32_t)((n - start) < q ? (n - start) : q);
             const int32_t *nodes = h->order + start;
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
@@ -953,6 +958,7 @@ int lfo_run_iterations(lfo *h, int32_t q, double theta, int32_t max_iters, int32
             }
             for (int32_t j = 0; j < cnt; j++) { joins += dec[j].join >= 0; leaves += dec[j].leave >= 0; }
             apply_chunk(h, nodes, cnt, dec, mode, joined_to, touched, tlist);
+            h->chunks_done++;
             if (check_every_chunk && lfo_check_state(h) != 0) {
                 snprintf(h->err, sizeof h->err, "state check failed (iteration %d, chunk at %lld)",
                          it + 1, (long long)start);
@@ -990,6 +996,11 @@ done:
 /* Getters and debug entry points                                                        */
 /* ------------------------------------------------------------------------------------ */
 int64_t lfo_num_nodes(lfo *h) { return h ? h->n : -1; }
+/* Timing samples: lfo_run_iterations stops after `limit` queues (0 = no limit); the
+   state is then mid-iteration and only good for timing.  lfo_chunks_done: queues the last
+   lfo_run_iterations evaluated and applied. */
+void lfo_set_chunk_limit(lfo *h, int64_t limit) { if (h) h->chunk_limit = limit > 0 ? limit : 0; }
+int64_t lfo_chunks_done(lfo *h) { return h ? h->chunks_done : -1; }
 int64_t lfo_num_edges(lfo *h) { return h ? h->nedges : -1; }
 int32_t lfo_num_communities_created(lfo *h) { return h ? h->K : -1; }
 

@@ -8,6 +8,7 @@ ids int32, little-endian, exactly as lf_get_memberships returns them), plus the 
 statistics' hashes.
 
     python tests/golden/make_golden.py social 4096      # ~ several minutes on 8 cores
+    python tests/golden/make_golden.py -j6 dense 16384  # -jN: oracle thread count
 """
 import hashlib
 import json
@@ -62,7 +63,11 @@ def make(name, q, seed=0, threshold=0.01, max_iters=50, nthreads=None):
 
 
 if __name__ == "__main__":
-    name = sys.argv[1] if len(sys.argv) > 1 else "social"
-    qs = [int(a) for a in sys.argv[2:]] or [4096]
+    args = sys.argv[1:]
+    nthreads = None
+    if args and args[0].startswith("-j"):
+        nthreads = int(args.pop(0)[2:])
+    name = args[0] if args else "social"
+    qs = [int(a) for a in args[1:]] or [4096]
     for q in qs:
-        make(name, q)
+        make(name, q, nthreads=nthreads)

@@ -796,3 +796,24 @@ def test_cover_f1_closed_forms(oracle_lib):
     dup = np.concatenate([[0], np.full(g.n, 2, np.int64)])
     with pytest.raises(oracle_lib.OracleError):
         o.cover_f1(dup, np.array([1, 1], np.int32))
+
+
+def test_queue_prefix_runs_stop_after_the_stated_queues(oracle_lib):
+    """Timing samples (run_queue_prefix): the first k queues of iteration 1 are evaluated
+    and applied exactly as in the full run, and the run stops there.  The prefix state
+    passes the from-scratch state check, and applying the same prefix with the factored
+    mode at several threads gives the same memberships as the naive mode at one."""
+    g = G.named_config("tiny_sbm")
+    covers = []
+    for mode, threads in ((oracle_lib.MODE_NAIVE, 1), (oracle_lib.MODE_FAST, 4)):
+        o = load(oracle_lib, g)
+        assert o.run_queue_prefix(64, 5, mode=mode, nthreads=threads) == 5
+        assert o.check_state() == 0
+        covers.append(o.memberships())
+    assert np.array_equal(covers[0][0], covers[1][0]) and np.array_equal(covers[0][1], covers[1][1])
+    o = load(oracle_lib, g)
+    # a limit beyond the queues of one iteration ends with that iteration
+    assert o.run_queue_prefix(64, 10_000) == (g.n + 63) // 64
+    full = load(oracle_lib, g)
+    full.run_iterations(64, 0.0, 1)
+    assert np.array_equal(o.memberships()[1], full.memberships()[1])
