@@ -327,6 +327,20 @@ int lf_autotune_forget(void);
 int lf_debug_exact_sum(lf_handle *h, const double *values_dev, int64_t n, double *out);
 
 /*
+ * lf_debug_exact_sum without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as lf_debug_exact_sum, plus LF_EINVAL for
+ * n > LF_NOALLOC_MAX_VALUES (2^40: with every |value| <= 2^30 the exact partial sums then
+ * stay inside the device accumulator).  Its scratch (1024 block partial sums, a range
+ * flag and the result, 32 KiB) is a fixed device array of the library, one per GPU, held
+ * until the process ends; every call on a GPU uses that GPU's copy, so calls that overlap
+ * on one GPU (from any handles or threads) race and must be serialised by the caller.
+ * The call calls no hipMalloc or hipFree; it waits for the handle's stream.
+ */
+#define LF_NOALLOC_MAX_VALUES (1ll << 40)
+int lf_exact_sum_noalloc(lf_handle *h, const double *values_dev, int64_t n, double *out);
+
+/*
  * Diagnostics of the library's own device primitives (the sorts behind "Remove
  * Multi-Edges" and "Node Order" in Methods, and the prefix sums behind every compaction).
  * lf_debug_sort_pairs: stable LSD radix sort in place of n keys (device, uint64) by their

@@ -84,6 +84,7 @@ def load_library():
         "lf_get_profile": [vp, C.POINTER(Profile)],
         "lf_reset_profile": [vp],
         "lf_debug_exact_sum": [vp, vp, i64, C.POINTER(dbl)],
+        "lf_exact_sum_noalloc": [vp, vp, i64, C.POINTER(dbl)],
         "lf_debug_sort_pairs": [vp, vp, vp, i64, i32],
         "lf_debug_sort_pairs_u32": [vp, vp, vp, i64],
         "lf_debug_exclusive_scan": [vp, vp, i32, vp, i64],
@@ -436,6 +437,19 @@ class Handle:
         out = C.c_double()
         self._check(self.L.lf_debug_exact_sum(self.h, C.c_void_p(p), int(values_dev.numel()), C.byref(out)),
                     "lf_debug_exact_sum")
+        return out.value
+
+    def lf_exact_sum_noalloc(self, values_dev):
+        """lf_debug_exact_sum on the library's fixed device scratch (allocates nothing)."""
+        p, is_dev = _ptr(values_dev)
+        if not is_dev:
+            raise ValueError("lf_exact_sum_noalloc takes a device array")
+        return self._noalloc_raw(values_dev, int(values_dev.numel()))
+
+    def _noalloc_raw(self, values_dev, n):
+        out = C.c_double()
+        self._check(self.L.lf_exact_sum_noalloc(self.h, C.c_void_p(_ptr(values_dev)[0]), int(n), C.byref(out)),
+                    "lf_exact_sum_noalloc")
         return out.value
 
     def lf_debug_sort_pairs(self, keys_dev, vals_dev=None, end_bit=64):

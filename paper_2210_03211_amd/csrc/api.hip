@@ -2,7 +2,43 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <mutex>
+
 #include "lf_internal.h"
+
+// Scratch of lf_exact_sum_noalloc: the block partial sums, the range flag and the rounded
+// result of the exact sum.  Each GPU the library runs on holds its own copy until the
+// process ends; host code uses only the per-device address resolved below, never the
+// array's name (which is a host-side stand-in).
+#define LF_NOALLOC_SCRATCH_BYTES 32768
+static __device__ __align__(256) unsigned char scratch[LF_NOALLOC_SCRATCH_BYTES];
+static_assert(sizeof(X192) * LF_EXACT_PARTIALS + 256 + sizeof(double) <= LF_NOALLOC_SCRATCH_BYTES,
+              "the no-allocation scratch holds the partials, the flag and the result");
+#define LF_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[LF_MAX_DEVICES];
+
+// Address of this device's scratch, resolved once per device with that device current.
+static int resolve_scratch(int device)
+{
+    if (device < 0 || device >= LF_MAX_DEVICES) return LF_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return LF_OK;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return LF_EDEVICE;
+    }
+    g_scratch_ptr[device] = p;
+    return LF_OK;
+}
+
+static void *scratch_of(int device)
+{
+    if (device < 0 || device >= LF_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 extern "C" {
 
@@ -41,6 +77,7 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return create_failed(h, LF_EDEVICE);
     if (hipSetDevice(device) != hipSuccess) return create_failed(h, LF_EDEVICE);
+    if (resolve_scratch(device) != LF_OK) return create_failed(h, LF_EDEVICE);
     if (hip_stream) {
         h->stream = (hipStream_t)hip_stream;
         h->own_stream = false;
@@ -366,6 +403,21 @@ int lf_debug_exact_sum(lf_handle *h, const double *values_dev, int64_t n, double
     if (!h || !out || n < 0 || (n > 0 && !values_dev)) return LF_EINVAL;
     LF_HIP(h, hipSetDevice(h->device));
     return lf_exact_sum_dev(h, values_dev, n, out);
+}
+
+int lf_exact_sum_noalloc(lf_handle *h, const double *values_dev, int64_t n, double *out)
+{
+    if (!h || !out || n < 0 || (n > 0 && !values_dev)) return LF_EINVAL;
+    if (n > LF_NOALLOC_MAX_VALUES)
+        return lf_set_error(h, LF_EINVAL, "lf_exact_sum_noalloc: n = %lld exceeds the maximum 2^40",
+                            (long long)n);
+    LF_HIP(h, hipSetDevice(h->device));
+    unsigned char *sp = (unsigned char *)scratch_of(h->device);
+    if (!sp) return lf_set_error(h, LF_EDEVICE, "no-allocation scratch not resolved for device %d", h->device);
+    X192 *part = (X192 *)sp;
+    int *err = (int *)(sp + sizeof(X192) * LF_EXACT_PARTIALS);
+    double *dout = (double *)(sp + sizeof(X192) * LF_EXACT_PARTIALS + 256);
+    return lf_exact_sum_run(h, values_dev, n, out, part, err, dout);
 }
 
 int lf_debug_sort_pairs(lf_handle *h, uint64_t *keys_dev, int32_t *vals_dev, int64_t n, int32_t end_bit)

@@ -615,20 +615,17 @@ __global__ void k_rank(const int *order, long long n, int *rank)
     rank[order[r]] = (int)r;
 }
 
-int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out)
+__global__ void k_clear_int(int *p) { *p = 0; }
+
+// The exact sum on caller-placed scratch: part (LF_EXACT_PARTIALS X192 entries), err (one
+// int) and dout (one double) in device memory; nothing is allocated here.
+int lf_exact_sum_run(lf_handle *h, const double *v, long long n, double *out, X192 *part, int *err, double *dout)
 {
-    TmpScope tmp_scope(h);
     hipStream_t st = h->stream;
     int nb = (int)((n + RED_BLOCK - 1) / RED_BLOCK);
-    if (nb > 1024) nb = 1024;
+    if (nb > LF_EXACT_PARTIALS) nb = LF_EXACT_PARTIALS;
     if (nb < 1) nb = 1;
-    X192 *part = nullptr;
-    int *err = nullptr;
-    double *dout = nullptr;
-    LF_TRY(lf_tmp_alloc(h, (void **)&part, sizeof(X192) * nb));
-    LF_TRY(lf_tmp_alloc(h, (void **)&err, sizeof(int)));
-    LF_TRY(lf_tmp_alloc(h, (void **)&dout, sizeof(double)));
-    LF_HIP(h, hipMemsetAsync(err, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(1), 0, st, err);
     hipLaunchKernelGGL(k_exact_partials, dim3(nb), dim3(RED_BLOCK), 0, st, v, n, part, err);
     hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(WAVE), 0, st, part, nb, 1.0, dout);
     int herr = 0;
@@ -638,6 +635,18 @@ int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out)
     LF_HIP(h, hipGetLastError());
     if (herr) return lf_set_error(h, LF_EOVERFLOW, "value outside the exact accumulator's range");
     return LF_OK;
+}
+
+int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out)
+{
+    TmpScope tmp_scope(h);
+    X192 *part = nullptr;
+    int *err = nullptr;
+    double *dout = nullptr;
+    LF_TRY(lf_tmp_alloc(h, (void **)&part, sizeof(X192) * LF_EXACT_PARTIALS));
+    LF_TRY(lf_tmp_alloc(h, (void **)&err, sizeof(int)));
+    LF_TRY(lf_tmp_alloc(h, (void **)&dout, sizeof(double)));
+    return lf_exact_sum_run(h, v, n, out, part, err, dout);
 }
 
 // Every triangle once, at its lowest endpoint in (degree, id) order: with wt == nullptr

@@ -364,6 +364,8 @@ int lf_build_graph(lf_handle *h, long long n, long long npairs, const long long 
                    const long long *dst, unsigned flags);
 int lf_node_stats(lf_handle *h);
 int lf_exact_sum_dev(lf_handle *h, const double *v, long long n, double *out);
+#define LF_EXACT_PARTIALS 1024     // block partial sums of the exact sum (fixed grid)
+int lf_exact_sum_run(lf_handle *h, const double *v, long long n, double *out, X192 *part, int *err, double *dout);
 
 // ---- community stages (communities.hip) ----------------------------------------------------
 // Exact-WCC pass over the triangles (wcc_hit in graph.hip): compact sorted memberships
