@@ -1,15 +1,20 @@
 """Benchmark of the LazyFox hot path on one MI355X.
 
-One step = the whole hot path on one synthetic graph whose edge list is already resident
-in HBM: graph build (dedup, CSR), triangles / local CC / node order, greedy initial
-clustering, LazyFox iterations until the stopping rule (threshold 0.01), memberships
-copied back.  Metric: node evaluations per second over the whole step (n x iterations /
-step time); the end-to-end seconds are ms_per_step.
+One step = the whole hot path on one synthetic graph, from its raw edge list in pinned
+host memory to the memberships in host memory: graph build (upload, dedup, CSR),
+triangles / local CC / node order, greedy initial clustering, LazyFox iterations until the
+stopping rule (threshold 0.01), memberships copied back.  Metric: node evaluations per
+second over the whole step (n x iterations / step time); the end-to-end seconds are
+ms_per_step.  Every timed step's memberships are hashed and checked against the oracle's
+stored result for the same graph, queue size and threshold when one exists.
 
 Prints one JSON line with, besides the contract fields, the roofline of the dominant
-kernel (algorithmic bytes per launch / average launch duration measured with HIP events
-on the library's stream inside the timed region) and the CPU oracle timed on a bounded
-sample of the same workload.
+kernel (algorithmic bytes per launch / average launch duration, measured with HIP events
+on the library's stream around every k-th launch of that kernel inside the timed steps),
+byte-model rooflines of every kernel class above 5 % of the step (evaluation, apply,
+triangles), the queue-size sweep, the dense workload, the serving comparison and the CPU
+oracle timed on the same graph (build and initialisation windows, and a stated prefix of
+queues of the first iteration at all host cores and at one thread).
 """
 import argparse
 import hashlib
@@ -45,10 +50,17 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-scale", type=float, default=0.2)
+    ap.add_argument("--cpu-queues", type=int, default=0,
+                    help="queues of the first iteration the oracle runs at all host cores (default: as many as "
+                         "fill about 10 s)")
+    ap.add_argument("--cpu-queues-1t", type=int, default=0,
+                    help="queues the oracle runs at one thread (default: as many as fill about 10 s)")
+    ap.add_argument("--event-stride", type=int, default=16,
+                    help="HIP events bracket every k-th launch of the dominant kernel in the timed steps")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense-workload run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (for HBM counter scaling)")
-    ap.add_argument("--sweep", default="1024,16384,65536",
+    ap.add_argument("--sweep", default="1024,2048,8192,16384,32768,65536",
                     help="comma-separated queue sizes run after the timed steps (end-to-end time, F1, "
                          "per-kernel bandwidth); empty to skip")
     ap.add_argument("--no-autotune", action="store_true",
@@ -65,32 +77,61 @@ def parse():
     return ap.parse_args()
 
 
-# Algorithmic bytes per unit of evaluation work, from the data layout: per decided node
-# 60 B (node record 16, node header 16, row offsets 4, decision 24); per neighbour 20 B
-# (column index 4, node header 16); per neighbour membership visited 12 B (slot 8,
-# community size 4); per candidate scored 44 B (size 4, internal edges 8, score 8, one
-# exact sum 24).
-B_NODE, B_NEIGHBOUR, B_VISIT, B_CAND = 60.0, 20.0, 12.0, 44.0
+# Algorithmic bytes per unit of evaluation work (the per-unit bytes of the method's data,
+# independent of how the kernels lay it out): per decided node 16 (its record) + 24 (the
+# decision) + 8 per own membership; per neighbour 4 (column index) + 4 + 16 (its record);
+# per neighbour membership visited 8; per candidate scored 44 (size 4, internal edges 8,
+# score 8, one exact sum 24).
+B_NODE, B_OWN, B_NEIGHBOUR, B_VISIT, B_CAND = 40.0, 8.0, 24.0, 8.0, 44.0
+# Apply (bulk apply of Algorithm 2), bytes per unit of the apply work counters:
+#   every queued node 24 (decision 12, order entry 4, join mark 8); every moved node 56
+#   (row offset 8, record 16, slot write 8, count 4, two sizes 8, two touched flags 8,
+#   member-list entry 4) + 8 per own membership scanned; every in-count work item 40
+#   written by the edits and 40 read; every neighbour of a moved node 28 (column 4,
+#   record 16, join mark 8) + 8 per membership of it scanned; every re-sum part 40
+#   written and 40 read; every touched community 24 to plan (list entry 4, member-list
+#   range 16, size 4) + 64 rewritten (its record); every member re-summed 20 (list entry
+#   4, record 16) + 8 per membership of it scanned.
+A_QNODE, A_MOVE, A_OWN, A_ITEM, A_NEIGH, A_SLOT, A_PART, A_PLAN, A_REC, A_MEMBER = (
+    24.0, 56.0, 8.0, 40.0, 28.0, 8.0, 40.0, 24.0, 64.0, 20.0)
 
 
-def kernel_bytes(kernel, paths):
+def path_bytes(w, with_candidates=True):
+    b = (B_NODE * w["nodes"] + B_OWN * w.get("own", 0) + B_NEIGHBOUR * w["neighbours"]
+         + B_VISIT * w["visits"])
+    return b + (B_CAND * w["candidates"] if with_candidates else 0.0)
+
+
+def apply_bytes(kernel, work):
+    """Algorithmic bytes one pass moves through an apply kernel (work = the profile)."""
+    a = work["apply"]
+    if kernel == "k_apply_edit":
+        return A_QNODE * work["node_evals"] + A_MOVE * a["moves"] + A_OWN * a["own_slots"] + A_ITEM * a["in_items"]
+    if kernel == "k_apply_in":
+        return (A_ITEM * a["in_items"] + A_NEIGH * a["in_neighbours"] + A_SLOT * a["in_slots"]
+                + A_PLAN * a["touched"] + A_PART * a["parts"])
+    if kernel == "k_refresh":
+        return (A_PART * a["parts"] + A_MEMBER * a["members"] + A_SLOT * a["member_slots"]
+                + A_REC * a["touched"])
+    return None
+
+
+def kernel_bytes(kernel, work):
     """Algorithmic bytes one pass moves through `kernel` (None if no model for it).  The
     small path's work is counted under k_eval: on the benchmark workload its queues (>= 1024
     small-path nodes) all launch it."""
-    def full(p):
-        w = paths[p]
-        return (B_NODE * w["nodes"] + B_NEIGHBOUR * w["neighbours"] + B_VISIT * w["visits"]
-                + B_CAND * w["candidates"])
-    t = paths["table"]
-    return {
-        "k_eval": lambda: full("small"),
-        "k_eval_big": lambda: (full("medium") + full("group") + B_NODE * t["nodes"]
-                               + B_NEIGHBOUR * t["neighbours"] + B_VISIT * t["visits"]),
-        "k_big_final": lambda: B_CAND * t["candidates"],
-    }.get(kernel, lambda: None)()
+    paths = work["paths"]
+    if kernel == "k_eval":
+        return path_bytes(paths["small"])
+    if kernel == "k_eval_big":
+        return path_bytes(paths["medium"]) + path_bytes(paths["group"]) + path_bytes(paths["table"], False)
+    if kernel == "k_big_final":
+        return B_CAND * paths["table"]["candidates"]
+    return apply_bytes(kernel, work)
 
 
 EVAL_KERNELS = ("k_eval", "k_eval_big", "k_big_final", "k_big_tie")
+APPLY_KERNELS = ("k_apply_edit", "k_apply_in", "k_refresh")
 
 
 def eval_rates(timing, work):
@@ -105,24 +146,56 @@ def eval_rates(timing, work):
             "membership_visits_per_s": sum(p["visits"] for p in paths) / sec}
 
 
-def kernel_rooflines(timing, paths):
-    """Achieved algorithmic GB/s of each evaluation kernel with a byte model (HIP-event
-    times of a profiled pass), and of the evaluation kernels together."""
+def kernel_rooflines(timing, work):
+    """Achieved algorithmic GB/s of each queue kernel with a byte model (HIP-event times of
+    a profiled pass, bytes of a counter pass), of the evaluation kernels together and of
+    the apply kernels together."""
     out = {}
-    tot_b, tot_ms = 0.0, 0.0
-    for k in ("k_eval", "k_eval_big", "k_big_final"):
-        b = kernel_bytes(k, paths)
+    groups = {"evaluation": [0.0, 0.0], "apply": [0.0, 0.0]}
+    for k in EVAL_KERNELS[:3] + APPLY_KERNELS:
+        b = kernel_bytes(k, work)
         ms = timing["ms"].get(k, 0.0)
         if b is None or ms <= 0.0:
             continue
         gbs = b / (ms * 1e-3) / 1e9
-        out[k] = {"GB_s": gbs, "frac": gbs / HBM_PEAK_GBS, "launches": timing["launches"][k], "ms": ms}
-        tot_b += b
-        tot_ms += ms
-    ms = tot_ms + timing["ms"].get("k_big_tie", 0.0)
-    if ms > 0.0:
-        out["evaluation"] = {"GB_s": tot_b / (ms * 1e-3) / 1e9, "frac": tot_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out[k] = {"GB_s": gbs, "frac": gbs / HBM_PEAK_GBS, "launches": timing["launches"][k], "ms": ms,
+                  "bytes_per_pass": b}
+        grp = groups["evaluation" if k in EVAL_KERNELS else "apply"]
+        grp[0] += b
+        grp[1] += ms
+    groups["evaluation"][1] += timing["ms"].get("k_big_tie", 0.0)
+    for name, (b, ms) in groups.items():
+        if ms > 0.0:
+            gbs = b / (ms * 1e-3) / 1e9
+            out[name] = {"GB_s": gbs, "frac": gbs / HBM_PEAK_GBS, "ms": ms}
     return out
+
+
+def triangle_roofline(h, timing_ms):
+    """Byte models of the triangle phase (orientation by (degree, id), counting) over its
+    measured time: B_min = 8(n+1) + 8|E| + 8n (the CSR once, the counts out) and the probe
+    model B_probe = 8(n+1) + 4|E| (out-lists as the hash side) + 4 P (P = sum over
+    oriented edges u->v of |N+(v)|, the probe side) + 8|E| (credits) + 8n."""
+    import numpy as np
+    rp, col = h.csr()
+    n = rp.size - 1
+    deg = np.diff(rp)
+    row = np.repeat(np.arange(n, dtype=np.int64), deg)
+    du, dv = deg[row], deg[col]
+    later = (dv > du) | ((dv == du) & (col > row))          # v after u in (degree, id) order
+    outd = np.bincount(row[later], minlength=n).astype(np.int64)
+    ind = deg - outd
+    E = int(col.size // 2)
+    P = int(np.dot(ind, outd))
+    b_min = 8.0 * (n + 1) + 8.0 * E + 8.0 * n
+    b_probe = 8.0 * (n + 1) + 4.0 * E + 4.0 * P + 8.0 * E + 8.0 * n
+    sec = timing_ms * 1e-3
+    if sec <= 0:
+        return None
+    return {"ms": timing_ms, "probes": P, "B_min": b_min, "B_probe": b_probe,
+            "GB_s_probe": b_probe / sec / 1e9, "frac_probe": b_probe / sec / 1e9 / HBM_PEAK_GBS,
+            "GB_s_min": b_min / sec / 1e9, "frac_min": b_min / sec / 1e9 / HBM_PEAK_GBS,
+            "what": "whole triangle phase (out-degrees, oriented lists, k_tri_wave / k_tri_group) by HIP events"}
 
 
 # the translation unit of the evaluation and apply kernels and every header it includes
@@ -200,22 +273,175 @@ def copy_peak_gbs(torch, nbytes=1 << 30, reps=5, device="cuda"):
     return 2.0 * nbytes / best / 1e9 if best else None
 
 
-def cpu_baseline(args, wl):
+def host_info():
+    """nproc, the CPUs this process may use, and the CPU model of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "allowed_cpus": allowed, "cpu_model": model,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(args, g, q, gpu_iterations, golden):
+    """The CPU oracle on the benchmark graph itself (same generator output, queue size and
+    threshold): graph build and initialisation windows at all usable host cores (at most
+    16, the host share of one GPU), then the first k queues of iteration 1 at one thread
+    and again, from the same initial state (warm start from the saved initial cover), at
+    all cores.  k is sized from a short pilot so that the one-thread window takes about
+    10 s.  value = node evaluations per second of the all-core window."""
+    import numpy as np
     import oracle
-    import graphgen
-    nthreads = min(16, os.cpu_count() or 1)
-    g = graphgen.named_config(wl[0], seed=args.seed, scale=args.cpu_sample_scale)
-    q = args.queue or wl[1]
-    q = max(1, int(q * args.cpu_sample_scale)) if args.cpu_sample_scale < 1 else q
+    hi = host_info()
+    threads = max(1, min(16, hi["allowed_cpus"] or 1))
     t0 = time.perf_counter()
-    o = oracle.Oracle().load_graph(g.n, g.src, g.dst).init_communities(nthreads)
-    info = o.run_iterations(q, args.threshold, args.max_iters, mode=oracle.MODE_FAST, nthreads=nthreads)
+    o = oracle.Oracle().load_graph(g.n, g.src, g.dst)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.init_communities(threads)
+    t_init = time.perf_counter() - t0
+    off0, ids0 = o.memberships()
+    K0 = int(o.L.lfo_num_communities_created(o.h))
+    n = o.n
+    nq = (n + q - 1) // q
+
+    def restore():
+        o.init_from_memberships(off0, ids0, K0, threads)
+
+    t0 = time.perf_counter()
+    o.run_queue_prefix(q, 2, nthreads=1)
+    pilot = (time.perf_counter() - t0) / 2
+    k1 = args.cpu_queues_1t or int(max(2, min(nq, 10.0 / max(pilot, 1e-3))))
+    k = args.cpu_queues or k1
+    restore()
+    t0 = time.perf_counter()
+    done1 = o.run_queue_prefix(q, k1, nthreads=1)
+    t_1 = time.perf_counter() - t0
+    off1, ids1 = o.memberships()
+    restore()
+    t0 = time.perf_counter()
+    done = o.run_queue_prefix(q, k, nthreads=threads)
+    t_all = time.perf_counter() - t0
+    if k == k1:                          # thread count must not change a bit (R23)
+        off2, ids2 = o.memberships()
+        if not (np.array_equal(off1, off2) and np.array_equal(ids1, ids2)):
+            print("[bench] ERROR: oracle prefix differs between thread counts", file=sys.stderr)
+            sys.exit(1)
+    evals_all = sum(min(q, n - j * q) for j in range(done))
+    evals_1 = sum(min(q, n - j * q) for j in range(done1))
+    rate = evals_all / t_all
+    total_evals = n * gpu_iterations
+    out = {"value": rate, "unit": "node-evals/s", "cores": threads, "kind": "oracle",
+           "sample": "the benchmark graph itself (%d nodes, %d edges), queue %d: build and initialisation "
+                     "windows at %d threads, then the first %d of %d queues of iteration 1 at %d threads "
+                     "(and the first %d at 1 thread), from the same initial state"
+                     % (n, o.nedges, q, threads, done, nq, threads, done1),
+           "host": hi, "threads": threads,
+           "windows_s": {"build": t_build, "init": t_init, "queues_all_cores": t_all, "queues_1_thread": t_1},
+           "queues_all_cores": done, "queues_1_thread": done1,
+           "node_evals_per_s_1_thread": evals_1 / t_1,
+           "end_to_end_estimate_s": t_build + t_init + total_evals / rate,
+           "end_to_end_estimate_what": "build + init + n x GPU iteration count / prefix rate at all cores"}
+    if golden and "oracle_seconds" in golden:
+        out["stored_full_run_s"] = dict(golden["oracle_seconds"], what=golden.get("made_by", ""))
+    return out
+
+
+def stored_oracle(name, q, seed, threshold):
+    """The oracle's stored result for (workload, queue size, seed), if one exists."""
+    path = os.path.join(ROOT, "tests", "golden", "%s_q%d_seed%d.json" % (name, q, seed))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        gd = json.load(f)
+    if gd.get("threshold") != threshold:
+        return None
+    gd["_file"] = os.path.relpath(path, ROOT)
+    return gd
+
+
+def check_against_oracle(gd, info, off, ids, what):
+    """Memberships hash, iteration count and score history against the stored oracle
+    result; exits with an error on any difference."""
+    import numpy as np
+    if gd is None:
+        return {"stored_oracle": None}
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(off.astype("<i8")).tobytes())
+    h.update(np.ascontiguousarray(ids.astype("<i4")).tobytes())
+    ok = (h.hexdigest() == gd["memberships_sha256"] and info["iterations"] == gd["iterations"]
+          and [float(w).hex() for w in info["wtilde_hist"]] == gd["wtilde_hist"])
+    if not ok:
+        print("[bench] ERROR: %s differs from the stored oracle result %s" % (what, gd["_file"]), file=sys.stderr)
+        sys.exit(1)
+    return {"stored_oracle": gd["_file"], "equal": True}
+
+
+def start_background_graph(name, seed, outdir):
+    """Generate a workload's edge list in a child process (before this process touches
+    the GPU), saved as .npy files; returns the process."""
+    import subprocess
+    code = ("import sys, numpy as np; sys.path.insert(0, %r); import graphgen; "
+            "g = graphgen.named_config(%r, seed=%d); np.save(%r, g.src); np.save(%r, g.dst); "
+            "open(%r, 'w').write(str(g.n))") % (ROOT, name, seed, os.path.join(outdir, "src.npy"),
+                                                 os.path.join(outdir, "dst.npy"), os.path.join(outdir, "n.txt"))
+    return subprocess.Popen([sys.executable, "-c", code])
+
+
+def dense_bench(args, lf, h, torch, proc, outdir):
+    """The dense workload (3M nodes, ~117M edges, hubs to 33k) from its pinned host edge
+    list: one untimed counter pass, one untimed kernel-timing pass and one timed run,
+    checked against the stored oracle result when one exists."""
+    import numpy as np
+    t0 = time.perf_counter()
+    if proc.wait() != 0:
+        return {"error": "generator failed"}
+    wait_s = time.perf_counter() - t0
+    n = int(open(os.path.join(outdir, "n.txt")).read())
+    src = torch.from_numpy(np.load(os.path.join(outdir, "src.npy"))).pin_memory()
+    dst = torch.from_numpy(np.load(os.path.join(outdir, "dst.npy"))).pin_memory()
+    q = WORKLOADS["dense"][1]
+
+    def run(mask):
+        h.lf_set_profiling(mask)
+        h.load_graph(n, src, dst)
+        h.init_communities()
+        info = h.run_iterations(q, args.threshold, args.max_iters)
+        off, ids = h.get_memberships()
+        return info, off, ids
+
+    h.lf_reset_profile()
+    run(1 << lf.PROF_COUNTERS_BIT)
+    work = h.lf_get_profile()
+    h.lf_reset_profile()
+    run(True)
+    timing = h.lf_get_profile()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info, off, ids = run(0)
     dt = time.perf_counter() - t0
-    evals = o.n * info["iterations"]
-    return {"value": evals / dt, "unit": "node-evals/s", "cores": nthreads, "kind": "oracle",
-            "sample": "same generator at %.0f%% scale (%d nodes, %d edges), queue %d, whole path "
-                      "(build, triangles, order, init, %d iterations) in %.1f s"
-                      % (100 * args.cpu_sample_scale, o.n, o.nedges, q, info["iterations"], dt)}
+    nn, ne, K = h.lf_get_graph_info()
+    gd = stored_oracle("dense", q, args.seed, args.threshold)
+    out = {"workload": WORKLOADS["dense"][2], "nodes": nn, "edges": ne, "queue": q, "iterations": info["iterations"],
+           "end_to_end_s": dt, "node_evals_per_s": nn * info["iterations"] / dt,
+           "generator_wait_s": wait_s, "communities_created": K, "max_degree": int(np.max(np.diff(h.csr()[0]))),
+           "kernel_ms_timing_pass": {k: round(v, 3) for k, v in timing["ms"].items()},
+           "kernel_rooflines": kernel_rooflines(timing, work),
+           "work_per_step": {"node_evals": work["node_evals"], "paths": work["paths"], "apply": work["apply"]}}
+    out.update(check_against_oracle(gd, info, off, ids, "dense run"))
+    print("[bench] dense: %.3fs, %d iterations, %s" % (dt, info["iterations"], out.get("stored_oracle")),
+          file=sys.stderr, flush=True)
+    h.lf_set_profiling(0)
+    return out
 
 
 def exact_wcc_bench(h, reps):
@@ -409,22 +635,31 @@ def main():
         print("bench.py measures one GPU only: the library runs each graph on one GPU and has no "
               "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    import tempfile
+
     import numpy as np
-    import torch
 
     import graphgen
-    import paper_2210_03211_amd as lf
 
     wl = WORKLOADS[args.workload]
     q = args.queue or wl[1]
+    dense_dir = dense_proc = None
+    if not args.no_dense and args.workload != "dense":
+        # generated by a child process while the main workload is measured
+        dense_dir = tempfile.mkdtemp(prefix="lf_dense_")
+        dense_proc = start_background_graph("dense", args.seed, dense_dir)
+    import torch
+
+    import paper_2210_03211_amd as lf
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     g = graphgen.named_config(wl[0], seed=args.seed, scale=args.scale)
     gen_s = time.perf_counter() - t0
     print("[bench] generated %s: n=%d pairs=%d in %.1fs" % (args.workload, g.n, g.npairs, gen_s),
           file=sys.stderr, flush=True)
-    src = torch.from_numpy(g.src).cuda()
-    dst = torch.from_numpy(g.dst).cuda()
+    # the step starts from the raw edge list in pinned host memory
+    src = torch.from_numpy(g.src).pin_memory()
+    dst = torch.from_numpy(g.dst).pin_memory()
     h = lf.Handle(0)
 
     def step(profile_mask=0):
@@ -449,17 +684,19 @@ def main():
         info, off, ids = step()
         print("[bench] warmup %d: %d iterations" % (w, info["iterations"]), file=sys.stderr, flush=True)
     # untimed pass with every kernel timed on its own: which kernel dominates
+    h.lf_set_option("prof_stride", 1)
     h.lf_reset_profile()
     step(True)
     timing = h.lf_get_profile()
     dom = max(timing["ms"], key=lambda k: timing["ms"][k] if k.startswith("k_") else -1.0)
     dom_bit = 1 << lf.KERNEL_CLASSES.index(dom)
     print("[bench] per-kernel ms (timing pass): %s" % json.dumps(timing["ms"]), file=sys.stderr, flush=True)
-    # untimed pass with the per-path work counters (their atomics would disturb timing)
+    # untimed pass with the work counters (their atomics would disturb timing)
     h.lf_reset_profile()
     step(1 << lf.PROF_COUNTERS_BIT)
     work = h.lf_get_profile()
-    print("[bench] work per step: %s" % json.dumps(work["paths"]), file=sys.stderr, flush=True)
+    print("[bench] work per step: %s %s" % (json.dumps(work["paths"]), json.dumps(work["apply"])), file=sys.stderr,
+          flush=True)
     if args.calibrate_copy_mib:
         # a plain device copy of known size, for scaling the HBM byte counters
         nb = args.calibrate_copy_mib << 20
@@ -472,6 +709,8 @@ def main():
         print("[bench] copy calibration: %d bytes read, %d written" % (nb, nb), file=sys.stderr, flush=True)
         del a, b
 
+    # timed steps: events around every k-th launch of the dominant kernel only
+    h.lf_set_option("prof_stride", max(1, args.event_stride))
     h.lf_reset_profile()
     hashes = set()
     torch.cuda.synchronize()
@@ -484,9 +723,12 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = h.lf_get_profile()
+    h.lf_set_option("prof_stride", 1)
     if len(hashes) != 1:
         print("[bench] ERROR: runs differ", file=sys.stderr)
         sys.exit(1)
+    golden = stored_oracle(args.workload, q, args.seed, args.threshold) if args.scale == 1.0 else None
+    parity = check_against_oracle(golden, info, off, ids, "timed run")
     n, ne, K = h.lf_get_graph_info()
     ms_per_step = 1000.0 * dt / args.steps
     evals_per_step = n * iters[0]
@@ -496,13 +738,14 @@ def main():
     # pass / launches per pass) over its average launch time in the timed steps
     launches = prof["launches"][dom]
     avg_ms = prof["ms"][dom] / max(1, launches)
-    pass_bytes = kernel_bytes(dom, work["paths"])
+    pass_bytes = kernel_bytes(dom, work)
     per_launch = pass_bytes / max(1, timing["launches"][dom]) if pass_bytes is not None else None
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if per_launch is not None else None
     traffic = stored_traffic(dom, args.workload, active_options(h))
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-            "kernel": dom, "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches": launches}
+            "kernel": dom, "bytes_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches_timed": launches,
+            "event_stride": max(1, args.event_stride)}
     try:                                # informative only: never fails the bench line
         cp = copy_peak_gbs(torch)
         roof["achievable_GB_s"] = cp
@@ -512,7 +755,6 @@ def main():
         print("[bench] device copy rate not measured: %s" % e, file=sys.stderr, flush=True)
         roof["achievable_GB_s"] = None
         roof["frac_of_achievable"] = None
-    eval_kernels = ("k_eval", "k_eval_big", "k_big_final", "k_big_tie")
     out = {
         "metric": "dWCC-hat node-evals/s (whole hot path, end-to-end)",
         "value": value, "unit": "node-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -522,20 +764,24 @@ def main():
                    "threshold": args.threshold, "iterations": iters[0], "seed": args.seed,
                    "communities_created": K, "memberships_sha256": next(iter(hashes))[:16]},
         "end_to_end_s": ms_per_step / 1000.0,
-        "kernel_node_evals_per_s": timing["node_evals"] / max(1e-9, sum(timing["ms"][k] for k in eval_kernels) * 1e-3),
+        "end_to_end_window": "raw edge list in pinned host memory -> memberships in host memory",
+        "parity": parity,
+        "kernel_node_evals_per_s": timing["node_evals"] / max(1e-9, sum(timing["ms"][k] for k in EVAL_KERNELS) * 1e-3),
         "kernel_eval_rates": eval_rates(timing, work),
-        "work_per_step": {"node_evals": work["node_evals"], "chunks": work["chunks"], "paths": work["paths"]},
+        "work_per_step": {"node_evals": work["node_evals"], "chunks": work["chunks"], "paths": work["paths"],
+                          "apply": work["apply"]},
         "kernel_ms_timing_pass": {k: round(v, 3) for k, v in timing["ms"].items()},
         "roofline": roof,
     }
     if tuned is not None:
         out["autotune"] = tuned
     out["options"] = active_options(h)
+    out["kernel_rooflines"] = kernel_rooflines(timing, work)
+    out["kernel_rooflines"]["triangles"] = triangle_roofline(h, timing["ms"].get("triangles", 0.0))
     out["exact_wcc"] = exact_wcc_bench(h, args.steps)
     out["postprocess"] = postprocess_bench(h, args.steps)
     out["cover_f1"] = cover_f1_bench(h, g, args.steps)
     out["warm_start"] = warm_start_bench(h, args.steps)
-    out["kernel_rooflines"] = kernel_rooflines(timing, work["paths"])
     if args.sweep:
         sweep = {}
         for qq in [int(x) for x in args.sweep.split(",") if x]:
@@ -545,11 +791,13 @@ def main():
             h.load_graph(g.n, src, dst)
             h.init_communities()
             si = h.run_iterations(qq, args.threshold, args.max_iters)
-            h.get_memberships()
+            soff, sids = h.get_memberships()
             torch.cuda.synchronize()
             s = time.perf_counter() - t1
             sweep[str(qq)] = {"end_to_end_s": s, "iterations": si["iterations"],
                               "node_evals_per_s": n * si["iterations"] / s, "wcc_hat": si["wcc_hat"]}
+            gq = stored_oracle(args.workload, qq, args.seed, args.threshold) if args.scale == 1.0 else None
+            sweep[str(qq)].update(check_against_oracle(gq, si, soff, sids, "sweep run q=%d" % qq))
             ref = g.planted_cover()
             if ref is not None:
                 sweep[str(qq)]["f1_vs_planted"] = h.cover_f1(*ref)[0]
@@ -565,14 +813,22 @@ def main():
                 else:
                     wprof = h.lf_get_profile()
             h.lf_set_profiling(0)
-            sweep[str(qq)]["kernel_rooflines"] = kernel_rooflines(tprof, wprof["paths"])
-            print("[bench] sweep q=%d: %.3fs %d iterations" % (qq, s, si["iterations"]), file=sys.stderr, flush=True)
+            sweep[str(qq)]["kernel_rooflines"] = kernel_rooflines(tprof, wprof)
+            print("[bench] sweep q=%d: %.3fs %d iterations %s" % (qq, s, si["iterations"],
+                                                                  sweep[str(qq)].get("stored_oracle")),
+                  file=sys.stderr, flush=True)
         out["queue_sweep"] = sweep
+    if dense_proc is not None:
+        out["dense"] = dense_bench(args, lf, h, torch, dense_proc, dense_dir)
+        import shutil
+        shutil.rmtree(dense_dir, ignore_errors=True)
+    h.close()
     if args.serving_jobs > 0:
         out["serving"] = serving_bench(args, lf)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args, wl)
+        out["cpu_baseline"] = cpu_baseline(args, g, q, iters[0], golden)
+        print("[bench] cpu baseline: %s" % json.dumps(out["cpu_baseline"]), file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

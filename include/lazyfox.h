@@ -87,6 +87,20 @@ typedef struct {
 #define LF_PATH_GROUP 2
 #define LF_PATH_TABLE 3
 #define LF_PATH_COUNT 4
+/* apply-step work counters (bit 1 << LF_PROF_COUNTERS_BIT), per step of Algorithm 2's
+   bulk apply: nodes that moved, own memberships the edits scanned, in-count work items,
+   neighbours of moved nodes visited, their memberships scanned, re-sum parts, touched
+   communities re-summed, members re-summed, and the memberships those members scanned */
+#define LF_APPLY_MOVES 0
+#define LF_APPLY_OWN_SLOTS 1
+#define LF_APPLY_IN_ITEMS 2
+#define LF_APPLY_IN_NEIGHBOURS 3
+#define LF_APPLY_IN_SLOTS 4
+#define LF_APPLY_PARTS 5
+#define LF_APPLY_TOUCHED 6
+#define LF_APPLY_MEMBERS 7
+#define LF_APPLY_MEMBER_SLOTS 8
+#define LF_APPLY_COUNT 9
 typedef struct {
     int64_t launches[LF_K_COUNT];
     double ms[LF_K_COUNT];
@@ -100,6 +114,8 @@ typedef struct {
     int64_t path_neighbours[LF_PATH_COUNT];
     int64_t path_visits[LF_PATH_COUNT];
     int64_t path_candidates[LF_PATH_COUNT];
+    int64_t path_own[LF_PATH_COUNT];   /* the decided nodes' own memberships */
+    int64_t apply_work[LF_APPLY_COUNT];
 } lf_profile;
 
 /* Create a handle on HIP device `device`.  `hip_stream` is a hipStream_t (for example
@@ -294,6 +310,10 @@ int lf_reset_profile(lf_handle *h);
 #define LF_OPT_GRP_TABLE 7         /* candidate-table entries per workgroup in the
                                       workgroup path (power of two, 16 .. 2048); nodes
                                       needing more go to the global-table path */
+#define LF_OPT_PROF_STRIDE 8       /* kernel timing (lf_set_profiling) brackets only every
+                                      k-th launch of each per-queue kernel class (1 ..
+                                      65536, default 1 = every launch); the profile's
+                                      launches count the bracketed ones */
 int lf_set_option(lf_handle *h, int option, int64_t value);
 int lf_get_option(lf_handle *h, int option, int64_t *value);
 

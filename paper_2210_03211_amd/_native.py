@@ -14,11 +14,13 @@ LF_EAGAIN, LF_EINTERNAL = -7, -8
 LF_RELABEL = 1
 LF_DEVICE_PTR = 2
 OPTIONS = {"tri_lds_cap": 1, "hub_blocks": 3, "refresh_blocks": 4, "wave_table": 5, "med_table": 6,
-           "grp_table": 7}
+           "grp_table": 7, "prof_stride": 8}
 KERNEL_CLASSES = ["build", "triangles", "order", "init_clustering", "k_eval", "k_eval_big", "k_big_final",
                   "k_big_tie", "k_apply_edit", "k_apply_in", "k_refresh", "iteration_end"]
 PROF_COUNTERS_BIT = 16
 PATHS = ["small", "medium", "group", "table"]
+APPLY_WORK = ["moves", "own_slots", "in_items", "in_neighbours", "in_slots", "parts", "touched", "members",
+              "member_slots"]
 
 
 class LazyFoxError(RuntimeError):
@@ -43,7 +45,8 @@ class Profile(C.Structure):
     _fields_ = [("launches", C.c_int64 * 12), ("ms", C.c_double * 12), ("chunks", C.c_int64),
                 ("node_evals", C.c_int64), ("visits", C.c_int64), ("candidates", C.c_int64),
                 ("path_nodes", C.c_int64 * 4), ("path_neighbours", C.c_int64 * 4),
-                ("path_visits", C.c_int64 * 4), ("path_candidates", C.c_int64 * 4)]
+                ("path_visits", C.c_int64 * 4), ("path_candidates", C.c_int64 * 4),
+                ("path_own", C.c_int64 * 4), ("apply_work", C.c_int64 * 9)]
 
 
 _lib = None
@@ -400,8 +403,10 @@ class Handle:
                     chunks=int(p.chunks), node_evals=int(p.node_evals), visits=int(p.visits),
                     candidates=int(p.candidates),
                     paths={name: dict(nodes=int(p.path_nodes[i]), neighbours=int(p.path_neighbours[i]),
-                                      visits=int(p.path_visits[i]), candidates=int(p.path_candidates[i]))
-                           for i, name in enumerate(PATHS)})
+                                      visits=int(p.path_visits[i]), candidates=int(p.path_candidates[i]),
+                                      own=int(p.path_own[i]))
+                           for i, name in enumerate(PATHS)},
+                apply={name: int(p.apply_work[i]) for i, name in enumerate(APPLY_WORK)})
 
     def lf_set_option(self, name, value):
         self._check(self.L.lf_set_option(self.h, OPTIONS[name], int(value)), "lf_set_option")

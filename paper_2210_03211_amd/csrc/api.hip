@@ -99,6 +99,7 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     h->eval_wave_cap = 128;
     h->eval_med_cap = 512;
     h->eval_grp_cap = 2048;
+    h->prof_stride = 1;
     h->hub_blocks = 2 * cus;
     h->refresh_blocks = 2 * cus;
     h->K = -1;
@@ -378,6 +379,11 @@ int lf_set_option(lf_handle *h, int option, int64_t value)
         if (value < 16 || value > 2048 || (value & (value - 1))) break;
         h->eval_grp_cap = (int)value;
         return LF_OK;
+    case LF_OPT_PROF_STRIDE:
+        if (value < 1 || value > 65536) break;
+        h->prof_stride = (int)value;
+        memset(h->prof_seq, 0, sizeof h->prof_seq);
+        return LF_OK;
     default:
         return lf_set_error(h, LF_EINVAL, "unknown option %d", option);
     }
@@ -394,6 +400,7 @@ int lf_get_option(lf_handle *h, int option, int64_t *value)
     case LF_OPT_WAVE_TABLE: *value = h->eval_wave_cap; return LF_OK;
     case LF_OPT_MED_TABLE: *value = h->eval_med_cap; return LF_OK;
     case LF_OPT_GRP_TABLE: *value = h->eval_grp_cap; return LF_OK;
+    case LF_OPT_PROF_STRIDE: *value = h->prof_stride; return LF_OK;
     default: return lf_set_error(h, LF_EINVAL, "unknown option %d", option);
     }
 }

@@ -427,6 +427,8 @@ int lf_batch_remove(lf_batch *b, int32_t member_id)
     if (!b || member_id < 0 || member_id >= (int32_t)b->members.size() || !b->members[member_id])
         return LF_EINVAL;
     BatchMember *m = b->members[member_id];
+    // mid-iteration the memberships live in the handle's lines: back to its slot layout
+    if (m->state == 0 && m->phase == PH_RUN) (void)lf_lines_back(m->h);
     (void)hipStreamSynchronize(b->stream);
     m->h->stream = m->saved_stream;
     (void)hipEventDestroy(m->ev);

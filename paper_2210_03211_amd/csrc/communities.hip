@@ -432,6 +432,7 @@ Ctx lf_ctx(lf_handle *h)
     c.order = h->order;
     c.nh = h->nh;
     c.slot = h->slot[h->cur];
+    c.ln = h->lines;
     c.cr = h->cr;
     c.cm_off = h->cm_off;
     c.cm_len = h->cm_len;
@@ -477,7 +478,7 @@ Ctx lf_ctx(lf_handle *h)
 
 void lf_free_partition(lf_handle *h)
 {
-    void **ptrs[] = {(void **)&h->nh, (void **)&h->slot[0], (void **)&h->slot[1], (void **)&h->cr,
+    void **ptrs[] = {(void **)&h->nh, (void **)&h->slot[0], (void **)&h->slot[1], (void **)&h->lines, (void **)&h->cr,
                      (void **)&h->cm_off, (void **)&h->cm_len, (void **)&h->cm_node, (void **)&h->tflag,
                      (void **)&h->tlist, (void **)&h->joined_to, (void **)&h->ovf_node,
                      (void **)&h->ovf_comm, (void **)&h->ovf_flag, (void **)&h->ctr,

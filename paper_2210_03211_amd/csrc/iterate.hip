@@ -196,32 +196,51 @@ __device__ __forceinline__ bool eval_node(const Ctx &cx, int j, const NodeRec nr
         int e = b * NT + tid;
         yv[b] = e < d ? cx.col[rb + e] : -1;
     }
-    const NodeHdr hx = cx.nh[x];
-    const int mcnt = hx.cnt;
-    if (mcnt > MXCAP) return false;
+    // own line: count, placement and (inline) memberships, read beside the adjacency
+    const NodeLine *lxp = cx.ln + x;
+    const int mcnt = lxp->cnt;
+    const long long xoff = lxp->off;
     Slot own = {-1, 0};
-    if (tid < mcnt) own = cx.slot[hx.off + tid];
-    NodeHdr hy[NB];
+    if (tid < LINE_SLOTS) own = lxp->s[tid];
+    if (mcnt > MXCAP) return false;
+    if (xoff >= 0) own = tid < mcnt ? cx.slot[xoff + tid] : Slot{-1, 0};
+    else if (tid >= mcnt) own = Slot{-1, 0};
+    // one line per neighbour: its count, degree and memberships in one gather
+    NodeLine ly[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        hy[b].off = 0;
-        hy[b].cnt = 0;
-        hy[b].deg = 0;
-        if (yv[b] >= 0) hy[b] = cx.nh[yv[b]];
+        if (yv[b] >= 0) {
+            ly[b] = cx.ln[yv[b]];
+        } else {
+            ly[b].cnt = 0;
+            ly[b].deg = 0;
+            ly[b].off = -1;
+        }
     }
-    // neighbour memberships flattened into the visit list
+    // neighbour memberships flattened into the visit list: an inline membership is kept
+    // as its (community, in-count) pair, one in the slot array as the complement of its
+    // slot index (read in phase 1)
     int V = 0;
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         if (b * NT < d) {                   // uniform over the NT threads
-            int yc = hy[b].cnt, tot;
+            int yc = ly[b].cnt, tot;
             int incl = node_incl_scan<NT>(yc, tid, L, &tot);
             int p0 = V + incl - yc;
             V += tot;
             if (V + mcnt > VCAP || 2 * (V + mcnt) > wcap) return false;   // uniform
-            for (int t = 0; t < yc; t++) {
-                L.vslot[p0 + t] = hy[b].off + t;
-                L.vdeg[p0 + t] = hy[b].deg;
+            if (ly[b].off < 0) {
+#pragma unroll
+                for (int t = 0; t < LINE_SLOTS; t++)
+                    if (t < yc) {
+                        L.vslot[p0 + t] = ((long long)ly[b].s[t].in << 32) | (unsigned)ly[b].s[t].comm;
+                        L.vdeg[p0 + t] = ly[b].deg;
+                    }
+            } else {
+                for (int t = 0; t < yc; t++) {
+                    L.vslot[p0 + t] = ~(ly[b].off + t);
+                    L.vdeg[p0 + t] = ly[b].deg;
+                }
             }
         }
     }
@@ -247,7 +266,15 @@ __device__ __forceinline__ bool eval_node(const Ctx &cx, int j, const NodeRec nr
         int v = b * NT + tid;
         sv[b].comm = -1;
         sv[b].in = 0;
-        if (v < V) sv[b] = cx.slot[L.vslot[v]];
+        if (v < V) {
+            const long long e = L.vslot[v];
+            if (e >= 0) {
+                sv[b].comm = (int)(unsigned)e;
+                sv[b].in = (int)(e >> 32);
+            } else {
+                sv[b] = cx.slot[~e];
+            }
+        }
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
@@ -426,16 +453,18 @@ __device__ __forceinline__ bool eval_node(const Ctx &cx, int j, const NodeRec nr
             atomicAdd(&w[1], (unsigned long long)d);
             atomicAdd(&w[2], (unsigned long long)V);
             atomicAdd(&w[3], (unsigned long long)NC);
+            atomicAdd(&w[4], (unsigned long long)mcnt);
         }
     }
     return true;
 }
 
-__device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg)
+__device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg, int own)
 {
     if (cx.stats) {
         atomicAdd(&cx.ctr->work[LF_PATH_TABLE][0], 1ull);
         atomicAdd(&cx.ctr->work[LF_PATH_TABLE][1], (unsigned long long)deg);
+        atomicAdd(&cx.ctr->work[LF_PATH_TABLE][4], (unsigned long long)own);
     }
     cx.big_idx[j] = Q_TABLE;
     cx.big_bj[j] = 0;
@@ -565,21 +594,25 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
                 long long e = ib0 + f - cx.titem_base[p];
                 int y = -1;
                 if (e < nr.d) y = cx.col[nr.rb + e];  // issued beside the node's header
-                NodeHdr hx = cx.nh[x];
-                if (e == 0) mark_table(cx, j, hx.deg);   // k_big_final reads it after this launch
-                if (e < hx.deg) {
-                    NodeHdr hy = cx.nh[y];
-                    vc = hy.cnt;
-                    sb = hy.off;
-                    dy = hy.deg;
-                } else if (e < (long long)hx.deg + hx.cnt) {
+                const NodeLine *lxp = cx.ln + x;
+                const int xdeg = lxp->deg, xc0 = lxp->cnt;
+                const long long xo0 = lxp->off;
+                Slot *xs = xo0 < 0 ? (Slot *)lxp->s : cx.slot + xo0;
+                if (e == 0) mark_table(cx, j, xdeg, xc0);   // k_big_final reads it after this launch
+                if (e < xdeg) {
+                    const NodeLine *lyp = cx.ln + y;
+                    vc = lyp->cnt;
+                    dy = lyp->deg;
+                    const long long yo = lyp->off;
+                    sb = (long long)(yo < 0 ? (Slot *)lyp->s : cx.slot + yo);
+                } else if (e < (long long)xdeg + xc0) {
                     vc = 1;
-                    sb = hx.off + (e - hx.deg);
+                    sb = (long long)(xs + (e - xdeg));
                     own = 1;
                 }
                 jj = j;
-                xoff = hx.off;
-                xcnt = hx.cnt;
+                xoff = (long long)xs;
+                xcnt = xc0;
             }
         }
         int incl = vc;
@@ -624,7 +657,7 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
                 dyv = s_dy[wv][lo];
                 xo = s_xoff[wv][lo];
                 xc = s_xcnt[wv][lo];
-                Slot sl = cx.slot[s_sbase[wv][lo] + (v - s_start[wv][lo])];
+                Slot sl = ((const Slot *)s_sbase[wv][lo])[v - s_start[wv][lo]];
                 C = sl.comm;
                 iv = sl.in;
                 hh = gfind(cx, j, C, claimed);
@@ -640,7 +673,7 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
             i64 t0 = 0, t1 = 0, t2 = 0, t3 = 0;
             if (extra) {
                 long long s = cx.cr[C].s;
-                bool leave = find_slot(cx.slot, xo, xc, C) >= 0;
+                bool leave = find_slot((const Slot *)xo, 0, xc, C) >= 0;
                 X192 term = visit_term(leave, iv, dyv, s, bad);
                 x192_digits(term, t0, t1, t2, t3);
             }
@@ -778,11 +811,11 @@ __device__ __forceinline__ void body_big_final(const Ctx &cx, const QStep &qs, i
         if (b >= 0) {
             {
                 int x = cx.order[cstart + b];
-                NodeHdr hx = cx.nh[x];
+                const NodeLine hx = cx.ln[x];
                 int k = ge.cnt + (ge.idy > 0 ? 1 : 0);
                 X192 corr = x192_from_digits(ge.d[0], ge.d[1], ge.d[2], ge.d[3]);
                 int own_in = 0;
-                int a = find_slot_in(cx.slot, hx.off, hx.cnt, C, &own_in);
+                int a = line_find(cx, hx, C, &own_in);
                 leave = a >= 0;
                 if (ge.idy > 0) {
                     X192 t = visit_term(leave, ge.ii, ge.idy, cx.cr[C].s, bad);
@@ -903,75 +936,104 @@ __device__ __forceinline__ void body_apply_edit(const Ctx &cx, const QStep &qs, 
     if (j == 0) cx.ctr->occ_cnt = 0;        // the table path of this queue is done
 
     bool inq = j < clen;
-    int J = -1, L = -1;
+    int J = -1, L = -1, x = -1;
     if (inq) {
-        if (cx.big_idx[j] == Q_TABLE) {
-            unsigned long long bj = cx.big_bj[j], bl = cx.big_bl[j];
-            J = bj ? cx.big_cj[j] : -1;
-            L = bl ? cx.big_cl[j] : -1;
+        // every array a decision may sit in, read in one round trip (the table path's
+        // arrays hold stale values for the other nodes, which are then ignored)
+        const int bi = cx.big_idx[j];
+        const int dj = cx.dj[j], dl = cx.dl[j];
+        const unsigned long long bj = cx.big_bj[j], bl = cx.big_bl[j];
+        const int cj = cx.big_cj[j], cl = cx.big_cl[j];
+        x = cx.order[cstart + j];
+        if (bi == Q_TABLE) {
+            J = bj ? cj : -1;
+            L = bl ? cl : -1;
             cx.dj[j] = J;
             cx.dl[j] = L;
             cx.djd[j] = __longlong_as_double((long long)bj);
             cx.dld[j] = __longlong_as_double((long long)bl);
         } else {
-            J = cx.dj[j];
-            L = cx.dl[j];
+            J = dj;
+            L = dl;
         }
+        const unsigned long long tag = (unsigned long long)cx.qtag << 32;
+        cx.joined_to[x] = tag | 0xffffffffull;  // no join (yet) in this queue
     }
     unsigned long long ml = __ballot(L >= 0);
     if (lane == 0 && ml) atomicAdd(&cx.ctr->leaves, (unsigned long long)__popcll(ml));
     const bool act = inq && (J >= 0 || L >= 0);
-    int x = -1;
-    if (inq) {
-        x = cx.order[cstart + j];
-        const unsigned long long tag = (unsigned long long)cx.qtag << 32;
-        cx.joined_to[x] = tag | 0xffffffffull;  // no join (yet) in this queue
-    }
     bool firstL = false, firstJ = false, joined = false;
-    int blocks = 0, deg = 0;
+    int blocks = 0, deg = 0, own_scanned = 0;
     long long rb = 0, jslot = 0;
     if (act) {
+        // the node's row offset, record and slot capacity, and J's member-list range,
+        // all in one round trip
         rb = cx.rowptr[x];
-        NodeHdr hx = cx.nh[x];
-        int cnt = hx.cnt;
-        if (L >= 0) {
-            int t = find_slot(cx.slot, hx.off, cnt, L);
-            cx.slot[hx.off + t] = cx.slot[hx.off + cnt - 1];
-            cnt--;
-            atomicSub(&cx.cr[L].s, 1);
-            firstL = atomicExch(&cx.tflag[L], 1) == 0;   // first touch of L in this queue
-        }
+        const NodeLine hx = cx.ln[x];
+        const long long nxt = cx.nh[x + 1].off;      // capacity of a node in the slot array
+        long long cmo = 0, cme = 0;
         if (J >= 0) {
-            long long capx = cx.nh[x + 1].off - hx.off;
-            if (cnt >= capx) {
-                atomicOr(&cx.ctr->error, LF_DEVERR_SLOTS);
-            } else {
-                Slot sn = {J, 0};
-                jslot = hx.off + cnt;
-                cx.slot[jslot] = sn;
-                cnt++;
-                atomicAdd(&cx.cr[J].s, 1);
-                cx.joined_to[x] = ((unsigned long long)cx.qtag << 32) | (unsigned)J;
-                joined = true;
-                int p = atomicAdd(&cx.cm_len[J], 1);
-                long long cap = cx.cm_off[J + 1] - cx.cm_off[J];
-                if (p < cap) {
-                    cx.cm_node[cx.cm_off[J] + p] = x;
-                } else {
-                    int e = atomicAdd(&cx.ctr->ovf_cnt, 1);
-                    cx.ovf_node[e] = x;
-                    cx.ovf_comm[e] = J;
-                    cx.ovf_flag[J] = 1;
-                }
-                firstJ = atomicExch(&cx.tflag[J], 1) == 0;
-            }
+            cmo = cx.cm_off[J];
+            cme = cx.cm_off[J + 1];
         }
-        cx.nh[x].cnt = cnt;
+        int cnt = hx.cnt;
+        own_scanned = L >= 0 ? cnt : 0;
+        // size, touched-flag and member-list atomics of both communities, issued together
+        int oldL = 1, oldJ = 1, p = 0;
+        const long long capx = hx.off < 0 ? LINE_SLOTS : nxt - hx.off;
+        Slot *xs = hx.off < 0 ? cx.ln[x].s : cx.slot + hx.off;
+        const bool jfits = J >= 0 && cnt - (L >= 0 ? 1 : 0) < capx;
+        if (J >= 0 && !jfits) atomicOr(&cx.ctr->error, LF_DEVERR_SLOTS);
+        if (L >= 0) {
+            atomicSub(&cx.cr[L].s, 1);
+            oldL = atomicExch(&cx.tflag[L], 1);
+        }
+        if (jfits) {
+            atomicAdd(&cx.cr[J].s, 1);
+            p = atomicAdd(&cx.cm_len[J], 1);
+            oldJ = atomicExch(&cx.tflag[J], 1);
+        }
+        if (L >= 0) {
+            // the leave's slot takes the last one (read in the same round trip as the search)
+            const Slot last = xs[cnt - 1];
+            int tin = 0;
+            int t = line_find(cx, hx, L, &tin);
+            if (t != cnt - 1) xs[t] = last;
+            cnt--;
+            firstL = oldL == 0;               // first touch of L in this queue
+        }
+        if (jfits) {
+            Slot sn = {J, 0};
+            xs[cnt] = sn;
+            jslot = (long long)(xs + cnt);
+            cnt++;
+            cx.joined_to[x] = ((unsigned long long)cx.qtag << 32) | (unsigned)J;
+            joined = true;
+            if (p < cme - cmo) {
+                cx.cm_node[cmo + p] = x;
+            } else {
+                int e = atomicAdd(&cx.ctr->ovf_cnt, 1);
+                cx.ovf_node[e] = x;
+                cx.ovf_comm[e] = J;
+                cx.ovf_flag[J] = 1;
+            }
+            firstJ = oldJ == 0;
+        }
+        cx.ln[x].cnt = cnt;
         deg = hx.deg;
         blocks = (deg + INB - 1) / INB;
     }
     unsigned long long mj = __ballot(joined);
     if (mj && lane == __ffsll((long long)mj) - 1) atomicAdd(&cx.ctr->joins, (unsigned long long)__popcll(mj));
+    if (cx.stats) {
+        const long long mv = wave_sum_i64(act ? 1 : 0), os = wave_sum_i64(act ? own_scanned : 0);
+        const long long it = wave_sum_i64(blocks);
+        if (lane == 0 && mv) {
+            atomicAdd(&cx.ctr->apply[LF_APPLY_MOVES], (unsigned long long)mv);
+            atomicAdd(&cx.ctr->apply[LF_APPLY_OWN_SLOTS], (unsigned long long)os);
+            atomicAdd(&cx.ctr->apply[LF_APPLY_IN_ITEMS], (unsigned long long)it);
+        }
+    }
     // touched communities and in-count work items: one reservation per block
     int tpos = 0, p0 = 0;
     block_reserve2((int)firstL + (int)firstJ, blocks, &cx.ctr->tcount, &cx.ctr->in_items, &tpos, &p0);
@@ -1010,39 +1072,66 @@ __device__ __forceinline__ void body_apply_in(const Ctx &cx, const QStep &qs, in
         refresh_plan(cx, blk * blockDim.x + threadIdx.x);
         return;
     }
-    int count = __atomic_load_n(&cx.ctr->in_items, __ATOMIC_RELAXED);
-    if (count > cx.in_cap) count = cx.in_cap;
     int lane = threadIdx.x & (WAVE - 1);
     long long nw = (long long)(nblk - plan_blocks) * (blockDim.x / WAVE);
-    for (long long p = ((blk - plan_blocks) * (long long)blockDim.x + threadIdx.x) / WAVE; p < count;
-         p += nw) {
-        const InItem it = cx.in_item[p];
+    long long p = ((blk - plan_blocks) * (long long)blockDim.x + threadIdx.x) / WAVE;
+    // the wave's first item is read beside the count (the buffer holds in_cap records)
+    InItem first;
+    if (p < cx.in_cap) first = cx.in_item[p];
+    int count = __atomic_load_n(&cx.ctr->in_items, __ATOMIC_RELAXED);
+    if (count > cx.in_cap) count = cx.in_cap;
+    for (bool at_first = true; p < count; p += nw, at_first = false) {
+        const InItem it = at_first ? first : cx.in_item[p];
         if (it.x < 0) continue;                    // only after a flagged overflow
         const int J = it.J, L = it.L;
         const int lo = it.k * INB, hi = lo + INB < it.d ? lo + INB : it.d;
         int fresh = 0;
         for (int e = lo + lane; e < hi; e += WAVE) {
             int y = cx.col[it.rb + e];
-            NodeHdr hy = cx.nh[y];
+            const NodeLine hy = cx.ln[y];            // count and inline memberships in one gather
             int jy = joined_in_queue(cx, y);
-            for (int t0 = 0; t0 < hy.cnt; t0 += 4) {   // four slot loads per round trip
-                int cc[4];
+            if (hy.off < 0) {
 #pragma unroll
-                for (int u = 0; u < 4; u++) cc[u] = t0 + u < hy.cnt ? cx.slot[hy.off + t0 + u].comm : -2;
-#pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    const int c = cc[u];
+                for (int u = 0; u < LINE_SLOTS; u++) {
+                    const int c = u < hy.cnt ? hy.s[u].comm : -2;
                     if (c == J && J >= 0) {
                         fresh++;
-                        if (jy != J) atomicAdd(&cx.slot[hy.off + t0 + u].in, 1);
+                        if (jy != J) atomicAdd(&cx.ln[y].s[u].in, 1);
                     } else if (c == L && L >= 0) {
-                        if (jy != L) atomicSub(&cx.slot[hy.off + t0 + u].in, 1);
+                        if (jy != L) atomicSub(&cx.ln[y].s[u].in, 1);
+                    }
+                }
+            } else {
+                Slot *ys = cx.slot + hy.off;
+                for (int t0 = 0; t0 < hy.cnt; t0 += 4) {   // four slot loads per round trip
+                    int cc[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) cc[u] = t0 + u < hy.cnt ? ys[t0 + u].comm : -2;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const int c = cc[u];
+                        if (c == J && J >= 0) {
+                            fresh++;
+                            if (jy != J) atomicAdd(&ys[t0 + u].in, 1);
+                        } else if (c == L && L >= 0) {
+                            if (jy != L) atomicSub(&ys[t0 + u].in, 1);
+                        }
                     }
                 }
             }
         }
         fresh = wave_sum_int(fresh);
-        if (lane == 0 && J >= 0 && fresh) atomicAdd(&cx.slot[it.jslot].in, fresh);
+        if (lane == 0 && J >= 0 && fresh) atomicAdd(&((Slot *)it.jslot)->in, fresh);
+        if (cx.stats) {
+            const long long nb = hi > lo ? hi - lo : 0;
+            long long sc = 0;
+            for (int e = lo + lane; e < hi; e += WAVE) sc += cx.ln[cx.col[it.rb + e]].cnt;
+            sc = wave_sum_i64(sc);
+            if (lane == 0) {
+                atomicAdd(&cx.ctr->apply[LF_APPLY_IN_NEIGHBOURS], (unsigned long long)nb);
+                atomicAdd(&cx.ctr->apply[LF_APPLY_IN_SLOTS], (unsigned long long)sc);
+            }
+        }
     }
 }
 QUEUE_KERNELS(k_apply_in, 256, NoLds, body_apply_in)
@@ -1126,13 +1215,17 @@ __device__ __forceinline__ X192 x192_from_digits6(const long long *D)
 __device__ __forceinline__ void body_refresh(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
 {
     (void)qs;
-    int count = __atomic_load_n(&cx.ctr->parts_total, __ATOMIC_RELAXED);
-    if (count > cx.part_cap) count = cx.part_cap;
     int lane = threadIdx.x & (WAVE - 1);
     long long nw = (long long)nblk * (blockDim.x / WAVE);
     int bad = 0;
-    for (long long p = (blk * (long long)blockDim.x + threadIdx.x) / WAVE; p < count; p += nw) {
-        const PartRec pr = cx.part_rec[p];
+    long long p = (blk * (long long)blockDim.x + threadIdx.x) / WAVE;
+    // the wave's first part is read beside the count (the buffer holds part_cap records)
+    PartRec first;
+    if (p < cx.part_cap) first = cx.part_rec[p];
+    int count = __atomic_load_n(&cx.ctr->parts_total, __ATOMIC_RELAXED);
+    if (count > cx.part_cap) count = cx.part_cap;
+    for (bool at_first = true; p < count; p += nw, at_first = false) {
+        const PartRec pr = at_first ? first : cx.part_rec[p];
         const int C = pr.C;
         if (C < 0 || C >= cx.K) continue;          // only after a flagged overflow
         const int k = pr.k, parts = pr.parts;
@@ -1141,11 +1234,22 @@ __device__ __forceinline__ void body_refresh(const Ctx &cx, const QStep &qs, int
         X192 a0 = x192_zero(), ap = x192_zero(), am = x192_zero();
         long long sumi = 0;
         for (long long q = lo + lane; q < hi; q += WAVE)
-            member_terms(cx, cx.cm_node[base + q], C, s, a0, ap, am, sumi, bad);
+            member_terms_line(cx, cx.cm_node[base + q], C, s, a0, ap, am, sumi, bad);
+        if (cx.stats) {
+            long long mslots = 0;
+            for (long long q = lo + lane; q < hi; q += WAVE) mslots += cx.ln[cx.cm_node[base + q]].cnt;
+            mslots = wave_sum_i64(mslots);
+            if (lane == 0) {
+                atomicAdd(&cx.ctr->apply[LF_APPLY_PARTS], 1ull);
+                if (k == 0) atomicAdd(&cx.ctr->apply[LF_APPLY_TOUCHED], 1ull);
+                atomicAdd(&cx.ctr->apply[LF_APPLY_MEMBERS], (unsigned long long)(hi > lo ? hi - lo : 0));
+                atomicAdd(&cx.ctr->apply[LF_APPLY_MEMBER_SLOTS], (unsigned long long)mslots);
+            }
+        }
         if (k == 0 && pr.ovf) {
             int no = __atomic_load_n(&cx.ctr->ovf_cnt, __ATOMIC_RELAXED);
             for (int e = lane; e < no; e += WAVE)
-                if (cx.ovf_comm[e] == C) member_terms(cx, cx.ovf_node[e], C, s, a0, ap, am, sumi, bad);
+                if (cx.ovf_comm[e] == C) member_terms_line(cx, cx.ovf_node[e], C, s, a0, ap, am, sumi, bad);
         }
         a0 = wave_sum_x192(a0);
         ap = wave_sum_x192(ap);
@@ -1317,6 +1421,42 @@ __global__ void __launch_bounds__(256) k_titem_fill(Ctx cx, const long long *nt_
     for (long long p = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE; p < nt; p += nw) {
         long long a = cx.titem_base[p], b = cx.titem_base[p + 1];
         for (long long f = a + lane; f < b; f += WAVE) cx.titem_node[f] = (int)p;
+    }
+}
+
+// the membership lines of an iteration, from the slot layout (nodes whose capacity fits a
+// line keep their memberships inline, the others point into the slot array)
+__global__ void __launch_bounds__(256) k_line_build(Ctx cx)
+{
+    const long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (x >= cx.n) return;
+    const NodeHdr hx = cx.nh[x];
+    const long long cap = cx.nh[x + 1].off - hx.off;
+    NodeLine l;
+    l.cnt = hx.cnt;
+    l.deg = hx.deg;
+    l.off = cap <= LINE_SLOTS ? -1 : hx.off;
+#pragma unroll
+    for (int t = 0; t < LINE_SLOTS; t++) {
+        Slot sl = {-1, 0};
+        if (l.off < 0 && t < hx.cnt) sl = cx.slot[hx.off + t];
+        l.s[t] = sl;
+    }
+    cx.ln[x] = l;
+}
+
+// back to the slot layout at the end of an iteration: counts, and inline memberships
+__global__ void __launch_bounds__(256) k_line_back(Ctx cx)
+{
+    const long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (x >= cx.n) return;
+    const NodeLine l = cx.ln[x];
+    cx.nh[x].cnt = l.cnt;
+    if (l.off < 0) {
+        const long long o = cx.nh[x].off;
+#pragma unroll
+        for (int t = 0; t < LINE_SLOTS; t++)
+            if (t < l.cnt) cx.slot[o + t] = l.s[t];
     }
 }
 
@@ -1536,6 +1676,13 @@ static int size_queue_complete(lf_handle *h, long long q)
 int lf_iter_begin_enqueue(lf_handle *h, long long qq)
 {
     LF_TRY(size_queue_enqueue(h, qq));
+    if (h->n > 0) {
+        if (!h->lines) {
+            LF_TRY(lf_dev_alloc(h, (void **)&h->lines, sizeof(NodeLine) * h->n));
+            h->graph_version++;
+        }
+        hipLaunchKernelGGL(k_line_build, dim3(grid_for(h->n, 256)), dim3(256), 0, h->stream, lf_ctx(h));
+    }
     LF_HIP(h, hipMemsetAsync(&h->ctr->joins, 0, sizeof(unsigned long long) * 2, h->stream));
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, h->stream, lf_ctx(h));
     return LF_OK;
@@ -1685,9 +1832,18 @@ void lf_multi_kernels(const void **fn, int *grid, int *block)
 
 // End of an iteration: counters reset, degenerate communities removed, exact score.
 // End of an iteration, in the same two halves as its start.
+// the membership lines back into the slot layout (a batch member leaving mid-iteration)
+int lf_lines_back(lf_handle *h)
+{
+    if (h->n > 0 && h->lines)
+        hipLaunchKernelGGL(k_line_back, dim3(grid_for(h->n, 256)), dim3(256), 0, h->stream, lf_ctx(h));
+    return hipGetLastError() == hipSuccess ? LF_OK : LF_EDEVICE;
+}
+
 int lf_iter_finish_enqueue(lf_handle *h)
 {
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, h->stream, lf_ctx(h));
+    if (h->n > 0) hipLaunchKernelGGL(k_line_back, dim3(grid_for(h->n, 256)), dim3(256), 0, h->stream, lf_ctx(h));
     LF_HIP(h, hipGetLastError());
     LF_TRY(lf_prof_begin(h, LF_K_ITEREND));
     LF_TRY(lf_iteration_end_enqueue(h));
@@ -1753,8 +1909,10 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
     if (!out->converged && out->iterations == max_iters) out->hit_max = 1;
     LF_TRY(lf_prof_flush(h));
     {
-        unsigned long long w[LF_PATH_COUNT][4];
+        unsigned long long w[LF_PATH_COUNT][5], aw[LF_APPLY_COUNT];
         LF_HIP(h, hipMemcpy(w, h->ctr->work, sizeof(w), hipMemcpyDeviceToHost));
+        LF_HIP(h, hipMemcpy(aw, h->ctr->apply, sizeof(aw), hipMemcpyDeviceToHost));
+        for (int k = 0; k < LF_APPLY_COUNT; k++) h->prof.apply_work[k] = (long long)aw[k];
         h->prof.visits = 0;
         h->prof.candidates = 0;
         for (int p = 0; p < LF_PATH_COUNT; p++) {
@@ -1762,6 +1920,7 @@ int lf_iterate(lf_handle *h, int q, double theta, int max_iters, lf_run_info *ou
             h->prof.path_neighbours[p] = (long long)w[p][1];
             h->prof.path_visits[p] = (long long)w[p][2];
             h->prof.path_candidates[p] = (long long)w[p][3];
+            h->prof.path_own[p] = (long long)w[p][4];
             h->prof.visits += (long long)w[p][2];
             h->prof.candidates += (long long)w[p][3];
         }

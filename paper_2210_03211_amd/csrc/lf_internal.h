@@ -23,11 +23,25 @@ struct Slot {
     int in;
 };
 
+// One node's memberships for the queue kernels, one 64-byte line: membership count,
+// degree and up to LINE_SLOTS memberships inline (off = -1); a node whose slot capacity
+// exceeds LINE_SLOTS keeps its memberships in the slot array from `off` on.  The lines
+// are built from the slot layout at every iteration start and written back at its end,
+// so within an iteration one gather of a node's line serves its whole membership list.
+#define LINE_SLOTS 6
+struct __align__(64) NodeLine {
+    int cnt;
+    int deg;
+    long long off;           // -1: memberships inline; else the first slot in the slot array
+    Slot s[LINE_SLOTS];
+};
+static_assert(sizeof(NodeLine) == 64, "one 64-byte line per node");
+
 // One in-count work item: a block of INB neighbours of a node that moved in this queue,
 // with everything the item needs (written by the membership edits).
 struct InItem {
     long long rb;            // first adjacency position of the moved node
-    long long jslot;         // absolute slot of its join (valid if J >= 0)
+    long long jslot;         // address of its join's slot (valid if J >= 0)
     int x;                   // the moved node
     int J, L;                // community joined (-1: none or it did not fit) and left (-1: none)
     int d;                   // its degree
@@ -87,8 +101,9 @@ struct __align__(64) GEntry {
 struct DevCounters {
     unsigned long long joins;      // per iteration
     unsigned long long leaves;     // per iteration
-    unsigned long long work[LF_PATH_COUNT][4]; // evaluation work per path (cumulative): nodes,
-                                   // neighbours, visits, candidates
+    unsigned long long work[LF_PATH_COUNT][5]; // evaluation work per path (cumulative): nodes,
+                                   // neighbours, visits, candidates, own memberships
+    unsigned long long apply[LF_APPLY_COUNT];  // apply work (cumulative, LF_APPLY_*)
     int tcount;                    // touched communities (queue)
     int unused0;
     int unused1;
@@ -122,6 +137,7 @@ struct Ctx {
     const int *order;
     NodeHdr *nh;
     Slot *slot;
+    NodeLine *ln;            // per-node membership lines (within an iteration)
     CommRec *cr;             // community records
     long long *cm_off;       // member-list capacity offsets (K + 1)
     int *cm_len;             // member-list fill (may exceed capacity: overflow)
@@ -229,6 +245,7 @@ struct lf_handle {
     // partition
     NodeHdr *nh;
     Slot *slot[2];
+    NodeLine *lines;         // [n] membership lines of the current iteration
     int cur;
     long long slot_capb[2];  // capacity of each slot buffer
     CommRec *cr;
@@ -291,6 +308,9 @@ struct lf_handle {
     int refresh_blocks;      // workgroups of the in-count and re-sum kernels
     // profiling
     int profiling;           // bit mask of timed kernel classes (1 << LF_K_*)
+    int prof_stride;         // bracket every prof_stride-th launch of a per-queue class
+    long long prof_seq[LF_K_COUNT];   // launches of each class seen while timing
+    int prof_skip;           // classes whose current launch is not bracketed (bit mask)
     lf_profile prof;
     hipEvent_t ev0, ev1;
     std::vector<hipEvent_t> *evpool;   // start/stop pairs recorded without host sync
@@ -398,6 +418,7 @@ int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int ca
 #define LF_MULTI_KERNELS 6       // kernels of a batch step (k_big_final and k_big_tie share a grid)
 void lf_multi_kernels(const void **fn, int *grid, int *block);
 int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long *live);
+int lf_lines_back(lf_handle *h);          // lines -> slot layout (mid-iteration stop)
 int lf_iter_finish_enqueue(lf_handle *h);
 int lf_iter_finish_complete(lf_handle *h, long long *joins, long long *leaves, long long *live);
 int lf_iteration_end_enqueue(lf_handle *h);

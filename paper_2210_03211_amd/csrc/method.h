@@ -180,6 +180,19 @@ __device__ __forceinline__ void wave_best(double &bd, int &bc)
     }
 }
 
+// the g-terms of one member of C with in-count i and degree d at sizes s, s+1, s-1
+__device__ __forceinline__ void member_add(long long i, long long d, long long s, X192 &a0, X192 &ap, X192 &am,
+                                           long long &sumi, int &bad)
+{
+    sumi += i;
+    X192 v = x192_from_double(g_term(i, d, s), bad);
+    x192_add(a0, v);
+    v = x192_from_double(g_term(i, d, s + 1), bad);
+    x192_add(ap, v);
+    v = x192_from_double(g_term(i, d, s - 1), bad);
+    x192_add(am, v);
+}
+
 // exact g-sums of one member y of C (at sizes s, s+1, s-1) if y is still in C
 __device__ __forceinline__ void member_terms(const Ctx &cx, int y, int C, long long s, X192 &a0, X192 &ap,
                                              X192 &am, long long &sumi, int &bad)
@@ -188,15 +201,42 @@ __device__ __forceinline__ void member_terms(const Ctx &cx, int y, int C, long l
     int in = 0;
     int t = find_slot_in(cx.slot, hy.off, hy.cnt, C, &in);
     if (t < 0) return;                       // left C earlier in this iteration
-    long long i = in;
-    long long d = hy.deg;
-    sumi += i;
-    X192 v = x192_from_double(g_term(i, d, s), bad);
-    x192_add(a0, v);
-    v = x192_from_double(g_term(i, d, s + 1), bad);
-    x192_add(ap, v);
-    v = x192_from_double(g_term(i, d, s - 1), bad);
-    x192_add(am, v);
+    member_add(in, hy.deg, s, a0, ap, am, sumi, bad);
+}
+
+// ---- membership lines (the queue kernels' view of the memberships) --------------------
+// first membership slot of a node whose line is l
+__device__ __forceinline__ Slot *line_slots(const Ctx &cx, int x, const NodeLine &l)
+{
+    return l.off < 0 ? cx.ln[x].s : cx.slot + l.off;
+}
+
+// position of community c among the memberships of the node with line l (-1 if absent)
+// and its in-count: inline memberships come from the line itself
+__device__ __forceinline__ int line_find(const Ctx &cx, const NodeLine &l, int c, int *in)
+{
+    if (l.off < 0) {
+        int a = -1, iv = 0;
+#pragma unroll
+        for (int t = 0; t < LINE_SLOTS; t++)
+            if (t < l.cnt && l.s[t].comm == c) {
+                a = t;
+                iv = l.s[t].in;
+            }
+        *in = iv;
+        return a;
+    }
+    return find_slot_in(cx.slot, l.off, l.cnt, c, in);
+}
+
+// member_terms on the membership lines
+__device__ __forceinline__ void member_terms_line(const Ctx &cx, int y, int C, long long s, X192 &a0, X192 &ap,
+                                                  X192 &am, long long &sumi, int &bad)
+{
+    const NodeLine ly = cx.ln[y];
+    int in = 0;
+    if (line_find(cx, ly, C, &in) < 0) return;   // left C earlier in this iteration
+    member_add(in, ly.deg, s, a0, ap, am, sumi, bad);
 }
 
 // The lanes executing this call with want = true receive consecutive indices from *ctr,

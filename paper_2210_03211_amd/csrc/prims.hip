@@ -102,9 +102,17 @@ static bool prof_on(lf_handle *h, int kind) { return kind < LF_K_COUNT && ((h->p
 int lf_prof_begin(lf_handle *h, int kind) { return lf_prof_begin_on(h, kind, h->stream); }
 int lf_prof_end(lf_handle *h, int kind, int launches) { return lf_prof_end_on(h, kind, launches, h->stream); }
 
+// the per-queue kernel classes, which a stride > 1 samples
+static bool per_queue_class(int kind) { return kind >= LF_K_EVAL && kind <= LF_K_REFRESH; }
+
 int lf_prof_begin_on(lf_handle *h, int kind, hipStream_t st)
 {
     if (!prof_on(h, kind)) return LF_OK;
+    if (per_queue_class(kind) && h->prof_stride > 1 && (h->prof_seq[kind]++ % h->prof_stride) != 0) {
+        h->prof_skip |= 1 << kind;
+        return LF_OK;
+    }
+    h->prof_skip &= ~(1 << kind);
     if (h->evused >= 4096) LF_TRY(lf_prof_flush(h));
     size_t need = 2 * (size_t)(h->evused + 1);
     while (h->evpool->size() < need) {
@@ -119,6 +127,10 @@ int lf_prof_begin_on(lf_handle *h, int kind, hipStream_t st)
 int lf_prof_end_on(lf_handle *h, int kind, int launches, hipStream_t st)
 {
     if (!prof_on(h, kind)) return LF_OK;
+    if ((h->prof_skip >> kind) & 1) {
+        h->prof_skip &= ~(1 << kind);
+        return LF_OK;
+    }
     LF_HIP(h, hipEventRecord((*h->evpool)[2 * h->evused + 1], st));
     if ((int)h->evkind->size() <= h->evused) {
         h->evkind->push_back(kind);

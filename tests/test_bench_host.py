@@ -83,32 +83,100 @@ def test_committed_traffic_file_is_well_formed():
 
 
 def paths(**w):
-    z = {"nodes": 0, "neighbours": 0, "visits": 0, "candidates": 0}
+    z = {"nodes": 0, "neighbours": 0, "visits": 0, "candidates": 0, "own": 0}
     return {p: dict(z, **w.get(p, {})) for p in ("small", "medium", "group", "table")}
 
 
+APPLY0 = {"moves": 0, "own_slots": 0, "in_items": 0, "in_neighbours": 0, "in_slots": 0, "parts": 0,
+          "touched": 0, "members": 0, "member_slots": 0}
+
+
+def work_of(p, node_evals=0, **apply):
+    return {"paths": p, "node_evals": node_evals, "apply": dict(APPLY0, **apply)}
+
+
 def test_kernel_byte_model():
-    p = paths(small={"nodes": 1, "neighbours": 2, "visits": 3, "candidates": 4},
+    """Per-unit bytes of the evaluation: node 16 + 24 and 8 per own membership, neighbour
+    4 + 4 + 16, visit 8, candidate 44."""
+    p = paths(small={"nodes": 1, "neighbours": 2, "visits": 3, "candidates": 4, "own": 2},
               medium={"nodes": 10}, group={"candidates": 1},
-              table={"nodes": 1, "neighbours": 1, "visits": 1, "candidates": 100})
-    assert bench.kernel_bytes("k_eval", p) == 60 + 2 * 20 + 3 * 12 + 4 * 44
+              table={"nodes": 1, "neighbours": 1, "visits": 1, "candidates": 100, "own": 3})
+    w = work_of(p)
+    assert bench.kernel_bytes("k_eval", w) == 40 + 2 * 8 + 2 * 24 + 3 * 8 + 4 * 44
     # the table path's candidates are scored in k_big_final, not in k_eval_big
-    assert bench.kernel_bytes("k_eval_big", p) == 10 * 60 + 44 + 60 + 20 + 12
-    assert bench.kernel_bytes("k_big_final", p) == 100 * 44
-    assert bench.kernel_bytes("k_refresh", p) is None
+    assert bench.kernel_bytes("k_eval_big", w) == 10 * 40 + 44 + 40 + 3 * 8 + 24 + 8
+    assert bench.kernel_bytes("k_big_final", w) == 100 * 44
+    assert bench.kernel_bytes("k_big_tie", w) is None
+
+
+def test_apply_byte_model():
+    w = work_of(paths(), node_evals=100, moves=10, own_slots=20, in_items=30, in_neighbours=40, in_slots=50,
+                parts=6, touched=5, members=70, member_slots=80)
+    assert bench.kernel_bytes("k_apply_edit", w) == 100 * 24 + 10 * 56 + 20 * 8 + 30 * 40
+    assert bench.kernel_bytes("k_apply_in", w) == 30 * 40 + 40 * 28 + 50 * 8 + 5 * 24 + 6 * 40
+    assert bench.kernel_bytes("k_refresh", w) == 6 * 40 + 70 * 20 + 80 * 8 + 5 * 64
 
 
 def test_kernel_rooflines_divide_bytes_by_event_time():
     p = paths(small={"nodes": 1_000_000}, medium={"neighbours": 1_000_000}, table={"candidates": 1_000_000})
-    timing = {"ms": {"k_eval": 0.06, "k_eval_big": 0.02, "k_big_final": 0.044, "k_big_tie": 0.0},
-              "launches": {"k_eval": 1, "k_eval_big": 1, "k_big_final": 1}}
-    r = bench.kernel_rooflines(timing, p)
-    for k in ("k_eval", "k_eval_big", "k_big_final"):
-        assert abs(r[k]["GB_s"] - 1000.0) < 1e-9
+    w = work_of(p, node_evals=1_000_000)
+    timing = {"ms": {"k_eval": 0.04, "k_eval_big": 0.024, "k_big_final": 0.044, "k_big_tie": 0.0,
+                     "k_apply_edit": 0.024},
+              "launches": {"k_eval": 1, "k_eval_big": 1, "k_big_final": 1, "k_apply_edit": 1}}
+    r = bench.kernel_rooflines(timing, w)
+    for k in ("k_eval", "k_eval_big", "k_big_final", "k_apply_edit"):
+        assert abs(r[k]["GB_s"] - 1000.0) < 1e-9, k
         assert abs(r[k]["frac"] - 1000.0 / bench.HBM_PEAK_GBS) < 1e-12
     assert abs(r["evaluation"]["GB_s"] - 1000.0) < 1e-9
-    timing["ms"]["k_big_tie"] = 0.124
-    assert abs(bench.kernel_rooflines(timing, p)["evaluation"]["GB_s"] - 500.0) < 1e-9
+    assert abs(r["apply"]["GB_s"] - 1000.0) < 1e-9
+    timing["ms"]["k_big_tie"] = 0.108
+    assert abs(bench.kernel_rooflines(timing, w)["evaluation"]["GB_s"] - 500.0) < 1e-9
+
+
+def test_triangle_byte_models_on_a_small_graph():
+    """B_min and the probe count P = sum over oriented edges u->v of |N+(v)| on a graph
+    whose orientation is known: the path 0-1-2 plus the triangle 2-3-4."""
+    import numpy as np
+
+    class FakeHandle:
+        def csr(self):
+            adj = {0: [1], 1: [0, 2], 2: [1, 3, 4], 3: [2, 4], 4: [2, 3]}
+            rp = np.zeros(6, np.int64)
+            rp[1:] = np.cumsum([len(adj[i]) for i in range(5)])
+            return rp, np.concatenate([adj[i] for i in range(5)]).astype(np.int32)
+    r = bench.triangle_roofline(FakeHandle(), 1.0)
+    # (degree, id) order: 0 (d1), 1 (d2), 3 (d2), 4 (d2), 2 (d3); each edge points to its
+    # later end: 0->1, 1->2, 3->2, 4->2, 3->4; out-degrees 0:1, 1:1, 2:0, 3:2, 4:1 and
+    # in-degrees 0:0, 1:1, 2:3, 3:0, 4:1, so P = 1*1 (node 1) + 3*0 (node 2) + 1*1 (node 4) = 2
+    assert r["probes"] == 2
+    assert r["B_min"] == 8 * 6 + 8 * 5 + 8 * 5
+    assert r["B_probe"] == 8 * 6 + 4 * 5 + 4 * 2 + 8 * 5 + 8 * 5
+
+
+def test_oracle_result_check(tmp_path, monkeypatch):
+    """A run equal to the stored oracle result passes; any difference exits with an error."""
+    import hashlib
+    import json
+    import numpy as np
+    off = np.array([0, 1, 3], np.int64)
+    ids = np.array([4, 1, 2], np.int32)
+    hs = hashlib.sha256(off.tobytes() + ids.tobytes()).hexdigest()
+    gd = {"memberships_sha256": hs, "iterations": 2, "wtilde_hist": [(1.5).hex(), (2.0).hex(), (2.25).hex()],
+          "threshold": 0.01, "_file": "x.json"}
+    info = {"iterations": 2, "wtilde_hist": np.array([1.5, 2.0, 2.25])}
+    assert bench.check_against_oracle(gd, info, off, ids, "t")["equal"] is True
+    assert bench.check_against_oracle(None, info, off, ids, "t") == {"stored_oracle": None}
+    with pytest.raises(SystemExit):
+        bench.check_against_oracle(gd, dict(info, iterations=3), off, ids, "t")
+    with pytest.raises(SystemExit):
+        bench.check_against_oracle(gd, info, off, np.array([4, 1, 3], np.int32), "t")
+    os.makedirs(tmp_path / "tests" / "golden")
+    with open(tmp_path / "tests" / "golden" / "w_q8_seed0.json", "w") as f:
+        json.dump(dict(gd, threshold=0.01), f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.stored_oracle("w", 8, 0, 0.01)["memberships_sha256"] == hs
+    assert bench.stored_oracle("w", 8, 0, 0.02) is None
+    assert bench.stored_oracle("w", 16, 0, 0.01) is None
 
 
 def test_copy_rate_counts_read_and_written_bytes():
