@@ -84,16 +84,18 @@ def parse():
 # score 8, one exact sum 24).
 B_NODE, B_OWN, B_NEIGHBOUR, B_VISIT, B_CAND = 40.0, 8.0, 24.0, 8.0, 44.0
 # Apply (bulk apply of Algorithm 2), bytes per unit of the apply work counters:
-#   every queued node 24 (decision 12, order entry 4, join mark 8); every moved node 56
-#   (row offset 8, record 16, slot write 8, count 4, two sizes 8, two touched flags 8,
-#   member-list entry 4) + 8 per own membership scanned; every in-count work item 40
-#   written by the edits and 40 read; every neighbour of a moved node 28 (column 4,
-#   record 16, join mark 8) + 8 per membership of it scanned; every re-sum part 40
-#   written and 40 read; every touched community 24 to plan (list entry 4, member-list
-#   range 16, size 4) + 64 rewritten (its record); every member re-summed 20 (list entry
-#   4, record 16) + 8 per membership of it scanned.
-A_QNODE, A_MOVE, A_OWN, A_ITEM, A_NEIGH, A_SLOT, A_PART, A_PLAN, A_REC, A_MEMBER = (
-    24.0, 56.0, 8.0, 40.0, 28.0, 8.0, 40.0, 24.0, 64.0, 20.0)
+#   k_apply: every queued node 24 (decision 12, order entry 4, join position 4, line
+#   placement 4); every moved node 52 (record 16, slot word 4, count 4, two sizes 8,
+#   two touched flags 8, member-list entry 4, two member-list ranges 8) + 8 per own
+#   membership scanned; every in-count unit of a moved node 24 (its record); every
+#   neighbour in those units 36 (column 4, line header 16, order position 4, its decision
+#   when queued ~12) + 8 per membership of it scanned; every touched community 24 to plan
+#   (member-list range 16, part record 8) + 40 per part written.
+#   k_refresh: every part 40 read + 16 (size, list length, overflow flag); every member
+#   re-summed 20 (list entry 4, line header 16) + 8 per membership of it scanned; every
+#   touched community 64 rewritten (its record).
+A_QNODE, A_MOVE, A_OWN, A_UNIT, A_NEIGH, A_SLOT, A_PART, A_PLAN, A_REC, A_MEMBER, A_PSTAT = (
+    24.0, 52.0, 8.0, 24.0, 36.0, 8.0, 40.0, 24.0, 64.0, 20.0, 16.0)
 
 
 def path_bytes(w, with_candidates=True):
@@ -105,13 +107,12 @@ def path_bytes(w, with_candidates=True):
 def apply_bytes(kernel, work):
     """Algorithmic bytes one pass moves through an apply kernel (work = the profile)."""
     a = work["apply"]
-    if kernel == "k_apply_edit":
-        return A_QNODE * work["node_evals"] + A_MOVE * a["moves"] + A_OWN * a["own_slots"] + A_ITEM * a["in_items"]
-    if kernel == "k_apply_in":
-        return (A_ITEM * a["in_items"] + A_NEIGH * a["in_neighbours"] + A_SLOT * a["in_slots"]
+    if kernel == "k_apply":
+        return (A_QNODE * work["node_evals"] + A_MOVE * a["moves"] + A_OWN * a["own_slots"]
+                + A_UNIT * a["in_units"] + A_NEIGH * a["in_neighbours"] + A_SLOT * a["in_slots"]
                 + A_PLAN * a["touched"] + A_PART * a["parts"])
     if kernel == "k_refresh":
-        return (A_PART * a["parts"] + A_MEMBER * a["members"] + A_SLOT * a["member_slots"]
+        return ((A_PART + A_PSTAT) * a["parts"] + A_MEMBER * a["members"] + A_SLOT * a["member_slots"]
                 + A_REC * a["touched"])
     return None
 
@@ -131,7 +132,7 @@ def kernel_bytes(kernel, work):
 
 
 EVAL_KERNELS = ("k_eval", "k_eval_big", "k_big_final", "k_big_tie")
-APPLY_KERNELS = ("k_apply_edit", "k_apply_in", "k_refresh")
+APPLY_KERNELS = ("k_apply", "k_refresh")
 
 
 def eval_rates(timing, work):

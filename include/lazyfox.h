@@ -75,8 +75,11 @@ typedef struct {
                                medium wave path (<= 256), small path of smaller queues */
 #define LF_K_TAB_FINAL 6    /* k_big_final: table path, candidate changes and maxima */
 #define LF_K_TAB_TIE 7      /* k_big_tie: table path, lowest id among equal maxima */
-#define LF_K_APPLY_EDIT 8   /* k_apply_edit: membership edits, sizes, member lists */
-#define LF_K_APPLY_IN 9     /* k_apply_in: neighbours' in-counts and re-sum planning */
+#define LF_K_APPLY_EDIT 8   /* k_apply: the bulk apply of a queue: membership edits, sizes,
+                               member lists and re-sum planning beside the in-count changes
+                               around the moved nodes */
+#define LF_K_APPLY_IN 9     /* no longer launched (its work is part of k_apply); kept so
+                               that the class indices stay the same */
 #define LF_K_REFRESH 10     /* k_refresh: exact re-sums of the touched communities */
 #define LF_K_ITEREND 11     /* iteration end: degenerate removal, compaction, score */
 #define LF_K_COUNT 12
@@ -88,9 +91,10 @@ typedef struct {
 #define LF_PATH_TABLE 3
 #define LF_PATH_COUNT 4
 /* apply-step work counters (bit 1 << LF_PROF_COUNTERS_BIT), per step of Algorithm 2's
-   bulk apply: nodes that moved, own memberships the edits scanned, in-count work items,
-   neighbours of moved nodes visited, their memberships scanned, re-sum parts, touched
-   communities re-summed, members re-summed, and the memberships those members scanned */
+   bulk apply: nodes that moved, own memberships the edits scanned, in-count units of
+   moved nodes, neighbours in those units, their memberships scanned, re-sum parts,
+   touched communities re-summed, members re-summed, and the memberships those members
+   scanned */
 #define LF_APPLY_MOVES 0
 #define LF_APPLY_OWN_SLOTS 1
 #define LF_APPLY_IN_ITEMS 2
@@ -405,7 +409,7 @@ int lf_batch_member_info(lf_batch *b, int32_t member_id, lf_run_info *out);
 int lf_batch_remove(lf_batch *b, int32_t member_id);
 int lf_batch_destroy(lf_batch *b);
 const char *lf_batch_last_error(lf_batch *b);
-/* on != 0 (the default): each step replays a graph of the seven per-step launches,
+/* on != 0 (the default): each step replays a graph of the per-step launches,
    captured once, with the step's grids and member count set on its kernel nodes;
    on = 0: the launches are issued one by one.  Results are the same either way. */
 int lf_batch_set_graph(lf_batch *b, int32_t on);
@@ -439,7 +443,9 @@ int lf_server_destroy(lf_server *s);
 const char *lf_server_last_error(lf_server *s);
 /* Host milliseconds spent so far in ms[0..4]: admission (graph load and initial
    clustering, on a stream of its own), batch steps, retirement (results copied back),
-   freeing device memory of retired jobs (done for many at once), whole ticks. */
+   freeing device memory of retired jobs (done for many at once), whole ticks; ms[5] the
+   part of the batch steps spent waiting for the device; ms[6] the batch steps that
+   launched work and ms[7] the queues they ran (counts).  ms holds 8 values. */
 int lf_server_timing(lf_server *s, double *ms);
 /* Graph replay of the server's batch steps (lf_batch_set_graph); on by default. */
 int lf_server_set_graph(lf_server *s, int32_t on);

@@ -16,10 +16,10 @@ LF_DEVICE_PTR = 2
 OPTIONS = {"tri_lds_cap": 1, "hub_blocks": 3, "refresh_blocks": 4, "wave_table": 5, "med_table": 6,
            "grp_table": 7, "prof_stride": 8}
 KERNEL_CLASSES = ["build", "triangles", "order", "init_clustering", "k_eval", "k_eval_big", "k_big_final",
-                  "k_big_tie", "k_apply_edit", "k_apply_in", "k_refresh", "iteration_end"]
+                  "k_big_tie", "k_apply", "k_apply_in", "k_refresh", "iteration_end"]
 PROF_COUNTERS_BIT = 16
 PATHS = ["small", "medium", "group", "table"]
-APPLY_WORK = ["moves", "own_slots", "in_items", "in_neighbours", "in_slots", "parts", "touched", "members",
+APPLY_WORK = ["moves", "own_slots", "in_units", "in_neighbours", "in_slots", "parts", "touched", "members",
               "member_slots"]
 
 
@@ -657,9 +657,10 @@ class Server:
     stats = lf_server_stats
 
     def lf_server_timing(self):
-        ms = (C.c_double * 5)()
+        ms = (C.c_double * 8)()
         self._check(self.L.lf_server_timing(self.s, ms), "lf_server_timing")
-        return dict(zip(("admit_ms", "step_ms", "retire_ms", "free_ms", "tick_ms"), list(ms)))
+        return dict(zip(("admit_ms", "step_ms", "retire_ms", "free_ms", "tick_ms", "step_wait_ms", "steps",
+                         "member_steps"), list(ms)))
 
     timing = lf_server_timing
 

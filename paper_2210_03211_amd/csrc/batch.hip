@@ -57,6 +57,8 @@ struct lf_batch {
     hipGraphNode_t node[LF_MULTI_KERNELS];
     int graph_cap;                           // cap the graph was captured for
     long long graph_steps;
+    long long steps, member_steps;           // steps that launched, queues they ran
+    double wait_ms;                          // host time waiting for the device in steps
     char err[512];
 };
 
@@ -224,6 +226,9 @@ int lf_batch_create(lf_batch **out, int device, void *hip_stream)
     b->exec = nullptr;
     b->graph_cap = 0;
     b->graph_steps = 0;
+    b->steps = 0;
+    b->member_steps = 0;
+    b->wait_ms = 0.0;
     b->err[0] = 0;
     for (int s = 0; s < 2; s++) {
         b->hmem[s] = nullptr;
@@ -342,24 +347,30 @@ int lf_batch_step(lf_batch *b, int32_t *running)
     }
     if (act.empty() && waiting) {
         // nothing to launch: wait for the oldest queued start or end instead of spinning
+        auto t0 = std::chrono::steady_clock::now();
         if (hipEventSynchronize(waiting->ev) != hipSuccess) return batch_error(b, LF_EDEVICE, "event sync failed");
+        b->wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     const int nm = (int)act.size();
     if (nm > 0) {
         LF_TRY(batch_reserve(b, nm));
         const int s = b->slot;
         b->slot ^= 1;
+        auto t0 = std::chrono::steady_clock::now();
         if (hipEventSynchronize(b->hev[s]) != hipSuccess) return batch_error(b, LF_EDEVICE, "event sync failed");
+        b->wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        b->steps++;
+        b->member_steps += nm;
         Member *hm = b->hmem[s];
         int *hb = b->hboff[s];
-        int total[LF_MULTI_GRIDS] = {0, 0, 0, 0, 0};
+        int total[LF_MULTI_GRIDS] = {0, 0, 0, 0};
         for (int i = 0; i < nm; i++) {
             BatchMember *m = act[i];
             QGrids g;
             lf_queue_params(m->h, m->k, m->nq, m->qq, true, &hm[i].qs, &g);
             m->cx.qtag = m->h->qtag++;
             hm[i].cx = m->cx;
-            const int blocks[LF_MULTI_GRIDS] = {g.big, g.fin, g.apply_edit, g.apply_in, g.refresh};
+            const int blocks[LF_MULTI_GRIDS] = {g.big, g.fin, g.apply, g.refresh};
             for (int t = 0; t < LF_MULTI_GRIDS; t++) {
                 hb[t * (b->cap + 1) + i] = total[t];
                 total[t] += blocks[t];
@@ -709,11 +720,15 @@ int lf_server_set_graph(lf_server *s, int32_t on)
 }
 
 // host milliseconds spent so far in: admission (load + initial clustering), batch steps,
-// retirement (results copied back), freeing device memory, whole ticks
+// retirement (results copied back), freeing device memory, whole ticks; the part of the
+// steps spent waiting for the device; steps that launched and the queues they ran
 int lf_server_timing(lf_server *s, double *ms)
 {
     if (!s || !ms) return LF_EINVAL;
     for (int k = 0; k < 5; k++) ms[k] = s->ms[k];
+    ms[5] = s->batch->wait_ms;
+    ms[6] = (double)s->batch->steps;
+    ms[7] = (double)s->batch->member_steps;
     return LF_OK;
 }
 

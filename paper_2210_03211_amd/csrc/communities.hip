@@ -439,7 +439,6 @@ Ctx lf_ctx(lf_handle *h)
     c.cm_node = h->cm_node;
     c.tflag = h->tflag;
     c.tlist = h->tlist;
-    c.joined_to = h->joined_to;
     c.ovf_node = h->ovf_node;
     c.ovf_comm = h->ovf_comm;
     c.ovf_flag = h->ovf_flag;
@@ -447,6 +446,7 @@ Ctx lf_ctx(lf_handle *h)
     c.dl = h->dl;
     c.djd = h->djd;
     c.dld = h->dld;
+    c.dpos = h->dpos;
     c.ctr = h->ctr;
     c.big_idx = h->big_idx;
     for (int k = 0; k < LF_PATH_COUNT; k++) {
@@ -465,8 +465,7 @@ Ctx lf_ctx(lf_handle *h)
     c.occ_key = h->occ_key;
     c.occ_d = h->occ_d;
     c.gmask = h->gT > 0 ? h->gT - 1 : 0;
-    c.in_item = h->in_item;
-    c.in_cap = (int)h->in_cap;
+    c.unit = h->unit;
     c.part_rec = h->part_rec;
     c.part_done = h->part_done;
     c.macc = h->macc;
@@ -480,7 +479,7 @@ void lf_free_partition(lf_handle *h)
 {
     void **ptrs[] = {(void **)&h->nh, (void **)&h->slot[0], (void **)&h->slot[1], (void **)&h->lines, (void **)&h->cr,
                      (void **)&h->cm_off, (void **)&h->cm_len, (void **)&h->cm_node, (void **)&h->tflag,
-                     (void **)&h->tlist, (void **)&h->joined_to, (void **)&h->ovf_node,
+                     (void **)&h->tlist, (void **)&h->ovf_node,
                      (void **)&h->ovf_comm, (void **)&h->ovf_flag, (void **)&h->ctr,
                      (void **)&h->part_done, (void **)&h->vbound,
                      (void **)&h->cls, (void **)&h->cscan, (void **)&h->plist[0], (void **)&h->plist[1],
@@ -693,13 +692,11 @@ static int alloc_partition_state(lf_handle *h, long long K, long long slots)
     LF_TRY(lf_dev_alloc(h, (void **)&h->prec_all, sizeof(NodeRec) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->pbase, sizeof(long long) * (LF_PATH_COUNT + 1)));
     for (int k = 0; k < LF_PATH_COUNT; k++) h->prec[k] = h->prec_all;
-    LF_TRY(lf_dev_alloc(h, (void **)&h->joined_to, sizeof(unsigned long long) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->ovf_node, sizeof(int) * nn));
     LF_TRY(lf_dev_alloc(h, (void **)&h->ovf_comm, sizeof(int) * nn));
     LF_HIP(h, hipMemsetAsync(h->cr, 0, sizeof(CommRec) * KK, st));
     LF_HIP(h, hipMemsetAsync(h->tflag, 0, sizeof(int) * KK, st));
     LF_HIP(h, hipMemsetAsync(h->ovf_flag, 0, sizeof(int) * KK, st));
-    LF_HIP(h, hipMemsetAsync(h->joined_to, 0xff, sizeof(unsigned long long) * nn, st));
     h->qtag = 0;
     return LF_OK;
 }

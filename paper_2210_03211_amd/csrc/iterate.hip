@@ -18,9 +18,9 @@
 //   k_big_final      every occupied table entry -> change of C's score; per node the
 //                    largest positive change (atomicMax on the bits of a positive double)
 //   k_big_tie        among the entries equal to that maximum the lowest community id
-//   k_apply_edit     membership edits, sizes, member-list appends, touched list
-//   k_apply_in       in-counts of the neighbours of moved nodes (neighbour blocks); its
-//                    first blocks split every touched community's member list into parts
+//   k_apply          the bulk apply: membership edits, sizes, member-list appends and
+//                    re-sum planning (a thread per queued node) beside the in-count
+//                    changes around the moved nodes (a wave per in-count unit)
 //   k_refresh        exact re-sum per part; multi-part communities combine their parts
 //                    through carry-save counters and the last part finalises
 // k_queue_reset clears the queue counters at the start and the end of an iteration.
@@ -32,7 +32,8 @@
 #define EW 4            // waves per block in the wave evaluation path
 #define ECAP 128        // table entries per wave (power of two)
 #define MXCAP 32        // own memberships kept in LDS (wave path)
-#define INB 64          // neighbours per in-count work item (one per lane)
+#define INB 64          // neighbours per in-count unit (one per lane)
+#define HOLE (-2)       // a membership left in the current iteration (removed at its end)
 #define PART 128        // members per re-sum part
 #define MACC 19         // carry-save counters per multi-part community (3 x 6 digits + in-sum)
 #define GEMPTY (~0ull)
@@ -44,9 +45,7 @@ __global__ void k_queue_reset(Ctx cx)
 {
     if (threadIdx.x == 0) {
         DevCounters *c = cx.ctr;
-        c->tcount = 0;
         c->occ_cnt = 0;
-        c->in_items = 0;
         c->parts_total = 0;
         c->mslots = 0;
     }
@@ -279,10 +278,11 @@ __device__ __forceinline__ bool eval_node(const Ctx &cx, int j, const NodeRec nr
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         // lanes of a wave that share the first pending community (a node's own
-        // communities often hold most of its neighbours) insert and count it once
+        // communities often hold most of its neighbours) insert and count it once; a
+        // membership its neighbour left earlier in this iteration is no visit
         const int v = b * NT + tid;
         const int C = sv[b].comm;
-        bool pend = v < V;
+        bool pend = v < V && C >= 0;
         int h = -1;
         for (int att = 0; att < 2; att++) {
             const unsigned long long pm = __ballot(pend);
@@ -308,7 +308,7 @@ __device__ __forceinline__ bool eval_node(const Ctx &cx, int j, const NodeRec nr
             atomicAdd(&L.kk[h], 1);
         }
         if (v < V) {
-            L.vhash[v] = h;
+            L.vhash[v] = h;                 // -1 for a left membership
             L.vin[v] = sv[b].in;
         }
     }
@@ -360,7 +360,7 @@ __device__ __forceinline__ bool eval_node(const Ctx &cx, int j, const NodeRec nr
     int bad = 0;
     for (int v0 = 0; v0 < V; v0 += NT) {    // same trip count on every lane of a wave
         const int v = v0 + tid;
-        const bool act = v < V;
+        const bool act = v < V && L.vhash[v] >= 0;
         int c = 0;
         i64 t0 = 0, t1 = 0, t2 = 0, t3 = 0;
         if (act) {
@@ -446,6 +446,7 @@ __device__ __forceinline__ bool eval_node(const Ctx &cx, int j, const NodeRec nr
         cx.djd[j] = bj >= 0 ? bjd : 0.0;
         cx.dl[j] = bl;
         cx.dld[j] = bl >= 0 ? bld : 0.0;
+        cx.dpos[j] = mcnt;
         cx.big_idx[j] = Q_DONE;
         if (cx.stats) {
             unsigned long long *w = cx.ctr->work[path];
@@ -467,6 +468,7 @@ __device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg, int ow
         atomicAdd(&cx.ctr->work[LF_PATH_TABLE][4], (unsigned long long)own);
     }
     cx.big_idx[j] = Q_TABLE;
+    cx.dpos[j] = own;
     cx.big_bj[j] = 0;
     cx.big_bl[j] = 0;
     cx.big_cj[j] = 0x7fffffff;
@@ -491,8 +493,6 @@ __device__ __forceinline__ void body_eval(const Ctx &cx, const QStep &qs, int bl
     const int p = blk * EW + wv;
     if (blk == 0 && threadIdx.x == 0) {
         DevCounters *c = cx.ctr;
-        c->tcount = 0;
-        c->in_items = 0;
         c->parts_total = 0;
         c->mslots = 0;
     }
@@ -660,8 +660,10 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
                 Slot sl = ((const Slot *)s_sbase[wv][lo])[v - s_start[wv][lo]];
                 C = sl.comm;
                 iv = sl.in;
-                hh = gfind(cx, j, C, claimed);
-                if (hh < 0) capfail = 1;
+                if (C >= 0) {                   // not a membership left in this iteration
+                    hh = gfind(cx, j, C, claimed);
+                    if (hh < 0) capfail = 1;
+                }
             }
             if (act) cx.occ[obase + v] = claimed ? (int)hh : -1;
             const bool vis = act && hh >= 0 && !ownv;
@@ -744,8 +746,6 @@ __device__ __forceinline__ void body_eval_big(const Ctx &cx, const QStep &qs, in
     const int cstart = qs.cstart;
     if (blk == 0 && threadIdx.x == 0) {     // the queue's apply counters (no role uses them)
         DevCounters *c = cx.ctr;
-        c->tcount = 0;
-        c->in_items = 0;
         c->parts_total = 0;
         c->mslots = 0;
     }
@@ -893,275 +893,53 @@ QUEUE_KERNELS(k_big_tie, 256, NoLds, body_big_tie)
 // bulk apply
 // ------------------------------------------------------------------------------------
 
-// community x joined in the current queue, -1 if none (entries of earlier queues are stale)
-__device__ __forceinline__ int joined_in_queue(const Ctx &cx, int x)
+// A queue's decisions are applied by one launch: the membership edits (one thread per
+// queued node) and the in-count changes around the moved nodes (one wave per in-count
+// unit of the queue) run side by side.  Slot positions stay put within an iteration: a
+// leave turns its slot's community into HOLE, a join writes its community into the
+// node's free slot (position dpos, in-count 0 from the iteration start).  So the in-count
+// updates can target slots while the edits run, and they take each neighbour's
+// membership after the queue from the neighbour's own decision rather than from its
+// slots: the result is a from-scratch recount of every in-count on the new partition.
+
+// decision of the node at queue position j: community joined J and left L (-1: none)
+__device__ __forceinline__ void queue_decision(const Ctx &cx, int j, int &J, int &L, unsigned long long *bjp,
+                                               unsigned long long *blp)
 {
-    unsigned long long v = cx.joined_to[x];
-    return (unsigned)(v >> 32) == cx.qtag ? (int)(unsigned)v : -1;
+    const int bi = cx.big_idx[j];
+    const int dj = cx.dj[j], dl = cx.dl[j];
+    const unsigned long long bj = cx.big_bj[j], bl = cx.big_bl[j];
+    const int cj = cx.big_cj[j], cl = cx.big_cl[j];
+    if (bi == Q_TABLE) {
+        J = bj ? cj : -1;
+        L = bl ? cl : -1;
+    } else {
+        J = dj;
+        L = dl;
+    }
+    if (bjp) *bjp = bi == Q_TABLE ? bj : 0;
+    if (blp) *blp = bi == Q_TABLE ? bl : 0;
 }
 
-// Block-wide reservation of a and b slots of two shared counters for each thread (one
-// returning atomic per counter and block: such atomics on one address serialise).  Every
-// thread of the block must call it; *pa / *pb get the thread's first slot.
-__device__ __forceinline__ void block_reserve2(int a, int b, int *ctr_a, int *ctr_b, int *pa, int *pb)
+// Re-sum parts of community C at its first touch in the queue, planned from its
+// member-list capacity (fixed within an iteration).  Every lane of the wave calls this
+// (want = false: it only takes part in the wave's reservation).
+__device__ __forceinline__ void plan_parts(const Ctx &cx, bool want, int C, long long base, long long cap)
 {
-    __shared__ int s_a[256 / WAVE], s_b[256 / WAVE], s_base[2];
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    int ia = a, ib = b;                       // inclusive scans within the wave
-    for (int o = 1; o < WAVE; o <<= 1) {
-        int ta = __shfl_up(ia, o, WAVE), tb = __shfl_up(ib, o, WAVE);
-        if (lane >= o) { ia += ta; ib += tb; }
-    }
-    if (lane == WAVE - 1) { s_a[wv] = ia; s_b[wv] = ib; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ta = 0, tb = 0;
-        for (int w = 0; w < nw; w++) { ta += s_a[w]; tb += s_b[w]; }
-        s_base[0] = ta > 0 ? atomicAdd(ctr_a, ta) : 0;
-        s_base[1] = tb > 0 ? atomicAdd(ctr_b, tb) : 0;
-    }
-    __syncthreads();
-    int oa = s_base[0] + ia - a, ob = s_base[1] + ib - b;
-    for (int w = 0; w < wv; w++) { oa += s_a[w]; ob += s_b[w]; }
-    *pa = oa;
-    *pb = ob;
-}
-
-__device__ __forceinline__ void body_apply_edit(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
-{
-    (void)nblk;
-    const int cstart = qs.cstart, clen = qs.clen;
-    int j = blk * blockDim.x + threadIdx.x;
-    int lane = threadIdx.x & (WAVE - 1);
-    if (j == 0) cx.ctr->occ_cnt = 0;        // the table path of this queue is done
-
-    bool inq = j < clen;
-    int J = -1, L = -1, x = -1;
-    if (inq) {
-        // every array a decision may sit in, read in one round trip (the table path's
-        // arrays hold stale values for the other nodes, which are then ignored)
-        const int bi = cx.big_idx[j];
-        const int dj = cx.dj[j], dl = cx.dl[j];
-        const unsigned long long bj = cx.big_bj[j], bl = cx.big_bl[j];
-        const int cj = cx.big_cj[j], cl = cx.big_cl[j];
-        x = cx.order[cstart + j];
-        if (bi == Q_TABLE) {
-            J = bj ? cj : -1;
-            L = bl ? cl : -1;
-            cx.dj[j] = J;
-            cx.dl[j] = L;
-            cx.djd[j] = __longlong_as_double((long long)bj);
-            cx.dld[j] = __longlong_as_double((long long)bl);
-        } else {
-            J = dj;
-            L = dl;
-        }
-        const unsigned long long tag = (unsigned long long)cx.qtag << 32;
-        cx.joined_to[x] = tag | 0xffffffffull;  // no join (yet) in this queue
-    }
-    unsigned long long ml = __ballot(L >= 0);
-    if (lane == 0 && ml) atomicAdd(&cx.ctr->leaves, (unsigned long long)__popcll(ml));
-    const bool act = inq && (J >= 0 || L >= 0);
-    bool firstL = false, firstJ = false, joined = false;
-    int blocks = 0, deg = 0, own_scanned = 0;
-    long long rb = 0, jslot = 0;
-    if (act) {
-        // the node's row offset, record and slot capacity, and J's member-list range,
-        // all in one round trip
-        rb = cx.rowptr[x];
-        const NodeLine hx = cx.ln[x];
-        const long long nxt = cx.nh[x + 1].off;      // capacity of a node in the slot array
-        long long cmo = 0, cme = 0;
-        if (J >= 0) {
-            cmo = cx.cm_off[J];
-            cme = cx.cm_off[J + 1];
-        }
-        int cnt = hx.cnt;
-        own_scanned = L >= 0 ? cnt : 0;
-        // size, touched-flag and member-list atomics of both communities, issued together
-        int oldL = 1, oldJ = 1, p = 0;
-        const long long capx = hx.off < 0 ? LINE_SLOTS : nxt - hx.off;
-        Slot *xs = hx.off < 0 ? cx.ln[x].s : cx.slot + hx.off;
-        const bool jfits = J >= 0 && cnt - (L >= 0 ? 1 : 0) < capx;
-        if (J >= 0 && !jfits) atomicOr(&cx.ctr->error, LF_DEVERR_SLOTS);
-        if (L >= 0) {
-            atomicSub(&cx.cr[L].s, 1);
-            oldL = atomicExch(&cx.tflag[L], 1);
-        }
-        if (jfits) {
-            atomicAdd(&cx.cr[J].s, 1);
-            p = atomicAdd(&cx.cm_len[J], 1);
-            oldJ = atomicExch(&cx.tflag[J], 1);
-        }
-        if (L >= 0) {
-            // the leave's slot takes the last one (read in the same round trip as the search)
-            const Slot last = xs[cnt - 1];
-            int tin = 0;
-            int t = line_find(cx, hx, L, &tin);
-            if (t != cnt - 1) xs[t] = last;
-            cnt--;
-            firstL = oldL == 0;               // first touch of L in this queue
-        }
-        if (jfits) {
-            Slot sn = {J, 0};
-            xs[cnt] = sn;
-            jslot = (long long)(xs + cnt);
-            cnt++;
-            cx.joined_to[x] = ((unsigned long long)cx.qtag << 32) | (unsigned)J;
-            joined = true;
-            if (p < cme - cmo) {
-                cx.cm_node[cmo + p] = x;
-            } else {
-                int e = atomicAdd(&cx.ctr->ovf_cnt, 1);
-                cx.ovf_node[e] = x;
-                cx.ovf_comm[e] = J;
-                cx.ovf_flag[J] = 1;
-            }
-            firstJ = oldJ == 0;
-        }
-        cx.ln[x].cnt = cnt;
-        deg = hx.deg;
-        blocks = (deg + INB - 1) / INB;
-    }
-    unsigned long long mj = __ballot(joined);
-    if (mj && lane == __ffsll((long long)mj) - 1) atomicAdd(&cx.ctr->joins, (unsigned long long)__popcll(mj));
-    if (cx.stats) {
-        const long long mv = wave_sum_i64(act ? 1 : 0), os = wave_sum_i64(act ? own_scanned : 0);
-        const long long it = wave_sum_i64(blocks);
-        if (lane == 0 && mv) {
-            atomicAdd(&cx.ctr->apply[LF_APPLY_MOVES], (unsigned long long)mv);
-            atomicAdd(&cx.ctr->apply[LF_APPLY_OWN_SLOTS], (unsigned long long)os);
-            atomicAdd(&cx.ctr->apply[LF_APPLY_IN_ITEMS], (unsigned long long)it);
-        }
-    }
-    // touched communities and in-count work items: one reservation per block
-    int tpos = 0, p0 = 0;
-    block_reserve2((int)firstL + (int)firstJ, blocks, &cx.ctr->tcount, &cx.ctr->in_items, &tpos, &p0);
-    if (firstL) cx.tlist[tpos++] = L;
-    if (firstJ) cx.tlist[tpos] = J;
-    if (blocks > 0) {
-        const bool fits = p0 + blocks <= cx.in_cap;
-        if (!fits) atomicOr(&cx.ctr->error, LF_DEVERR_CAP);   // the run fails with this error
-        InItem it;
-        it.rb = rb;
-        it.jslot = jslot;
-        it.x = fits ? x : -1;                 // over capacity: the slots that exist stay empty
-        it.J = fits && joined ? J : -1;
-        it.L = fits ? L : -1;
-        it.d = fits ? deg : 0;
-        it.pad = 0;
-        for (int k = 0; k < blocks && p0 + k < cx.in_cap; k++) {
-            it.k = k;
-            cx.in_item[p0 + k] = it;
-        }
-    }
-}
-QUEUE_KERNELS(k_apply_edit, 256, NoLds, body_apply_edit)
-
-// in-counts: a surviving member y of J (L) gains (loses) one per neighbour that joined
-// (left); a node that joined J in this queue gets its in-count counted afresh.  One wave
-// per block of INB neighbours of a moved node.
-__device__ void refresh_plan(const Ctx &cx, int t);
-
-// Blocks [0, plan_blocks) split the touched communities into re-sum parts (one thread
-// each); the other blocks apply the in-count changes.  Both only need the edits.
-__device__ __forceinline__ void body_apply_in(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
-{
-    const int plan_blocks = qs.plan_blocks;
-    if (blk < plan_blocks) {
-        refresh_plan(cx, blk * blockDim.x + threadIdx.x);
-        return;
-    }
-    int lane = threadIdx.x & (WAVE - 1);
-    long long nw = (long long)(nblk - plan_blocks) * (blockDim.x / WAVE);
-    long long p = ((blk - plan_blocks) * (long long)blockDim.x + threadIdx.x) / WAVE;
-    // the wave's first item is read beside the count (the buffer holds in_cap records)
-    InItem first;
-    if (p < cx.in_cap) first = cx.in_item[p];
-    int count = __atomic_load_n(&cx.ctr->in_items, __ATOMIC_RELAXED);
-    if (count > cx.in_cap) count = cx.in_cap;
-    for (bool at_first = true; p < count; p += nw, at_first = false) {
-        const InItem it = at_first ? first : cx.in_item[p];
-        if (it.x < 0) continue;                    // only after a flagged overflow
-        const int J = it.J, L = it.L;
-        const int lo = it.k * INB, hi = lo + INB < it.d ? lo + INB : it.d;
-        int fresh = 0;
-        for (int e = lo + lane; e < hi; e += WAVE) {
-            int y = cx.col[it.rb + e];
-            const NodeLine hy = cx.ln[y];            // count and inline memberships in one gather
-            int jy = joined_in_queue(cx, y);
-            if (hy.off < 0) {
-#pragma unroll
-                for (int u = 0; u < LINE_SLOTS; u++) {
-                    const int c = u < hy.cnt ? hy.s[u].comm : -2;
-                    if (c == J && J >= 0) {
-                        fresh++;
-                        if (jy != J) atomicAdd(&cx.ln[y].s[u].in, 1);
-                    } else if (c == L && L >= 0) {
-                        if (jy != L) atomicSub(&cx.ln[y].s[u].in, 1);
-                    }
-                }
-            } else {
-                Slot *ys = cx.slot + hy.off;
-                for (int t0 = 0; t0 < hy.cnt; t0 += 4) {   // four slot loads per round trip
-                    int cc[4];
-#pragma unroll
-                    for (int u = 0; u < 4; u++) cc[u] = t0 + u < hy.cnt ? ys[t0 + u].comm : -2;
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        const int c = cc[u];
-                        if (c == J && J >= 0) {
-                            fresh++;
-                            if (jy != J) atomicAdd(&ys[t0 + u].in, 1);
-                        } else if (c == L && L >= 0) {
-                            if (jy != L) atomicSub(&ys[t0 + u].in, 1);
-                        }
-                    }
-                }
-            }
-        }
-        fresh = wave_sum_int(fresh);
-        if (lane == 0 && J >= 0 && fresh) atomicAdd(&((Slot *)it.jslot)->in, fresh);
-        if (cx.stats) {
-            const long long nb = hi > lo ? hi - lo : 0;
-            long long sc = 0;
-            for (int e = lo + lane; e < hi; e += WAVE) sc += cx.ln[cx.col[it.rb + e]].cnt;
-            sc = wave_sum_i64(sc);
-            if (lane == 0) {
-                atomicAdd(&cx.ctr->apply[LF_APPLY_IN_NEIGHBOURS], (unsigned long long)nb);
-                atomicAdd(&cx.ctr->apply[LF_APPLY_IN_SLOTS], (unsigned long long)sc);
-            }
-        }
-    }
-}
-QUEUE_KERNELS(k_apply_in, 256, NoLds, body_apply_in)
-
-// ------------------------------------------------------------------------------------
-// exact re-sum of the touched communities
-// ------------------------------------------------------------------------------------
-__device__ void refresh_plan(const Ctx &cx, int t)
-{
-    int count = __atomic_load_n(&cx.ctr->tcount, __ATOMIC_RELAXED);
-    if (t >= count) return;
-    int C = cx.tlist[t];
-    PartRec pr;
-    pr.base = cx.cm_off[C];
-    long long cap = cx.cm_off[C + 1] - pr.base;
-    long long len = cx.cm_len[C];
-    if (len > cap) len = cap;
-    int parts = (int)((len + PART - 1) / PART);
+    int parts = (int)((cap + PART - 1) / PART);
     if (parts < 1) parts = 1;
+    int p0 = wave_reserve(&cx.ctr->parts_total, want && parts == 1);
+    if (!want) return;
+    if (parts > 1) p0 = atomicAdd(&cx.ctr->parts_total, parts);
+    PartRec pr;
+    pr.base = base;
     pr.C = C;
     pr.parts = parts;
-    pr.s = cx.cr[C].s;
-    pr.len = (int)len;
-    pr.ovf = cx.ovf_flag[C];
+    pr.cap = (int)cap;
     pr.ms = -1;
     pr.pad = 0;
-    int p0 = wave_reserve(&cx.ctr->parts_total, parts == 1);
-    if (parts > 1) p0 = atomicAdd(&cx.ctr->parts_total, parts);
     if (p0 + parts > cx.part_cap) {
-        atomicOr(&cx.ctr->error, LF_DEVERR_CAP);    // the run fails with this error
+        atomicOr(&cx.ctr->error, LF_DEVERR_CAP);     // the run fails with this error
         pr.C = -1;                                    // the records that exist stay empty
     } else if (parts > 1) {
         cx.part_done[C] = 0;
@@ -1179,6 +957,185 @@ __device__ void refresh_plan(const Ctx &cx, int t)
     }
 }
 
+// membership edits of queue position j (threads past the queue only take part in the
+// wave-wide counting and reservations)
+__device__ __forceinline__ void apply_edit(const Ctx &cx, const QStep &qs, int j)
+{
+    const int cstart = qs.cstart, clen = qs.clen;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (j == 0) cx.ctr->occ_cnt = 0;        // the table path of this queue is done
+    const bool inq = j < clen;
+    int J = -1, L = -1, x = -1;
+    if (inq) {
+        unsigned long long bj = 0, bl = 0;
+        queue_decision(cx, j, J, L, &bj, &bl);
+        x = cx.order[cstart + j];
+        if (bj || bl || cx.big_idx[j] == Q_TABLE) {
+            cx.dj[j] = J;
+            cx.dl[j] = L;
+            cx.djd[j] = __longlong_as_double((long long)bj);
+            cx.dld[j] = __longlong_as_double((long long)bl);
+        }
+    }
+    unsigned long long ml = __ballot(L >= 0);
+    if (lane == 0 && ml) atomicAdd(&cx.ctr->leaves, (unsigned long long)__popcll(ml));
+    const bool act = inq && (J >= 0 || L >= 0);
+    bool firstL = false, firstJ = false, joined = false;
+    long long cmoL = 0, cmeL = 0, cmoJ = 0, cmeJ = 0;
+    int own_scanned = 0;
+    if (act) {
+        // the node's line and slot capacity and both member-list ranges in one round trip
+        const NodeLine hx = cx.ln[x];
+        const long long nxt = cx.nh[x + 1].off;
+        if (L >= 0) {
+            cmoL = cx.cm_off[L];
+            cmeL = cx.cm_off[L + 1];
+        }
+        if (J >= 0) {
+            cmoJ = cx.cm_off[J];
+            cmeJ = cx.cm_off[J + 1];
+        }
+        // a node's slots change only in its own queue, so they hold no hole yet and its
+        // free slot is at cnt
+        const int cnt = hx.cnt;
+        const long long capx = hx.off < 0 ? LINE_SLOTS : nxt - hx.off;
+        Slot *xs = hx.off < 0 ? cx.ln[x].s : cx.slot + hx.off;
+        const bool jfits = J >= 0 && cnt < capx;
+        if (J >= 0 && !jfits) atomicOr(&cx.ctr->error, LF_DEVERR_SLOTS);
+        own_scanned = L >= 0 ? cnt : 0;
+        int oldL = 1, oldJ = 1, p = 0;
+        if (L >= 0) {
+            atomicSub(&cx.cr[L].s, 1);
+            oldL = atomicExch(&cx.tflag[L], 1);
+        }
+        if (jfits) {
+            atomicAdd(&cx.cr[J].s, 1);
+            p = atomicAdd(&cx.cm_len[J], 1);
+            oldJ = atomicExch(&cx.tflag[J], 1);
+        }
+        if (L >= 0) {
+            int tin = 0;
+            const int t = line_find(cx, hx, L, &tin);
+            if (t >= 0) xs[t].comm = HOLE;  // only the community word: in-counts are updated beside
+            firstL = oldL == 0;             // first touch of L in this queue
+        }
+        if (jfits) {
+            xs[cnt].comm = J;               // the free slot; its in-count is counted by the units
+            cx.ln[x].cnt = cnt + 1;
+            joined = true;
+            if (p < cmeJ - cmoJ) {
+                cx.cm_node[cmoJ + p] = x;
+            } else {
+                int e = atomicAdd(&cx.ctr->ovf_cnt, 1);
+                cx.ovf_node[e] = x;
+                cx.ovf_comm[e] = J;
+                cx.ovf_flag[J] = 1;
+            }
+            firstJ = oldJ == 0;
+        }
+    }
+    unsigned long long mj = __ballot(joined);
+    if (mj && lane == __ffsll((long long)mj) - 1) atomicAdd(&cx.ctr->joins, (unsigned long long)__popcll(mj));
+    if (cx.stats) {
+        const long long mv = wave_sum_i64(act ? 1 : 0), os = wave_sum_i64(own_scanned);
+        if (lane == 0 && mv) {
+            atomicAdd(&cx.ctr->apply[LF_APPLY_MOVES], (unsigned long long)mv);
+            atomicAdd(&cx.ctr->apply[LF_APPLY_OWN_SLOTS], (unsigned long long)os);
+        }
+    }
+    plan_parts(cx, firstL, L, cmoL, cmeL - cmoL);
+    plan_parts(cx, firstJ, J, cmoJ, cmeJ - cmoJ);
+}
+
+// in-count changes of the neighbours in unit u (one wave): a neighbour y that holds J
+// (L) from before this queue and keeps it gains (loses) one; the node's new J slot counts
+// its neighbours in J after the queue (those that keep J and those that join it)
+__device__ __forceinline__ void apply_unit(const Ctx &cx, const QStep &qs, long long u)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const UnitRec ur = cx.unit[u];
+    const int j = ur.r - qs.cstart;
+    // the unit's neighbours, the node's decision, join position and line placement
+    const int y = lane < ur.cnt ? cx.col[ur.rb + lane] : -1;
+    int J, L;
+    queue_decision(cx, j, J, L, nullptr, nullptr);
+    const int pos = cx.dpos[j];
+    const long long xoff = cx.ln[ur.x].off;
+    if (J < 0 && L < 0) return;             // uniform over the wave
+    NodeLine ly;
+    ly.cnt = 0;
+    ly.off = -1;
+    int Jy = -1, Ly = -1;
+    if (y >= 0) {
+        ly = cx.ln[y];
+        const int jy = cx.rank[y] - qs.cstart;
+        if (jy >= 0 && jy < qs.clen) queue_decision(cx, jy, Jy, Ly, nullptr, nullptr);
+    }
+    bool inJ = false;
+    if (y >= 0) {
+        if (ly.off < 0) {
+#pragma unroll
+            for (int t = 0; t < LINE_SLOTS; t++) {
+                const int c = t < ly.cnt ? ly.s[t].comm : -1;
+                if (J >= 0 && c == J) {
+                    inJ = true;
+                    if (Jy != J && Ly != J) atomicAdd(&cx.ln[y].s[t].in, 1);
+                } else if (L >= 0 && c == L) {
+                    if (Ly != L && Jy != L) atomicSub(&cx.ln[y].s[t].in, 1);
+                }
+            }
+        } else {
+            Slot *ys = cx.slot + ly.off;
+            for (int t0 = 0; t0 < ly.cnt; t0 += 4) {   // four slot loads per round trip
+                int cc[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) cc[q] = t0 + q < ly.cnt ? ys[t0 + q].comm : -1;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int c = cc[q];
+                    if (J >= 0 && c == J) {
+                        inJ = true;
+                        if (Jy != J && Ly != J) atomicAdd(&ys[t0 + q].in, 1);
+                    } else if (L >= 0 && c == L) {
+                        if (Ly != L && Jy != L) atomicSub(&ys[t0 + q].in, 1);
+                    }
+                }
+            }
+        }
+    }
+    int fresh = (J >= 0 && y >= 0 && (Jy == J || (inJ && Ly != J))) ? 1 : 0;
+    fresh = wave_sum_int(fresh);
+    if (lane == 0 && J >= 0 && fresh) {
+        Slot *xs = xoff < 0 ? cx.ln[ur.x].s : cx.slot + xoff;
+        if (xoff >= 0 || pos < LINE_SLOTS) atomicAdd(&xs[pos].in, fresh);
+    }
+    if (cx.stats) {
+        const long long sc = wave_sum_i64(y >= 0 ? ly.cnt : 0);
+        if (lane == 0) {
+            atomicAdd(&cx.ctr->apply[LF_APPLY_IN_ITEMS], 1ull);
+            atomicAdd(&cx.ctr->apply[LF_APPLY_IN_NEIGHBOURS], (unsigned long long)ur.cnt);
+            atomicAdd(&cx.ctr->apply[LF_APPLY_IN_SLOTS], (unsigned long long)sc);
+        }
+    }
+}
+
+// blocks [0, eb) edit (a thread per queued node), the rest take one in-count unit per wave
+__device__ __forceinline__ void body_apply(const Ctx &cx, const QStep &qs, int blk, int nblk, NoLds &)
+{
+    (void)nblk;
+    const int eb = (qs.clen + 255) / 256;
+    if (blk < eb) {
+        apply_edit(cx, qs, blk * 256 + threadIdx.x);
+        return;
+    }
+    const long long w = (long long)(blk - eb) * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (w < qs.un) apply_unit(cx, qs, qs.ub + w);
+}
+QUEUE_KERNELS(k_apply, 256, NoLds, body_apply)
+
+// ------------------------------------------------------------------------------------
+// exact re-sum of the touched communities
+// ------------------------------------------------------------------------------------
 __device__ __forceinline__ void x192_to_digits6(const X192 &v, long long *dg)
 {
     dg[0] = (long long)(v.w0 & 0xffffffffull);
@@ -1228,16 +1185,35 @@ __device__ __forceinline__ void body_refresh(const Ctx &cx, const QStep &qs, int
         const PartRec pr = at_first ? first : cx.part_rec[p];
         const int C = pr.C;
         if (C < 0 || C >= cx.K) continue;          // only after a flagged overflow
-        const int k = pr.k, parts = pr.parts;
-        const long long s = pr.s, base = pr.base, len = pr.len;
-        long long lo = (long long)k * PART, hi = lo + PART < len ? lo + PART : len;
+        const int k = pr.k;
+        const long long base = pr.base, cap = pr.cap;
+        // size, list length and overflow after the edits, read beside the part's entries
+        const long long s = cx.cr[C].s;
+        long long len = cx.cm_len[C];
+        const int ovf = cx.ovf_flag[C];
+        const long long lo = (long long)k * PART;
+        int mem[PART / WAVE];
+#pragma unroll
+        for (int i = 0; i < PART / WAVE; i++) {
+            const long long q = lo + i * WAVE + lane;
+            mem[i] = q < cap ? cx.cm_node[base + q] : -1;
+        }
+        if (len > cap) len = cap;
+        // the plan covers the list's capacity; the parts that hold members after the edits
+        // (the same count for every part of C: the length is final here) do the re-sum
+        int parts = (int)((len + PART - 1) / PART);
+        if (parts < 1) parts = 1;
+        if (k >= parts) continue;
+        const long long hi = lo + PART < len ? lo + PART : len;
         X192 a0 = x192_zero(), ap = x192_zero(), am = x192_zero();
         long long sumi = 0;
-        for (long long q = lo + lane; q < hi; q += WAVE)
-            member_terms_line(cx, cx.cm_node[base + q], C, s, a0, ap, am, sumi, bad);
+#pragma unroll
+        for (int i = 0; i < PART / WAVE; i++)
+            if (lo + i * WAVE + lane < hi) member_terms_line(cx, mem[i], C, s, a0, ap, am, sumi, bad);
         if (cx.stats) {
             long long mslots = 0;
-            for (long long q = lo + lane; q < hi; q += WAVE) mslots += cx.ln[cx.cm_node[base + q]].cnt;
+            for (int i = 0; i < PART / WAVE; i++)
+                if (lo + i * WAVE + lane < hi) mslots += cx.ln[mem[i]].cnt;
             mslots = wave_sum_i64(mslots);
             if (lane == 0) {
                 atomicAdd(&cx.ctr->apply[LF_APPLY_PARTS], 1ull);
@@ -1246,7 +1222,7 @@ __device__ __forceinline__ void body_refresh(const Ctx &cx, const QStep &qs, int
                 atomicAdd(&cx.ctr->apply[LF_APPLY_MEMBER_SLOTS], (unsigned long long)mslots);
             }
         }
-        if (k == 0 && pr.ovf) {
+        if (k == 0 && ovf) {
             int no = __atomic_load_n(&cx.ctr->ovf_cnt, __ATOMIC_RELAXED);
             for (int e = lane; e < no; e += WAVE)
                 if (cx.ovf_comm[e] == C) member_terms_line(cx, cx.ovf_node[e], C, s, a0, ap, am, sumi, bad);
@@ -1445,19 +1421,60 @@ __global__ void __launch_bounds__(256) k_line_build(Ctx cx)
     cx.ln[x] = l;
 }
 
-// back to the slot layout at the end of an iteration: counts, and inline memberships
+// back to the slot layout at the end of an iteration (or of a stop within one): the
+// memberships in order without the ones left (holes), and their count
 __global__ void __launch_bounds__(256) k_line_back(Ctx cx)
 {
     const long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (x >= cx.n) return;
     const NodeLine l = cx.ln[x];
-    cx.nh[x].cnt = l.cnt;
+    const long long o = cx.nh[x].off;
+    int w = 0;
     if (l.off < 0) {
-        const long long o = cx.nh[x].off;
 #pragma unroll
         for (int t = 0; t < LINE_SLOTS; t++)
-            if (t < l.cnt) cx.slot[o + t] = l.s[t];
+            if (t < l.cnt && l.s[t].comm >= 0) cx.slot[o + w++] = l.s[t];
+    } else {
+        for (int t = 0; t < l.cnt; t++) {
+            const Slot sl = cx.slot[o + t];
+            if (sl.comm >= 0) cx.slot[o + w++] = sl;
+        }
     }
+    cx.nh[x].cnt = w;
+}
+
+// in-count units of every node in node order (one per INB neighbours; ubase = their
+// exclusive scan), and the first unit of every queue
+__global__ void k_unit_counts(const int *order, const int *deg, long long n, long long *cnt)
+{
+    const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (r < n) cnt[r] = (deg[order[r]] + INB - 1) / INB;
+    else if (r == n) cnt[n] = 0;
+}
+
+__global__ void k_unit_fill(const int *order, const long long *rowptr, const int *deg, const long long *ubase,
+                            long long n, UnitRec *unit, long long cap)
+{
+    const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int x = order[r], d = deg[x];
+    const long long rb = rowptr[x], b = ubase[r];
+    for (int k = 0; k * INB < d; k++) {
+        if (b + k >= cap) break;            // cannot happen: cap bounds the total
+        UnitRec u;
+        u.rb = rb + (long long)k * INB;
+        u.x = x;
+        u.r = (int)r;
+        u.cnt = d - k * INB < INB ? d - k * INB : INB;
+        u.pad = 0;
+        unit[b + k] = u;
+    }
+}
+
+__global__ void k_queue_units(const long long *ubase, long long n, int q, long long nq, long long *out)
+{
+    const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (k <= nq) out[k] = ubase[k * q < n ? k * q : n];
 }
 
 __global__ void k_empty_table(GEntry *t, long long n)
@@ -1475,7 +1492,7 @@ void lf_free_iteration_buffers(lf_handle *h)
                      (void **)&h->big_idx,
                      (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl,
                      (void **)&h->gt, (void **)&h->occ, (void **)&h->occ_key, (void **)&h->occ_d,
-                     (void **)&h->in_item, (void **)&h->part_rec, (void **)&h->macc,
+                     (void **)&h->unit, (void **)&h->dpos, (void **)&h->part_rec, (void **)&h->macc,
                      (void **)&h->titem_base, (void **)&h->titem_node};
     for (void **p : ptrs) {
         lf_dev_free(h, *p);
@@ -1483,11 +1500,20 @@ void lf_free_iteration_buffers(lf_handle *h)
     }
     h->q_cap = 0;
     h->gT = 0;
-    h->in_cap = 0;
+    h->unit_cap = 0;
     h->part_cap = 0;
     h->mslot_cap = 0;
     h->titem_cap = 0;
 }
+
+// The iteration start's report (device dq, copied to the pinned host hqoff), for nq
+// queues: per path the first list position of every queue ([LF_PATH_COUNT][nq + 1]),
+// the first table-path work item of every queue, the first in-count unit of every queue,
+// then 4 bounds of k_chunk_bounds.
+#define REP_ITEMS(nq) ((long long)LF_PATH_COUNT * ((nq) + 1))
+#define REP_UNITS(nq) ((long long)(LF_PATH_COUNT + 1) * ((nq) + 1))
+#define REP_BOUNDS(nq) ((long long)(LF_PATH_COUNT + 2) * ((nq) + 1))
+#define REP_LEN(nq) (REP_BOUNDS(nq) + 4)
 
 // Start of an iteration, first half: everything the host does not need to see, queued on
 // the stream, ending with one copy of the queue offsets and bounds to pinned host memory.
@@ -1500,13 +1526,14 @@ static int size_queue_enqueue(lf_handle *h, long long q)
     long long n = h->n;
     bool moved = false;
     if (q > h->q_cap) {
-        void **ptrs[] = {(void **)&h->dj, (void **)&h->dl, (void **)&h->djd, (void **)&h->dld,
+        void **ptrs[] = {(void **)&h->dj, (void **)&h->dl, (void **)&h->djd, (void **)&h->dld, (void **)&h->dpos,
                          (void **)&h->big_idx,
                          (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl};
         for (void **p : ptrs) {
             lf_dev_free(h, *p);
             *p = nullptr;
         }
+        LF_TRY(lf_dev_alloc(h, (void **)&h->dpos, sizeof(int) * q));
         LF_TRY(lf_dev_alloc(h, (void **)&h->dj, sizeof(int) * q));
         LF_TRY(lf_dev_alloc(h, (void **)&h->dl, sizeof(int) * q));
         LF_TRY(lf_dev_alloc(h, (void **)&h->djd, sizeof(double) * q));
@@ -1529,12 +1556,12 @@ static int size_queue_enqueue(lf_handle *h, long long q)
         if (h->hqoff) (void)hipHostFree(h->hqoff);
         h->hqoff = nullptr;
         h->hqoff_cap = 0;
-        if (hipHostMalloc((void **)&h->hqoff, sizeof(long long) * ((LF_PATH_COUNT + 1) * (nq + 1) + 4),
+        if (hipHostMalloc((void **)&h->hqoff, sizeof(long long) * REP_LEN(nq),
                           hipHostMallocDefault) != hipSuccess)
             return lf_set_error(h, LF_ENOMEM, "host queue offsets");
         h->hqoff_cap = nq + 1;
     }
-    const long long nrep = (LF_PATH_COUNT + 1) * (nq + 1) + 4;   // list offsets, queue items, bounds
+    const long long nrep = REP_LEN(nq);    // list offsets, queue items, queue units, bounds
     if (nrep > h->dq_cap) {                 // kept across the two halves (and iterations)
         lf_dev_free(h, h->dq);
         h->dq = nullptr;
@@ -1559,7 +1586,7 @@ static int size_queue_enqueue(lf_handle *h, long long q)
                            (const long long *)h->pbase, h->prec_all);
         hipLaunchKernelGGL(k_path_base, dim3(1), dim3(1), 0, st, (const long long *)h->cscan, n, c, h->pbase);
     }
-    unsigned long long *dout = (unsigned long long *)(dq + (LF_PATH_COUNT + 1) * (nq + 1));
+    unsigned long long *dout = (unsigned long long *)(dq + REP_BOUNDS(nq));
     LF_HIP(h, hipMemsetAsync(dout, 0, sizeof(unsigned long long) * 4, st));
     hipLaunchKernelGGL(k_chunk_bounds, dim3((unsigned)nq), dim3(BS), 0, st, cx, (const long long *)h->vbound,
                        (const int *)h->cls, (int)q, dout);
@@ -1580,7 +1607,30 @@ static int size_queue_enqueue(lf_handle *h, long long q)
     hipLaunchKernelGGL(k_titem_fill, dim3(fill_grid), dim3(BS), 0, st, lf_ctx(h), nt_dev, h->titem_cap);
     // first table-path work item of every queue (sizes the table-visit role)
     hipLaunchKernelGGL(k_queue_items, dim3(grid_for(nq + 1, BS)), dim3(BS), 0, st, (const long long *)h->titem_base,
-                       (const long long *)(dq + LF_PATH_TABLE * (nq + 1)), nq, dq + LF_PATH_COUNT * (nq + 1));
+                       (const long long *)(dq + LF_PATH_TABLE * (nq + 1)), nq, dq + REP_ITEMS(nq));
+    // in-count units of every node in node order, and the first unit of every queue
+    {
+        const long long ucap = n + 2 * h->ne / INB + 1;   // >= sum of ceil(degree / INB)
+        if (ucap > h->unit_cap) {
+            lf_dev_free(h, h->unit);
+            h->unit = nullptr;
+            LF_TRY(lf_dev_alloc(h, (void **)&h->unit, sizeof(UnitRec) * ucap));
+            h->unit_cap = ucap;
+            moved = true;
+        }
+        long long *ucnt = nullptr, *ubase = nullptr;
+        LF_TRY(lf_tmp_alloc(h, (void **)&ucnt, sizeof(long long) * (n + 1)));
+        LF_TRY(lf_tmp_alloc(h, (void **)&ubase, sizeof(long long) * (n + 1)));
+        hipLaunchKernelGGL(k_unit_counts, dim3(grid_for(n + 1, BS)), dim3(BS), 0, st, (const int *)h->order,
+                           (const int *)h->deg, n, ucnt);
+        LF_TRY(lf_exclusive_scan_i64(h, ucnt, ubase, n + 1));
+        if (n > 0)
+            hipLaunchKernelGGL(k_unit_fill, dim3(grid_for(n, BS)), dim3(BS), 0, st, (const int *)h->order,
+                               (const long long *)h->rowptr, (const int *)h->deg, (const long long *)ubase, n, h->unit,
+                               h->unit_cap);
+        hipLaunchKernelGGL(k_queue_units, dim3(grid_for(nq + 1, BS)), dim3(BS), 0, st, (const long long *)ubase, n,
+                           (int)q, nq, dq + REP_UNITS(nq));
+    }
     // the host's one wait of the iteration start: list offsets per queue and path, the
     // queues' first table items, the bounds
     LF_HIP(h, hipMemcpyAsync(h->hqoff, dq, sizeof(long long) * nrep, hipMemcpyDeviceToHost, st));
@@ -1601,7 +1651,7 @@ static int size_queue_complete(lf_handle *h, long long q)
     bool moved = h->pending_moved;
     const unsigned fill_grid = h->fill_grid;
     const long long *nt_dev = h->dq + LF_PATH_TABLE * (nq + 1) + nq;
-    const unsigned long long *hb = (const unsigned long long *)(h->hqoff + (LF_PATH_COUNT + 1) * (nq + 1));
+    const unsigned long long *hb = (const unsigned long long *)(h->hqoff + REP_BOUNDS(nq));
     {   // the records of path c start after those of the paths before it
         long long base = 0;
         for (int c = 0; c < LF_PATH_COUNT; c++) {
@@ -1610,11 +1660,10 @@ static int size_queue_complete(lf_handle *h, long long q)
         }
     }
     long long keys = (long long)hb[1] + 64;
-    long long initems = (long long)hb[2] + 64;
-    if (keys >= (1ll << 30) || initems >= (1ll << 31))
+    if (keys >= (1ll << 30))
         return lf_set_error(h, LF_EOVERFLOW, "queue of %lld nodes too large for the table path", q);
     const long long nt = h->hqoff[LF_PATH_TABLE * (nq + 1) + nq];
-    const long long items = h->hqoff[LF_PATH_COUNT * (nq + 1) + nq];
+    const long long items = h->hqoff[REP_ITEMS(nq) + nq];
     if (items > h->titem_cap) {             // rare: grow and lay the items out again
         lf_dev_free(h, h->titem_node);
         h->titem_node = nullptr;
@@ -1640,14 +1689,6 @@ static int size_queue_complete(lf_handle *h, long long q)
         LF_HIP(h, hipMemsetAsync(h->gt, 0, sizeof(GEntry) * T, st));
         hipLaunchKernelGGL(k_empty_table, dim3(grid_for(T, BS)), dim3(BS), 0, st, h->gt, T);
         h->gT = T;
-        moved = true;
-    }
-    if (initems > h->in_cap) {
-        lf_dev_free(h, h->in_item);
-        h->in_item = nullptr;
-        long long want = initems + initems / 4;
-        LF_TRY(lf_dev_alloc(h, (void **)&h->in_item, sizeof(InItem) * want));
-        h->in_cap = want;
         moved = true;
     }
     long long pcap = 2 * q + (h->cm_cap + n) / PART + 64;
@@ -1708,7 +1749,8 @@ void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool
                      QGrids *g)
 {
     const long long *qo = h->hqoff;                                // [path][nq + 1]
-    const long long *hit = h->hqoff + LF_PATH_COUNT * (nq + 1);   // first table item per queue
+    const long long *hit = h->hqoff + REP_ITEMS(nq);   // first table-path work item per queue
+    const long long *hu = h->hqoff + REP_UNITS(nq);    // first in-count unit per queue
     const long long start = k * qq;
     const int clen = (int)((h->n - start) < qq ? (h->n - start) : qq);
     int ls[LF_PATH_COUNT], ln[LF_PATH_COUNT];
@@ -1746,13 +1788,13 @@ void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool
     br.ng = ln[LF_PATH_GROUP];
     br.lm = ls[LF_PATH_MED];
     br.nm = ln[LF_PATH_MED];
-    qs->plan_blocks = (int)grid_for(2ll * clen, 256);
+    qs->ub = hu[k];
+    qs->un = (int)(hu[k + 1] - hu[k]);
     g->eval = own_small ? (int)grid_for(ln[LF_PATH_SMALL], EW) : 0;
     g->big = br.bt + br.bg + br.bm + br.bs;
     if (g->big < 1 && g->eval == 0) g->big = 1;   // block 0 resets the queue's counters
     g->fin = ln[LF_PATH_TABLE] > 0 ? (compact_grids ? (br.bt > 0 ? br.bt : 1) : gb) : 0;
-    g->apply_edit = (int)grid_for(clen, 256);
-    g->apply_in = qs->plan_blocks + rbk;
+    g->apply = (int)grid_for(clen, 256) + (int)grid_for(qs->un, 256 / WAVE);
     g->refresh = rbk;
 }
 
@@ -1780,11 +1822,8 @@ int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g)
         LF_TRY(lf_prof_end(h, LF_K_TAB_TIE, 1));
     }
     LF_TRY(lf_prof_begin(h, LF_K_APPLY_EDIT));
-    hipLaunchKernelGGL(k_apply_edit, dim3(g.apply_edit), dim3(256), 0, st, cx, qs);
+    hipLaunchKernelGGL(k_apply, dim3(g.apply), dim3(256), 0, st, cx, qs);
     LF_TRY(lf_prof_end(h, LF_K_APPLY_EDIT, 1));
-    LF_TRY(lf_prof_begin(h, LF_K_APPLY_IN));
-    hipLaunchKernelGGL(k_apply_in, dim3(g.apply_in), dim3(256), 0, st, cx, qs);
-    LF_TRY(lf_prof_end(h, LF_K_APPLY_IN, 1));
     LF_TRY(lf_prof_begin(h, LF_K_REFRESH));
     hipLaunchKernelGGL(k_refresh, dim3(g.refresh), dim3(256), 0, st, cx, qs);
     LF_TRY(lf_prof_end(h, LF_K_REFRESH, 1));
@@ -1793,7 +1832,7 @@ int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g)
     return LF_OK;
 }
 
-// One queue of each of nm graphs: five grids (k_big_final and k_big_tie share one), each
+// One queue of each of nm graphs: four grids (k_big_final and k_big_tie share one), each
 // block finding its graph from dboff (LF_MULTI_GRIDS arrays of first-block offsets, at
 // stride cap + 1, each with nm + 1 entries); total[i] = blocks of grid i.
 int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int cap, int nm, const int *total)
@@ -1806,11 +1845,9 @@ int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int ca
         hipLaunchKernelGGL(k_big_tie_multi, dim3(total[1]), dim3(256), 0, st, dmem, o, nm);
     }
     o += cap + 1;
-    if (total[2] > 0) hipLaunchKernelGGL(k_apply_edit_multi, dim3(total[2]), dim3(256), 0, st, dmem, o, nm);
+    if (total[2] > 0) hipLaunchKernelGGL(k_apply_multi, dim3(total[2]), dim3(256), 0, st, dmem, o, nm);
     o += cap + 1;
-    if (total[3] > 0) hipLaunchKernelGGL(k_apply_in_multi, dim3(total[3]), dim3(256), 0, st, dmem, o, nm);
-    o += cap + 1;
-    if (total[4] > 0) hipLaunchKernelGGL(k_refresh_multi, dim3(total[4]), dim3(256), 0, st, dmem, o, nm);
+    if (total[3] > 0) hipLaunchKernelGGL(k_refresh_multi, dim3(total[3]), dim3(256), 0, st, dmem, o, nm);
     return hipGetLastError() == hipSuccess ? LF_OK : LF_EDEVICE;
 }
 
@@ -1819,10 +1856,10 @@ int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int ca
 void lf_multi_kernels(const void **fn, int *grid, int *block)
 {
     const void *f[LF_MULTI_KERNELS] = {(const void *)k_eval_big_multi, (const void *)k_big_final_multi,
-                                       (const void *)k_big_tie_multi, (const void *)k_apply_edit_multi,
-                                       (const void *)k_apply_in_multi, (const void *)k_refresh_multi};
-    const int gr[LF_MULTI_KERNELS] = {0, 1, 1, 2, 3, 4};
-    const int b[LF_MULTI_KERNELS] = {GT, 256, 256, 256, 256, 256};
+                                       (const void *)k_big_tie_multi, (const void *)k_apply_multi,
+                                       (const void *)k_refresh_multi};
+    const int gr[LF_MULTI_KERNELS] = {0, 1, 1, 2, 3};
+    const int b[LF_MULTI_KERNELS] = {GT, 256, 256, 256, 256};
     for (int i = 0; i < LF_MULTI_KERNELS; i++) {
         fn[i] = f[i];
         grid[i] = gr[i];

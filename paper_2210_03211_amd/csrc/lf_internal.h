@@ -37,28 +37,26 @@ struct __align__(64) NodeLine {
 };
 static_assert(sizeof(NodeLine) == 64, "one 64-byte line per node");
 
-// One in-count work item: a block of INB neighbours of a node that moved in this queue,
-// with everything the item needs (written by the membership edits).
-struct InItem {
-    long long rb;            // first adjacency position of the moved node
-    long long jslot;         // address of its join's slot (valid if J >= 0)
-    int x;                   // the moved node
-    int J, L;                // community joined (-1: none or it did not fit) and left (-1: none)
-    int d;                   // its degree
-    int k;                   // which block of neighbours
+// One in-count unit: up to INB consecutive neighbours of the node at order position r
+// (units are laid out for every node at the start of an iteration, so a queue's units are
+// a contiguous range; the apply step skips those of nodes that did not move).
+struct UnitRec {
+    long long rb;            // adjacency position of the unit's first neighbour
+    int x;                   // the node
+    int r;                   // its order position
+    int cnt;                 // neighbours in the unit (1 .. INB)
     int pad;
 };
 
-// One re-sum part: up to PART members of a touched community, with everything the re-sum
-// needs (written by the planning blocks of the in-count kernel).
+// One re-sum part: up to PART entries of a touched community's member list, planned at
+// the community's first touch in a queue from the list's capacity (fixed within an
+// iteration); size, list length and overflow are read when the part is summed.
 struct PartRec {
     long long base;          // the community's member-list offset
     int C;                   // the community (-1: an empty record after a flagged overflow)
     int k, parts;            // this part and the community's number of parts
-    int s;                   // its size
-    int len;                 // members in its list
+    int cap;                 // member-list capacity
     int ms;                  // carry-save counter slot of a multi-part community (-1: one part)
-    int ovf;                 // members also sit in the overflow list
     int pad;
 };
 
@@ -104,11 +102,11 @@ struct DevCounters {
     unsigned long long work[LF_PATH_COUNT][5]; // evaluation work per path (cumulative): nodes,
                                    // neighbours, visits, candidates, own memberships
     unsigned long long apply[LF_APPLY_COUNT];  // apply work (cumulative, LF_APPLY_*)
-    int tcount;                    // touched communities (queue)
+    int tcount;                    // communities re-summed at initialisation
     int unused0;
     int unused1;
     int occ_cnt;                   // occupied entries of the global table (queue)
-    int in_items;                  // in-count work items (queue)
+    int unused2;
     int parts_total;               // re-sum parts (queue)
     int mslots;                    // multi-part re-sum accumulators in use (queue)
     int refresh_next;              // work counter of the full re-sum at initialisation
@@ -142,16 +140,16 @@ struct Ctx {
     long long *cm_off;       // member-list capacity offsets (K + 1)
     int *cm_len;             // member-list fill (may exceed capacity: overflow)
     int *cm_node;            // member lists
-    int *tflag;              // touched flag per community
-    int *tlist;              // touched list
-    unsigned long long *joined_to;  // per node (queue tag << 32 | community joined, -1 if
-                                    // none); only entries with the current tag are valid
+    int *tflag;              // touched flag per community (1: in this queue, 2: removed)
+    int *tlist;              // community list of the re-sum at initialisation
     unsigned qtag;           // tag of the current queue (unique within a run)
     int *ovf_node;           // overflow joiners (node, community)
     int *ovf_comm;
     int *ovf_flag;
     int *dj, *dl;            // decisions of the current queue
     double *djd, *dld;
+    int *dpos;               // [q] slot count of each queued node when it was evaluated
+                             // (where a join is appended)
     DevCounters *ctr;
     // table path (nodes whose candidates do not fit one wave), indexed by queue position j
     int *big_idx;            // [q] evaluation state of queue index j (Q_* in iterate.hip)
@@ -169,9 +167,8 @@ struct Ctx {
     unsigned long long *occ_key;  // [gT] key | leave << 63
     double *occ_d;             // [gT] change of each occupied entry
     long long gmask;           // gT - 1
-    // in-count work items
-    InItem *in_item;         // [in_cap] the in-count work items of the queue
-    int in_cap;
+    // in-count units of the current iteration (every node's, in node order)
+    const UnitRec *unit;
     // re-sum parts
     PartRec *part_rec;       // [part_cap] the re-sum parts of the queue
     int *part_done;          // [K] parts of a multi-part community finished
@@ -197,7 +194,8 @@ struct QStep {
     int wcap, mcap, gcap;    // LDS table sizes of the small, medium and workgroup paths
     int ls, ln;              // small-path list positions
     BigRoles br;
-    int plan_blocks;         // re-sum planning blocks of k_apply_in
+    long long ub;            // the queue's in-count units: [ub, ub + un)
+    int un;
 };
 
 // One graph's queue in a multi-graph launch.
@@ -208,7 +206,7 @@ struct Member {
 
 // launch grids of one queue's kernels (0 = not launched)
 struct QGrids {
-    int eval, big, fin, apply_edit, apply_in, refresh;
+    int eval, big, fin, apply, refresh;
 };
 
 struct TmpChunk {
@@ -254,11 +252,11 @@ struct lf_handle {
     int *cm_node;
     long long cm_cap;        // capacity of cm_node
     int *tflag, *tlist;
-    unsigned long long *joined_to;
     unsigned qtag;           // next queue tag
     int *ovf_node, *ovf_comm, *ovf_flag;
     int *dj, *dl;
     double *djd, *dld;
+    int *dpos;
     long long q_cap;         // capacity of the per-queue arrays
     // table path and work lists (sized per iteration)
     int *big_idx;
@@ -289,8 +287,8 @@ struct lf_handle {
     unsigned long long *occ_key;
     double *occ_d;
     long long gT;
-    InItem *in_item;         // [in_cap]
-    long long in_cap;
+    UnitRec *unit;           // [unit_cap] in-count units of the iteration
+    long long unit_cap;
     PartRec *part_rec;
     int *part_done;
     long long *macc;
@@ -414,8 +412,8 @@ void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool
                      QGrids *g);
 int lf_launch_queue(lf_handle *h, Ctx &cx, const QStep &qs, const QGrids &g);
 int lf_launch_multi(hipStream_t st, const Member *dmem, const int *dboff, int cap, int nm, const int *total);
-#define LF_MULTI_GRIDS 5         // per-step launches of a batch with grids of their own
-#define LF_MULTI_KERNELS 6       // kernels of a batch step (k_big_final and k_big_tie share a grid)
+#define LF_MULTI_GRIDS 4         // per-step launches of a batch with grids of their own
+#define LF_MULTI_KERNELS 5       // kernels of a batch step (k_big_final and k_big_tie share a grid)
 void lf_multi_kernels(const void **fn, int *grid, int *block);
 int lf_iter_finish(lf_handle *h, long long *joins, long long *leaves, long long *live);
 int lf_lines_back(lf_handle *h);          // lines -> slot layout (mid-iteration stop)

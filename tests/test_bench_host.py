@@ -87,7 +87,7 @@ def paths(**w):
     return {p: dict(z, **w.get(p, {})) for p in ("small", "medium", "group", "table")}
 
 
-APPLY0 = {"moves": 0, "own_slots": 0, "in_items": 0, "in_neighbours": 0, "in_slots": 0, "parts": 0,
+APPLY0 = {"moves": 0, "own_slots": 0, "in_units": 0, "in_neighbours": 0, "in_slots": 0, "parts": 0,
           "touched": 0, "members": 0, "member_slots": 0}
 
 
@@ -110,21 +110,22 @@ def test_kernel_byte_model():
 
 
 def test_apply_byte_model():
-    w = work_of(paths(), node_evals=100, moves=10, own_slots=20, in_items=30, in_neighbours=40, in_slots=50,
+    w = work_of(paths(), node_evals=100, moves=10, own_slots=20, in_units=30, in_neighbours=40, in_slots=50,
                 parts=6, touched=5, members=70, member_slots=80)
-    assert bench.kernel_bytes("k_apply_edit", w) == 100 * 24 + 10 * 56 + 20 * 8 + 30 * 40
-    assert bench.kernel_bytes("k_apply_in", w) == 30 * 40 + 40 * 28 + 50 * 8 + 5 * 24 + 6 * 40
-    assert bench.kernel_bytes("k_refresh", w) == 6 * 40 + 70 * 20 + 80 * 8 + 5 * 64
+    assert bench.kernel_bytes("k_apply", w) == (100 * 24 + 10 * 52 + 20 * 8 + 30 * 24 + 40 * 36 + 50 * 8
+                                                + 5 * 24 + 6 * 40)
+    assert bench.kernel_bytes("k_refresh", w) == 6 * (40 + 16) + 70 * 20 + 80 * 8 + 5 * 64
+    assert bench.kernel_bytes("k_apply_in", w) is None            # no longer launched
 
 
 def test_kernel_rooflines_divide_bytes_by_event_time():
     p = paths(small={"nodes": 1_000_000}, medium={"neighbours": 1_000_000}, table={"candidates": 1_000_000})
     w = work_of(p, node_evals=1_000_000)
     timing = {"ms": {"k_eval": 0.04, "k_eval_big": 0.024, "k_big_final": 0.044, "k_big_tie": 0.0,
-                     "k_apply_edit": 0.024},
-              "launches": {"k_eval": 1, "k_eval_big": 1, "k_big_final": 1, "k_apply_edit": 1}}
+                     "k_apply": 0.024},
+              "launches": {"k_eval": 1, "k_eval_big": 1, "k_big_final": 1, "k_apply": 1}}
     r = bench.kernel_rooflines(timing, w)
-    for k in ("k_eval", "k_eval_big", "k_big_final", "k_apply_edit"):
+    for k in ("k_eval", "k_eval_big", "k_big_final", "k_apply"):
         assert abs(r[k]["GB_s"] - 1000.0) < 1e-9, k
         assert abs(r[k]["frac"] - 1000.0 / bench.HBM_PEAK_GBS) < 1e-12
     assert abs(r["evaluation"]["GB_s"] - 1000.0) < 1e-9
