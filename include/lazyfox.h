@@ -419,12 +419,18 @@ int lf_batch_set_graph(lf_batch *b, int32_t on);
  * job's edge list (host memory, as for lf_load_graph without flags) and queues it;
  * LF_ENOMEM if its estimated device footprint exceeds the whole budget.  Each
  * lf_server_tick admits queued jobs in arrival order while their estimated footprints fit
- * the budget and fewer than max_batch jobs run (load, initial clustering, join the
- * batch), runs one batch step, and retires finished jobs: memberships and run info are
- * copied to host memory and the job's device memory is released (retired jobs' memory is
- * freed for many at once, at the latest when a queued job needs it), so jobs that arrived
- * meanwhile are admitted as memory frees up.  *pending = jobs queued or running.
+ * the budget and fewer than max_batch jobs run, runs one batch step, and hands finished
+ * jobs over for retirement.  Four worker threads of the server, each with a stream of its
+ * own, load admitted jobs (graph load, initial clustering; they join the batch at the
+ * next tick) and retire finished ones (memberships copied to host memory, device memory
+ * returned to the library's allocation cache; the job is done at the next tick after
+ * that), so the ticking thread never waits for either.  A job's footprint stays reserved
+ * from admission until its retirement has completed; jobs that arrived meanwhile are
+ * admitted as memory frees up.  *pending = jobs queued or running.
  * lf_server_poll: *state = 0 queued, 1 running, 2 done, < 0 failed with that status.
+ * lf_server_take_done: ids of the jobs that finished or failed since the last call (in
+ *   completion order, at most capacity; *count = how many were written), so a caller can
+ *   fetch exactly those instead of polling every job.
  * lf_server_fetch: results of a done job, two-call pattern as lf_get_memberships
  *   (LF_EAGAIN if not done); after a copy of the memberships the job is forgotten.
  * lf_server_stats: device bytes reserved by admitted jobs, the budget, running and queued
@@ -436,16 +442,22 @@ int lf_server_submit(lf_server *s, int64_t n, int64_t n_pairs, const int64_t *sr
                      int32_t queue_size, double threshold, int32_t max_iters, int64_t *job_id);
 int lf_server_tick(lf_server *s, int32_t *pending);
 int lf_server_poll(lf_server *s, int64_t job_id, int32_t *state);
+int lf_server_take_done(lf_server *s, int64_t *ids, int32_t capacity, int32_t *count);
 int lf_server_fetch(lf_server *s, int64_t job_id, int64_t *offsets, int32_t *comm_ids, int64_t capacity,
                     int64_t *total, lf_run_info *info);
 int lf_server_stats(lf_server *s, uint64_t *used, uint64_t *budget, int32_t *running, int32_t *queued);
 int lf_server_destroy(lf_server *s);
 const char *lf_server_last_error(lf_server *s);
 /* Host milliseconds spent so far in ms[0..4]: admission (graph load and initial
-   clustering, on a stream of its own), batch steps, retirement (results copied back),
-   freeing device memory of retired jobs (done for many at once), whole ticks; ms[5] the
+   clustering) and retirement (results copied back, device state released), summed over
+   the worker threads, in ms[0] and ms[2]; batch steps; handing jobs to and from the
+   workers (batch add, member info, detach); whole ticks; ms[5] the
    part of the batch steps spent waiting for the device; ms[6] the batch steps that
-   launched work and ms[7] the queues they ran (counts).  ms holds 8 values. */
+   launched work and ms[7] the queues they ran (counts); ms[8..10] the host time of the
+   steps in iteration starts and ends, in per-member queue parameters, and in the
+   descriptor upload and launch; ms[11..13] the iteration starts and ends of retired jobs
+   that ran plainly, were captured into graphs, and were replayed from them (counts).
+   ms holds 14 values. */
 int lf_server_timing(lf_server *s, double *ms);
 /* Graph replay of the server's batch steps (lf_batch_set_graph); on by default. */
 int lf_server_set_graph(lf_server *s, int32_t on);

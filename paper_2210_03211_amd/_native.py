@@ -109,6 +109,7 @@ def load_library():
         "lf_server_stats": [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(i32), C.POINTER(i32)],
         "lf_server_destroy": [vp],
         "lf_server_timing": [vp, C.POINTER(C.c_double)],
+        "lf_server_take_done": [vp, vp, i32, C.POINTER(i32)],
         "lf_server_set_graph": [vp, i32],
         "lf_autotune": [vp, i32, i32, C.POINTER(TuneResult)],
         "lf_autotune_forget": [],
@@ -630,6 +631,16 @@ class Server:
 
     poll = lf_server_poll
 
+    def lf_server_take_done(self, capacity=4096):
+        """Ids of the jobs that finished or failed since the last call."""
+        ids = np.zeros(max(1, capacity), np.int64)
+        cnt = C.c_int32()
+        self._check(self.L.lf_server_take_done(self.s, C.c_void_p(ids.ctypes.data), int(capacity), C.byref(cnt)),
+                    "lf_server_take_done")
+        return [int(x) for x in ids[: cnt.value]]
+
+    take_done = lf_server_take_done
+
     def lf_server_fetch(self, job):
         """(offsets, community ids, run info) of a done job; None while it is not done."""
         arrays = _run_info_arrays(self._max_iters.get(job, 1))
@@ -657,10 +668,11 @@ class Server:
     stats = lf_server_stats
 
     def lf_server_timing(self):
-        ms = (C.c_double * 8)()
+        ms = (C.c_double * 14)()
         self._check(self.L.lf_server_timing(self.s, ms), "lf_server_timing")
-        return dict(zip(("admit_ms", "step_ms", "retire_ms", "free_ms", "tick_ms", "step_wait_ms", "steps",
-                         "member_steps"), list(ms)))
+        return dict(zip(("admit_ms", "step_ms", "retire_ms", "handover_ms", "tick_ms", "step_wait_ms", "steps",
+                         "member_steps", "step_phase_ms", "step_params_ms", "step_launch_ms", "phases_plain",
+                         "phases_captured", "phases_replayed"), list(ms)))
 
     timing = lf_server_timing
 

@@ -46,7 +46,7 @@ extern "C" {
 // the handle is zero-initialised, so members not created yet are null).
 static int create_failed(lf_handle *h, int rc)
 {
-    if (h->hrep) (void)hipHostFree(h->hrep);
+    if (h->hrep) lf_host_release(h->hrep, sizeof(long long) * 16);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -90,7 +90,7 @@ int lf_create(lf_handle **out, int device, void *hip_stream, uint32_t flags)
     }
     if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
         return create_failed(h, LF_EDEVICE);
-    if (hipHostMalloc((void **)&h->hrep, sizeof(long long) * 16, hipHostMallocDefault) != hipSuccess) {
+    if (lf_host_alloc((void **)&h->hrep, sizeof(long long) * 16) != LF_OK) {
         h->hrep = nullptr;
         return create_failed(h, LF_ENOMEM);
     }
@@ -112,7 +112,10 @@ int lf_destroy(lf_handle *h)
     if (!h) return LF_OK;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
-    for (void *p : *h->allocs) (void)hipFree(p);
+    lf_phase_graphs_drop(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    // the handle's work has completed on its stream: its blocks can serve other handles
+    for (size_t k = 0; k < h->allocs->size(); k++) lf_dev_release(h->device, (*h->allocs)[k], (*h->alloc_sizes)[k]);
     delete h->allocs;
     delete h->alloc_sizes;
     delete h->tmp_chunks;
@@ -123,8 +126,8 @@ int lf_destroy(lf_handle *h)
     (void)hipEventDestroy(h->ev0);
     (void)hipEventDestroy(h->ev1);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
-    if (h->hqoff) (void)hipHostFree(h->hqoff);
-    if (h->hrep) (void)hipHostFree(h->hrep);
+    if (h->hqoff) lf_host_release(h->hqoff, sizeof(long long) * h->hqoff_len);
+    if (h->hrep) lf_host_release(h->hrep, sizeof(long long) * 16);
     free(h);
     return LF_OK;
 }

@@ -15,9 +15,12 @@
 // and retires finished jobs (memberships copied back, device memory released), so jobs
 // that arrive while others run join as memory frees up.
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <stdlib.h>
+#include <thread>
 #include <vector>
 
 #include "lf_internal.h"
@@ -59,6 +62,8 @@ struct lf_batch {
     long long graph_steps;
     long long steps, member_steps;           // steps that launched, queues they ran
     double wait_ms;                          // host time waiting for the device in steps
+    double phase_ms, params_ms, launch_ms;   // host time: iteration starts and ends,
+                                             // per-member parameters, upload and launch
     char err[512];
 };
 
@@ -229,6 +234,9 @@ int lf_batch_create(lf_batch **out, int device, void *hip_stream)
     b->steps = 0;
     b->member_steps = 0;
     b->wait_ms = 0.0;
+    b->phase_ms = 0.0;
+    b->params_ms = 0.0;
+    b->launch_ms = 0.0;
     b->err[0] = 0;
     for (int s = 0; s < 2; s++) {
         b->hmem[s] = nullptr;
@@ -280,6 +288,7 @@ int lf_batch_add(lf_batch *b, lf_handle *h, int32_t queue_size, double threshold
     m->h = h;
     m->saved_stream = h->stream;
     h->stream = b->stream;
+    h->phase_graphs = 1;          // iteration starts and ends replayed from graphs
     long long n = h->n;
     m->qq = queue_size < n ? queue_size : (n > 0 ? n : 1);
     m->nq = 0;
@@ -303,6 +312,7 @@ int lf_batch_step(lf_batch *b, int32_t *running)
     if (!b) return LF_EINVAL;
     std::vector<BatchMember *> act;
     BatchMember *waiting = nullptr;
+    auto tp = std::chrono::steady_clock::now();
     for (BatchMember *m : b->members) {
         if (!m || m->state != 0) continue;
         if (m->phase == PH_END_WAIT || m->phase == PH_BEGIN_WAIT) {
@@ -345,6 +355,7 @@ int lf_batch_step(lf_batch *b, int32_t *running)
         }
         act.push_back(m);
     }
+    b->phase_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
     if (act.empty() && waiting) {
         // nothing to launch: wait for the oldest queued start or end instead of spinning
         auto t0 = std::chrono::steady_clock::now();
@@ -361,6 +372,7 @@ int lf_batch_step(lf_batch *b, int32_t *running)
         b->wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         b->steps++;
         b->member_steps += nm;
+        auto t1 = std::chrono::steady_clock::now();
         Member *hm = b->hmem[s];
         int *hb = b->hboff[s];
         int total[LF_MULTI_GRIDS] = {0, 0, 0, 0};
@@ -377,6 +389,8 @@ int lf_batch_step(lf_batch *b, int32_t *running)
             }
         }
         for (int t = 0; t < LF_MULTI_GRIDS; t++) hb[t * (b->cap + 1) + nm] = total[t];
+        auto t2 = std::chrono::steady_clock::now();
+        b->params_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
         if (hipMemcpyAsync(b->dmem, hm, sizeof(Member) * nm, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
             hipMemcpyAsync(b->dboff, hb, sizeof(int) * LF_MULTI_GRIDS * (b->cap + 1), hipMemcpyHostToDevice, b->stream) !=
                 hipSuccess ||
@@ -387,6 +401,8 @@ int lf_batch_step(lf_batch *b, int32_t *running)
         } else if (lf_launch_multi(b->stream, b->dmem, b->dboff, b->cap, nm, total) != LF_OK) {
             return batch_error(b, LF_EDEVICE, "multi-graph launch failed");
         }
+        auto t3 = std::chrono::steady_clock::now();
+        b->launch_ms += std::chrono::duration<double, std::milli>(t3 - t2).count();
         for (BatchMember *m : act) {
             m->k++;
             if (m->k == m->nq) {
@@ -396,6 +412,7 @@ int lf_batch_step(lf_batch *b, int32_t *running)
                 else m->phase = PH_END_WAIT;
             }
         }
+        b->phase_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t3).count();
     }
     int live = 0;
     for (BatchMember *m : b->members)
@@ -442,10 +459,31 @@ int lf_batch_remove(lf_batch *b, int32_t member_id)
     if (m->state == 0 && m->phase == PH_RUN) (void)lf_lines_back(m->h);
     (void)hipStreamSynchronize(b->stream);
     m->h->stream = m->saved_stream;
+    m->h->phase_graphs = 0;
+    lf_phase_graphs_drop(m->h);
     (void)hipEventDestroy(m->ev);
     delete m;
     b->members[member_id] = nullptr;
     return LF_OK;
+}
+
+// Take a finished member out of the batch without waiting: *left is recorded behind its
+// last work on the batch stream, and the caller waits for it before using the handle
+// (which is back on its own stream) and destroys it afterwards.
+int lf_batch_detach(lf_batch *b, int32_t member_id, hipEvent_t *left)
+{
+    *left = nullptr;
+    if (!b || member_id < 0 || member_id >= (int32_t)b->members.size() || !b->members[member_id])
+        return LF_EINVAL;
+    BatchMember *m = b->members[member_id];
+    if (m->state == 0 && m->phase == PH_RUN) (void)lf_lines_back(m->h);
+    int rc = hipEventRecord(m->ev, b->stream) == hipSuccess ? LF_OK : LF_EDEVICE;
+    *left = m->ev;
+    m->h->stream = m->saved_stream;
+    m->h->phase_graphs = 0;         // its graphs go with the handle, after the wait
+    delete m;
+    b->members[member_id] = nullptr;
+    return rc;
 }
 
 int lf_batch_destroy(lf_batch *b)
@@ -474,6 +512,12 @@ int lf_batch_destroy(lf_batch *b)
 // ------------------------------------------------------------------------------------
 // serving runtime
 // ------------------------------------------------------------------------------------
+// The thread that ticks the server only steps the batch and moves jobs in and out of it.
+// Worker threads, each with a stream of its own, load and initialise admitted jobs and
+// retire finished ones (memberships copied back, device state released to the allocation
+// cache), so neither waits in the stepping thread.
+#define SERVER_WORKERS 4
+
 struct Job {
     long long id;
     int state;               // 0 queued, 1 running, 2 done, < 0 failed (status)
@@ -484,7 +528,9 @@ struct Job {
     int max_iters;
     size_t footprint;
     lf_handle *h;
-    int member;
+    int member;              // batch member id while in the batch, else -1
+    int rc;                  // status of the worker's step (load or retirement)
+    hipEvent_t left;         // recorded behind the job's last work in the batch
     std::vector<int64_t> off;
     std::vector<int32_t> ids;
     lf_run_info info;
@@ -495,18 +541,28 @@ struct Job {
 struct lf_server {
     int device;
     hipStream_t stream;      // the batch's work
-    hipStream_t admit;       // loading and initial clustering of admitted jobs
     bool own_stream;
     lf_batch *batch;
     size_t budget, used;
     int max_batch, running;
-    std::deque<Job *> queue;
+    std::deque<Job *> queue;          // submitted, not yet admitted (arrival order)
+    std::deque<long long> done;       // finished or failed, not yet taken
     std::map<long long, Job *> jobs;
-    std::vector<std::pair<lf_handle *, size_t>> retired;   // handles whose memory is not yet freed
+    std::vector<Job *> active;        // jobs in the batch
     long long next_id;
-    double ms[5];            // host time: admission, batch steps, retirement, freeing, ticks
-    std::chrono::steady_clock::time_point last_free;
+    double ms[5];            // admission and retirement (worker time), batch steps, hand-over, ticks
     char err[512];
+    // workers
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> wstream;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Job *> to_load, to_retire;     // work for the workers
+    std::deque<Job *> loaded, retired;        // their results, taken by the next tick
+    bool stop;
+    double wms[2];                            // worker time: loading, retiring
+    long long phase_runs[3];                  // retired jobs' iteration starts and ends:
+                                              // plain, captured, replayed
 };
 
 static double ms_since(std::chrono::steady_clock::time_point t0)
@@ -514,28 +570,15 @@ static double ms_since(std::chrono::steady_clock::time_point t0)
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// free the device memory of retired jobs (hipFree synchronises the device, so this is
-// done for many handles at once)
-static void server_free_retired(lf_server *s)
-{
-    if (s->retired.empty()) return;
-    auto t0 = std::chrono::steady_clock::now();
-    for (auto &r : s->retired) {
-        lf_destroy(r.first);
-        s->used -= r.second;
-    }
-    s->retired.clear();
-    s->last_free = std::chrono::steady_clock::now();
-    s->ms[3] += ms_since(t0);
-}
-
 // Device bytes a job may hold at most: graph build scratch, CSR, node arrays, membership
-// slots, community records and member lists, and the per-queue work lists.
+// slots, community records and member lists, and the per-queue work lists; blocks are
+// rounded up to their allocation class (at most one eighth more).
 static size_t job_footprint(long long n, long long npairs, int q)
 {
     long long nn = n > 0 ? n : 1;
     long long qq = q < nn ? q : nn;
-    return (size_t)(48ll << 20) + (size_t)nn * 480 + (size_t)npairs * 64 + (size_t)qq * 256;
+    size_t b = (size_t)(48ll << 20) + (size_t)nn * 480 + (size_t)npairs * 64 + (size_t)qq * 256;
+    return b + b / 8;
 }
 
 static int server_error(lf_server *s, int code, const char *msg)
@@ -544,44 +587,28 @@ static int server_error(lf_server *s, int code, const char *msg)
     return code;
 }
 
-// the job leaves the batch; its handle is destroyed later with others (its footprint
-// stays reserved until then)
-static void job_release_device(lf_server *s, Job *j)
+// worker: load the graph and the initial clustering of a job on the worker's stream
+static int job_load(lf_server *s, Job *j, hipStream_t st)
 {
-    if (j->member >= 0) lf_batch_remove(s->batch, j->member);
-    j->member = -1;
-    if (j->h) s->retired.push_back({j->h, j->footprint});
-    else s->used -= j->footprint;
-    j->h = nullptr;
-    s->running--;
-}
-
-// load the graph and the initial clustering of a job, then add it to the batch
-static int job_start(lf_server *s, Job *j)
-{
-    int rc = lf_create(&j->h, s->device, (void *)s->admit, 0);
-    if (rc != LF_OK) return rc;
-    rc = lf_load_graph(j->h, j->n, (int64_t)j->src.size(), j->src.data(), j->dst.data(), 0);
+    int rc = lf_create(&j->h, s->device, (void *)st, 0);
+    if (rc == LF_OK) rc = lf_load_graph(j->h, j->n, (int64_t)j->src.size(), j->src.data(), j->dst.data(), 0);
     if (rc == LF_OK) rc = lf_init_communities(j->h);
-    if (rc == LF_OK) rc = lf_batch_add(s->batch, j->h, j->q, j->theta, j->max_iters, &j->member);
+    if (rc == LF_OK && hipStreamSynchronize(st) != hipSuccess) rc = LF_EDEVICE;
     std::vector<int64_t>().swap(j->src);
     std::vector<int64_t>().swap(j->dst);
     return rc;
 }
 
-// copy a finished job's results to host memory and release its device state
-static void job_finish(lf_server *s, Job *j)
+// worker: once the job's work in the batch has completed, copy its memberships to host
+// memory and release its device state
+static int job_collect(Job *j)
 {
-    j->hist.assign(j->max_iters + 1, 0.0);
-    j->joins.assign(j->max_iters > 0 ? j->max_iters : 1, 0);
-    j->leaves.assign(j->joins.size(), 0);
-    j->comms.assign(j->joins.size(), 0);
-    memset(&j->info, 0, sizeof j->info);
-    j->info.wtilde_hist = j->hist.data();
-    j->info.joins = (int64_t *)j->joins.data();
-    j->info.leaves = (int64_t *)j->leaves.data();
-    j->info.communities = (int64_t *)j->comms.data();
-    int rc = lf_batch_member_info(s->batch, j->member, &j->info);
+    int rc = LF_OK;
+    if (j->left) {
+        if (hipEventSynchronize(j->left) != hipSuccess) rc = LF_EDEVICE;
+        (void)hipEventDestroy(j->left);
+        j->left = nullptr;
+    }
     int64_t total = 0;
     if (rc == LF_OK) rc = lf_get_memberships(j->h, nullptr, nullptr, 0, &total);
     if (rc == LF_OK) {
@@ -590,8 +617,38 @@ static void job_finish(lf_server *s, Job *j)
         rc = lf_get_memberships(j->h, j->off.data(), j->ids.data(), (int64_t)j->ids.size(), &total);
         j->ids.resize(total);
     }
-    j->state = rc == LF_OK ? 2 : rc;
-    job_release_device(s, j);
+    lf_destroy(j->h);
+    j->h = nullptr;
+    return rc;
+}
+
+static void worker_main(lf_server *s, int w)
+{
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        s->cv.wait(lk, [&] { return s->stop || !s->to_load.empty() || !s->to_retire.empty(); });
+        if (s->stop) return;
+        const bool retire = !s->to_retire.empty();   // retiring frees memory: first
+        Job *j = retire ? s->to_retire.front() : s->to_load.front();
+        if (retire) s->to_retire.pop_front();
+        else s->to_load.pop_front();
+        lk.unlock();
+        auto t0 = std::chrono::steady_clock::now();
+        j->rc = retire ? job_collect(j) : job_load(s, j, s->wstream[w]);
+        const double ms = ms_since(t0);
+        lk.lock();
+        s->wms[retire ? 1 : 0] += ms;
+        (retire ? s->retired : s->loaded).push_back(j);
+    }
+}
+
+// the job has left the server's device memory (done or failed)
+static void job_gone(lf_server *s, Job *j)
+{
+    s->used -= j->footprint;
+    s->running--;
+    s->done.push_back(j->id);
 }
 
 extern "C" {
@@ -609,30 +666,31 @@ int lf_server_create(lf_server **out, int device, void *hip_stream, uint64_t hbm
     s->running = 0;
     s->next_id = 0;
     s->err[0] = 0;
+    s->stop = false;
     for (int k = 0; k < 5; k++) s->ms[k] = 0.0;
-    s->last_free = std::chrono::steady_clock::now();
-    if (hipStreamCreateWithFlags(&s->admit, hipStreamNonBlocking) != hipSuccess) {
-        delete s;
-        return LF_EDEVICE;
+    s->wms[0] = s->wms[1] = 0.0;
+    for (int k = 0; k < 3; k++) s->phase_runs[k] = 0;
+    bool ok = true;
+    for (int w = 0; w < SERVER_WORKERS && ok; w++) {
+        hipStream_t st = nullptr;
+        ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        if (ok) s->wstream.push_back(st);
     }
-    if (hip_stream) {
+    if (ok && hip_stream) {
         s->stream = (hipStream_t)hip_stream;
         s->own_stream = false;
-    } else {
-        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
-            (void)hipStreamDestroy(s->admit);
-            delete s;
-            return LF_EDEVICE;
-        }
-        s->own_stream = true;
+    } else if (ok) {
+        ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+        s->own_stream = ok;
     }
-    int rc = lf_batch_create(&s->batch, device, (void *)s->stream);
+    int rc = ok ? lf_batch_create(&s->batch, device, (void *)s->stream) : LF_EDEVICE;
     if (rc != LF_OK) {
-        if (s->own_stream) (void)hipStreamDestroy(s->stream);
-        (void)hipStreamDestroy(s->admit);
+        if (ok && s->own_stream) (void)hipStreamDestroy(s->stream);
+        for (hipStream_t st : s->wstream) (void)hipStreamDestroy(st);
         delete s;
         return rc;
     }
+    for (int w = 0; w < SERVER_WORKERS; w++) s->workers.emplace_back(worker_main, s, w);
     *out = s;
     return LF_OK;
 }
@@ -659,55 +717,106 @@ int lf_server_submit(lf_server *s, int64_t n, int64_t n_pairs, const int64_t *sr
     j->footprint = fp;
     j->h = nullptr;
     j->member = -1;
+    j->rc = LF_OK;
+    j->left = nullptr;
     s->queue.push_back(j);
     s->jobs[j->id] = j;
     *job_id = j->id;
     return LF_OK;
 }
 
-// Admit queued jobs that fit, run one step of the batch, retire finished jobs.
+// Take the workers' results (loaded jobs join the batch, retired jobs are done), admit
+// queued jobs that fit, run one step of the batch, hand finished jobs to the workers.
 // *pending = jobs queued or running afterwards.
 int lf_server_tick(lf_server *s, int32_t *pending)
 {
     if (!s) return LF_EINVAL;
     auto t_tick = std::chrono::steady_clock::now();
-    if (ms_since(s->last_free) > 50.0) server_free_retired(s);
-    auto t0 = std::chrono::steady_clock::now();
-    while (!s->queue.empty() && s->running < s->max_batch) {
-        Job *j = s->queue.front();
-        if (s->used + j->footprint > s->budget) {          // arrival order: wait for memory
-            if (s->retired.empty()) break;
-            server_free_retired(s);
+    std::deque<Job *> loaded, retired;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        loaded.swap(s->loaded);
+        retired.swap(s->retired);
+        s->ms[0] = s->wms[0];
+        s->ms[2] = s->wms[1];
+    }
+    for (Job *j : retired) {
+        j->state = j->rc == LF_OK ? 2 : j->rc;
+        job_gone(s, j);
+    }
+    bool more = false;
+    for (Job *j : loaded) {
+        int rc = j->rc;
+        if (rc == LF_OK) rc = lf_batch_add(s->batch, j->h, j->q, j->theta, j->max_iters, &j->member);
+        if (rc == LF_OK) {
+            s->active.push_back(j);
             continue;
         }
+        j->state = rc;
+        if (j->h) lf_destroy(j->h);
+        j->h = nullptr;
+        j->member = -1;
+        job_gone(s, j);
+    }
+    // admission in arrival order while the job fits the budget (its memory is reserved
+    // from now until its retirement has completed)
+    while (!s->queue.empty() && s->running < s->max_batch) {
+        Job *j = s->queue.front();
+        if (s->used + j->footprint > s->budget) break;
         s->queue.pop_front();
         s->used += j->footprint;
         s->running++;
         j->state = 1;
-        int rc = job_start(s, j);
-        if (rc != LF_OK) {
-            j->state = rc;
-            job_release_device(s, j);
-        }
+        std::lock_guard<std::mutex> g(s->mu);
+        s->to_load.push_back(j);
+        more = true;
     }
-    s->ms[0] += ms_since(t0);
-    t0 = std::chrono::steady_clock::now();
+    if (more) s->cv.notify_all();
+    s->ms[3] += ms_since(t_tick);
+    auto t0 = std::chrono::steady_clock::now();
     int32_t live = 0;
     LF_TRY(lf_batch_step(s->batch, &live));
     s->ms[1] += ms_since(t0);
     t0 = std::chrono::steady_clock::now();
-    for (auto &kv : s->jobs) {
-        Job *j = kv.second;
-        if (j->state != 1) continue;
+    more = false;
+    for (size_t k = 0; k < s->active.size();) {
+        Job *j = s->active[k];
         int rc = lf_batch_member_info(s->batch, j->member, nullptr);
-        if (rc == LF_EAGAIN) continue;
-        if (rc == LF_OK) job_finish(s, j);
-        else {
-            j->state = rc;
-            job_release_device(s, j);
+        if (rc == LF_EAGAIN) {
+            k++;
+            continue;
         }
+        j->hist.assign(j->max_iters + 1, 0.0);
+        j->joins.assign(j->max_iters > 0 ? j->max_iters : 1, 0);
+        j->leaves.assign(j->joins.size(), 0);
+        j->comms.assign(j->joins.size(), 0);
+        memset(&j->info, 0, sizeof j->info);
+        j->info.wtilde_hist = j->hist.data();
+        j->info.joins = (int64_t *)j->joins.data();
+        j->info.leaves = (int64_t *)j->leaves.data();
+        j->info.communities = (int64_t *)j->comms.data();
+        if (rc == LF_OK) rc = lf_batch_member_info(s->batch, j->member, &j->info);
+        for (int k = 0; k < 3; k++) s->phase_runs[k] += j->h->phase_runs[k];
+        int drc = lf_batch_detach(s->batch, j->member, &j->left);
+        j->member = -1;
+        s->active[k] = s->active.back();
+        s->active.pop_back();
+        if (rc != LF_OK || drc != LF_OK) {        // failed in the batch: release at once
+            (void)hipStreamSynchronize(s->stream);
+            if (j->left) (void)hipEventDestroy(j->left);
+            j->left = nullptr;
+            lf_destroy(j->h);
+            j->h = nullptr;
+            j->state = rc != LF_OK ? rc : drc;
+            job_gone(s, j);
+            continue;
+        }
+        std::lock_guard<std::mutex> g(s->mu);
+        s->to_retire.push_back(j);
+        more = true;
     }
-    s->ms[2] += ms_since(t0);
+    if (more) s->cv.notify_all();
+    s->ms[3] += ms_since(t0);
     if (pending) *pending = (int32_t)s->queue.size() + s->running;
     s->ms[4] += ms_since(t_tick);
     return LF_OK;
@@ -719,20 +828,45 @@ int lf_server_set_graph(lf_server *s, int32_t on)
     return lf_batch_set_graph(s->batch, on);
 }
 
-// host milliseconds spent so far in: admission (load + initial clustering), batch steps,
-// retirement (results copied back), freeing device memory, whole ticks; the part of the
-// steps spent waiting for the device; steps that launched and the queues they ran
+// host milliseconds: admission and retirement (summed over the worker threads), batch
+// steps, handing jobs to and from the workers, whole ticks; the part of the steps spent
+// waiting for the device; steps that launched and the queues they ran; host time of the
+// steps in iteration starts and ends, per-member parameters, upload and launch; the
+// iteration starts and ends of retired jobs run plainly, captured and replayed (counts)
 int lf_server_timing(lf_server *s, double *ms)
 {
     if (!s || !ms) return LF_EINVAL;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->ms[0] = s->wms[0];
+        s->ms[2] = s->wms[1];
+    }
     for (int k = 0; k < 5; k++) ms[k] = s->ms[k];
     ms[5] = s->batch->wait_ms;
     ms[6] = (double)s->batch->steps;
     ms[7] = (double)s->batch->member_steps;
+    ms[8] = s->batch->phase_ms;
+    ms[9] = s->batch->params_ms;
+    ms[10] = s->batch->launch_ms;
+    for (int k = 0; k < 3; k++) ms[11 + k] = (double)s->phase_runs[k];
     return LF_OK;
 }
 
 // 0 queued, 1 running, 2 done (results waiting), < 0 failed with that status
+// ids of jobs that finished (or failed) since the last call, in completion order, at
+// most capacity of them; *count = how many were written
+int lf_server_take_done(lf_server *s, int64_t *ids, int32_t capacity, int32_t *count)
+{
+    if (!s || !count || capacity < 0 || (capacity > 0 && !ids)) return LF_EINVAL;
+    int32_t k = 0;
+    while (k < capacity && !s->done.empty()) {
+        ids[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *count = k;
+    return LF_OK;
+}
+
 int lf_server_poll(lf_server *s, int64_t job_id, int32_t *state)
 {
     if (!s || !state) return LF_EINVAL;
@@ -792,15 +926,23 @@ int lf_server_destroy(lf_server *s)
 {
     if (!s) return LF_OK;
     (void)hipSetDevice(s->device);
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;                      // workers finish the job in hand and leave
+    }
+    s->cv.notify_all();
+    for (std::thread &t : s->workers) t.join();
+    (void)hipStreamSynchronize(s->stream);
     for (auto &kv : s->jobs) {
         Job *j = kv.second;
-        if (j->state == 1) job_release_device(s, j);
+        if (j->member >= 0) lf_batch_remove(s->batch, j->member);
+        if (j->left) (void)hipEventDestroy(j->left);
+        if (j->h) lf_destroy(j->h);
         delete j;
     }
-    server_free_retired(s);
     lf_batch_destroy(s->batch);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
-    (void)hipStreamDestroy(s->admit);
+    for (hipStream_t st : s->wstream) (void)hipStreamDestroy(st);
     delete s;
     return LF_OK;
 }

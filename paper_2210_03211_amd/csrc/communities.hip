@@ -424,6 +424,7 @@ __global__ void k_score_fold(const X256 *part, int np, double *out)
 Ctx lf_ctx(lf_handle *h)
 {
     Ctx c;
+    memset(&c, 0, sizeof c);   // padding too: the bytes of a Ctx key captured graphs
     c.n = h->n;
     c.K = h->K;
     c.rowptr = h->rowptr;
@@ -507,7 +508,7 @@ static int rebuild_member_lists_async(lf_handle *h)
     int K = h->K;
     long long *capx = nullptr;
     LF_TRY(lf_tmp_alloc(h, (void **)&capx, sizeof(long long) * (K + 1)));
-    LF_HIP(h, hipMemsetAsync(capx, 0, sizeof(long long) * (K + 1), st));
+    LF_TRY(lf_zero(h, capx, sizeof(long long) * (K + 1)));
     Ctx cx = lf_ctx(h);
     if (n > 0) hipLaunchKernelGGL(k_member_extra, dim3(grid_for(n, BS)), dim3(BS), 0, st, h->nh, cx.slot, n, capx);
     if (K > 0) hipLaunchKernelGGL(k_member_cap, dim3(grid_for(K, BS)), dim3(BS), 0, st, capx, h->cr, K, n);
@@ -517,7 +518,7 @@ static int rebuild_member_lists_async(lf_handle *h)
         LF_TRY(lf_dev_alloc(h, (void **)&h->cm_node, sizeof(int) * want));
         h->cm_cap = want;
     }
-    LF_HIP(h, hipMemsetAsync(h->cm_len, 0, sizeof(int) * (K > 0 ? K : 1), st));
+    LF_TRY(lf_zero(h, h->cm_len, sizeof(int) * (K > 0 ? K : 1)));
     if (n > 0)
         hipLaunchKernelGGL(k_member_fill, dim3(grid_for(n, BS)), dim3(BS), 0, st, h->nh, cx.slot, n, K, h->cm_off,
                            h->cm_len, h->cm_node, h->cm_cap);
@@ -792,15 +793,15 @@ int lf_iteration_end_enqueue(lf_handle *h)
     long long n = h->n;
     int K = h->K;
     Ctx cx = lf_ctx(h);
-    LF_HIP(h, hipMemsetAsync(&h->ctr->live, 0, sizeof(int) * 2, st));   // live, max_mem
-    LF_HIP(h, hipMemsetAsync(&h->ctr->ovf_cnt, 0, sizeof(int), st));
+    LF_TRY(lf_zero(h, &h->ctr->live, sizeof(int) * 2));   // live, max_mem
+    LF_TRY(lf_zero(h, &h->ctr->ovf_cnt, sizeof(int)));
     if (K > 0) hipLaunchKernelGGL(k_mark_dead, dim3(grid_for(K, BS)), dim3(BS), 0, st, cx);
     long long *newcap = nullptr, *noff = nullptr;
     LF_TRY(lf_tmp_alloc(h, (void **)&newcap, sizeof(long long) * (n + 1)));
     LF_TRY(lf_tmp_alloc(h, (void **)&noff, sizeof(long long) * (n + 1)));
     if (n > 0) hipLaunchKernelGGL(k_drop_dead, dim3(grid_for(n, BS)), dim3(BS), 0, st, cx, newcap);
     if (K > 0) hipLaunchKernelGGL(k_clear_dead, dim3(grid_for(K, BS)), dim3(BS), 0, st, cx);
-    LF_HIP(h, hipMemsetAsync(newcap + n, 0, sizeof(long long), st));
+    LF_TRY(lf_zero(h, newcap + n, sizeof(long long)));
     LF_TRY(lf_exclusive_scan_i64(h, newcap, noff, n + 1));
     // the new layout holds at most the current one's entries plus one per node (a node's
     // count grows only into its free slot), so the copy needs no wait for its size

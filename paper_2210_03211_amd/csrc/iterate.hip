@@ -1553,13 +1553,14 @@ static int size_queue_enqueue(lf_handle *h, long long q)
                        h->eval_wave_cap < 2 * VSMALL ? h->eval_wave_cap : 2 * VSMALL, h->eval_med_cap,
                        h->eval_grp_cap);
     if (h->hqoff_cap < nq + 1) {            // pinned, so the one copy below is truly asynchronous
-        if (h->hqoff) (void)hipHostFree(h->hqoff);
+        // (the last copy into the old buffer was read by the previous iteration start)
+        if (h->hqoff) lf_host_release(h->hqoff, sizeof(long long) * h->hqoff_len);
         h->hqoff = nullptr;
         h->hqoff_cap = 0;
-        if (hipHostMalloc((void **)&h->hqoff, sizeof(long long) * REP_LEN(nq),
-                          hipHostMallocDefault) != hipSuccess)
+        if (lf_host_alloc((void **)&h->hqoff, sizeof(long long) * REP_LEN(nq)) != LF_OK)
             return lf_set_error(h, LF_ENOMEM, "host queue offsets");
         h->hqoff_cap = nq + 1;
+        h->hqoff_len = REP_LEN(nq);
     }
     const long long nrep = REP_LEN(nq);    // list offsets, queue items, queue units, bounds
     if (nrep > h->dq_cap) {                 // kept across the two halves (and iterations)
@@ -1573,7 +1574,7 @@ static int size_queue_enqueue(lf_handle *h, long long q)
         LF_TRY(lf_dev_alloc(h, (void **)&h->titem_base, sizeof(long long) * (n + 1)));
         moved = true;
     }
-    LF_HIP(h, hipMemsetAsync(h->pbase, 0, sizeof(long long), st));
+    LF_TRY(lf_zero(h, h->pbase, sizeof(long long)));
     for (int c = 0; c < LF_PATH_COUNT; c++) {
         // titem_base serves as the flag array until the table-path items are laid out
         hipLaunchKernelGGL(k_class_flags, dim3(grid_for(n + 1, BS)), dim3(BS), 0, st, (const int *)h->cls, c,
@@ -1587,7 +1588,7 @@ static int size_queue_enqueue(lf_handle *h, long long q)
         hipLaunchKernelGGL(k_path_base, dim3(1), dim3(1), 0, st, (const long long *)h->cscan, n, c, h->pbase);
     }
     unsigned long long *dout = (unsigned long long *)(dq + REP_BOUNDS(nq));
-    LF_HIP(h, hipMemsetAsync(dout, 0, sizeof(unsigned long long) * 4, st));
+    LF_TRY(lf_zero(h, dout, sizeof(unsigned long long) * 4));
     hipLaunchKernelGGL(k_chunk_bounds, dim3((unsigned)nq), dim3(BS), 0, st, cx, (const long long *)h->vbound,
                        (const int *)h->cls, (int)q, dout);
     // static work-item layout of the table-path nodes (list position p owns deg + cnt + 1),
@@ -1714,7 +1715,7 @@ static int size_queue_complete(lf_handle *h, long long q)
 // Start of an iteration: buffers and path lists for queues of qq nodes, counters reset.
 // lf_iter_begin_enqueue queues the work; lf_iter_begin_complete must follow once it is done
 // (after a stream sync or a completed event recorded behind it).
-int lf_iter_begin_enqueue(lf_handle *h, long long qq)
+static int begin_enqueue_plain(lf_handle *h, long long qq)
 {
     LF_TRY(size_queue_enqueue(h, qq));
     if (h->n > 0) {
@@ -1724,10 +1725,133 @@ int lf_iter_begin_enqueue(lf_handle *h, long long qq)
         }
         hipLaunchKernelGGL(k_line_build, dim3(grid_for(h->n, 256)), dim3(256), 0, h->stream, lf_ctx(h));
     }
-    LF_HIP(h, hipMemsetAsync(&h->ctr->joins, 0, sizeof(unsigned long long) * 2, h->stream));
+    LF_TRY(lf_zero(h, &h->ctr->joins, sizeof(unsigned long long) * 2));
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, h->stream, lf_ctx(h));
     return LF_OK;
 }
+
+// ---- iteration starts and ends replayed from graphs --------------------------------
+// A member of a batch repeats the same launch sequence at every iteration start (and end):
+// the same buffers, sizes and temporaries, with only the slot buffer alternating.  Once a
+// plain run has left every allocation as it found it, the next run in the same state is
+// captured and later ones replay the graph: one host call for some thirty launches and
+// copies.  The key covers whatever the launches bake in (the Ctx, every allocation, the
+// temporaries' position, the options the start reads, the queue size and the slot
+// parity); any change makes the next run a plain one.
+static int finish_enqueue_plain(lf_handle *h);
+
+static unsigned long long fnv_add(unsigned long long k, const void *p, size_t n)
+{
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; i++) k = (k ^ b[i]) * 1099511628211ull;
+    return k;
+}
+
+static unsigned long long phase_key(lf_handle *h, long long qq, int which)
+{
+    unsigned long long k = 14695981039346656037ull;
+    Ctx cx = lf_ctx(h);
+    cx.qtag = 0;
+    // the path lists' record pointers move with the path counts at every start and are
+    // read only by the queue kernels
+    for (int c = 0; c < LF_PATH_COUNT; c++) cx.prec[c] = nullptr;
+    k = fnv_add(k, &cx, sizeof cx);
+    const long long v[] = {which, qq, h->cur, h->profiling, h->tmp_chunk, (long long)h->tmp_off,
+                           h->eval_wave_cap, h->eval_med_cap, h->eval_grp_cap,
+                           (long long)h->allocs->size(), (long long)h->tmp_chunks->size()};
+    k = fnv_add(k, v, sizeof v);
+    k = fnv_add(k, h->allocs->data(), sizeof(void *) * h->allocs->size());
+    k = fnv_add(k, h->alloc_sizes->data(), sizeof(size_t) * h->alloc_sizes->size());
+    for (const TmpChunk &c : *h->tmp_chunks) k = fnv_add(k, &c, sizeof c);
+    const void *hp[] = {h->hqoff, h->hrep};
+    k = fnv_add(k, hp, sizeof hp);
+    return k;
+}
+
+void lf_phase_graphs_drop(lf_handle *h)
+{
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            if (h->pg[a][b].exec) (void)hipGraphExecDestroy(h->pg[a][b].exec);
+            h->pg[a][b].exec = nullptr;
+            h->pg[a][b].key = 0;
+            h->pg[a][b].stable = 0;
+        }
+}
+
+// capture one plain run of the start (which = 0) or end (1) on the capture stream; the
+// host-side effects of the run (slot parity, start bookkeeping) happen as in a plain run
+static int capture_phase(lf_handle *h, int which, long long qq, hipGraphExec_t *exec)
+{
+    *exec = nullptr;
+    if (!h->cap_stream) LF_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipStream_t saved = h->stream;
+    LF_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    h->stream = h->cap_stream;
+    int rc = which == 0 ? begin_enqueue_plain(h, qq) : finish_enqueue_plain(h);
+    h->stream = saved;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc == LF_OK && (e != hipSuccess || !g)) rc = lf_set_error(h, LF_EDEVICE, "iteration phase capture failed");
+    if (rc == LF_OK && hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        *exec = nullptr;
+        rc = lf_set_error(h, LF_EDEVICE, "iteration phase graph instantiation failed");
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return rc;
+}
+
+// one iteration start (0) or end (1), from a graph where the state allows
+static int run_phase(lf_handle *h, int which, long long qq)
+{
+    if (!h->phase_graphs || h->profiling) {
+        h->phase_runs[0]++;
+        return which == 0 ? begin_enqueue_plain(h, qq) : finish_enqueue_plain(h);
+    }
+    PhaseGraph &pg = h->pg[which][h->cur];
+    // the end copies the slots into the other buffer; a replay cannot grow it
+    const bool fits = which == 0 || h->slot_used + h->n + 1 <= h->slot_capb[1 - h->cur];
+    const unsigned long long key = phase_key(h, qq, which);
+    if (fits && pg.exec && pg.key == key) {
+        LF_HIP(h, hipGraphLaunch(pg.exec, h->stream));
+        h->phase_runs[2]++;
+        if (which == 0) {
+            h->pending_moved = false;
+            h->fill_grid = pg.fill_grid;
+        } else {
+            h->cur = 1 - h->cur;
+        }
+        return LF_OK;
+    }
+    if (fits && pg.stable == key) {
+        if (pg.exec) (void)hipGraphExecDestroy(pg.exec);
+        pg.exec = nullptr;
+        pg.key = 0;
+        hipGraphExec_t ex = nullptr;
+        LF_TRY(capture_phase(h, which, qq, &ex));
+        pg.exec = ex;
+        pg.key = key;
+        pg.fill_grid = h->fill_grid;
+        LF_HIP(h, hipGraphLaunch(ex, h->stream));
+        h->phase_runs[1]++;
+        return LF_OK;
+    }
+    const int cur = h->cur;
+    h->phase_runs[0]++;
+    LF_TRY(which == 0 ? begin_enqueue_plain(h, qq) : finish_enqueue_plain(h));
+    // stable if the run changed no allocation (the end flips the parity: key it as it was)
+    const int now = h->cur;
+    h->cur = cur;
+    const bool same = phase_key(h, qq, which) == key;
+    h->cur = now;
+    h->pg[which][cur].stable = same ? key : 0;
+    return LF_OK;
+}
+
+int lf_iter_begin_enqueue(lf_handle *h, long long qq) { return run_phase(h, 0, qq); }
+
+int lf_iter_finish_enqueue(lf_handle *h) { return run_phase(h, 1, 0); }
 
 int lf_iter_begin_complete(lf_handle *h, long long qq, long long *nq)
 {
@@ -1877,7 +2001,7 @@ int lf_lines_back(lf_handle *h)
     return hipGetLastError() == hipSuccess ? LF_OK : LF_EDEVICE;
 }
 
-int lf_iter_finish_enqueue(lf_handle *h)
+static int finish_enqueue_plain(lf_handle *h)
 {
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(WAVE), 0, h->stream, lf_ctx(h));
     if (h->n > 0) hipLaunchKernelGGL(k_line_back, dim3(grid_for(h->n, 256)), dim3(256), 0, h->stream, lf_ctx(h));

@@ -219,6 +219,15 @@ struct TmpMark {
     size_t off;
 };
 
+// An iteration start or end captured into a graph, for one slot-buffer parity: key of
+// the state it was captured in, key of the last plain run that changed no allocation (the
+// next run in that state is captured), and what the start leaves on the host.
+struct PhaseGraph {
+    unsigned long long key, stable;
+    hipGraphExec_t exec;
+    unsigned fill_grid;
+};
+
 struct lf_handle {
     int device;
     hipStream_t stream;
@@ -273,6 +282,7 @@ struct lf_handle {
                              // queue, then [nq + 1] first table-path work item per queue,
                              // then the 4 bounds of k_chunk_bounds
     long long hqoff_cap;     // queues (nq + 1) it has room for
+    long long hqoff_len;     // its length in long longs (as allocated)
     long long *hrep;         // pinned host report of an iteration end (REP_* entries)
     long long slot_used;     // slot entries of the current layout (nh[n].off)
     int last_dev_error;      // device error flags read with the last iteration-end report
@@ -322,6 +332,11 @@ struct lf_handle {
     int tmp_chunk;
     size_t tmp_off;
     size_t dev_bytes, dev_bytes_peak;   // device memory the handle holds (now / at most)
+    // iteration starts and ends replayed from graphs (members of a batch)
+    int phase_graphs;
+    PhaseGraph pg[2][2];                // [start, end][slot parity]
+    long long phase_runs[3];            // starts and ends run plainly, captured, replayed
+    hipStream_t cap_stream;             // the stream they are captured on
 };
 
 // ---- host helpers --------------------------------------------------------------------
@@ -343,6 +358,15 @@ int lf_set_error(lf_handle *h, int code, const char *fmt, ...);
 
 int lf_dev_alloc(lf_handle *h, void **p, size_t bytes);
 void lf_dev_free(lf_handle *h, void *p);
+// size an lf_dev_alloc request occupies; a block whose device work has completed goes
+// back to the per-device cache (or to HIP)
+size_t lf_alloc_class(size_t bytes);
+void lf_dev_release(int device, void *p, size_t bytes);
+int lf_host_alloc(void **p, size_t bytes);       // pinned, from the same kind of cache
+int lf_zero(lf_handle *h, void *p, size_t bytes); // kernel fill on h->stream (bytes % 4 == 0)
+void lf_phase_graphs_drop(lf_handle *h);
+extern "C" int lf_batch_detach(lf_batch *b, int32_t member_id, hipEvent_t *left);
+void lf_host_release(void *p, size_t bytes);
 int lf_tmp_alloc(lf_handle *h, void **p, size_t bytes);
 TmpMark lf_tmp_mark(lf_handle *h);
 void lf_tmp_release(lf_handle *h, TmpMark m);

@@ -1,7 +1,10 @@
 // prims.hip -- library primitives: device-wide LSD radix sorts and exclusive prefix sums
 // written for gfx950 (wave64 ballots, LDS tiles), plus the handle's allocation registry
 // and error/profiling helpers.
+#include <map>
+#include <mutex>
 #include <stdarg.h>
+#include <utility>
 
 #include "lf_internal.h"
 
@@ -16,11 +19,128 @@ int lf_set_error(lf_handle *h, int code, const char *fmt, ...)
     return code;
 }
 
+// Device blocks of destroyed handles, kept per device and size class for later handles.
+// hipFree waits for the whole device, so a serving loop that retires jobs while others
+// run would stall the device at every retirement; a block goes back to HIP only when the
+// cache is full or the block is large.  Blocks are allocated at their class size (eight
+// classes per power of two), so one class serves every request it covers.
+namespace {
+struct BlockCache {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void *>> free;   // device blocks
+    std::map<size_t, std::vector<void *>> host;                  // pinned host blocks
+    size_t bytes = 0;
+};
+BlockCache &block_cache()
+{
+    static BlockCache *c = new BlockCache();   // never destroyed: handles may outlive statics
+    return *c;
+}
+constexpr size_t CACHE_BLOCK_MAX = 256ull << 20;
+constexpr size_t CACHE_TOTAL_MAX = 8ull << 30;
+
+size_t size_class(size_t b)
+{
+    if (b <= 256) return 256;
+    const int lg = 63 - __builtin_clzll((unsigned long long)(b - 1));    // 2^lg < b <= 2^(lg+1)
+    const size_t step = (size_t)1 << (lg - 3);
+    return (b + step - 1) / step * step;
+}
+}  // namespace
+
+size_t lf_alloc_class(size_t bytes) { return size_class(bytes == 0 ? 256 : bytes); }
+
+// a block whose last use on the device has completed (the caller has synchronised)
+void lf_dev_release(int device, void *p, size_t bytes)
+{
+    if (!p) return;
+    BlockCache &c = block_cache();
+    if (bytes <= CACHE_BLOCK_MAX && bytes == size_class(bytes)) {
+        std::lock_guard<std::mutex> g(c.mu);
+        if (c.bytes + bytes <= CACHE_TOTAL_MAX) {
+            c.free[{device, bytes}].push_back(p);
+            c.bytes += bytes;
+            return;
+        }
+    }
+    (void)hipFree(p);
+}
+
+// pinned host memory of the same class scheme (hipHostFree may wait for the device too)
+int lf_host_alloc(void **p, size_t bytes)
+{
+    *p = nullptr;
+    bytes = lf_alloc_class(bytes);
+    {
+        BlockCache &c = block_cache();
+        std::lock_guard<std::mutex> g(c.mu);
+        auto it = c.host.find(bytes);
+        if (it != c.host.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            return LF_OK;
+        }
+    }
+    if (hipHostMalloc(p, bytes, hipHostMallocDefault) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return LF_ENOMEM;
+    }
+    return LF_OK;
+}
+
+// a pinned block no pending copy writes any more, of the size lf_host_alloc was asked for
+void lf_host_release(void *p, size_t bytes)
+{
+    if (!p) return;
+    bytes = lf_alloc_class(bytes);
+    if (bytes <= ((size_t)1 << 20)) {
+        BlockCache &c = block_cache();
+        std::lock_guard<std::mutex> g(c.mu);
+        if (c.host[bytes].size() < 4096) {
+            c.host[bytes].push_back(p);
+            return;
+        }
+    }
+    (void)hipHostFree(p);
+}
+
+// zero `bytes` (a multiple of 4) at p with a kernel on the handle's stream: the iteration
+// starts and ends, which a batch captures into graphs, clear with kernels only
+__global__ void k_zero_words(unsigned *p, long long words)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < words;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+int lf_zero(lf_handle *h, void *p, size_t bytes)
+{
+    if (bytes % 4 != 0) return lf_set_error(h, LF_EINTERNAL, "lf_zero of %zu bytes", bytes);
+    const long long words = (long long)(bytes / 4);
+    if (words == 0) return LF_OK;
+    long long g = (words + 255) / 256;
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)g), dim3(256), 0, h->stream, (unsigned *)p, words);
+    LF_HIP(h, hipGetLastError());
+    return LF_OK;
+}
+
 int lf_dev_alloc(lf_handle *h, void **p, size_t bytes)
 {
     *p = nullptr;
-    if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(p, bytes);
+    bytes = lf_alloc_class(bytes);
+    if (bytes <= CACHE_BLOCK_MAX) {
+        BlockCache &c = block_cache();
+        std::lock_guard<std::mutex> g(c.mu);
+        auto it = c.free.find({h->device, bytes});
+        if (it != c.free.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            c.bytes -= bytes;
+        }
+    }
+    hipError_t e = *p ? hipSuccess : hipMalloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
