@@ -120,14 +120,15 @@ def apply_bytes(kernel, work):
 
 
 def kernel_bytes(kernel, work):
-    """Algorithmic bytes one pass moves through `kernel` (None if no model for it).  The
-    small path's work is counted under k_eval: on the benchmark workload its queues (>= 1024
-    small-path nodes) all launch it."""
+    """Algorithmic bytes one pass moves through `kernel` (None if no model for it).  A single
+    graph's medium-path nodes are evaluated by k_eval, and so is the small path's work on
+    the benchmark workload (its queues, >= 1024 small-path nodes, all give them k_eval
+    blocks); k_eval_big holds the workgroup path and the table path's visits."""
     paths = work["paths"]
     if kernel == "k_eval":
-        return path_bytes(paths["small"])
+        return path_bytes(paths["small"]) + path_bytes(paths["medium"])
     if kernel == "k_eval_big":
-        return path_bytes(paths["medium"]) + path_bytes(paths["group"]) + path_bytes(paths["table"], False)
+        return path_bytes(paths["group"]) + path_bytes(paths["table"], False)
     if kernel == "k_big_final":
         return B_CAND * paths["table"]["candidates"]
     return apply_bytes(kernel, work)

@@ -64,6 +64,15 @@ def load_library():
     if not os.path.exists(_LIB_PATH):
         raise ImportError("liblazyfox.so is not built (run `python -m paper_2210_03211_amd.build` "
                           "or __graft_entry__.build()); the HIP library is required")
+    # PyTorch's ROCm wheels carry a HIP runtime of their own: when both are in the process,
+    # torch's must have initialised the device before the library is loaded, or the
+    # library's runtime finds no device
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     L = C.CDLL(_LIB_PATH)
     vp, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
     sig = {

@@ -14,6 +14,7 @@
 // arrival order while their estimated device footprint fits the budget, steps the batch,
 // and retires finished jobs (memberships copied back, device memory released), so jobs
 // that arrive while others run join as memory frees up.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -47,6 +48,9 @@ struct lf_batch {
     hipStream_t stream;
     bool own_stream;
     std::vector<BatchMember *> members;      // by member id; nullptr once removed
+    std::vector<BatchMember *> live;         // members still iterating (any order)
+    std::deque<BatchMember *> waitq;         // members whose queued start or end is not yet
+                                             // read, in queue order (the stream runs them so)
     Member *hmem[2];
     int *hboff[2];
     hipEvent_t hev[2];
@@ -304,44 +308,57 @@ int lf_batch_add(lf_batch *b, lf_handle *h, int32_t queue_size, double threshold
     m->hist.push_back(h->Wt);
     *member_id = (int32_t)b->members.size();
     b->members.push_back(m);
+    if (m->state == 0) b->live.push_back(m);
     return LF_OK;
+}
+
+// a member's queued start or end has completed: read its report and move it on
+static int member_phase_done(BatchMember *m)
+{
+    if (m->phase == PH_END_WAIT) return member_iteration_done(m);   // PH_BEGIN, or done
+    int rc = lf_iter_begin_complete(m->h, m->qq, &m->nq);
+    if (rc == LF_OK) {
+        m->cx = lf_ctx(m->h);
+        m->k = 0;
+        m->phase = PH_RUN;
+    }
+    return rc;
+}
+
+static void drop_member(lf_batch *b, BatchMember *m)
+{
+    auto w = std::find(b->waitq.begin(), b->waitq.end(), m);
+    if (w != b->waitq.end()) b->waitq.erase(w);
+    auto l = std::find(b->live.begin(), b->live.end(), m);
+    if (l != b->live.end()) {
+        *l = b->live.back();
+        b->live.pop_back();
+    }
 }
 
 int lf_batch_step(lf_batch *b, int32_t *running)
 {
     if (!b) return LF_EINVAL;
     std::vector<BatchMember *> act;
-    BatchMember *waiting = nullptr;
     auto tp = std::chrono::steady_clock::now();
-    for (BatchMember *m : b->members) {
-        if (!m || m->state != 0) continue;
-        if (m->phase == PH_END_WAIT || m->phase == PH_BEGIN_WAIT) {
-            hipError_t q = hipEventQuery(m->ev);
-            if (q == hipErrorNotReady) {
-                if (!waiting) waiting = m;
-                continue;
-            }
-            if (q != hipSuccess) {
-                m->state = LF_EDEVICE;
-                continue;
-            }
-            int rc = LF_OK;
-            if (m->phase == PH_END_WAIT) {
-                rc = member_iteration_done(m);        // PH_BEGIN, or done
-            } else {
-                rc = lf_iter_begin_complete(m->h, m->qq, &m->nq);
-                if (rc == LF_OK) {
-                    m->cx = lf_ctx(m->h);
-                    m->k = 0;
-                    m->phase = PH_RUN;
-                }
-            }
-            if (rc != LF_OK) {
-                m->state = rc;
-                continue;
-            }
-            if (m->state != 0) continue;
+    // queued starts and ends that have completed, oldest first: the batch stream runs
+    // them in queue order, so the first one not done ends the scan
+    while (!b->waitq.empty()) {
+        BatchMember *m = b->waitq.front();
+        hipError_t q = hipEventQuery(m->ev);
+        if (q == hipErrorNotReady) break;
+        b->waitq.pop_front();
+        int rc = q == hipSuccess ? member_phase_done(m) : LF_EDEVICE;
+        if (rc != LF_OK) m->state = rc;
+    }
+    for (size_t i = 0; i < b->live.size();) {
+        BatchMember *m = b->live[i];
+        if (m->state != 0) {                  // done or failed: no longer stepped
+            b->live[i] = b->live.back();
+            b->live.pop_back();
+            continue;
         }
+        i++;
         if (m->phase == PH_BEGIN) {
             int rc = lf_iter_begin_enqueue(m->h, m->qq);
             if (rc == LF_OK && hipEventRecord(m->ev, b->stream) != hipSuccess) rc = LF_EDEVICE;
@@ -350,16 +367,17 @@ int lf_batch_step(lf_batch *b, int32_t *running)
                 continue;
             }
             m->phase = PH_BEGIN_WAIT;
-            if (!waiting) waiting = m;
-            continue;
+            b->waitq.push_back(m);
+        } else if (m->phase == PH_RUN) {
+            act.push_back(m);
         }
-        act.push_back(m);
     }
     b->phase_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
-    if (act.empty() && waiting) {
+    if (act.empty() && !b->waitq.empty()) {
         // nothing to launch: wait for the oldest queued start or end instead of spinning
         auto t0 = std::chrono::steady_clock::now();
-        if (hipEventSynchronize(waiting->ev) != hipSuccess) return batch_error(b, LF_EDEVICE, "event sync failed");
+        if (hipEventSynchronize(b->waitq.front()->ev) != hipSuccess)
+            return batch_error(b, LF_EDEVICE, "event sync failed");
         b->wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     const int nm = (int)act.size();
@@ -408,15 +426,19 @@ int lf_batch_step(lf_batch *b, int32_t *running)
             if (m->k == m->nq) {
                 int rc = lf_iter_finish_enqueue(m->h);
                 if (rc == LF_OK && hipEventRecord(m->ev, b->stream) != hipSuccess) rc = LF_EDEVICE;
-                if (rc != LF_OK) m->state = rc;
-                else m->phase = PH_END_WAIT;
+                if (rc != LF_OK) {
+                    m->state = rc;
+                } else {
+                    m->phase = PH_END_WAIT;
+                    b->waitq.push_back(m);
+                }
             }
         }
         b->phase_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t3).count();
     }
     int live = 0;
-    for (BatchMember *m : b->members)
-        if (m && m->state == 0) live++;
+    for (BatchMember *m : b->live)
+        if (m->state == 0) live++;
     if (running) *running = live;
     return LF_OK;
 }
@@ -455,6 +477,7 @@ int lf_batch_remove(lf_batch *b, int32_t member_id)
     if (!b || member_id < 0 || member_id >= (int32_t)b->members.size() || !b->members[member_id])
         return LF_EINVAL;
     BatchMember *m = b->members[member_id];
+    drop_member(b, m);
     // mid-iteration the memberships live in the handle's lines: back to its slot layout
     if (m->state == 0 && m->phase == PH_RUN) (void)lf_lines_back(m->h);
     (void)hipStreamSynchronize(b->stream);
@@ -476,6 +499,7 @@ int lf_batch_detach(lf_batch *b, int32_t member_id, hipEvent_t *left)
     if (!b || member_id < 0 || member_id >= (int32_t)b->members.size() || !b->members[member_id])
         return LF_EINVAL;
     BatchMember *m = b->members[member_id];
+    drop_member(b, m);
     if (m->state == 0 && m->phase == PH_RUN) (void)lf_lines_back(m->h);
     int rc = hipEventRecord(m->ev, b->stream) == hipSuccess ? LF_OK : LF_EDEVICE;
     *left = m->ev;
@@ -571,13 +595,13 @@ static double ms_since(std::chrono::steady_clock::time_point t0)
 }
 
 // Device bytes a job may hold at most: graph build scratch, CSR, node arrays, membership
-// slots, community records and member lists, and the per-queue work lists; blocks are
-// rounded up to their allocation class (at most one eighth more).
+// slots, community records and member lists (grown faster in a batch), and the per-queue
+// work lists; blocks are rounded up to their allocation class (at most one eighth more).
 static size_t job_footprint(long long n, long long npairs, int q)
 {
     long long nn = n > 0 ? n : 1;
     long long qq = q < nn ? q : nn;
-    size_t b = (size_t)(48ll << 20) + (size_t)nn * 480 + (size_t)npairs * 64 + (size_t)qq * 256;
+    size_t b = (size_t)(48ll << 20) + (size_t)nn * 768 + (size_t)npairs * 64 + (size_t)qq * 256;
     return b + b / 8;
 }
 

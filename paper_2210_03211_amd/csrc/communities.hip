@@ -529,10 +529,12 @@ static int rebuild_member_lists_async(lf_handle *h)
 // grow cm_node to hold `total` member entries and fill the lists again (waits)
 static int grow_member_lists(lf_handle *h, long long total)
 {
-    LF_HIP(h, hipStreamSynchronize(h->stream));
+    if (!h->phase_graphs) LF_HIP(h, hipStreamSynchronize(h->stream));   // a batch member keeps the old list
     lf_dev_free(h, h->cm_node);
     h->cm_node = nullptr;
-    long long want = total + total / 8 + 1024;
+    // grown two-fold (four-fold for a batch member, whose captured iteration starts and
+    // ends a moved buffer invalidates), so a growing cover reallocates only a few times
+    long long want = (h->phase_graphs ? 4 : 2) * total + 1024;
     LF_TRY(lf_dev_alloc(h, (void **)&h->cm_node, sizeof(int) * want));
     h->cm_cap = want;
     return rebuild_member_lists_async(h);
@@ -808,7 +810,7 @@ int lf_iteration_end_enqueue(lf_handle *h)
     int other = 1 - h->cur;
     const long long bound = h->slot_used + n + 1;
     if (bound > h->slot_capb[other]) {
-        long long want = bound + bound / 4 + 1024;
+        long long want = (h->phase_graphs ? 3 * bound : bound + bound / 2) + 1024;
         lf_dev_free(h, h->slot[other]);
         h->slot[other] = nullptr;
         LF_TRY(lf_dev_alloc(h, (void **)&h->slot[other], sizeof(Slot) * want));
@@ -839,7 +841,7 @@ int lf_iteration_end_complete(lf_handle *h, long long *joins, long long *leaves,
     h->slot_used = r[REP_SLOTS];
     if (r[REP_MEMBERS] > h->cm_cap) {        // rare: member lists outgrew their buffer
         LF_TRY(grow_member_lists(h, r[REP_MEMBERS]));
-        LF_HIP(h, hipStreamSynchronize(st));
+        if (!h->phase_graphs) LF_HIP(h, hipStreamSynchronize(st));
     }
     double wt;
     memcpy(&wt, &r[REP_SCORE], sizeof wt);

@@ -479,27 +479,39 @@ __device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg, int ow
 // The in-LDS evaluation paths take their queue's nodes from their path lists; the path
 // was chosen so that the node fits, and a node that does not is an internal error.
 
-// Small wave path on its own launch (one wave per node, 21 KB of LDS per block, so seven
-// blocks per CU): used for queues with many small-path nodes; otherwise the small path is
-// a block role of k_eval_big.  Block 0 also resets the queue's apply counters.
-struct EvalLds {
+// The small and medium paths of a single graph's queue in one launch of 256-thread
+// blocks with 21 KB of LDS (seven blocks per CU): the first es blocks evaluate small-path
+// nodes, one wave each (queues with many of them; otherwise they are a block role of
+// k_eval_big), the next em blocks one medium-path node each, one visit per thread.
+// Block 0 also resets the queue's apply counters.
+union EvalLds {
     NodeLds<VSMALL> w[EW];
+    NodeLds<VMED> m;
 };
 
 __device__ __forceinline__ void body_eval(const Ctx &cx, const QStep &qs, int blk, int nblk, EvalLds &L)
 {
     (void)nblk;
     const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    const int p = blk * EW + wv;
     if (blk == 0 && threadIdx.x == 0) {
         DevCounters *c = cx.ctr;
         c->parts_total = 0;
         c->mslots = 0;
     }
-    if (p >= qs.ln) return;                 // no block barriers in this kernel
-    const int j = cx.plist[LF_PATH_SMALL][qs.ls + p] - qs.cstart;
-    const NodeRec nr = cx.prec[LF_PATH_SMALL][qs.ls + p];
-    if (!eval_node<WAVE, VSMALL>(cx, j, nr, lane, L.w[wv], qs.wcap, LF_PATH_SMALL) && lane == 0)
+    if (blk < qs.es) {
+        const int p = blk * EW + wv;
+        if (p >= qs.ln) return;             // small blocks have no block barriers
+        const int j = cx.plist[LF_PATH_SMALL][qs.ls + p] - qs.cstart;
+        const NodeRec nr = cx.prec[LF_PATH_SMALL][qs.ls + p];
+        if (!eval_node<WAVE, VSMALL>(cx, j, nr, lane, L.w[wv], qs.wcap, LF_PATH_SMALL) && lane == 0)
+            atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
+        return;
+    }
+    const int m = blk - qs.es;              // a medium block: every thread takes part
+    if (m >= qs.em) return;
+    const int j = cx.plist[LF_PATH_MED][qs.br.lm + m] - qs.cstart;
+    const NodeRec nr = cx.prec[LF_PATH_MED][qs.br.lm + m];
+    if (!eval_node<EW * WAVE, VMED>(cx, j, nr, threadIdx.x, L.m, qs.mcap, LF_PATH_MED) && threadIdx.x == 0)
         atomicOr(&cx.ctr->error, LF_DEVERR_CAP);
 }
 
@@ -1668,7 +1680,7 @@ static int size_queue_complete(lf_handle *h, long long q)
     if (items > h->titem_cap) {             // rare: grow and lay the items out again
         lf_dev_free(h, h->titem_node);
         h->titem_node = nullptr;
-        long long want = items + items / 8 + 1024;
+        long long want = (h->phase_graphs ? 4 : 2) * items + 1024;
         LF_TRY(lf_dev_alloc(h, (void **)&h->titem_node, sizeof(int) * want));
         h->titem_cap = want;
         moved = true;
@@ -1678,6 +1690,7 @@ static int size_queue_complete(lf_handle *h, long long q)
     long long T = 1024;
     while (T < 2 * keys) T <<= 1;
     if (T > h->gT) {
+        if (h->phase_graphs) T *= 4;        // a batch member's graphs survive more growth
         void **ptrs[] = {(void **)&h->gt, (void **)&h->occ, (void **)&h->occ_key, (void **)&h->occ_d};
         for (void **p : ptrs) {
             lf_dev_free(h, *p);
@@ -1694,6 +1707,7 @@ static int size_queue_complete(lf_handle *h, long long q)
     }
     long long pcap = 2 * q + (h->cm_cap + n) / PART + 64;
     if (pcap > h->part_cap) {
+        if (h->phase_graphs) pcap *= 2;
         lf_dev_free(h, h->part_rec);
         h->part_rec = nullptr;
         LF_TRY(lf_dev_alloc(h, (void **)&h->part_rec, sizeof(PartRec) * pcap));
@@ -1732,12 +1746,13 @@ static int begin_enqueue_plain(lf_handle *h, long long qq)
 
 // ---- iteration starts and ends replayed from graphs --------------------------------
 // A member of a batch repeats the same launch sequence at every iteration start (and end):
-// the same buffers, sizes and temporaries, with only the slot buffer alternating.  Once a
-// plain run has left every allocation as it found it, the next run in the same state is
-// captured and later ones replay the graph: one host call for some thirty launches and
-// copies.  The key covers whatever the launches bake in (the Ctx, every allocation, the
-// temporaries' position, the options the start reads, the queue size and the slot
-// parity); any change makes the next run a plain one.
+// the same buffers, sizes and temporaries, with only the slot buffer alternating.  A run
+// that will allocate nothing (the host makes the run's own size checks first) is captured
+// and later runs in the same state replay the graph: one host call for some thirty
+// launches and copies.  The key covers whatever the launches bake in (the Ctx, every
+// allocation, the temporaries' position, the options the start reads, the queue size and
+// the slot parity); after a change the next run is captured again (the graph is updated
+// in place).
 static int finish_enqueue_plain(lf_handle *h);
 
 static unsigned long long fnv_add(unsigned long long k, const void *p, size_t n)
@@ -1775,15 +1790,15 @@ void lf_phase_graphs_drop(lf_handle *h)
             if (h->pg[a][b].exec) (void)hipGraphExecDestroy(h->pg[a][b].exec);
             h->pg[a][b].exec = nullptr;
             h->pg[a][b].key = 0;
-            h->pg[a][b].stable = 0;
         }
 }
 
 // capture one plain run of the start (which = 0) or end (1) on the capture stream; the
-// host-side effects of the run (slot parity, start bookkeeping) happen as in a plain run
+// host-side effects of the run (slot parity, start bookkeeping) happen as in a plain run.
+// *exec, if set, is updated in place when the new graph has its shape (a moved buffer
+// changes only kernel arguments), else replaced.
 static int capture_phase(lf_handle *h, int which, long long qq, hipGraphExec_t *exec)
 {
-    *exec = nullptr;
     if (!h->cap_stream) LF_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     hipStream_t saved = h->stream;
     LF_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -1793,7 +1808,16 @@ static int capture_phase(lf_handle *h, int which, long long qq, hipGraphExec_t *
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
     if (rc == LF_OK && (e != hipSuccess || !g)) rc = lf_set_error(h, LF_EDEVICE, "iteration phase capture failed");
-    if (rc == LF_OK && hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    if (rc == LF_OK && *exec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        if (hipGraphExecUpdate(*exec, g, &err_node, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(*exec);
+            *exec = nullptr;
+        }
+    }
+    if (rc == LF_OK && !*exec && hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) {
         *exec = nullptr;
         rc = lf_set_error(h, LF_EDEVICE, "iteration phase graph instantiation failed");
     }
@@ -1802,18 +1826,32 @@ static int capture_phase(lf_handle *h, int which, long long qq, hipGraphExec_t *
     return rc;
 }
 
+// whether a start (0) or end (1) would allocate: its size checks, made on the host
+// beforehand (the temporaries it takes exist once it has run plainly)
+static bool phase_allocates(lf_handle *h, int which, long long qq)
+{
+    if (!h->phase_ran[which]) return true;
+    const long long n = h->n;
+    if (which == 1) return !h->cm_node || h->slot_used + n + 1 > h->slot_capb[1 - h->cur];
+    const long long nq = (n + qq - 1) / qq;
+    const long long nrep = REP_LEN(nq);
+    const long long ucap = n + 2 * h->ne / INB + 1;
+    return qq > h->q_cap || h->hqoff_cap < nq + 1 || nrep > h->dq_cap || !h->titem_base || !h->titem_node ||
+           ucap > h->unit_cap || (n > 0 && !h->lines);
+}
+
 // one iteration start (0) or end (1), from a graph where the state allows
 static int run_phase(lf_handle *h, int which, long long qq)
 {
     if (!h->phase_graphs || h->profiling) {
         h->phase_runs[0]++;
+        h->phase_ran[which] = 1;
         return which == 0 ? begin_enqueue_plain(h, qq) : finish_enqueue_plain(h);
     }
     PhaseGraph &pg = h->pg[which][h->cur];
-    // the end copies the slots into the other buffer; a replay cannot grow it
-    const bool fits = which == 0 || h->slot_used + h->n + 1 <= h->slot_capb[1 - h->cur];
     const unsigned long long key = phase_key(h, qq, which);
-    if (fits && pg.exec && pg.key == key) {
+    const bool allocates = phase_allocates(h, which, qq);
+    if (!allocates && pg.exec && pg.key == key) {
         LF_HIP(h, hipGraphLaunch(pg.exec, h->stream));
         h->phase_runs[2]++;
         if (which == 0) {
@@ -1824,29 +1862,17 @@ static int run_phase(lf_handle *h, int which, long long qq)
         }
         return LF_OK;
     }
-    if (fits && pg.stable == key) {
-        if (pg.exec) (void)hipGraphExecDestroy(pg.exec);
-        pg.exec = nullptr;
-        pg.key = 0;
-        hipGraphExec_t ex = nullptr;
-        LF_TRY(capture_phase(h, which, qq, &ex));
-        pg.exec = ex;
+    if (!allocates) {
+        LF_TRY(capture_phase(h, which, qq, &pg.exec));
         pg.key = key;
         pg.fill_grid = h->fill_grid;
-        LF_HIP(h, hipGraphLaunch(ex, h->stream));
+        LF_HIP(h, hipGraphLaunch(pg.exec, h->stream));
         h->phase_runs[1]++;
         return LF_OK;
     }
-    const int cur = h->cur;
     h->phase_runs[0]++;
-    LF_TRY(which == 0 ? begin_enqueue_plain(h, qq) : finish_enqueue_plain(h));
-    // stable if the run changed no allocation (the end flips the parity: key it as it was)
-    const int now = h->cur;
-    h->cur = cur;
-    const bool same = phase_key(h, qq, which) == key;
-    h->cur = now;
-    h->pg[which][cur].stable = same ? key : 0;
-    return LF_OK;
+    h->phase_ran[which] = 1;
+    return which == 0 ? begin_enqueue_plain(h, qq) : finish_enqueue_plain(h);
 }
 
 int lf_iter_begin_enqueue(lf_handle *h, long long qq) { return run_phase(h, 0, qq); }
@@ -1900,8 +1926,12 @@ void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool
     br.bt = ln[LF_PATH_TABLE] > 0 ? (int)grid_for(titems, 2 * EWB * WAVE) : 0;
     if (br.bt > gb) br.bt = gb;
     br.bg = ln[LF_PATH_GROUP] < gb ? ln[LF_PATH_GROUP] : gb;
-    br.bm = (int)grid_for(ln[LF_PATH_MED], GT / WAVE);
-    // a queue with many small-path nodes gives them a launch of their own (more blocks per
+    // a single graph's medium-path nodes take one k_eval block each (one visit per thread,
+    // seven blocks per CU); in a multi-graph step they are a role of k_eval_big (one wave
+    // per node), as is everything there
+    const bool own_med = !compact_grids;
+    br.bm = own_med ? 0 : (int)grid_for(ln[LF_PATH_MED], GT / WAVE);
+    // a queue with many small-path nodes gives them blocks of k_eval too (more blocks per
     // CU than the fused kernel's LDS allows); otherwise they are a role of k_eval_big
     const bool own_small = !compact_grids && ln[LF_PATH_SMALL] >= SMALL_OWN_LAUNCH;
     br.ns = own_small ? 0 : ln[LF_PATH_SMALL];
@@ -1911,10 +1941,12 @@ void lf_queue_params(lf_handle *h, long long k, long long nq, long long qq, bool
     br.lg = ls[LF_PATH_GROUP];
     br.ng = ln[LF_PATH_GROUP];
     br.lm = ls[LF_PATH_MED];
-    br.nm = ln[LF_PATH_MED];
+    br.nm = own_med ? 0 : ln[LF_PATH_MED];
     qs->ub = hu[k];
     qs->un = (int)(hu[k + 1] - hu[k]);
-    g->eval = own_small ? (int)grid_for(ln[LF_PATH_SMALL], EW) : 0;
+    qs->es = own_small ? (int)grid_for(ln[LF_PATH_SMALL], EW) : 0;
+    qs->em = own_med ? ln[LF_PATH_MED] : 0;
+    g->eval = qs->es + qs->em;
     g->big = br.bt + br.bg + br.bm + br.bs;
     if (g->big < 1 && g->eval == 0) g->big = 1;   // block 0 resets the queue's counters
     g->fin = ln[LF_PATH_TABLE] > 0 ? (compact_grids ? (br.bt > 0 ? br.bt : 1) : gb) : 0;

@@ -193,6 +193,8 @@ struct QStep {
     int cstart, clen;        // the queue: order positions [cstart, cstart + clen)
     int wcap, mcap, gcap;    // LDS table sizes of the small, medium and workgroup paths
     int ls, ln;              // small-path list positions
+    int es, em;              // k_eval: blocks of small-path nodes (four per block), then one
+                             // block per medium-path node (the first em of list br.lm)
     BigRoles br;
     long long ub;            // the queue's in-count units: [ub, ub + un)
     int un;
@@ -220,10 +222,9 @@ struct TmpMark {
 };
 
 // An iteration start or end captured into a graph, for one slot-buffer parity: key of
-// the state it was captured in, key of the last plain run that changed no allocation (the
-// next run in that state is captured), and what the start leaves on the host.
+// the state it was captured in, and what the start leaves on the host.
 struct PhaseGraph {
-    unsigned long long key, stable;
+    unsigned long long key;
     hipGraphExec_t exec;
     unsigned fill_grid;
 };
@@ -336,6 +337,7 @@ struct lf_handle {
     int phase_graphs;
     PhaseGraph pg[2][2];                // [start, end][slot parity]
     long long phase_runs[3];            // starts and ends run plainly, captured, replayed
+    int phase_ran[2];                   // a start / an end has run plainly (its temporaries exist)
     hipStream_t cap_stream;             // the stream they are captured on
 };
 

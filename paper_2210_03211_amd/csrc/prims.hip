@@ -156,6 +156,10 @@ int lf_dev_alloc(lf_handle *h, void **p, size_t bytes)
 void lf_dev_free(lf_handle *h, void *p)
 {
     if (!p) return;
+    // a batch member's superseded block may still be read by work queued on the shared
+    // stream: it stays the handle's until lf_destroy, which waits for the handle's work
+    // (no hipFree here, which would wait for the whole device)
+    if (h->phase_graphs) return;
     for (size_t k = 0; k < h->allocs->size(); k++)
         if ((*h->allocs)[k] == p) {
             h->dev_bytes -= (*h->alloc_sizes)[k];
