@@ -68,13 +68,13 @@ def parse():
     ap.add_argument("--options", default="",
                     help="fixed options instead of tuning, e.g. wave_table=128,med_table=512,grp_table=2048,"
                          "hub_blocks=1024,refresh_blocks=1024")
-    ap.add_argument("--serving-jobs", type=int, default=300,
+    ap.add_argument("--serving-jobs", type=int, default=10000,
                     help="jobs of the serving comparison (0 = skip it)")
     ap.add_argument("--serving-rate", type=float, default=200.0, help="Poisson arrival rate (jobs/s)")
     ap.add_argument("--serving-max-batch", type=int, default=256)
     ap.add_argument("--serving-budget-gib", type=float, default=64.0)
     ap.add_argument("--serving-no-graph", action="store_true", help="issue batch steps launch by launch")
-    ap.add_argument("--serving-plain-jobs", type=int, default=-1,
+    ap.add_argument("--serving-plain-jobs", type=int, default=500,
                     help="jobs of the trace (a prefix, in arrival order) also run one at a time (-1: all)")
     return ap.parse_args()
 

@@ -35,7 +35,10 @@ struct BatchMember {
     int it;                  // iterations completed
     int phase;               // PH_*: where the member is between and within iterations
     hipEvent_t ev;           // recorded behind its queued iteration start or end
+    hipEvent_t ran;          // recorded behind its last queue step (its end waits for it)
+    int side;                // side stream of its iteration starts and ends
     int state;               // 0 iterating, 1 done, < 0 failed (status)
+    bool begun;              // its start's host half is read; ev covers the device work it queued
     double prev;
     int converged, hit_max;
     Ctx cx;
@@ -43,14 +46,19 @@ struct BatchMember {
     std::vector<long long> joins, leaves, comms;
 };
 
+#define BATCH_SIDES 2
+
 struct lf_batch {
     int device;
     hipStream_t stream;
     bool own_stream;
     std::vector<BatchMember *> members;      // by member id; nullptr once removed
     std::vector<BatchMember *> live;         // members still iterating (any order)
-    std::deque<BatchMember *> waitq;         // members whose queued start or end is not yet
-                                             // read, in queue order (the stream runs them so)
+    // Iteration starts and ends run on side streams, beside the steps: an end waits (on the
+    // device) for its member's last step; a start follows an end the host has seen done.
+    hipStream_t side[BATCH_SIDES];
+    std::deque<BatchMember *> waitq[BATCH_SIDES];   // members whose queued start or end is
+                                             // not yet read, in each side stream's order
     Member *hmem[2];
     int *hboff[2];
     hipEvent_t hev[2];
@@ -250,6 +258,9 @@ int lf_batch_create(lf_batch **out, int device, void *hip_stream)
     bool ok = hipEventCreateWithFlags(&b->hev[0], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&b->hev[1], hipEventDisableTiming) == hipSuccess;
     b->own_stream = false;
+    for (int k = 0; k < BATCH_SIDES; k++) b->side[k] = nullptr;
+    for (int k = 0; k < BATCH_SIDES && ok; k++)
+        ok = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) == hipSuccess;
     if (ok && hip_stream) {
         b->stream = (hipStream_t)hip_stream;
     } else if (ok) {
@@ -259,6 +270,8 @@ int lf_batch_create(lf_batch **out, int device, void *hip_stream)
     if (!ok) {
         for (int s = 0; s < 2; s++)
             if (b->hev[s]) (void)hipEventDestroy(b->hev[s]);
+        for (int k = 0; k < BATCH_SIDES; k++)
+            if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
         delete b;
         return LF_EDEVICE;
     }
@@ -289,6 +302,11 @@ int lf_batch_add(lf_batch *b, lf_handle *h, int32_t queue_size, double threshold
         delete m;
         return batch_error(b, LF_EDEVICE, "event creation failed");
     }
+    if (hipEventCreateWithFlags(&m->ran, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(m->ev);
+        delete m;
+        return batch_error(b, LF_EDEVICE, "event creation failed");
+    }
     m->h = h;
     m->saved_stream = h->stream;
     h->stream = b->stream;
@@ -301,34 +319,58 @@ int lf_batch_add(lf_batch *b, lf_handle *h, int32_t queue_size, double threshold
     m->theta = threshold;
     m->it = 0;
     m->phase = PH_BEGIN;
+    m->begun = false;
     m->state = (h->cc == 0.0 || max_iters == 0) ? 1 : 0;
     m->converged = h->cc == 0.0 ? 1 : 0;
     m->hit_max = 0;
     m->prev = h->Wt;
     m->hist.push_back(h->Wt);
     *member_id = (int32_t)b->members.size();
+    m->side = *member_id % BATCH_SIDES;
     b->members.push_back(m);
     if (m->state == 0) b->live.push_back(m);
     return LF_OK;
 }
 
-// a member's queued start or end has completed: read its report and move it on
-static int member_phase_done(BatchMember *m)
+// A member's queued start or end has completed: read its report and move it on.  The
+// host halves run with the member's side stream current, so device work they queue (a
+// grown buffer refilled) stays in order with its starts and ends; a start whose host
+// half queued some is waited for once more (*requeue) before the member steps.
+static int member_phase_done(lf_batch *b, BatchMember *m, bool *requeue)
 {
-    if (m->phase == PH_END_WAIT) return member_iteration_done(m);   // PH_BEGIN, or done
-    int rc = lf_iter_begin_complete(m->h, m->qq, &m->nq);
-    if (rc == LF_OK) {
-        m->cx = lf_ctx(m->h);
-        m->k = 0;
+    *requeue = false;
+    lf_handle *h = m->h;
+    hipStream_t sd = b->side[m->side];
+    h->stream = sd;
+    int rc = LF_OK;
+    if (m->phase == PH_END_WAIT) {
+        rc = member_iteration_done(m);          // PH_BEGIN, or done
+    } else if (m->begun) {
+        m->begun = false;
         m->phase = PH_RUN;
+    } else {
+        rc = lf_iter_begin_complete(h, m->qq, &m->nq);
+        if (rc == LF_OK) {
+            m->cx = lf_ctx(h);
+            m->k = 0;
+            if (h->second_half_work) {
+                rc = hipEventRecord(m->ev, sd) == hipSuccess ? LF_OK : LF_EDEVICE;
+                m->begun = true;
+                *requeue = true;
+            } else {
+                m->phase = PH_RUN;
+            }
+        }
     }
+    h->stream = b->stream;
     return rc;
 }
 
 static void drop_member(lf_batch *b, BatchMember *m)
 {
-    auto w = std::find(b->waitq.begin(), b->waitq.end(), m);
-    if (w != b->waitq.end()) b->waitq.erase(w);
+    std::deque<BatchMember *> &q = b->waitq[m->side];
+    auto w = std::find(q.begin(), q.end(), m);
+    if (w != q.end()) q.erase(w);
     auto l = std::find(b->live.begin(), b->live.end(), m);
     if (l != b->live.end()) {
         *l = b->live.back();
@@ -341,15 +383,20 @@ int lf_batch_step(lf_batch *b, int32_t *running)
     if (!b) return LF_EINVAL;
     std::vector<BatchMember *> act;
     auto tp = std::chrono::steady_clock::now();
-    // queued starts and ends that have completed, oldest first: the batch stream runs
-    // them in queue order, so the first one not done ends the scan
-    while (!b->waitq.empty()) {
-        BatchMember *m = b->waitq.front();
-        hipError_t q = hipEventQuery(m->ev);
-        if (q == hipErrorNotReady) break;
-        b->waitq.pop_front();
-        int rc = q == hipSuccess ? member_phase_done(m) : LF_EDEVICE;
-        if (rc != LF_OK) m->state = rc;
+    // queued starts and ends that have completed, oldest first: a side stream runs them in
+    // queue order, so its first one not done ends its scan
+    for (int k = 0; k < BATCH_SIDES; k++) {
+        std::deque<BatchMember *> &wq = b->waitq[k];
+        while (!wq.empty()) {
+            BatchMember *m = wq.front();
+            hipError_t q = hipEventQuery(m->ev);
+            if (q == hipErrorNotReady) break;
+            wq.pop_front();
+            bool requeue = false;
+            int rc = q == hipSuccess ? member_phase_done(b, m, &requeue) : LF_EDEVICE;
+            if (rc != LF_OK) m->state = rc;
+            else if (requeue) wq.push_back(m);
+        }
     }
     for (size_t i = 0; i < b->live.size();) {
         BatchMember *m = b->live[i];
@@ -360,25 +407,32 @@ int lf_batch_step(lf_batch *b, int32_t *running)
         }
         i++;
         if (m->phase == PH_BEGIN) {
+            hipStream_t sd = b->side[m->side];
+            m->h->stream = sd;
             int rc = lf_iter_begin_enqueue(m->h, m->qq);
-            if (rc == LF_OK && hipEventRecord(m->ev, b->stream) != hipSuccess) rc = LF_EDEVICE;
+            if (rc == LF_OK && hipEventRecord(m->ev, sd) != hipSuccess) rc = LF_EDEVICE;
+            m->h->stream = b->stream;
             if (rc != LF_OK) {
                 m->state = rc;
                 continue;
             }
             m->phase = PH_BEGIN_WAIT;
-            b->waitq.push_back(m);
+            b->waitq[m->side].push_back(m);
         } else if (m->phase == PH_RUN) {
             act.push_back(m);
         }
     }
     b->phase_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
-    if (act.empty() && !b->waitq.empty()) {
-        // nothing to launch: wait for the oldest queued start or end instead of spinning
-        auto t0 = std::chrono::steady_clock::now();
-        if (hipEventSynchronize(b->waitq.front()->ev) != hipSuccess)
-            return batch_error(b, LF_EDEVICE, "event sync failed");
-        b->wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (act.empty()) {
+        // nothing to launch: wait for a queued start or end instead of spinning
+        for (int k = 0; k < BATCH_SIDES; k++) {
+            if (b->waitq[k].empty()) continue;
+            auto t0 = std::chrono::steady_clock::now();
+            if (hipEventSynchronize(b->waitq[k].front()->ev) != hipSuccess)
+                return batch_error(b, LF_EDEVICE, "event sync failed");
+            b->wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            break;
+        }
     }
     const int nm = (int)act.size();
     if (nm > 0) {
@@ -424,13 +478,20 @@ int lf_batch_step(lf_batch *b, int32_t *running)
         for (BatchMember *m : act) {
             m->k++;
             if (m->k == m->nq) {
-                int rc = lf_iter_finish_enqueue(m->h);
-                if (rc == LF_OK && hipEventRecord(m->ev, b->stream) != hipSuccess) rc = LF_EDEVICE;
+                // the end runs on the member's side stream once this step is done
+                hipStream_t sd = b->side[m->side];
+                int rc = LF_OK;
+                if (hipEventRecord(m->ran, b->stream) != hipSuccess || hipStreamWaitEvent(sd, m->ran, 0) != hipSuccess)
+                    rc = LF_EDEVICE;
+                m->h->stream = sd;
+                if (rc == LF_OK) rc = lf_iter_finish_enqueue(m->h);
+                if (rc == LF_OK && hipEventRecord(m->ev, sd) != hipSuccess) rc = LF_EDEVICE;
+                m->h->stream = b->stream;
                 if (rc != LF_OK) {
                     m->state = rc;
                 } else {
                     m->phase = PH_END_WAIT;
-                    b->waitq.push_back(m);
+                    b->waitq[m->side].push_back(m);
                 }
             }
         }
@@ -481,18 +542,20 @@ int lf_batch_remove(lf_batch *b, int32_t member_id)
     // mid-iteration the memberships live in the handle's lines: back to its slot layout
     if (m->state == 0 && m->phase == PH_RUN) (void)lf_lines_back(m->h);
     (void)hipStreamSynchronize(b->stream);
+    for (int k = 0; k < BATCH_SIDES; k++) (void)hipStreamSynchronize(b->side[k]);
     m->h->stream = m->saved_stream;
     m->h->phase_graphs = 0;
     lf_phase_graphs_drop(m->h);
     (void)hipEventDestroy(m->ev);
+    (void)hipEventDestroy(m->ran);
     delete m;
     b->members[member_id] = nullptr;
     return LF_OK;
 }
 
 // Take a finished member out of the batch without waiting: *left is recorded behind its
-// last work on the batch stream, and the caller waits for it before using the handle
-// (which is back on its own stream) and destroys it afterwards.
+// last work on the batch stream and its side stream, and the caller waits for it before
+// using the handle (which is back on its own stream) and destroys it afterwards.
 int lf_batch_detach(lf_batch *b, int32_t member_id, hipEvent_t *left)
 {
     *left = nullptr;
@@ -501,7 +564,12 @@ int lf_batch_detach(lf_batch *b, int32_t member_id, hipEvent_t *left)
     BatchMember *m = b->members[member_id];
     drop_member(b, m);
     if (m->state == 0 && m->phase == PH_RUN) (void)lf_lines_back(m->h);
-    int rc = hipEventRecord(m->ev, b->stream) == hipSuccess ? LF_OK : LF_EDEVICE;
+    hipStream_t sd = b->side[m->side];
+    int rc = hipEventRecord(m->ran, b->stream) == hipSuccess && hipStreamWaitEvent(sd, m->ran, 0) == hipSuccess &&
+                     hipEventRecord(m->ev, sd) == hipSuccess
+                 ? LF_OK
+                 : LF_EDEVICE;
+    (void)hipEventDestroy(m->ran);          // released once the wait on it has passed
     *left = m->ev;
     m->h->stream = m->saved_stream;
     m->h->phase_graphs = 0;         // its graphs go with the handle, after the wait
@@ -527,6 +595,7 @@ int lf_batch_destroy(lf_batch *b)
     if (b->dmem) (void)hipFree(b->dmem);
     if (b->dboff) (void)hipFree(b->dboff);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    for (int k = 0; k < BATCH_SIDES; k++) (void)hipStreamDestroy(b->side[k]);
     delete b;
     return LF_OK;
 }

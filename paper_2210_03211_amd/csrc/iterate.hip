@@ -1662,6 +1662,7 @@ static int size_queue_complete(lf_handle *h, long long q)
     const long long n = h->n;
     const long long nq = (n + q - 1) / q;
     bool moved = h->pending_moved;
+    h->second_half_work = false;
     const unsigned fill_grid = h->fill_grid;
     const long long *nt_dev = h->dq + LF_PATH_TABLE * (nq + 1) + nq;
     const unsigned long long *hb = (const unsigned long long *)(h->hqoff + REP_BOUNDS(nq));
@@ -1684,8 +1685,10 @@ static int size_queue_complete(lf_handle *h, long long q)
         LF_TRY(lf_dev_alloc(h, (void **)&h->titem_node, sizeof(int) * want));
         h->titem_cap = want;
         moved = true;
-        if (nt > 0)
+        if (nt > 0) {
             hipLaunchKernelGGL(k_titem_fill, dim3(fill_grid), dim3(BS), 0, st, lf_ctx(h), nt_dev, h->titem_cap);
+            h->second_half_work = true;
+        }
     }
     long long T = 1024;
     while (T < 2 * keys) T <<= 1;
@@ -1701,6 +1704,7 @@ static int size_queue_complete(lf_handle *h, long long q)
         LF_TRY(lf_dev_alloc(h, (void **)&h->occ_key, sizeof(unsigned long long) * T));
         LF_TRY(lf_dev_alloc(h, (void **)&h->occ_d, sizeof(double) * T));
         LF_HIP(h, hipMemsetAsync(h->gt, 0, sizeof(GEntry) * T, st));
+        h->second_half_work = true;
         hipLaunchKernelGGL(k_empty_table, dim3(grid_for(T, BS)), dim3(BS), 0, st, h->gt, T);
         h->gT = T;
         moved = true;

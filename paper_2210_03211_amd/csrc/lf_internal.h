@@ -290,6 +290,7 @@ struct lf_handle {
     long long *dq;           // [dq_cap] device: what the iteration start copies to hqoff
     long long dq_cap;
     bool pending_moved;      // buffers moved in the first half of an iteration start
+    bool second_half_work;   // the second half of the last start queued device work
     unsigned fill_grid;      // grid of the table work-item fill of that start
     unsigned long long *big_bj, *big_bl;
     int *big_cj, *big_cl;
