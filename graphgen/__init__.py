@@ -159,7 +159,7 @@ def _membership_matrix(n, mnode, mcomm, width):
 
 
 def planted_powerlaw(n, target_edges, deg_exp, deg_max, deg_min_floor, mem_max, size_exp,
-                     size_min, size_max, mu, seed, mem_ratio=0.5, excess=1.04):
+                     size_min, size_max, mu, seed, mem_ratio=0.5, excess=1.04, cap_intra=False):
     """LFR-style planted-overlap graph with power-law degrees and community sizes.
 
     1. degrees: floor of a continuous power law (exponent deg_exp, max deg_max); the lower
@@ -170,7 +170,9 @@ def planted_powerlaw(n, target_edges, deg_exp, deg_max, deg_min_floor, mem_max, 
        membership count; memberships paired with community slots at random;
     4. (1-mu)*d intra stubs split over the node's communities, matched by a configuration
        model inside each community; mu*d inter stubs matched globally, pairs that share a
-       community rejected.
+       community rejected.  With cap_intra a node's stubs in a community are capped at the
+       community's size minus one and the rest become inter stubs, so that a hub whose
+       communities are smaller than its degree still realises its degree.
     """
     rng = _rng(seed)
     target_mean = 2.0 * target_edges / n * excess   # excess: multi-edges are dropped later
@@ -212,6 +214,11 @@ def planted_powerlaw(n, target_edges, deg_exp, deg_max, deg_min_floor, mem_max, 
     for j in range(mem_max):
         has = mc > j
         cnt = np.where(has, base + (j < rem), 0)
+        if cap_intra:
+            room = np.where(has, sizes[np.maximum(M[:, j], 0)] - 1, 0)
+            over = np.maximum(cnt - room, 0)
+            cnt = cnt - over
+            inter = inter + over
         owners = np.repeat(np.arange(n, dtype=np.int64), cnt)
         stub_owner.append(owners)
         stub_group.append(M[owners, j])
@@ -327,7 +334,7 @@ def named_config(name: str, seed: int = 0, scale: float = 1.0) -> Graph:
     if name == "social":
         n = max(1000, int(4_000_000 * scale))
         return planted_powerlaw(n, 35_000_000 * n / 4_000_000, 2.3, 15_000, 2, 4, 1.5, 10, 3000,
-                                0.4, seed, excess=1.166)
+                                0.4, seed, excess=1.10, cap_intra=True)
     if name == "dense":
         n = max(1000, int(3_000_000 * scale))
         return planted_powerlaw(n, 117_000_000 * n / 3_000_000, 2.1, 33_000, 2, 5, 1.5, 10, 3000,

@@ -47,6 +47,7 @@ def test_benchmark_workload_is_the_stored_one():
     deg = np.bincount(np.concatenate([u, v]), minlength=g.n)
     assert abs(deg.mean() / (2 * 35_000_000 / 4_000_000) - 1) < 0.01
     assert deg.max() <= 15_000
+    assert deg.max() >= 12_000 and (deg >= 7_000).sum() >= 100   # the hubs of the degree law exist
     cnt = np.diff(g.planted_cover()[0])
     assert cnt.min() == 1 and cnt.max() == 4
 
