@@ -461,6 +461,7 @@ Ctx lf_ctx(lf_handle *h)
     c.big_bl = h->big_bl;
     c.big_cj = h->big_cj;
     c.big_cl = h->big_cl;
+    c.big_ln = h->big_ln;
     c.gt = h->gt;
     c.occ = h->occ;
     c.occ_key = h->occ_key;

@@ -460,8 +460,9 @@ __device__ __forceinline__ bool eval_node(const Ctx &cx, int j, const NodeRec nr
     return true;
 }
 
-__device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg, int own)
+__device__ __forceinline__ void mark_table(const Ctx &cx, int j, int deg, int own, const NodeLine &line)
 {
+    cx.big_ln[j] = line;                    // k_big_final reads it beside each entry's record
     if (cx.stats) {
         atomicAdd(&cx.ctr->work[LF_PATH_TABLE][0], 1ull);
         atomicAdd(&cx.ctr->work[LF_PATH_TABLE][1], (unsigned long long)deg);
@@ -610,7 +611,7 @@ __device__ __forceinline__ void table_visits(const Ctx &cx, int cstart, int ls, 
                 const int xdeg = lxp->deg, xc0 = lxp->cnt;
                 const long long xo0 = lxp->off;
                 Slot *xs = xo0 < 0 ? (Slot *)lxp->s : cx.slot + xo0;
-                if (e == 0) mark_table(cx, j, xdeg, xc0);   // k_big_final reads it after this launch
+                if (e == 0) mark_table(cx, j, xdeg, xc0, *lxp);   // k_big_final reads it after this launch
                 if (e < xdeg) {
                     const NodeLine *lyp = cx.ln + y;
                     vc = lyp->cnt;
@@ -821,22 +822,28 @@ __device__ __forceinline__ void body_big_final(const Ctx &cx, const QStep &qs, i
         double dlt = 0.0;
         bool leave = false;
         if (b >= 0) {
-            {
-                int x = cx.order[cstart + b];
-                const NodeLine hx = cx.ln[x];
-                int k = ge.cnt + (ge.idy > 0 ? 1 : 0);
-                X192 corr = x192_from_digits(ge.d[0], ge.d[1], ge.d[2], ge.d[3]);
-                int own_in = 0;
-                int a = line_find(cx, hx, C, &own_in);
-                leave = a >= 0;
-                if (ge.idy > 0) {
-                    X192 t = visit_term(leave, ge.ii, ge.idy, cx.cr[C].s, bad);
-                    x192_add(corr, t);
-                }
-                if (leave && own_in != k) atomicOr(&cx.ctr->error, LF_DEVERR_INCOUNT);
-                dlt = candidate_delta(cx, C, leave, k, hx.deg, corr, bad);
-                ncand++;
+            // the node's line (copied at its marking) and the whole community record are
+            // gathered side by side; the leave test then picks the record's half
+            const NodeLine hx = cx.big_ln[b];
+            const CommRec rec = cx.cr[C];
+            int k = ge.cnt + (ge.idy > 0 ? 1 : 0);
+            X192 corr = x192_from_digits(ge.d[0], ge.d[1], ge.d[2], ge.d[3]);
+            int own_in = 0;
+            int a = line_find(cx, hx, C, &own_in);
+            leave = a >= 0;
+            if (ge.idy > 0) {
+                X192 t = visit_term(leave, ge.ii, ge.idy, rec.s, bad);
+                x192_add(corr, t);
             }
+            if (leave && own_in != k) atomicOr(&cx.ctr->error, LF_DEVERR_INCOUNT);
+            CandRec r;
+            r.s = rec.s;
+            r.m = rec.m;
+            r.W = rec.W;
+#pragma unroll
+            for (int q = 0; q < 5; q++) r.S[q] = leave ? rec.Sm[q] : rec.Sp[q];
+            dlt = cand_delta(r, leave, k, hx.deg, corr, bad);
+            ncand++;
         }
         // per-node maximum of the positive changes; one atomic per wave when every active
         // lane works on the same node (the common case: a node's entries are contiguous)
@@ -1503,6 +1510,7 @@ void lf_free_iteration_buffers(lf_handle *h)
     void **ptrs[] = {(void **)&h->dj, (void **)&h->dl, (void **)&h->djd, (void **)&h->dld,
                      (void **)&h->big_idx,
                      (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl,
+                     (void **)&h->big_ln,
                      (void **)&h->gt, (void **)&h->occ, (void **)&h->occ_key, (void **)&h->occ_d,
                      (void **)&h->unit, (void **)&h->dpos, (void **)&h->part_rec, (void **)&h->macc,
                      (void **)&h->titem_base, (void **)&h->titem_node};
@@ -1540,7 +1548,8 @@ static int size_queue_enqueue(lf_handle *h, long long q)
     if (q > h->q_cap) {
         void **ptrs[] = {(void **)&h->dj, (void **)&h->dl, (void **)&h->djd, (void **)&h->dld, (void **)&h->dpos,
                          (void **)&h->big_idx,
-                         (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl};
+                         (void **)&h->big_bj, (void **)&h->big_bl, (void **)&h->big_cj, (void **)&h->big_cl,
+                         (void **)&h->big_ln};
         for (void **p : ptrs) {
             lf_dev_free(h, *p);
             *p = nullptr;
@@ -1555,6 +1564,7 @@ static int size_queue_enqueue(lf_handle *h, long long q)
         LF_TRY(lf_dev_alloc(h, (void **)&h->big_bl, sizeof(unsigned long long) * q));
         LF_TRY(lf_dev_alloc(h, (void **)&h->big_cj, sizeof(int) * q));
         LF_TRY(lf_dev_alloc(h, (void **)&h->big_cl, sizeof(int) * q));
+        LF_TRY(lf_dev_alloc(h, (void **)&h->big_ln, sizeof(NodeLine) * q));
         h->q_cap = q;
         moved = true;
     }

@@ -162,6 +162,7 @@ struct Ctx {
     int *titem_node;         // [items] table-path list position owning each item
     unsigned long long *big_bj, *big_bl;   // [q] best join / leave change (bits; 0 = none)
     int *big_cj, *big_cl;    // [q] lowest community id among the best
+    NodeLine *big_ln;        // [q] a table-path node's line at the queue start
     GEntry *gt;                // [gT] key (j << 32 | C), empty = ~0
     int *occ;                  // [gT] occupied entries
     unsigned long long *occ_key;  // [gT] key | leave << 63
@@ -294,6 +295,7 @@ struct lf_handle {
     unsigned fill_grid;      // grid of the table work-item fill of that start
     unsigned long long *big_bj, *big_bl;
     int *big_cj, *big_cl;
+    NodeLine *big_ln;
     GEntry *gt;
     int *occ;
     unsigned long long *occ_key;
