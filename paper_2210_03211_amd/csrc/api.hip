@@ -138,7 +138,8 @@ static void reset_graph(lf_handle *h)
 {
     lf_free_partition(h);
     void **ptrs[] = {(void **)&h->rowptr, (void **)&h->col, (void **)&h->deg, (void **)&h->orig_id,
-                     (void **)&h->tri, (void **)&h->ccl, (void **)&h->order, (void **)&h->rank};
+                     (void **)&h->tri, (void **)&h->ccl, (void **)&h->order, (void **)&h->rank,
+                     (void **)&h->col_rank};
     for (void **p : ptrs) {
         lf_dev_free(h, *p);
         *p = nullptr;
@@ -185,7 +186,8 @@ int lf_init_communities(lf_handle *h)
     if (h->state < 1) return lf_set_error(h, LF_ESTATE, "lf_load_graph has not been called");
     LF_HIP(h, hipSetDevice(h->device));
     if (h->state == 1 || !h->order) {
-        void **ptrs[] = {(void **)&h->tri, (void **)&h->ccl, (void **)&h->order, (void **)&h->rank};
+        void **ptrs[] = {(void **)&h->tri, (void **)&h->ccl, (void **)&h->order, (void **)&h->rank,
+                     (void **)&h->col_rank};
         for (void **p : ptrs) {
             lf_dev_free(h, *p);
             *p = nullptr;
@@ -208,7 +210,8 @@ int lf_init_from_memberships(lf_handle *h, const int64_t *offsets, const int32_t
     if (total + h->n >= (1ll << 31) - 1) return lf_set_error(h, LF_EOVERFLOW, "cover too large");
     LF_HIP(h, hipSetDevice(h->device));
     if (h->state == 1 || !h->order) {
-        void **ptrs[] = {(void **)&h->tri, (void **)&h->ccl, (void **)&h->order, (void **)&h->rank};
+        void **ptrs[] = {(void **)&h->tri, (void **)&h->ccl, (void **)&h->order, (void **)&h->rank,
+                     (void **)&h->col_rank};
         for (void **p : ptrs) {
             lf_dev_free(h, *p);
             *p = nullptr;

@@ -455,6 +455,7 @@ Ctx lf_ctx(lf_handle *h)
         c.prec[k] = h->prec[k];
     }
     c.rank = h->rank;
+    c.col_rank = h->col_rank;
     c.titem_base = h->titem_base;
     c.titem_node = h->titem_node;
     c.big_bj = h->big_bj;

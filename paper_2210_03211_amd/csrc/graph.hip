@@ -615,6 +615,15 @@ __global__ void k_rank(const int *order, long long n, int *rank)
     rank[order[r]] = (int)r;
 }
 
+// the order position of every adjacency entry's node, so that a pass over a node's
+// neighbours reads their positions with its column indices instead of one hop later
+__global__ void k_col_rank(const int *col, long long m, const int *rank, int *out)
+{
+    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    out[e] = rank[col[e]];
+}
+
 __global__ void k_clear_int(int *p) { *p = 0; }
 
 // The exact sum on caller-placed scratch: part (LF_EXACT_PARTIALS X192 entries), err (one
@@ -762,6 +771,8 @@ int lf_node_stats(lf_handle *h)
     // order: stable sort by degree descending, then stable sort by CC descending
     LF_TRY(lf_dev_alloc(h, (void **)&h->order, sizeof(int) * (n > 0 ? n : 1)));
     LF_TRY(lf_dev_alloc(h, (void **)&h->rank, sizeof(int) * (n > 0 ? n : 1)));
+    const long long m = 2 * h->ne;
+    LF_TRY(lf_dev_alloc(h, (void **)&h->col_rank, sizeof(int) * (m > 0 ? m : 1)));
     unsigned *k1 = nullptr, *k1b = nullptr;
     int *v1 = nullptr, *v1b = nullptr;
     unsigned long long *k2 = nullptr, *k2b = nullptr;
@@ -782,6 +793,7 @@ int lf_node_stats(lf_handle *h)
     LF_TRY(lf_sort_pairs_u64_i32(h, k2, k2b, rv1, other, n, 62, &rk2, &rv2));
     LF_HIP(h, hipMemcpyAsync(h->order, rv2, sizeof(int) * (n > 0 ? n : 1), hipMemcpyDeviceToDevice, st));
     if (n > 0) hipLaunchKernelGGL(k_rank, dim3(grid_for(n, BS)), dim3(BS), 0, st, h->order, n, h->rank);
+    if (m > 0) hipLaunchKernelGGL(k_col_rank, dim3(grid_for(m, BS)), dim3(BS), 0, st, h->col, m, h->rank, h->col_rank);
     unsigned long long ht = 0;
     LF_HIP(h, hipMemcpyAsync(&h->cc, dcc, sizeof(double), hipMemcpyDeviceToHost, st));
     LF_HIP(h, hipMemcpyAsync(&ht, tsum, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));

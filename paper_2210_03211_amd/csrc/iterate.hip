@@ -1076,6 +1076,7 @@ __device__ __forceinline__ void apply_unit(const Ctx &cx, const QStep &qs, long 
     const int j = ur.r - qs.cstart;
     // the unit's neighbours, the node's decision, join position and line placement
     const int y = lane < ur.cnt ? cx.col[ur.rb + lane] : -1;
+    const int ry = lane < ur.cnt ? cx.col_rank[ur.rb + lane] : -1;
     int J, L;
     queue_decision(cx, j, J, L, nullptr, nullptr);
     const int pos = cx.dpos[j];
@@ -1087,7 +1088,7 @@ __device__ __forceinline__ void apply_unit(const Ctx &cx, const QStep &qs, long 
     int Jy = -1, Ly = -1;
     if (y >= 0) {
         ly = cx.ln[y];
-        const int jy = cx.rank[y] - qs.cstart;
+        const int jy = ry - qs.cstart;
         if (jy >= 0 && jy < qs.clen) queue_decision(cx, jy, Jy, Ly, nullptr, nullptr);
     }
     bool inJ = false;
@@ -1299,7 +1300,7 @@ __global__ void __launch_bounds__(256) k_node_bounds(Ctx cx, long long *vbound, 
     for (long long e = rb + lane; e < re; e += WAVE) {
         int y = cx.col[e];
         v += cx.nh[y].cnt;
-        pre += cx.rank[y] < rx ? 1 : 0;
+        pre += cx.col_rank[e] < rx ? 1 : 0;
     }
     v = wave_sum_i64(v);
     pre = wave_sum_i64(pre);

@@ -158,6 +158,7 @@ struct Ctx {
     int *plist[LF_PATH_COUNT];
     const NodeRec *prec[LF_PATH_COUNT];   // parallel to plist: the node's record
     const int *rank;         // [n] order position of each node
+    const int *col_rank;     // [2 ne] order position of col[e], beside col
     long long *titem_base;   // [table-path nodes + 1] first work item of each
     int *titem_node;         // [items] table-path list position owning each item
     unsigned long long *big_bj, *big_bl;   // [q] best join / leave change (bits; 0 = none)
@@ -249,6 +250,7 @@ struct lf_handle {
     double *ccl;
     int *order;
     int *rank;
+    int *col_rank;
     double cc;
     long long T;
     // partition
