@@ -268,20 +268,26 @@ __global__ void k_iota(int *a, long long n)
 }
 
 // ------------------------------------------------------------------------------------
-// exact re-sum of touched communities (persistent: each wave takes communities from the
-// touched list until it is exhausted)
+// exact re-sum of touched communities (persistent: each wave takes REFRESH_CHUNK
+// consecutive entries of the touched list at a time until it is exhausted; one returning
+// atomic per community on the shared counter would serialise the launch)
 // ------------------------------------------------------------------------------------
+#define REFRESH_CHUNK 16
 __global__ void __launch_bounds__(256) k_refresh_list(Ctx cx, int fixed_count)
 {
     int lane = threadIdx.x & (WAVE - 1);
     int count = fixed_count >= 0 ? fixed_count : __atomic_load_n(&cx.ctr->tcount, __ATOMIC_RELAXED);
     int bad = 0;
+    // unsigned: the last grabs may pass 2^31 when the list nears the int range
+    unsigned idx = 0, end = 0;
     while (true) {
-        int idx = 0;
-        if (lane == 0) idx = atomicAdd(&cx.ctr->refresh_next, 1);
-        idx = __shfl(idx, 0, WAVE);
-        if (idx >= count) break;
-        int C = cx.tlist[idx];
+        if (idx == end) {
+            if (lane == 0) idx = atomicAdd((unsigned *)&cx.ctr->refresh_next, (unsigned)REFRESH_CHUNK);
+            idx = __shfl(idx, 0, WAVE);
+            end = idx + REFRESH_CHUNK;
+        }
+        if (idx >= (unsigned)count) break;
+        int C = cx.tlist[idx++];
         long long s = cx.cr[C].s;
         long long base = cx.cm_off[C];
         long long cap = cx.cm_off[C + 1] - base;
