@@ -1288,31 +1288,67 @@ QUEUE_KERNELS(k_refresh, 256, NoLds, body_refresh)
 // in the same queue are read at the queue's start).  So visits at evaluation <=
 // B = visits at the iteration start + neighbours earlier in the order, and the path
 // chosen from B always fits.  vbound[x] = B + own + 1 bounds x's distinct table keys.
+// NB_NODES consecutive nodes per wave: their neighbour ranges are walked as one flattened
+// range (most nodes have far fewer than 64 neighbours), each lane finding its node in the
+// wave's range starts, and the per-node sums collect in LDS.
+#define NB_NODES 16
 __global__ void __launch_bounds__(256) k_node_bounds(Ctx cx, long long *vbound, int *cls, int wcap, int mcap,
                                                      int gcap)
 {
-    long long x = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / WAVE;
-    int lane = threadIdx.x & (WAVE - 1);
-    if (x >= cx.n) return;
-    const long long rb = cx.rowptr[x], re = cx.rowptr[x + 1];
-    const int rx = cx.rank[x];
-    long long v = 0, pre = 0;
-    for (long long e = rb + lane; e < re; e += WAVE) {
-        int y = cx.col[e];
-        v += cx.nh[y].cnt;
-        pre += cx.col_rank[e] < rx ? 1 : 0;
+    __shared__ long long s_start[256 / WAVE][NB_NODES + 1];
+    __shared__ long long s_rb[256 / WAVE][NB_NODES];
+    __shared__ unsigned long long s_v[256 / WAVE][NB_NODES];
+    __shared__ unsigned s_pre[256 / WAVE][NB_NODES];
+    __shared__ int s_rx[256 / WAVE][NB_NODES];
+    const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const long long x0 = (blockIdx.x * (long long)(blockDim.x / WAVE) + wv) * NB_NODES;
+    if (x0 >= cx.n) return;                 // uniform over the wave; only wave-level syncs below
+    const int nn = cx.n - x0 < NB_NODES ? (int)(cx.n - x0) : NB_NODES;
+    long long rb = 0, d = 0;
+    int rx = 0;
+    if (lane < nn) {
+        rb = cx.rowptr[x0 + lane];
+        d = cx.rowptr[x0 + lane + 1] - rb;
+        rx = cx.rank[x0 + lane];
     }
-    v = wave_sum_i64(v);
-    pre = wave_sum_i64(pre);
-    if (lane == 0) {
+    long long incl = d;                     // lanes >= nn add nothing
+    for (int o = 1; o < NB_NODES; o <<= 1) {
+        const long long t = __shfl_up(incl, o, WAVE);
+        if (lane >= o) incl += t;
+    }
+    const long long D = __shfl(incl, NB_NODES - 1, WAVE);
+    if (lane < NB_NODES) {
+        s_start[wv][lane + 1] = incl;
+        s_rb[wv][lane] = rb;
+        s_rx[wv][lane] = rx;
+        s_v[wv][lane] = 0;
+        s_pre[wv][lane] = 0;
+    }
+    if (lane == 0) s_start[wv][0] = 0;
+    WAVE_SYNC();
+    for (long long f = lane; f < D; f += WAVE) {
+        int lo = 0, hi = nn - 1;            // the last node whose range starts at or before f
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[wv][mid] <= f) lo = mid; else hi = mid - 1;
+        }
+        const long long e = s_rb[wv][lo] + (f - s_start[wv][lo]);
+        const int y = cx.col[e];
+        const int ry = cx.col_rank[e];
+        atomicAdd(&s_v[wv][lo], (unsigned long long)cx.nh[y].cnt);
+        if (ry < s_rx[wv][lo]) atomicAdd(&s_pre[wv][lo], 1u);
+    }
+    WAVE_SYNC();
+    if (lane < nn) {
+        const long long x = x0 + lane;
         NodeHdr hx = cx.nh[x];
-        const long long B = v + pre, M = hx.cnt, d = hx.deg;
+        const long long B = (long long)s_v[wv][lane] + s_pre[wv][lane], M = hx.cnt, dd = hx.deg;
         vbound[x] = B + M + 1;
         int c = LF_PATH_TABLE;
         if (M <= MXCAP) {
-            if (d <= VSMALL && B + M <= VSMALL && 2 * (B + M) <= wcap) c = LF_PATH_SMALL;
-            else if (d <= VMED && B + M <= VMED && 2 * (B + M) <= mcap) c = LF_PATH_MED;
-            else if (d <= VGRP && B + M <= VGRP && 2 * (B + M) <= gcap) c = LF_PATH_GROUP;
+            if (dd <= VSMALL && B + M <= VSMALL && 2 * (B + M) <= wcap) c = LF_PATH_SMALL;
+            else if (dd <= VMED && B + M <= VMED && 2 * (B + M) <= mcap) c = LF_PATH_MED;
+            else if (dd <= VGRP && B + M <= VGRP && 2 * (B + M) <= gcap) c = LF_PATH_GROUP;
         }
         cls[rx] = c;
     }
@@ -1572,7 +1608,8 @@ static int size_queue_enqueue(lf_handle *h, long long q)
     // paths of this iteration, then bounds of the table path and in-count items
     const long long nq = (n + q - 1) / q;
     Ctx cx = lf_ctx(h);
-    hipLaunchKernelGGL(k_node_bounds, dim3(grid_for(n * WAVE, BS)), dim3(BS), 0, st, cx, h->vbound, h->cls,
+    hipLaunchKernelGGL(k_node_bounds, dim3(grid_for((n + NB_NODES - 1) / NB_NODES * WAVE, BS)), dim3(BS), 0, st,
+                       cx, h->vbound, h->cls,
                        h->eval_wave_cap < 2 * VSMALL ? h->eval_wave_cap : 2 * VSMALL, h->eval_med_cap,
                        h->eval_grp_cap);
     if (h->hqoff_cap < nq + 1) {            // pinned, so the one copy below is truly asynchronous
