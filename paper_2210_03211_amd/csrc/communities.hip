@@ -37,6 +37,7 @@
 #include "method.h"
 
 static inline unsigned grid_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
+static inline unsigned min_u(unsigned a, unsigned b) { return a < b ? a : b; }
 
 // ------------------------------------------------------------------------------------
 // A3: initial clustering
@@ -314,43 +315,78 @@ __global__ void __launch_bounds__(256) k_refresh_list(Ctx cx, int fixed_count)
 // ------------------------------------------------------------------------------------
 // A6: iteration end
 // ------------------------------------------------------------------------------------
-// communities with fewer than two members are removed: mark them (tflag = 2), zero their
-// statistics, count the live ones
-__global__ void k_mark_dead(Ctx cx)
+// The iteration-end kernels fold their shared counters per block (a grid of at most
+// END_BLOCKS blocks striding over the range): one atomic per wave on a single address
+// would serialise the launch (about 15 ns each).
+#define END_BLOCKS 2048
+
+__device__ __forceinline__ int block_fold_int(int v, bool take_max)
 {
-    long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (c >= cx.K) return;
-    CommRec *r = &cx.cr[c];
-    int s = r->s;
-    if (s < 2) {
-        if (s == 1) cx.tflag[c] = 2;
-        r->s = 0;
-        r->m = 0;
-        r->W = 0.0;
-        for (int k = 0; k < 5; k++) { r->Sp[k] = 0; r->Sm[k] = 0; }
-    } else {
-        atomicAdd(&cx.ctr->live, 1);
+    __shared__ int s_part[256 / WAVE];
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const int t = __shfl_xor(v, o, WAVE);
+        v = take_max ? (t > v ? t : v) : v + t;
     }
-    cx.cm_len[c] = 0;
-    cx.ovf_flag[c] = 0;
+    if ((threadIdx.x & (WAVE - 1)) == 0) s_part[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    v = s_part[0];
+    for (int w = 1; w < (int)blockDim.x / WAVE; w++) v = take_max ? (s_part[w] > v ? s_part[w] : v) : v + s_part[w];
+    return v;
 }
 
-// drop removed communities from every node's slots; next capacity = count + 1
-__global__ void k_drop_dead(Ctx cx, long long *newcap)
+// communities with fewer than two members are removed: mark them (tflag = 2), zero their
+// statistics, count the live ones
+__global__ void __launch_bounds__(256) k_mark_dead(Ctx cx)
 {
-    long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (x >= cx.n) return;
-    NodeHdr hx = cx.nh[x];
-    int w = 0;
-    for (int t = 0; t < hx.cnt; t++) {
-        Slot sl = cx.slot[hx.off + t];
-        if (cx.tflag[sl.comm] == 2) continue;
-        cx.slot[hx.off + w] = sl;
-        w++;
+    int live = 0;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < cx.K;
+         c += (long long)gridDim.x * blockDim.x) {
+        CommRec *r = &cx.cr[c];
+        int s = r->s;
+        if (s < 2) {
+            if (s == 1) cx.tflag[c] = 2;
+            r->s = 0;
+            r->m = 0;
+            r->W = 0.0;
+            for (int k = 0; k < 5; k++) { r->Sp[k] = 0; r->Sm[k] = 0; }
+        } else {
+            live++;
+        }
+        cx.cm_len[c] = 0;
+        cx.ovf_flag[c] = 0;
     }
-    cx.nh[x].cnt = w;
-    newcap[x] = w + 1;
-    atomicMax(&cx.ctr->max_mem, w);
+    live = block_fold_int(live, false);
+    if (threadIdx.x == 0 && live) atomicAdd(&cx.ctr->live, live);
+}
+
+// drop removed communities from every node's slots (four slots and their flags per round
+// trip; a kept slot moves only to a position already read); next capacity = count + 1
+__global__ void __launch_bounds__(256) k_drop_dead(Ctx cx, long long *newcap)
+{
+    int mx = 0;
+    for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < cx.n;
+         x += (long long)gridDim.x * blockDim.x) {
+        NodeHdr hx = cx.nh[x];
+        Slot *xs = cx.slot + hx.off;
+        int w = 0;
+        for (int t0 = 0; t0 < hx.cnt; t0 += 4) {
+            Slot sl[4];
+            bool keep[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (t0 + q < hx.cnt) sl[q] = xs[t0 + q];
+#pragma unroll
+            for (int q = 0; q < 4; q++) keep[q] = t0 + q < hx.cnt && cx.tflag[sl[q].comm] != 2;
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (keep[q]) xs[w++] = sl[q];
+        }
+        cx.nh[x].cnt = w;
+        newcap[x] = w + 1;
+        mx = w > mx ? w : mx;
+    }
+    mx = block_fold_int(mx, true);
+    if (threadIdx.x == 0) atomicMax(&cx.ctr->max_mem, mx);
 }
 
 __global__ void k_clear_dead(Ctx cx)
@@ -805,11 +841,12 @@ int lf_iteration_end_enqueue(lf_handle *h)
     Ctx cx = lf_ctx(h);
     LF_TRY(lf_zero(h, &h->ctr->live, sizeof(int) * 2));   // live, max_mem
     LF_TRY(lf_zero(h, &h->ctr->ovf_cnt, sizeof(int)));
-    if (K > 0) hipLaunchKernelGGL(k_mark_dead, dim3(grid_for(K, BS)), dim3(BS), 0, st, cx);
+    if (K > 0) hipLaunchKernelGGL(k_mark_dead, dim3(min_u(grid_for(K, BS), END_BLOCKS)), dim3(BS), 0, st, cx);
     long long *newcap = nullptr, *noff = nullptr;
     LF_TRY(lf_tmp_alloc(h, (void **)&newcap, sizeof(long long) * (n + 1)));
     LF_TRY(lf_tmp_alloc(h, (void **)&noff, sizeof(long long) * (n + 1)));
-    if (n > 0) hipLaunchKernelGGL(k_drop_dead, dim3(grid_for(n, BS)), dim3(BS), 0, st, cx, newcap);
+    if (n > 0)
+        hipLaunchKernelGGL(k_drop_dead, dim3(min_u(grid_for(n, BS), END_BLOCKS)), dim3(BS), 0, st, cx, newcap);
     if (K > 0) hipLaunchKernelGGL(k_clear_dead, dim3(grid_for(K, BS)), dim3(BS), 0, st, cx);
     LF_TRY(lf_zero(h, newcap + n, sizeof(long long)));
     LF_TRY(lf_exclusive_scan_i64(h, newcap, noff, n + 1));
