@@ -6,15 +6,17 @@
 // its visits that holds for the whole iteration (k_node_bounds), and each path gets the
 // list of its nodes in order.  Per queue (all launches on the handle's stream, no host
 // synchronisation):
-//   k_eval           small path (queues with >= 1024 such nodes): one wave per node
-//                    with <= 64 visits, decided entirely in an LDS hash table
+//   k_eval           the small path (queues with >= 1024 such nodes): one wave per node
+//                    with <= 64 visits; then the medium path: one 256-thread block per
+//                    node with <= 256 visits, one visit per thread; each node decided
+//                    entirely in an LDS hash table
 //   k_eval_big       by block role: the table path's visits (largest nodes): every
 //                    neighbour membership (y in C) adds its exact correction to the entry
 //                    (node, C) of a global open-addressing table, own memberships add the
 //                    leave candidates; the workgroup path (one workgroup per node with
-//                    <= 1024 visits, LDS tables); the medium path (one wave per node with
-//                    <= 256 visits); the small path of smaller queues; block 0 of either
-//                    launch resets the queue's counters
+//                    <= 1024 visits, LDS tables); the small path of smaller queues; in
+//                    multi-graph steps also the medium path (one wave per node); block 0
+//                    of either launch resets the queue's counters
 //   k_big_final      every occupied table entry -> change of C's score; per node the
 //                    largest positive change (atomicMax on the bits of a positive double)
 //   k_big_tie        among the entries equal to that maximum the lowest community id
